@@ -1,0 +1,147 @@
+"""Pins of the oracle's WENO5 reconstruction (paper Sec. 2.2, eqs. for the three
+third-order candidates, the fifth-order combination, the weights and the
+smoothness indicators).  Each pin checks the oracle against something fixed
+independently of its code: exact integrals, printed coefficients, the
+Jiang-Shu integral definition of the indicators, and convergence order."""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+
+def cell_avgs_poly(coeffs, centres, h=1.0):
+    """Exact cell averages over [x - h/2, x + h/2] of the polynomial sum c_n x^n (Fractions)."""
+    out = []
+    for x in centres:
+        a = Fr(x) - Fr(h) / 2
+        b = Fr(x) + Fr(h) / 2
+        s = Fr(0)
+        for n, c in enumerate(coeffs):
+            s += Fr(c) * (b ** (n + 1) - a ** (n + 1)) / (n + 1)
+        out.append(s / Fr(h))
+    return out
+
+
+def poly_val(coeffs, x):
+    return sum(Fr(c) * Fr(x) ** n for n, c in enumerate(coeffs))
+
+
+def test_candidates_exact_for_quadratic_cell_averages(orc):
+    # interface j+1/2 with j = 0 at x = 0 and unit spacing: evaluate at x = 1/2
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        coeffs = [Fr(int(c), 7) for c in rng.integers(-20, 20, size=3)]
+        avg = cell_avgs_poly(coeffs, [-2, -1, 0, 1, 2])
+        exact = float(poly_val(coeffs, Fr(1, 2)))
+        _, parts = orc.weno5(*[float(v) for v in avg], eps=1e-6, parts=True)
+        for k in range(3):
+            assert parts[6 + k] == pytest.approx(exact, rel=1e-14, abs=1e-13)
+
+
+def test_linear_weights_give_printed_fifth_order_interpolant(orc):
+    # Data with equal smoothness indicators (affine data) makes alpha_k
+    # proportional to c_k, so omega = c and the result must be the printed
+    # fifth-order interpolant (2, -13, 47, 27, -3)/60.
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        a0, a1 = rng.uniform(-3, 3, size=2)
+        f = [a0 + a1 * m for m in (-2, -1, 0, 1, 2)]
+        r, parts = orc.weno5(*f, eps=1e-6, parts=True)
+        np.testing.assert_allclose(parts[3:6], [0.1, 0.6, 0.3], rtol=1e-13)
+        printed = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60.0
+        assert r == pytest.approx(printed, rel=1e-13, abs=1e-13)
+
+
+def test_linear_scheme_is_exact_for_quartic_cell_averages(orc):
+    # With the optimal weights the scheme is the fifth-order interpolant, exact
+    # for cell averages of polynomials up to degree 4.  Check through the
+    # returned candidates: sum c_k fhat_k must equal the exact point value.
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        coeffs = [Fr(int(c), 5) for c in rng.integers(-9, 9, size=5)]
+        avg = [float(v) for v in cell_avgs_poly(coeffs, [-2, -1, 0, 1, 2])]
+        _, parts = orc.weno5(*avg, eps=1e-6, parts=True)
+        lin = 0.1 * parts[6] + 0.6 * parts[7] + 0.3 * parts[8]
+        assert lin == pytest.approx(float(poly_val(coeffs, Fr(1, 2))), rel=1e-12, abs=1e-12)
+
+
+def js_indicator(avgs3, offset):
+    """Jiang-Shu smoothness indicator from its integral definition:
+    beta = sum_{l=1,2} h^{2l-1} int_{cell j} (d^l p / dx^l)^2 dx, with p the
+    quadratic whose cell averages over the three cells (offset, offset+1,
+    offset+2) relative to j=0 equal avgs3; h = 1, cell j = [-1/2, 1/2]."""
+    # solve for p(x) = q0 + q1 x + q2 x^2 from exact cell-average conditions
+    rows = []
+    for m in range(3):
+        c = offset + m
+        a, b = Fr(c) - Fr(1, 2), Fr(c) + Fr(1, 2)
+        rows.append([b - a, (b ** 2 - a ** 2) / 2, (b ** 3 - a ** 3) / 3])
+    A = np.array(rows, dtype=object)
+    # 3x3 solve with Fractions (Cramer)
+    def det3(M):
+        return (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
+                - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
+                + M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]))
+    D = det3(A)
+    q = []
+    for col in range(3):
+        M = [list(r) for r in A]
+        for r in range(3):
+            M[r][col] = avgs3[r]
+        q.append(det3(M) / D)
+    q0, q1, q2 = q
+    # p' = q1 + 2 q2 x ; p'' = 2 q2 ; integrate over [-1/2, 1/2]
+    int_p1sq = q1 * q1 + Fr(4) * q2 * q2 * Fr(1, 12)  # int (q1 + 2 q2 x)^2 dx
+    int_p2sq = Fr(4) * q2 * q2
+    return int_p1sq + int_p2sq
+
+
+def test_smoothness_indicators_match_integral_definition(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        f = [Fr(int(v), 3) for v in rng.integers(-30, 30, size=5)]
+        _, parts = orc.weno5(*[float(v) for v in f], eps=1e-6, parts=True)
+        b1 = js_indicator(f[0:3], -2)
+        b2 = js_indicator(f[1:4], -1)
+        b3 = js_indicator(f[2:5], 0)
+        np.testing.assert_allclose(parts[0:3], [float(b1), float(b2), float(b3)], rtol=1e-13, atol=1e-12)
+
+
+def test_weights_are_convex_and_reject_a_discontinuous_stencil(orc):
+    # A unit jump between f_{j+1} and f_{j+2}: only stencil 3 crosses it.
+    r, parts = orc.weno5(0.0, 0.0, 0.0, 0.0, 1.0, eps=1e-6, parts=True)
+    w = parts[3:6]
+    assert w.sum() == pytest.approx(1.0, rel=1e-15)
+    assert np.all(w >= 0)
+    # exponent 2 with eps = 1e-6 puts the crossing stencil's weight near
+    # c3 * (eps/beta3)^2 / (c1 + c2) ~ 1e-13; exponent 1 would leave ~1e-6.
+    assert w[2] < 1e-10
+    assert abs(r) < 1e-10  # the two smooth stencils both give 0
+
+
+def weno_flux_difference(f, eps=1e-6):
+    """(W_{j+1/2} - W_{j-1/2}) on a periodic array through the oracle's W."""
+    n = len(f)
+    W = np.array([orc_w(f[(j - 2) % n], f[(j - 1) % n], f[j], f[(j + 1) % n], f[(j + 2) % n], eps)
+                  for j in range(n)])
+    return W - np.roll(W, 1)
+
+
+orc_w = None
+
+
+def test_fifth_order_convergence_on_smooth_data(orc):
+    global orc_w
+    orc_w = orc.weno5
+    errs = []
+    ns = [32, 64, 128, 256]
+    for n in ns:
+        h = 2 * math.pi / n
+        x = np.arange(n) * h
+        f = np.sin(x + 0.3)
+        d = weno_flux_difference(f) / h
+        errs.append(np.abs(d - np.cos(x + 0.3)).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    # Jiang-Shu weights keep fifth order on sin (no critical-point degeneracy)
+    assert min(orders) > 4.8 and max(orders) < 5.5, (errs, orders)

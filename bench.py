@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64 WENO5-Roe / central-viscous RK4 path on one MI355X.
+
+Workload: 128^3 triply periodic decaying turbulence (seeded synthetic IC with the
+HIT spectrum, Mt = 0.3, Re = 400, gamma = 1.4, Pr = 0.72), classical RK4 at
+CFL 0.5 with kinetic energy and enstrophy reduced after every step.  One "step"
+is one RK4 step = 4 right-hand-side evaluations of the whole grid.
+
+Metric: grid-point RHS evaluations per second (4 * N^3 per step), with the
+state resident in HBM before the timed region starts.
+
+Prints one JSON line.  The roofline object describes the kernel with the
+largest share of the step, timed with HIP events on the plan's stream; the
+cpu_baseline object times the CPU oracle on a bounded sample of the same
+workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP64 operations per grid point of one launch (add, sub, mul, div and
+# sqrt count one each; an FMA counts two), from the kernels' formulation:
+#   point flux 18, WENO5 L+R pair 122 x 10 scalars, Roe dissipation 116,
+#   interface flux 20, viscous interface flux 24, difference 10, plus the output
+#   update (write 0 / accumulate 5 / fused RK4 stage ~30).
+FLOPS_PER_POINT = {
+    "sweep_x": 18 + 1220 + 5 + 116 + 20 + 24 + 10,
+    "sweep_y": 18 + 1220 + 5 + 116 + 20 + 24 + 10 + 5,
+    "sweep_z_rk4": 18 + 1220 + 5 + 116 + 20 + 24 + 10 + 30,
+    "visc_prim": 13,
+    "visc_flux": 12 * 5 + 40,
+    "diagnostics": 120,
+}
+# Algorithmic HBM bytes per grid point of one launch (FP64): each array element
+# read or written once.
+BYTES_PER_POINT = {
+    "sweep_x": 8 * (5 + 4 + 5),            # u, 4 viscous fluxes -> rhs
+    "sweep_y": 8 * (5 + 4 + 5 + 5),        # + rhs read-modify-write
+    "sweep_z_rk4": 8 * (5 + 4 + 5 + 5 + 5 + 5 + 5),  # + u^n, acc (rmw), next stage
+    "visc_prim": 8 * (5 + 4),
+    "visc_flux": 8 * (4 + 9),
+    "diagnostics": 8 * 5,
+}
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=128, help="grid points per direction (128 = the named workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="RK4 steps of the oracle sample")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the workload, copy a buffer of this many MiB device-to-device once "
+                         "(a known-size reference for hardware byte counters)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2211_16718_amd import inputs as I
+    from paper_2211_16718_amd.api import Plan
+
+    if args.calibrate_copy_mib > 0:
+        nb = args.calibrate_copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    n = args.n
+    wl = I.WORKLOADS["hit128"]
+    mu = 1.0 / wl.re
+    rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)
+    plan = Plan((n, n, n), mu_eff=mu, precision="fp64", device="cuda:0")
+    u = plan.init_state(rho, vel, p)
+    smax = plan.diagnostics_host(u)[7]
+    dt = I.dt_from_speed(smax, n, cfl=I.CFL)
+    stream = plan.stream
+
+    # untimed warmup
+    if args.warmup > 0:
+        plan.rk4(u, dt, args.warmup)
+    torch.cuda.synchronize()
+    u_start = u.clone()
+
+    # timed region: exactly K steps, state resident in HBM
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    diag = plan.rk4(u, dt, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    diag_h = diag.cpu().numpy()
+    if np.any(diag_h[:, 8] > 0):
+        print("bench: non-finite or non-physical state during the timed run", file=sys.stderr)
+        sys.exit(3)
+
+    seconds = gpu_ms / 1e3
+    point_rhs = 4.0 * n ** 3 * args.steps
+    value = point_rhs / seconds
+
+    # per-kernel timing of the same K steps (events around every launch)
+    u.copy_(u_start)
+    plan.profile(True)
+    plan.rk4(u, dt, args.steps)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    kernels = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt:
+            kernels[name] = {"avg_ms": ms / cnt, "launches": cnt, "share": None, "total_ms": ms}
+    tot = sum(k["total_ms"] for k in kernels.values())
+    for k in kernels.values():
+        k["share"] = k["total_ms"] / tot
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    avg_s = kernels[dom]["avg_ms"] / 1e3
+    flops = FLOPS_PER_POINT[dom] * n ** 3
+    achieved = flops / avg_s / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            t = json.load(open(tfile))
+            src = open(os.path.join(ROOT, "paper_2211_16718_amd", "csrc", "cns_kernels.hip"), "rb").read()
+            import hashlib
+
+            if t.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and dom in t.get("kernels", {}) \
+                    and t.get("n") == n:
+                traffic = t["kernels"][dom]["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    roofline = {
+        "bound": "alu",
+        "kernel": dom,
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": BYTES_PER_POINT[dom] * n ** 3,
+        "hbm_frac_algorithmic": round(BYTES_PER_POINT[dom] * n ** 3 / avg_s / 1e9 / PEAK_HBM_GBS, 4),
+        "flops_per_point": FLOPS_PER_POINT[dom],
+        "avg_launch_ms": round(kernels[dom]["avg_ms"], 5),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ph = oracle.make_phys(mu_eff=mu)
+        uh = oracle.init_state(rho, vel, p)
+        oracle.rhs(np.ascontiguousarray(uh[:, :8, :8, :8]), ph)  # load the library
+        t0 = time.perf_counter()
+        oracle.rk4(uh, dt, args.cpu_steps, ph)
+        ct = time.perf_counter() - t0
+        cpu = {"value": 4.0 * n ** 3 * args.cpu_steps / ct, "unit": "point-RHS/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{args.cpu_steps} RK4 steps (with diagnostics) of the same {n}^3 workload, "
+                         f"{ct:.1f} s, OpenMP over grid points"}
+
+    out = {
+        "metric": "grid-point RHS evaluations per second (FP64 WENO5-Roe + central viscous, RK4)",
+        "value": value,
+        "unit": "point-RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded HIT-spectrum initial condition)",
+        "config": {"workload": f"hit{n}_re400_rk4_diag_every_step", "grid": [n, n, n], "re": wl.re, "mt": wl.mt,
+                   "cfl": I.CFL, "dt": dt, "precision": "fp64"},
+        "roofline": roofline,
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "launches": v["launches"], "share": round(v["share"], 4)}
+                    for k, v in kernels.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

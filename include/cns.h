@@ -1,0 +1,134 @@
+/*
+ * cns.h -- C-ABI of the MI355X (gfx950) library for the right-hand side of the
+ * 3-D compressible Navier-Stokes equations on a triply periodic Cartesian grid
+ * and its classical RK4 time integration.
+ *
+ * Method (arXiv 2211.16718): Sec. 2.1 defines the equations -- conserved state
+ * u = [rho, rho u, rho v, rho w, e], convective fluxes f, g, h, the equation of
+ * state e = p/(gamma-1) + rho |v|^2 / 2, the viscous fluxes with stress tau_ij
+ * and heat flux q_i, T = gamma p / rho, Pr = 0.72.  Sec. 2.2 defines the
+ * discretisation -- conservative finite differences, the Roe flux with Harten's
+ * entropy fix and |A| = X |Lambda| X^-1 at the Roe average, component-wise
+ * WENO5 (Jiang-Shu weights, epsilon = 1e-6) of f^{L,R} and u^{L,R}, 4th-order
+ * central differences for the viscous terms, and RK4 in time.
+ *
+ * Conventions shared by every call:
+ *  - Return value: CNS_OK (0) or a negative CNS_E* code; cns_last_error() gives a
+ *    thread-local message for the last failure on the calling thread.  No C++
+ *    exception crosses this interface.
+ *  - Memory: every array argument named *_dev or typed as a state is DEVICE
+ *    memory owned by the caller (allocated through PyTorch or hipMalloc).  The
+ *    library never allocates device memory; the scratch it needs is the caller's
+ *    workspace (cns_workspace_bytes / cns_set_workspace).  A plan owns host-side
+ *    state only.
+ *  - State layout: structure-of-arrays u[v][k][j][i], v = 0..4 the conserved
+ *    variable, i (x) fastest, contiguous, 256-byte aligned.  The element type is
+ *    double for CNS_FP64 plans and float for CNS_MIXED plans.
+ *  - Streams: `stream` is a hipStream_t passed as void*.  Calls enqueue on the
+ *    plan's stream and return without synchronising, except where a call
+ *    returns host values (stated per call).
+ *  - Periodic grid: x_i = i * lx / nx, i = 0..nx-1, likewise y and z; nx, ny, nz >= 8.
+ */
+#ifndef CNS_H
+#define CNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CNS_OK 0
+#define CNS_EINVAL (-1)        /* null/misaligned pointer, bad size, bad parameter */
+#define CNS_EHIP (-2)          /* a HIP runtime error (message from hipGetErrorString) */
+#define CNS_ENONFINITE (-3)    /* a non-finite value was produced or found */
+#define CNS_ENONPHYSICAL (-4)  /* rho <= 0 or p <= 0 found */
+#define CNS_EWORKSPACE (-5)    /* workspace missing or too small */
+#define CNS_EUNSUPPORTED (-6)  /* operation not available for this plan */
+
+/* diagnostics record: K = <|m|^2/(2 rho)>, Omega = <|curl v|^2>/2 (4th-order central
+ * derivatives), <rho>, <rho u>, <rho v>, <rho w>, <e> (grid means),
+ * max over points and directions of |v_d| + c, count of bad points
+ * (non-finite, rho <= 0 or p <= 0). */
+#define CNS_NDIAG 9
+
+typedef struct {
+    int32_t nx, ny, nz;
+    double lx, ly, lz;
+} cns_grid;
+
+typedef struct {
+    double gamma;        /* ratio of specific heats, > 1 */
+    double prandtl;      /* Prandtl number, > 0 when mu_eff > 0 */
+    double mu_eff;       /* mu * M_inf / Re_inf (Sec. 2.1 scaling); 0 = Euler (viscous terms skipped) */
+    double weno_eps;     /* epsilon of the WENO weights, > 0 (paper: 1e-6) */
+    double harten_delta; /* Harten threshold delta >= 0; 0 = plain |lambda| */
+} cns_physics;
+
+enum { CNS_FP64 = 0, CNS_MIXED = 1 };
+
+typedef struct cns_plan cns_plan;
+
+/* Create a plan for one periodic box.  precision: CNS_FP64 (state and arithmetic in
+ * double) or CNS_MIXED (state, stage states and WENO/flux arithmetic in float; WENO
+ * smoothness-indicator sums and the RK4 accumulator in double).  stream: hipStream_t
+ * or NULL for the default stream.  *out receives the plan. */
+int cns_plan_create(cns_plan **out, const cns_grid *grid, const cns_physics *phys, int32_t precision,
+                    void *stream);
+int cns_plan_destroy(cns_plan *plan);
+
+/* Bytes of device workspace the plan needs (for every call below). */
+size_t cns_workspace_bytes(const cns_plan *plan);
+/* Bind caller-owned device workspace (>= cns_workspace_bytes, 256-byte aligned). */
+int cns_set_workspace(cns_plan *plan, void *ws_dev, size_t bytes);
+
+/* Launch tuning: segment length (points per thread along the sweep) for each
+ * direction's sweep kernel, and threads per block.  0 keeps the current value.
+ * Results do not depend on these values (bitwise). */
+int cns_set_tiles(cns_plan *plan, int32_t seg_x, int32_t seg_y, int32_t seg_z, int32_t block);
+
+/* Sec. 2.1 equation of state: u = [rho, rho v, p/(gamma-1) + rho|v|^2/2] from device
+ * primitives rho[N3], vel[3][N3], p[N3] (double).  u in plan precision. */
+int cns_init_state(const cns_plan *plan, const double *rho_dev, const double *vel_dev, const double *p_dev,
+                   void *u_dev);
+
+/* Sec. 2.2: full right-hand side rhs = du/dt of the semi-discrete equations. */
+int cns_rhs(const cns_plan *plan, const void *u_dev, void *rhs_dev);
+
+/* Sec. 2.2: the convective term along one direction, out = -(F_{j+1/2} - F_{j-1/2})/dx_dir,
+ * dir 0 = x, 1 = y, 2 = z (Roe + Harten + WENO5 interface fluxes). */
+int cns_rhs_dir(const cns_plan *plan, const void *u_dev, int32_t dir, void *out_dev);
+
+/* Sec. 2.1/2.2: the viscous and heat-flux terms, out = sum_d D_d G^v_d. */
+int cns_viscous(const cns_plan *plan, const void *u_dev, void *out_dev);
+
+/* nsteps classical RK4 steps of size dt, in place on u.  diag_dev (may be NULL)
+ * receives [nsteps][CNS_NDIAG] diagnostics of the state after each step.
+ * Bad points are reported in the diagnostics (the call does not synchronise). */
+int cns_rk4(cns_plan *plan, void *u_dev, double dt, int32_t nsteps, double *diag_dev);
+
+/* Diagnostics of u into device memory out_dev[CNS_NDIAG]. */
+int cns_diagnostics(const cns_plan *plan, const void *u_dev, double *out_dev);
+/* Same, copied to host memory out_host[CNS_NDIAG]; synchronises the plan's stream.
+ * Returns CNS_ENONFINITE / CNS_ENONPHYSICAL when bad points are present (the record
+ * is still written). */
+int cns_diagnostics_host(const cns_plan *plan, const void *u_dev, double *out_host);
+
+/* Per-kernel timing of cns_rk4 with HIP events recorded on the plan's stream around
+ * every launch (an event wait after each step).  Kernel kinds, in order:
+ * viscous primitives, viscous fluxes, x sweep, y sweep, z sweep with the fused RK4
+ * stage update, diagnostics.  enable != 0 clears the totals and turns timing on. */
+#define CNS_NKERNEL 6
+int cns_profile_enable(cns_plan *plan, int32_t enable);
+/* Summed milliseconds and launch counts per kernel kind since the last enable
+ * (host arrays of CNS_NKERNEL entries). */
+int cns_profile_read(const cns_plan *plan, double *ms_host, int64_t *count_host);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char *cns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,136 @@
+"""Python binding of the HIP library (argument marshalling only).
+
+PyTorch supplies device memory and the stream; every step of the computation
+runs in the library's kernels.  A state is a contiguous tensor of shape
+``(5, nz, ny, nx)`` (float64 for ``precision="fp64"``, float32 for
+``precision="mixed"``) on the plan's device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CNS_NDIAG, check
+
+TWO_PI = 2.0 * math.pi
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class Plan:
+    """One periodic box: grid, physics, precision, stream and workspace."""
+
+    def __init__(self, shape, length=(TWO_PI, TWO_PI, TWO_PI), gamma=1.4, prandtl=0.72, mu_eff=0.01,
+                 weno_eps=1e-6, harten_delta=1e-6, precision="fp64", device="cuda:0", stream=None):
+        self.lib = _lib.load()
+        nz, ny, nx = (int(s) for s in shape)
+        self.shape = (nz, ny, nx)
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the HIP library needs a GPU device")
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        prec = _lib.CNS_FP64 if precision == "fp64" else _lib.CNS_MIXED
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.grid = _lib.Grid(nx, ny, nz, *length)
+        self.phys = _lib.Physics(gamma, prandtl, mu_eff, weno_eps, harten_delta)
+        h = C.c_void_p()
+        check(self.lib.cns_plan_create(C.byref(h), C.byref(self.grid), C.byref(self.phys), prec,
+                                       C.c_void_p(self.stream.cuda_stream)), "cns_plan_create")
+        self.h = h
+        nbytes = int(self.lib.cns_workspace_bytes(h))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        check(self.lib.cns_set_workspace(h, _ptr(self.workspace), nbytes), "cns_set_workspace")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.cns_plan_destroy(h)
+            self.h = None
+
+    # ---- helpers -------------------------------------------------------
+    def _state(self, u: torch.Tensor, name="u"):
+        if u.dtype != self.dtype or u.device != self.device or not u.is_contiguous() \
+                or tuple(u.shape) != (5,) + self.shape:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {(5,) + self.shape} "
+                             f"on {self.device}")
+        return u
+
+    def empty_state(self):
+        return torch.empty((5,) + self.shape, dtype=self.dtype, device=self.device)
+
+    def set_tiles(self, seg=(0, 0, 0), block=0):
+        check(self.lib.cns_set_tiles(self.h, int(seg[0]), int(seg[1]), int(seg[2]), int(block)), "cns_set_tiles")
+
+    # ---- calls ---------------------------------------------------------
+    def init_state(self, rho, vel, p) -> torch.Tensor:
+        """Conserved state from primitive arrays (numpy or tensors, float64)."""
+        def dev(a):
+            t = torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+                                dtype=torch.float64, device=self.device)
+            return t.contiguous()
+        r, v, pp = dev(rho), dev(vel), dev(p)
+        u = self.empty_state()
+        with torch.cuda.stream(self.stream):
+            check(self.lib.cns_init_state(self.h, _ptr(r), _ptr(v), _ptr(pp), _ptr(u)), "cns_init_state")
+        self._keep = (r, v, pp)  # alive until the stream has consumed them
+        return u
+
+    def rhs(self, u, out=None):
+        self._state(u)
+        out = self.empty_state() if out is None else self._state(out, "out")
+        check(self.lib.cns_rhs(self.h, _ptr(u), _ptr(out)), "cns_rhs")
+        return out
+
+    def rhs_dir(self, u, direction, out=None):
+        self._state(u)
+        out = self.empty_state() if out is None else self._state(out, "out")
+        check(self.lib.cns_rhs_dir(self.h, _ptr(u), int(direction), _ptr(out)), "cns_rhs_dir")
+        return out
+
+    def viscous(self, u, out=None):
+        self._state(u)
+        out = self.empty_state() if out is None else self._state(out, "out")
+        check(self.lib.cns_viscous(self.h, _ptr(u), _ptr(out)), "cns_viscous")
+        return out
+
+    def rk4(self, u, dt, nsteps, diag=True):
+        """Advance ``u`` in place; returns the per-step diagnostics tensor
+        ``[nsteps][9]`` (float64, device) or None."""
+        self._state(u)
+        d = torch.empty((max(int(nsteps), 1), CNS_NDIAG), dtype=torch.float64, device=self.device) if diag else None
+        check(self.lib.cns_rk4(self.h, _ptr(u), float(dt), int(nsteps), _ptr(d) if d is not None else None),
+              "cns_rk4")
+        return d[:nsteps] if d is not None else None
+
+    def diagnostics(self, u, out=None):
+        self._state(u)
+        out = torch.empty(CNS_NDIAG, dtype=torch.float64, device=self.device) if out is None else out
+        check(self.lib.cns_diagnostics(self.h, _ptr(u), _ptr(out)), "cns_diagnostics")
+        return out
+
+    def diagnostics_host(self, u, raise_bad=True):
+        self._state(u)
+        out = np.zeros(CNS_NDIAG)
+        rc = self.lib.cns_diagnostics_host(self.h, _ptr(u), out.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc != 0 and (raise_bad or rc not in (-3, -4)):
+            check(rc, "cns_diagnostics_host")
+        return out
+
+    # ---- per-kernel timing -------------------------------------------------
+    def profile(self, enable=True):
+        check(self.lib.cns_profile_enable(self.h, 1 if enable else 0), "cns_profile_enable")
+
+    def profile_read(self):
+        """``{kernel: (total_ms, launches)}`` since the last ``profile(True)``."""
+        ms = np.zeros(_lib.CNS_NKERNEL)
+        cnt = np.zeros(_lib.CNS_NKERNEL, dtype=np.int64)
+        check(self.lib.cns_profile_read(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                        cnt.ctypes.data_as(C.POINTER(C.c_int64))), "cns_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.KERNEL_NAMES)}

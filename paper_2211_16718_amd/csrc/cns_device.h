@@ -1,0 +1,146 @@
+// cns_device.h -- device arithmetic of the WENO5-Roe / central-viscous discretisation
+// for gfx950.  Templated on the arithmetic type T (double, or float in the mixed form)
+// and on B, the type of the WENO smoothness-indicator sums (always double).
+//
+// Formulation choices (same operator as Sec. 2.2 of the paper, different
+// arithmetic order):
+//  * WENO5: the left-biased value at j+1/2 reads q_{j-2..j+2}, the right-biased one
+//    is its mirror image and reads q_{j-1..j+3}.  The two share two of their three
+//    candidate interpolants and two of their four second differences, so one
+//    interface evaluates 4 candidates and 4 second differences instead of 6 and 6.
+//  * Nonlinear weights: alpha_k = c_k / d_k with d_k = (eps + beta_k)^2 are scaled by
+//    d_1 d_2 d_3, so omega needs one division per reconstruction instead of four.
+//  * Roe dissipation |A| (u^R - u^L) is evaluated with wave strengths (projections
+//    on the left eigenvectors, written out) instead of explicit 5x5 matrices;
+//    |A| = X |Lambda| X^-1 is basis independent so the operator is the same.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cns {
+
+struct PhysT {
+    double gamma, prandtl, mu_eff, eps, delta;
+};
+
+template <typename T>
+__device__ __forceinline__ T harten_abs(T lam, T delta) {
+    // |lam| if |lam| >= delta, else (lam^2 + delta^2) / (2 delta)  (Harten's entropy fix)
+    T a = fabs(lam);
+    return (a >= delta) ? a : (lam * lam + delta * delta) / (T(2) * delta);
+}
+
+// ---------------------------------------------------------------------------
+// WENO5, left- and right-biased values at j+1/2 from q_{j-2} .. q_{j+3}
+// ---------------------------------------------------------------------------
+template <typename T, typename B>
+__device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T eps, T &L, T &R) {
+    const T r6 = T(1) / T(6);
+    // third-order candidates; the mirror reconstruction reuses L2 and L3
+    T L1 = (T(2) * m2 - T(7) * m1 + T(11) * c0) * r6;
+    T L2 = (-m1 + T(5) * c0 + T(2) * p1) * r6;
+    T L3 = (T(2) * c0 + T(5) * p1 - p2) * r6;
+    T R1 = (T(2) * p3 - T(7) * p2 + T(11) * p1) * r6;
+
+    // Jiang-Shu smoothness indicators, accumulated in B
+    const B k13 = B(13) / B(12);
+    const B bm2 = B(m2), bm1 = B(m1), bc0 = B(c0), bp1 = B(p1), bp2 = B(p2), bp3 = B(p3);
+    B da = bm2 - B(2) * bm1 + bc0;  // second differences centred at j-1, j, j+1, j+2
+    B db = bm1 - B(2) * bc0 + bp1;
+    B dc = bc0 - B(2) * bp1 + bp2;
+    B dd = bp1 - B(2) * bp2 + bp3;
+    B ea = bm2 - B(4) * bm1 + B(3) * bc0;
+    B eb = bm1 - bp1;
+    B ec = B(3) * bc0 - B(4) * bp1 + bp2;
+    B fa = bp3 - B(4) * bp2 + B(3) * bp1;
+    B fb = bp2 - bc0;
+    B fc = B(3) * bp1 - B(4) * bc0 + bm1;
+    B bL1 = k13 * da * da + B(0.25) * ea * ea;
+    B bL2 = k13 * db * db + B(0.25) * eb * eb;
+    B bL3 = k13 * dc * dc + B(0.25) * ec * ec;
+    B bR1 = k13 * dd * dd + B(0.25) * fa * fa;
+    B bR2 = k13 * dc * dc + B(0.25) * fb * fb;
+    B bR3 = k13 * db * db + B(0.25) * fc * fc;
+
+    T s1 = eps + T(bL1), s2 = eps + T(bL2), s3 = eps + T(bL3);
+    T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+    T a1 = T(0.1) * (d2 * d3), a2 = T(0.6) * (d1 * d3), a3 = T(0.3) * (d1 * d2);
+    L = (a1 * L1 + a2 * L2 + a3 * L3) / (a1 + a2 + a3);
+
+    T t1 = eps + T(bR1), t2 = eps + T(bR2), t3 = eps + T(bR3);
+    T e1 = t1 * t1, e2 = t2 * t2, e3 = t3 * t3;
+    T b1 = T(0.1) * (e2 * e3), b2 = T(0.6) * (e1 * e3), b3 = T(0.3) * (e1 * e2);
+    R = (b1 * R1 + b2 * L3 + b3 * L2) / (b1 + b2 + b3);
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2.1: convective flux along DIR of the conserved state w[5]
+// ---------------------------------------------------------------------------
+template <typename T, int DIR>
+__device__ __forceinline__ void euler_flux(const T w[5], T gm1, T f[5]) {
+    T inv = T(1) / w[0];
+    T vx = w[1] * inv, vy = w[2] * inv, vz = w[3] * inv;
+    T p = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
+    T vn = DIR == 0 ? vx : (DIR == 1 ? vy : vz);
+    f[0] = w[1 + DIR];
+    f[1] = w[1] * vn;
+    f[2] = w[2] * vn;
+    f[3] = w[3] * vn;
+    f[1 + DIR] += p;
+    f[4] = (w[4] + p) * vn;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2.2: Roe dissipation D = |A| (uR - uL) at the Roe average of the cell
+// states a (= u_j) and b (= u_{j+1}), with Harten's fix on every eigenvalue.
+// ---------------------------------------------------------------------------
+template <typename T, int DIR>
+__device__ __forceinline__ void roe_dissipation(const T a[5], const T b[5], const T du[5], T gamma, T delta,
+                                                T D[5]) {
+    constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+    const T gm1 = gamma - T(1);
+    T ia = T(1) / a[0], ib = T(1) / b[0];
+    T va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
+    T vb[3] = {b[1] * ib, b[2] * ib, b[3] * ib};
+    T pa = gm1 * (a[4] - T(0.5) * (a[1] * va[0] + a[2] * va[1] + a[3] * va[2]));
+    T pb = gm1 * (b[4] - T(0.5) * (b[1] * vb[0] + b[2] * vb[1] + b[3] * vb[2]));
+    T Ha = (a[4] + pa) * ia, Hb = (b[4] + pb) * ib;
+    T sa = sqrt(a[0]), sb = sqrt(b[0]);
+    T iw = T(1) / (sa + sb);
+    T wa = sa * iw, wb = sb * iw;
+    T v[3] = {wa * va[0] + wb * vb[0], wa * va[1] + wb * vb[1], wa * va[2] + wb * vb[2]};
+    T H = wa * Ha + wb * Hb;
+    T q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    T c2 = gm1 * (H - T(0.5) * q2);
+    T c = sqrt(c2);
+    T vn = v[N];
+
+    // wave strengths alpha = X^-1 du
+    T at1 = du[1 + T1] - v[T1] * du[0];
+    T at2 = du[1 + T2] - v[T2] * du[0];
+    T dEb = du[4] - at1 * v[T1] - at2 * v[T2];
+    T a2 = gm1 / c2 * (du[0] * (H - vn * vn) + vn * du[1 + N] - dEb);
+    T a1 = (du[0] * (vn + c) - du[1 + N] - c * a2) / (T(2) * c);
+    T a5 = du[0] - (a1 + a2);
+
+    T l1 = harten_abs(vn - c, delta), l2 = harten_abs(vn, delta), l5 = harten_abs(vn + c, delta);
+    T s1 = l1 * a1, s2 = l2 * a2, s5 = l5 * a5, st1 = l2 * at1, st2 = l2 * at2;
+
+    // D = sum_k |lam_k| alpha_k K_k with the right eigenvectors K_k
+    T ssum = s1 + s2 + s5;
+    D[0] = ssum;
+    D[1] = ssum * v[0];
+    D[2] = ssum * v[1];
+    D[3] = ssum * v[2];
+    D[1 + N] += c * (s5 - s1);
+    D[1 + T1] += st1;
+    D[1 + T2] += st2;
+    D[4] = s1 * (H - vn * c) + s2 * (T(0.5) * q2) + s5 * (H + vn * c) + st1 * v[T1] + st2 * v[T2];
+}
+
+// 5-point 4th-order central first derivative (times h)
+template <typename T>
+__device__ __forceinline__ T dcen(T m2, T m1, T p1, T p2) {
+    return (T(8) * (p1 - m1) - (p2 - m2)) * (T(1) / T(12));
+}
+
+}  // namespace cns

@@ -88,6 +88,11 @@ int cns_set_workspace(cns_plan *plan, void *ws_dev, size_t bytes);
  * Results do not depend on these values (bitwise). */
 int cns_set_tiles(cns_plan *plan, int32_t seg_x, int32_t seg_y, int32_t seg_z, int32_t block);
 
+/* x-direction sweep kernel: 0 = whole periodic rows staged in LDS, one thread per
+ * interface (default; used when a row fits: nx * rows <= 1024 threads and 64 KiB of
+ * LDS), 1 = the marching kernel used for y and z.  Results agree to round-off. */
+int cns_set_x_kernel(cns_plan *plan, int32_t kind);
+
 /* Sec. 2.1 equation of state: u = [rho, rho v, p/(gamma-1) + rho|v|^2/2] from device
  * primitives rho[N3], vel[3][N3], p[N3] (double).  u in plan precision. */
 int cns_init_state(const cns_plan *plan, const double *rho_dev, const double *vel_dev, const double *p_dev,
@@ -124,6 +129,44 @@ int cns_profile_enable(cns_plan *plan, int32_t enable);
 /* Summed milliseconds and launch counts per kernel kind since the last enable
  * (host arrays of CNS_NKERNEL entries). */
 int cns_profile_read(const cns_plan *plan, double *ms_host, int64_t *count_host);
+
+/* hipGraph replay of cns_rk4: the launches of all nsteps are captured once per
+ * (u, dt, nsteps, diag) and replayed; enable = 0 launches eagerly.  Needs a plan
+ * created on a non-default stream (else CNS_EUNSUPPORTED).  Replays are bitwise
+ * identical to eager launches. */
+int cns_set_graph(cns_plan *plan, int32_t enable);
+
+/* ---- ensembles: independent periodic boxes of uneven sizes advanced together ----
+ * Every kernel launch covers all boxes (virtual blocks mapped to boxes by prefix
+ * sums), so one RK4 step of the whole ensemble is 21 launches, optionally replayed
+ * from a captured hipGraph.  A box advanced in an ensemble gives bitwise the result
+ * of its own single-box plan (same kernels, same arithmetic).  Extension beyond the
+ * paper, which advances one domain. */
+typedef struct cns_ensemble cns_ensemble;
+/* grids[nbox], phys[nbox], dt[nbox]: host arrays.  u_packed: device buffer holding
+ * every box's state [5][N3_i] at element offset offsets[i] (host array; each box
+ * 256-byte aligned, no overlap), element type by precision.  The ensemble keeps
+ * u_packed, which must outlive it. */
+int cns_ensemble_create(cns_ensemble **out, int32_t nbox, const cns_grid *grids, const cns_physics *phys,
+                        const double *dt, int32_t precision, void *u_packed, const int64_t *offsets, void *stream);
+int cns_ensemble_destroy(cns_ensemble *ens);
+size_t cns_ensemble_workspace_bytes(const cns_ensemble *ens);
+int cns_ensemble_set_workspace(cns_ensemble *ens, void *ws_dev, size_t bytes);
+/* segment lengths of box `box` (-1: every box) and the block size; 0 keeps a value. */
+int cns_ensemble_set_tiles(cns_ensemble *ens, int32_t box, int32_t seg_x, int32_t seg_y, int32_t seg_z,
+                           int32_t block);
+int cns_ensemble_get_tiles(const cns_ensemble *ens, int32_t box, int32_t *seg3_host, int32_t *block_host);
+/* Time the y/z sweeps for candidate segment lengths per box size and candidate block
+ * sizes on the device, keep the fastest.  cache_path (may be NULL): a JSON file
+ * read first (known sizes are not re-timed) and rewritten with new choices.
+ * Synchronises the ensemble's stream.  Tiles never change results. */
+int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path);
+/* nsteps RK4 steps of every box with its own dt; diag_dev (may be NULL) receives
+ * [nbox][nsteps][CNS_NDIAG].  use_graph != 0 captures the whole run once and
+ * replays it (non-default stream required). */
+int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag_dev, int32_t use_graph);
+int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable);
+int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t *count_host);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *cns_last_error(void);

@@ -46,6 +46,7 @@ SIGNATURES = {
     "cns_workspace_bytes": (C.c_size_t, [_vp]),
     "cns_set_workspace": (C.c_int, [_vp, _vp, C.c_size_t]),
     "cns_set_tiles": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "cns_set_x_kernel": (C.c_int, [_vp, C.c_int32]),
     "cns_init_state": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "cns_rhs": (C.c_int, [_vp, _vp, _vp]),
     "cns_rhs_dir": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
@@ -55,6 +56,18 @@ SIGNATURES = {
     "cns_diagnostics_host": (C.c_int, [_vp, _vp, _dp]),
     "cns_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "cns_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
+    "cns_set_graph": (C.c_int, [_vp, C.c_int32]),
+    "cns_ensemble_create": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(Grid), C.POINTER(Physics), _dp,
+                                      C.c_int32, _vp, C.POINTER(C.c_int64), _vp]),
+    "cns_ensemble_destroy": (C.c_int, [_vp]),
+    "cns_ensemble_workspace_bytes": (C.c_size_t, [_vp]),
+    "cns_ensemble_set_workspace": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "cns_ensemble_set_tiles": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "cns_ensemble_get_tiles": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "cns_ensemble_autotune": (C.c_int, [_vp, C.c_char_p]),
+    "cns_ensemble_run": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32]),
+    "cns_ensemble_profile_enable": (C.c_int, [_vp, C.c_int32]),
+    "cns_ensemble_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
     "cns_last_error": (C.c_char_p, []),
 }
 

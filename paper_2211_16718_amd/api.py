@@ -68,16 +68,24 @@ class Plan:
     def set_tiles(self, seg=(0, 0, 0), block=0):
         check(self.lib.cns_set_tiles(self.h, int(seg[0]), int(seg[1]), int(seg[2]), int(block)), "cns_set_tiles")
 
+    def set_x_kernel(self, kind: str = "rows"):
+        """``"rows"`` (whole rows in LDS, default) or ``"march"`` for the x sweep."""
+        check(self.lib.cns_set_x_kernel(self.h, 0 if kind == "rows" else 1), "cns_set_x_kernel")
+
     # ---- calls ---------------------------------------------------------
-    def init_state(self, rho, vel, p) -> torch.Tensor:
+    def set_graph(self, enable=True):
+        """Replay cns_rk4 from a captured hipGraph (needs a non-default stream)."""
+        check(self.lib.cns_set_graph(self.h, 1 if enable else 0), "cns_set_graph")
+
+    def init_state(self, rho, vel, p, out=None) -> torch.Tensor:
         """Conserved state from primitive arrays (numpy or tensors, float64)."""
         def dev(a):
             t = torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
                                 dtype=torch.float64, device=self.device)
             return t.contiguous()
-        r, v, pp = dev(rho), dev(vel), dev(p)
-        u = self.empty_state()
         with torch.cuda.stream(self.stream):
+            r, v, pp = dev(rho), dev(vel), dev(p)
+            u = self.empty_state() if out is None else self._state(out, "out")
             check(self.lib.cns_init_state(self.h, _ptr(r), _ptr(v), _ptr(pp), _ptr(u)), "cns_init_state")
         self._keep = (r, v, pp)  # alive until the stream has consumed them
         return u
@@ -133,4 +141,99 @@ class Plan:
         cnt = np.zeros(_lib.CNS_NKERNEL, dtype=np.int64)
         check(self.lib.cns_profile_read(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)),
                                         cnt.ctypes.data_as(C.POINTER(C.c_int64))), "cns_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.KERNEL_NAMES)}
+
+
+def _align_elems(dtype):
+    return 256 // torch.tensor([], dtype=dtype).element_size()
+
+
+class Ensemble:
+    """Independent periodic boxes of uneven sizes advanced together.
+
+    ``boxes``: list of dicts with ``shape`` (nz, ny, nx), ``mu_eff``, ``dt`` and
+    optionally ``length``, ``gamma``, ``prandtl``, ``weno_eps``, ``harten_delta``.
+    The states live in one packed device buffer; ``state(i)`` is box i's view.
+    """
+
+    def __init__(self, boxes, precision="fp64", device="cuda:0", stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        prec = _lib.CNS_FP64 if precision == "fp64" else _lib.CNS_MIXED
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = len(boxes)
+        self.shapes = [tuple(int(x) for x in b["shape"]) for b in boxes]
+        al = _align_elems(self.dtype)
+        offs, o = [], 0
+        for sh in self.shapes:
+            offs.append(o)
+            n = 5 * sh[0] * sh[1] * sh[2]
+            o += (n + al - 1) // al * al
+        self.offsets = offs
+        self.u = torch.zeros(max(o, al), dtype=self.dtype, device=self.device)
+        grids = (_lib.Grid * nb)()
+        phys = (_lib.Physics * nb)()
+        dts = (C.c_double * nb)()
+        for i, b in enumerate(boxes):
+            nz, ny, nx = self.shapes[i]
+            L = b.get("length", (TWO_PI, TWO_PI, TWO_PI))
+            grids[i] = _lib.Grid(nx, ny, nz, *L)
+            phys[i] = _lib.Physics(b.get("gamma", 1.4), b.get("prandtl", 0.72), b["mu_eff"],
+                                   b.get("weno_eps", 1e-6), b.get("harten_delta", 1e-6))
+            dts[i] = float(b["dt"])
+        coffs = (C.c_int64 * nb)(*offs)
+        h = C.c_void_p()
+        check(self.lib.cns_ensemble_create(C.byref(h), nb, grids, phys, dts, prec, _ptr(self.u), coffs,
+                                           C.c_void_p(self.stream.cuda_stream)), "cns_ensemble_create")
+        self.h = h
+        self.nbox = nb
+        nbytes = int(self.lib.cns_ensemble_workspace_bytes(h))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)  # the zero fill of the packed states is complete
+        check(self.lib.cns_ensemble_set_workspace(h, _ptr(self.workspace), nbytes), "cns_ensemble_set_workspace")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.cns_ensemble_destroy(h)
+            self.h = None
+
+    def state(self, i) -> torch.Tensor:
+        nz, ny, nx = self.shapes[i]
+        n = 5 * nz * ny * nx
+        return self.u[self.offsets[i]:self.offsets[i] + n].view(5, nz, ny, nx)
+
+    def set_tiles(self, box=-1, seg=(0, 0, 0), block=0):
+        check(self.lib.cns_ensemble_set_tiles(self.h, int(box), int(seg[0]), int(seg[1]), int(seg[2]), int(block)),
+              "cns_ensemble_set_tiles")
+
+    def get_tiles(self, box):
+        seg = (C.c_int32 * 3)()
+        blk = C.c_int32()
+        check(self.lib.cns_ensemble_get_tiles(self.h, int(box), seg, C.byref(blk)), "cns_ensemble_get_tiles")
+        return tuple(seg), blk.value
+
+    def autotune(self, cache_path=None):
+        check(self.lib.cns_ensemble_autotune(self.h, cache_path.encode() if cache_path else None),
+              "cns_ensemble_autotune")
+
+    def run(self, nsteps, diag=True, graph=True):
+        """nsteps RK4 steps of every box; returns diagnostics ``[nbox][nsteps][9]`` or None."""
+        d = torch.empty((self.nbox, max(int(nsteps), 1), CNS_NDIAG), dtype=torch.float64,
+                        device=self.device) if diag else None
+        check(self.lib.cns_ensemble_run(self.h, int(nsteps), _ptr(d) if d is not None else None,
+                                        1 if graph else 0), "cns_ensemble_run")
+        return d[:, :nsteps] if d is not None else None
+
+    def profile(self, enable=True):
+        check(self.lib.cns_ensemble_profile_enable(self.h, 1 if enable else 0), "cns_ensemble_profile_enable")
+
+    def profile_read(self):
+        ms = np.zeros(_lib.CNS_NKERNEL)
+        cnt = np.zeros(_lib.CNS_NKERNEL, dtype=np.int64)
+        check(self.lib.cns_ensemble_profile_read(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                                 cnt.ctypes.data_as(C.POINTER(C.c_int64))),
+              "cns_ensemble_profile_read")
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.KERNEL_NAMES)}

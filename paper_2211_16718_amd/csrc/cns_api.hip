@@ -1,12 +1,17 @@
-// cns_api.hip -- the C-ABI (include/cns.h): argument checks, plans, workspace carving,
-// error reporting.  All compute is enqueued through the launchers in cns_kernels.hip.
+// cns_api.hip -- the C-ABI (include/cns.h): argument checks, plans and ensembles,
+// workspace carving, device tables, hipGraph capture, the tile autotuner, errors.
+// All compute is enqueued through the launchers in cns_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "cns_internal.h"
 
@@ -28,52 +33,8 @@ static int check_hip(const char *what) {
     return CNS_OK;
 }
 
-struct cns_plan {
-    Box box;
-    int precision;
-    hipStream_t stream;
-    Tiles tiles;
-    Workspace wl;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    Prof prof;
-    ~cns_plan() {
-        if (prof.ev[0])
-            for (auto &e : prof.ev) hipEventDestroy(e);
-    }
-};
-
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-static Workspace layout(const Box &b, size_t esz) {
-    Workspace w{};
-    size_t n3 = b.n3();
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
-    w.W = take(4 * n3 * esz);
-    w.G = take(9 * n3 * esz);
-    w.rhs = take(5 * n3 * esz);
-    w.stA = take(5 * n3 * esz);
-    w.stB = take(5 * n3 * esz);
-    w.acc = take(5 * n3 * sizeof(double));
-    w.part = take((size_t)kDiagBlocks * CNS_NDIAG * sizeof(double));
-    w.dhost = take(CNS_NDIAG * sizeof(double));
-    w.total = off;
-    return w;
-}
-
 static bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
-
-static int check_plan(const cns_plan *p, bool need_ws) {
-    if (!p) return set_err(CNS_EINVAL, "null plan");
-    if (need_ws && (!p->ws || p->ws_bytes < p->wl.total))
-        return set_err(CNS_EWORKSPACE, "workspace of %zu bytes required (have %zu)", p->wl.total, p->ws_bytes);
-    return CNS_OK;
-}
 
 static int check_ptr(const void *ptr, const char *name) {
     if (!ptr) return set_err(CNS_EINVAL, "%s is null", name);
@@ -81,27 +42,380 @@ static int check_ptr(const void *ptr, const char *name) {
     return CNS_OK;
 }
 
-template <typename T>
-static T *ws_at(const cns_plan *p, size_t off) {
-    return (T *)(p->ws + off);
+static int validate(const cns_grid *g, const cns_physics *ph) {
+    if (!g || !ph) return set_err(CNS_EINVAL, "null grid or physics");
+    if (g->nx < 8 || g->ny < 8 || g->nz < 8)
+        return set_err(CNS_EINVAL, "grid must have at least 8 points per direction (got %d x %d x %d)", g->nx, g->ny,
+                       g->nz);
+    if ((double)g->nx * g->ny * g->nz > 2.0e9) return set_err(CNS_EINVAL, "grid too large (more than 2e9 points)");
+    if (!(g->lx > 0 && g->ly > 0 && g->lz > 0)) return set_err(CNS_EINVAL, "box lengths must be positive");
+    if (!(ph->gamma > 1.0) || !std::isfinite(ph->gamma)) return set_err(CNS_EINVAL, "gamma must exceed 1");
+    if (!(ph->mu_eff >= 0.0) || !std::isfinite(ph->mu_eff)) return set_err(CNS_EINVAL, "mu_eff must be >= 0");
+    if (ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return set_err(CNS_EINVAL, "prandtl must be > 0");
+    if (!(ph->weno_eps > 0.0)) return set_err(CNS_EINVAL, "weno_eps must be > 0");
+    if (!(ph->harten_delta >= 0.0)) return set_err(CNS_EINVAL, "harten_delta must be >= 0");
+    return CNS_OK;
 }
 
-template <typename T>
-static void rk4_steps(cns_plan *p, T *u, double dt, int nsteps, double *diag) {
-    T *A = ws_at<T>(p, p->wl.stA), *Bs = ws_at<T>(p, p->wl.stB), *rhs = ws_at<T>(p, p->wl.rhs);
-    T *W = ws_at<T>(p, p->wl.W), *G = ws_at<T>(p, p->wl.G);
-    double *acc = ws_at<double>(p, p->wl.acc);
-    double *part = ws_at<double>(p, p->wl.part);
-    for (int n = 0; n < nsteps; ++n) {
-        // stage s reads U_s and writes U_{s+1}; U_1 = u, U_2 -> A, U_3 -> B, U_4 -> A, u^{n+1} -> u
-        Prof *pf = p->prof.on ? &p->prof : nullptr;
-        launch_rk4_stage<T>(p->box, p->tiles, 1, u, u, A, acc, dt, rhs, W, G, p->stream, pf);
-        launch_rk4_stage<T>(p->box, p->tiles, 2, A, u, Bs, acc, dt, rhs, W, G, p->stream, pf);
-        launch_rk4_stage<T>(p->box, p->tiles, 3, Bs, u, A, acc, dt, rhs, W, G, p->stream, pf);
-        launch_rk4_stage<T>(p->box, p->tiles, 4, A, u, u, acc, dt, rhs, W, G, p->stream, pf);
-        if (diag) launch_diag<T>(p->box, u, part, diag + (size_t)n * CNS_NDIAG, p->stream, pf);
-        prof_flush(pf);
+// ----------------------------------------------------------------------------
+// Core: a batch of boxes with its workspace, device tables, profiling and graphs
+// ----------------------------------------------------------------------------
+struct Core {
+    int prec = CNS_FP64;
+    size_t esz = 8;
+    hipStream_t stream = nullptr;
+    int block = 256;
+    int xrows_pref = 1;
+    std::vector<BoxDesc> boxes;
+    std::vector<void *> ustate;  // per-box state pointer (ensembles) or null (plans)
+    std::vector<char> active;    // boxes given blocks (all, except while autotuning)
+    // workspace layout
+    std::vector<size_t> box_off;  // per-box scratch base
+    size_t table_off = 0, dhost_off = 0, need = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool dirty = true;
+    std::vector<unsigned char> staging;
+    long long total[F_N] = {};
+    int rowP = 1;
+    size_t rowLds = 0;
+    bool any_visc = false;
+    Prof prof;
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    const void *g_u = nullptr;
+    double g_dt = 0, *g_diag = nullptr;
+    int g_nsteps = -1;
+
+    ~Core() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (prof.ev[0])
+            for (auto &e : prof.ev) hipEventDestroy(e);
     }
+
+    int nbox() const { return (int)boxes.size(); }
+
+    static size_t box_scratch_bytes(const BoxDesc &b, size_t esz) {
+        size_t n3 = b.n3, off = 0;
+        auto take = [&](size_t bytes) { off = align256(off + bytes); };
+        take(4 * n3 * esz);  // W
+        take(9 * n3 * esz);  // G
+        take(5 * n3 * esz);  // rhs
+        take(5 * n3 * esz);  // A
+        take(5 * n3 * esz);  // B
+        take(5 * n3 * sizeof(double));                         // acc
+        take((size_t)kDiagBlocksMax * CNS_NDIAG * sizeof(double));  // part
+        return off;
+    }
+
+    void layout() {
+        size_t off = 0;
+        box_off.resize(boxes.size());
+        for (size_t i = 0; i < boxes.size(); ++i) {
+            box_off[i] = off;
+            off += box_scratch_bytes(boxes[i], esz);
+        }
+        table_off = off;
+        off = align256(off + boxes.size() * sizeof(BoxDesc) + (size_t)F_N * (boxes.size() + 1) * sizeof(long long));
+        dhost_off = off;
+        off = align256(off + CNS_NDIAG * sizeof(double));
+        need = off;
+    }
+
+    void add_box(const cns_grid &g, const cns_physics &ph, double dt, void *u) {
+        BoxDesc b{};
+        b.nx = g.nx;
+        b.ny = g.ny;
+        b.nz = g.nz;
+        for (int d = 0; d < 3; ++d) b.seg[d] = 16;
+        b.n3 = (size_t)g.nx * g.ny * g.nz;
+        b.inv_h[0] = g.nx / g.lx;
+        b.inv_h[1] = g.ny / g.ly;
+        b.inv_h[2] = g.nz / g.lz;
+        b.gamma = ph.gamma;
+        b.prandtl = ph.prandtl;
+        b.mu = ph.mu_eff;
+        b.eps = ph.weno_eps;
+        b.delta = ph.harten_delta;
+        b.dt = dt;
+        boxes.push_back(b);
+        ustate.push_back(u);
+        active.push_back(1);
+    }
+
+    // fill pointers, shapes and prefixes; upload the device table (synchronous)
+    int sync_table() {
+        if (!dirty) return CNS_OK;
+        if (!ws) return set_err(CNS_EWORKSPACE, "no workspace bound");
+        const int n = nbox();
+        std::vector<long long> off[F_N];
+        rowP = 1;
+        rowLds = 0;
+        any_visc = false;
+        for (int i = 0; i < n; ++i) {
+            BoxDesc &b = boxes[i];
+            const size_t n3 = b.n3;
+            char *base = ws + box_off[i];
+            size_t o = 0;
+            auto take = [&](size_t bytes) {
+                char *p = base + o;
+                o = align256(o + bytes);
+                return (void *)p;
+            };
+            b.W = take(4 * n3 * esz);
+            b.G = take(9 * n3 * esz);
+            b.rhs = take(5 * n3 * esz);
+            b.A = take(5 * n3 * esz);
+            b.B = take(5 * n3 * esz);
+            b.acc = (double *)take(5 * n3 * sizeof(double));
+            b.part = (double *)take((size_t)kDiagBlocksMax * CNS_NDIAG * sizeof(double));
+            b.u = ustate[i];
+            int P = 1;
+            b.rows = rows_for(b.nx);
+            b.xrows = (xrows_pref && rows_fits(b.nx, esz, &P)) ? 1 : 0;
+            if (b.xrows) {
+                rowP = std::max(rowP, P);
+                rowLds = std::max(rowLds, (size_t)14 * b.rows * b.nx * esz);
+            }
+            for (int d = 0; d < 3; ++d) {
+                const int nl = d == 0 ? b.nx : (d == 1 ? b.ny : b.nz);
+                b.seg[d] = std::max(1, std::min(b.seg[d], nl));
+            }
+            any_visc = any_visc || b.mu > 0.0;
+        }
+        for (int f = 0; f < F_N; ++f) {
+            off[f].assign(n + 1, 0);
+            for (int i = 0; i < n; ++i) off[f][i + 1] = off[f][i] + (active[i] ? family_blocks(boxes[i], f, block) : 0);
+            total[f] = off[f][n];
+        }
+        const size_t tb = n * sizeof(BoxDesc) + (size_t)F_N * (n + 1) * sizeof(long long);
+        staging.assign(tb, 0);
+        memcpy(staging.data(), boxes.data(), n * sizeof(BoxDesc));
+        for (int f = 0; f < F_N; ++f)
+            memcpy(staging.data() + n * sizeof(BoxDesc) + (size_t)f * (n + 1) * sizeof(long long), off[f].data(),
+                   (n + 1) * sizeof(long long));
+        hipError_t e = hipMemcpyAsync(ws + table_off, staging.data(), tb, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return set_err(CNS_EHIP, "table upload: %s", hipGetErrorString(e));
+        dirty = false;
+        drop_graph();
+        return CNS_OK;
+    }
+
+    Batch batch() {
+        Batch bt;
+        bt.nbox = nbox();
+        bt.prec = prec;
+        bt.block = block;
+        bt.any_visc = any_visc;
+        bt.d_boxes = (const BoxDesc *)(ws + table_off);
+        const long long *offs = (const long long *)(ws + table_off + nbox() * sizeof(BoxDesc));
+        for (int f = 0; f < F_N; ++f) {
+            bt.d_off[f] = offs + (size_t)f * (nbox() + 1);
+            bt.total[f] = total[f];
+        }
+        bt.rowP = rowP;
+        bt.rowLds = rowLds;
+        bt.stream = stream;
+        bt.prof = prof.on ? &prof : nullptr;
+        return bt;
+    }
+
+    void drop_graph() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        g_nsteps = -1;
+    }
+
+    // nsteps RK4 steps; diag layout [nbox][nsteps][CNS_NDIAG]
+    int rk4(const void *u_ov, double dt_ov, int nsteps, double *diag) {
+        int rc = sync_table();
+        if (rc) return rc;
+        Batch bt = batch();
+        auto enqueue = [&]() {
+            for (int n = 0; n < nsteps; ++n) {
+                launch_rk4_step(bt, u_ov, dt_ov, diag, nsteps, n);
+                prof_flush(bt.prof);
+            }
+        };
+        if (!use_graph || prof.on || nsteps == 0) {
+            enqueue();
+            return check_hip("rk4");
+        }
+        if (!stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
+        if (!(gexec && g_u == u_ov && g_dt == dt_ov && g_diag == diag && g_nsteps == nsteps)) {
+            drop_graph();
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return set_err(CNS_EHIP, "begin capture: %s", hipGetErrorString(e));
+            enqueue();
+            e = hipStreamEndCapture(stream, &graph);
+            if (e != hipSuccess) return set_err(CNS_EHIP, "end capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                gexec = nullptr;
+                return set_err(CNS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+            }
+            g_u = u_ov;
+            g_dt = dt_ov;
+            g_diag = diag;
+            g_nsteps = nsteps;
+        }
+        hipError_t e = hipGraphLaunch(gexec, stream);
+        if (e != hipSuccess) return set_err(CNS_EHIP, "graph launch: %s", hipGetErrorString(e));
+        return CNS_OK;
+    }
+
+    int profile_enable(int on) {
+        if (on && !prof.ev[0])
+            for (auto &e : prof.ev)
+                if (hipEventCreate(&e) != hipSuccess) return set_err(CNS_EHIP, "hipEventCreate failed");
+        prof.on = on != 0;
+        prof.n = 0;
+        for (int k = 0; k < K_NKIND; ++k) {
+            prof.ms[k] = 0.0;
+            prof.count[k] = 0;
+        }
+        return CNS_OK;
+    }
+};
+
+struct cns_plan {
+    Core c;
+};
+struct cns_ensemble {
+    Core c;
+};
+
+// ----------------------------------------------------------------------------
+// autotuner: segment length of the marching y/z sweeps per box size, then the
+// block size of the batch.  The choice never changes results (bitwise).
+// ----------------------------------------------------------------------------
+static std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string s = p.gcnArchName;
+    size_t c = s.find(':');
+    return c == std::string::npos ? s : s.substr(0, c);
+}
+
+static std::map<std::string, int> read_cache(const char *path) {
+    std::map<std::string, int> m;
+    if (!path) return m;
+    FILE *f = fopen(path, "r");
+    if (!f) return m;
+    char key[256];
+    int val;
+    // format: one `"key": value` pair per line inside braces
+    char line[512];
+    while (fgets(line, sizeof line, f))
+        if (sscanf(line, " \"%255[^\"]\" : %d", key, &val) == 2) m[key] = val;
+    fclose(f);
+    return m;
+}
+
+static void write_cache(const char *path, const std::map<std::string, int> &m) {
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+}
+
+static int autotune(Core &c, const char *cache_path) {
+    int rc = c.sync_table();
+    if (rc) return rc;
+    const std::string pre = arch_name() + (c.prec == CNS_FP64 ? "|fp64|" : "|mixed|");
+    std::map<std::string, int> cache = read_cache(cache_path);
+    bool changed = false;
+    // size classes
+    std::map<std::string, std::vector<int>> cls;
+    for (int i = 0; i < c.nbox(); ++i) {
+        const BoxDesc &b = c.boxes[i];
+        char k[64];
+        snprintf(k, sizeof k, "%dx%dx%d|mu%d", b.nx, b.ny, b.nz, b.mu > 0 ? 1 : 0);
+        cls[k].push_back(i);
+    }
+    const int segs[] = {4, 8, 16, 32, 64};
+    std::vector<BoxDesc> saved = c.boxes;
+    for (auto &kv : cls) {
+        const std::string key = pre + kv.first + "|seg";
+        int best = -1;
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            best = it->second;
+        } else {
+            // time this class alone: other boxes get no blocks (sweeps skip them)
+            float best_ms = 1e30f;
+            const BoxDesc &b0 = c.boxes[kv.second[0]];
+            for (int s : segs) {
+                if (s > std::max(b0.ny, b0.nz)) continue;
+                for (int i = 0; i < c.nbox(); ++i) {
+                    c.boxes[i] = saved[i];
+                    c.active[i] = std::find(kv.second.begin(), kv.second.end(), i) != kv.second.end();
+                    if (c.active[i]) c.boxes[i].seg[1] = c.boxes[i].seg[2] = s;
+                }
+                c.dirty = true;
+                if ((rc = c.sync_table())) return rc;
+                Batch bt = c.batch();
+                time_sweeps_yz(bt, 1);  // warm
+                float ms = time_sweeps_yz(bt, 3);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = s;
+                }
+            }
+            cache[key] = best;
+            changed = true;
+        }
+        for (int i : kv.second) saved[i].seg[1] = saved[i].seg[2] = best;
+    }
+    for (int i = 0; i < c.nbox(); ++i) {
+        c.boxes[i] = saved[i];
+        c.active[i] = 1;
+    }
+    // block size of the batch
+    const std::string bkey = pre + "block|n" + std::to_string(c.nbox());
+    auto bit = cache.find(bkey);
+    if (bit != cache.end()) {
+        c.block = bit->second;
+    } else {
+        float best_ms = 1e30f;
+        int best = 256;
+        for (int blk : {64, 128, 256}) {
+            c.block = blk;
+            c.dirty = true;
+            if ((rc = c.sync_table())) return rc;
+            Batch bt = c.batch();
+            time_sweeps_yz(bt, 1);
+            float ms = time_sweeps_yz(bt, 3);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = blk;
+            }
+        }
+        c.block = best;
+        cache[bkey] = best;
+        changed = true;
+    }
+    c.dirty = true;
+    if ((rc = c.sync_table())) return rc;
+    if (changed) write_cache(cache_path, cache);
+    return check_hip("autotune");
+}
+
+// ----------------------------------------------------------------------------
+// C-ABI
+// ----------------------------------------------------------------------------
+static int check_plan(const cns_plan *p) {
+    if (!p) return set_err(CNS_EINVAL, "null plan");
+    if (!p->c.ws) return set_err(CNS_EWORKSPACE, "workspace of %zu bytes required (none bound)", p->c.need);
+    return CNS_OK;
 }
 
 extern "C" {
@@ -109,31 +423,18 @@ extern "C" {
 const char *cns_last_error(void) { return g_err; }
 
 int cns_plan_create(cns_plan **out, const cns_grid *grid, const cns_physics *phys, int32_t precision, void *stream) {
-    if (!out || !grid || !phys) return set_err(CNS_EINVAL, "null argument");
+    if (!out) return set_err(CNS_EINVAL, "null output pointer");
     *out = nullptr;
-    if (grid->nx < 8 || grid->ny < 8 || grid->nz < 8)
-        return set_err(CNS_EINVAL, "grid must have at least 8 points per direction (got %d x %d x %d)", grid->nx,
-                       grid->ny, grid->nz);
-    if (!(grid->lx > 0 && grid->ly > 0 && grid->lz > 0)) return set_err(CNS_EINVAL, "box lengths must be positive");
-    if ((double)grid->nx * grid->ny * grid->nz * 5.0 > 9.0e18) return set_err(CNS_EINVAL, "grid too large");
-    if (!(phys->gamma > 1.0)) return set_err(CNS_EINVAL, "gamma must exceed 1");
-    if (!(phys->mu_eff >= 0.0) || !std::isfinite(phys->mu_eff)) return set_err(CNS_EINVAL, "mu_eff must be >= 0");
-    if (phys->mu_eff > 0.0 && !(phys->prandtl > 0.0)) return set_err(CNS_EINVAL, "prandtl must be > 0");
-    if (!(phys->weno_eps > 0.0)) return set_err(CNS_EINVAL, "weno_eps must be > 0");
-    if (!(phys->harten_delta >= 0.0)) return set_err(CNS_EINVAL, "harten_delta must be >= 0");
+    int rc = validate(grid, phys);
+    if (rc) return rc;
     if (precision != CNS_FP64 && precision != CNS_MIXED) return set_err(CNS_EINVAL, "unknown precision %d", precision);
     cns_plan *p = new (std::nothrow) cns_plan();
     if (!p) return set_err(CNS_EINVAL, "out of host memory");
-    p->box.nx = grid->nx;
-    p->box.ny = grid->ny;
-    p->box.nz = grid->nz;
-    p->box.lx = grid->lx;
-    p->box.ly = grid->ly;
-    p->box.lz = grid->lz;
-    p->box.ph = PhysT{phys->gamma, phys->prandtl, phys->mu_eff, phys->weno_eps, phys->harten_delta};
-    p->precision = precision;
-    p->stream = (hipStream_t)stream;
-    p->wl = layout(p->box, precision == CNS_FP64 ? sizeof(double) : sizeof(float));
+    p->c.prec = precision;
+    p->c.esz = precision == CNS_FP64 ? sizeof(double) : sizeof(float);
+    p->c.stream = (hipStream_t)stream;
+    p->c.add_box(*grid, *phys, 0.0, nullptr);
+    p->c.layout();
     *out = p;
     return CNS_OK;
 }
@@ -143,157 +444,251 @@ int cns_plan_destroy(cns_plan *plan) {
     return CNS_OK;
 }
 
-size_t cns_workspace_bytes(const cns_plan *plan) { return plan ? plan->wl.total : 0; }
+size_t cns_workspace_bytes(const cns_plan *plan) { return plan ? plan->c.need : 0; }
 
 int cns_set_workspace(cns_plan *plan, void *ws, size_t bytes) {
     if (!plan) return set_err(CNS_EINVAL, "null plan");
     if (!ws || !aligned(ws)) return set_err(CNS_EINVAL, "workspace must be non-null and 256-byte aligned");
-    if (bytes < plan->wl.total)
-        return set_err(CNS_EWORKSPACE, "workspace of %zu bytes required (got %zu)", plan->wl.total, bytes);
-    plan->ws = (char *)ws;
-    plan->ws_bytes = bytes;
-    return CNS_OK;
+    if (bytes < plan->c.need)
+        return set_err(CNS_EWORKSPACE, "workspace of %zu bytes required (got %zu)", plan->c.need, bytes);
+    plan->c.ws = (char *)ws;
+    plan->c.ws_bytes = bytes;
+    plan->c.dirty = true;
+    return plan->c.sync_table();
 }
 
 int cns_set_tiles(cns_plan *plan, int32_t sx, int32_t sy, int32_t sz, int32_t block) {
     if (!plan) return set_err(CNS_EINVAL, "null plan");
-    int32_t s[3] = {sx, sy, sz};
-    int n[3] = {plan->box.nx, plan->box.ny, plan->box.nz};
-    for (int d = 0; d < 3; ++d) {
+    const int32_t s[3] = {sx, sy, sz};
+    for (int d = 0; d < 3; ++d)
         if (s[d] < 0) return set_err(CNS_EINVAL, "segment length must be >= 0");
-        if (s[d] > 0) plan->tiles.seg[d] = s[d] > n[d] ? n[d] : s[d];
-    }
-    if (block != 0) {
-        if (block < 64 || block > 256 || (block % 64) != 0)
-            return set_err(CNS_EINVAL, "block must be 64, 128, 192 or 256");
-        plan->tiles.block = block;
-    }
+    if (block != 0 && (block < 64 || block > 256 || (block % 64) != 0))
+        return set_err(CNS_EINVAL, "block must be 64, 128, 192 or 256");
+    for (int d = 0; d < 3; ++d)
+        if (s[d] > 0) plan->c.boxes[0].seg[d] = s[d];
+    if (block) plan->c.block = block;
+    plan->c.dirty = true;
+    return plan->c.ws ? plan->c.sync_table() : CNS_OK;
+}
+
+int cns_set_x_kernel(cns_plan *plan, int32_t kind) {
+    if (!plan) return set_err(CNS_EINVAL, "null plan");
+    if (kind != 0 && kind != 1) return set_err(CNS_EINVAL, "x kernel kind must be 0 (rows in LDS) or 1 (marching)");
+    plan->c.xrows_pref = kind == 0 ? 1 : 0;
+    plan->c.dirty = true;
+    return plan->c.ws ? plan->c.sync_table() : CNS_OK;
+}
+
+int cns_set_graph(cns_plan *plan, int32_t enable) {
+    if (!plan) return set_err(CNS_EINVAL, "null plan");
+    if (enable && !plan->c.stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
+    plan->c.use_graph = enable != 0;
+    plan->c.drop_graph();
     return CNS_OK;
 }
 
 int cns_init_state(const cns_plan *plan, const double *rho, const double *vel, const double *p, void *u) {
-    int rc = check_plan(plan, false);
-    if (!rc) rc = check_ptr(rho, "rho");
+    if (!plan) return set_err(CNS_EINVAL, "null plan");
+    int rc = check_ptr(rho, "rho");
     if (!rc) rc = check_ptr(vel, "vel");
     if (!rc) rc = check_ptr(p, "p");
     if (!rc) rc = check_ptr(u, "u");
     if (rc) return rc;
-    if (plan->precision == CNS_FP64)
-        launch_init_state<double>(plan->box, rho, vel, p, (double *)u, plan->stream);
-    else
-        launch_init_state<float>(plan->box, rho, vel, p, (float *)u, plan->stream);
+    const BoxDesc &b = plan->c.boxes[0];
+    launch_init_state(plan->c.prec, b.n3, b.gamma, rho, vel, p, u, plan->c.stream);
     return check_hip("init_state");
 }
 
 int cns_rhs(const cns_plan *plan, const void *u, void *rhs) {
-    int rc = check_plan(plan, true);
+    int rc = check_plan(plan);
     if (!rc) rc = check_ptr(u, "u");
     if (!rc) rc = check_ptr(rhs, "rhs");
     if (rc) return rc;
     if (u == rhs) return set_err(CNS_EINVAL, "u and rhs must not alias");
-    if (plan->precision == CNS_FP64)
-        launch_rhs<double>(plan->box, plan->tiles, (const double *)u, (double *)rhs, ws_at<double>(plan, plan->wl.W),
-                           ws_at<double>(plan, plan->wl.G), plan->stream);
-    else
-        launch_rhs<float>(plan->box, plan->tiles, (const float *)u, (float *)rhs, ws_at<float>(plan, plan->wl.W),
-                          ws_at<float>(plan, plan->wl.G), plan->stream);
+    cns_plan *p = const_cast<cns_plan *>(plan);
+    if ((rc = p->c.sync_table())) return rc;
+    launch_rhs(p->c.batch(), u, rhs);
     return check_hip("rhs");
 }
 
 int cns_rhs_dir(const cns_plan *plan, const void *u, int32_t dir, void *out) {
-    int rc = check_plan(plan, false);
+    int rc = check_plan(plan);
     if (!rc) rc = check_ptr(u, "u");
     if (!rc) rc = check_ptr(out, "out");
     if (rc) return rc;
     if (dir < 0 || dir > 2) return set_err(CNS_EINVAL, "dir must be 0, 1 or 2");
     if (u == out) return set_err(CNS_EINVAL, "u and out must not alias");
-    if (plan->precision == CNS_FP64)
-        launch_rhs_dir<double>(plan->box, plan->tiles, (const double *)u, dir, (double *)out, plan->stream);
-    else
-        launch_rhs_dir<float>(plan->box, plan->tiles, (const float *)u, dir, (float *)out, plan->stream);
+    cns_plan *p = const_cast<cns_plan *>(plan);
+    if ((rc = p->c.sync_table())) return rc;
+    launch_rhs_dir(p->c.batch(), u, dir, out);
     return check_hip("rhs_dir");
 }
 
 int cns_viscous(const cns_plan *plan, const void *u, void *out) {
-    int rc = check_plan(plan, true);
+    int rc = check_plan(plan);
     if (!rc) rc = check_ptr(u, "u");
     if (!rc) rc = check_ptr(out, "out");
     if (rc) return rc;
     if (u == out) return set_err(CNS_EINVAL, "u and out must not alias");
-    if (plan->precision == CNS_FP64)
-        launch_viscous<double>(plan->box, (const double *)u, (double *)out, ws_at<double>(plan, plan->wl.W),
-                               ws_at<double>(plan, plan->wl.G), plan->stream);
-    else
-        launch_viscous<float>(plan->box, (const float *)u, (float *)out, ws_at<float>(plan, plan->wl.W),
-                              ws_at<float>(plan, plan->wl.G), plan->stream);
+    cns_plan *p = const_cast<cns_plan *>(plan);
+    if ((rc = p->c.sync_table())) return rc;
+    if (!(p->c.boxes[0].mu > 0.0)) launch_fill(p->c.prec, 5 * p->c.boxes[0].n3, out, p->c.stream);
+    else launch_viscous(p->c.batch(), u, out);
     return check_hip("viscous");
 }
 
 int cns_rk4(cns_plan *plan, void *u, double dt, int32_t nsteps, double *diag) {
-    int rc = check_plan(plan, true);
+    int rc = check_plan(plan);
     if (!rc) rc = check_ptr(u, "u");
     if (rc) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(CNS_EINVAL, "dt must be positive and finite");
     if (nsteps < 0) return set_err(CNS_EINVAL, "nsteps must be >= 0");
     if (diag && ((uintptr_t)diag & 7u)) return set_err(CNS_EINVAL, "diag must be 8-byte aligned");
-    if (plan->precision == CNS_FP64)
-        rk4_steps<double>(plan, (double *)u, dt, nsteps, diag);
-    else
-        rk4_steps<float>(plan, (float *)u, dt, nsteps, diag);
-    return check_hip("rk4");
+    return plan->c.rk4(u, dt, nsteps, diag);
 }
 
 int cns_diagnostics(const cns_plan *plan, const void *u, double *out) {
-    int rc = check_plan(plan, true);
+    int rc = check_plan(plan);
     if (!rc) rc = check_ptr(u, "u");
     if (rc) return rc;
     if (!out || ((uintptr_t)out & 7u)) return set_err(CNS_EINVAL, "out must be non-null and 8-byte aligned");
-    double *part = ws_at<double>(plan, plan->wl.part);
-    if (plan->precision == CNS_FP64)
-        launch_diag<double>(plan->box, (const double *)u, part, out, plan->stream);
-    else
-        launch_diag<float>(plan->box, (const float *)u, part, out, plan->stream);
+    cns_plan *p = const_cast<cns_plan *>(plan);
+    if ((rc = p->c.sync_table())) return rc;
+    launch_diag(p->c.batch(), u, out, 0, 0);
     return check_hip("diagnostics");
 }
 
 int cns_diagnostics_host(const cns_plan *plan, const void *u, double *out_host) {
     if (!out_host) return set_err(CNS_EINVAL, "out_host is null");
-    int rc = check_plan(plan, true);
+    int rc = check_plan(plan);
     if (rc) return rc;
-    double *dev = ws_at<double>(plan, plan->wl.dhost);
+    double *dev = (double *)(plan->c.ws + plan->c.dhost_off);
     rc = cns_diagnostics(plan, u, dev);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(out_host, dev, CNS_NDIAG * sizeof(double), hipMemcpyDeviceToHost, plan->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    hipError_t e = hipMemcpyAsync(out_host, dev, CNS_NDIAG * sizeof(double), hipMemcpyDeviceToHost, plan->c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->c.stream);
     if (e != hipSuccess) return set_err(CNS_EHIP, "diagnostics_host: %s", hipGetErrorString(e));
-    if (out_host[8] > 0) {
+    if (out_host[8] > 0)
         return set_err(std::isfinite(out_host[0]) ? CNS_ENONPHYSICAL : CNS_ENONFINITE,
                        "%.0f bad grid points (non-finite, rho <= 0 or p <= 0)", out_host[8]);
-    }
     return CNS_OK;
 }
 
 int cns_profile_enable(cns_plan *plan, int32_t enable) {
     if (!plan) return set_err(CNS_EINVAL, "null plan");
-    Prof &pf = plan->prof;
-    if (enable && !pf.ev[0]) {
-        for (auto &e : pf.ev)
-            if (hipEventCreate(&e) != hipSuccess) return set_err(CNS_EHIP, "hipEventCreate failed");
-    }
-    pf.on = enable != 0;
-    pf.n = 0;
-    for (int k = 0; k < K_NKIND; ++k) {
-        pf.ms[k] = 0.0;
-        pf.count[k] = 0;
-    }
-    return CNS_OK;
+    return plan->c.profile_enable(enable);
 }
 
 int cns_profile_read(const cns_plan *plan, double *ms_host, int64_t *count_host) {
     if (!plan || !ms_host || !count_host) return set_err(CNS_EINVAL, "null argument");
     for (int k = 0; k < K_NKIND; ++k) {
-        ms_host[k] = plan->prof.ms[k];
-        count_host[k] = plan->prof.count[k];
+        ms_host[k] = plan->c.prof.ms[k];
+        count_host[k] = plan->c.prof.count[k];
+    }
+    return CNS_OK;
+}
+
+// ---- ensembles ---------------------------------------------------------------
+int cns_ensemble_create(cns_ensemble **out, int32_t nbox, const cns_grid *grids, const cns_physics *phys,
+                        const double *dt, int32_t precision, void *u_packed, const int64_t *offsets, void *stream) {
+    if (!out) return set_err(CNS_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (nbox < 1 || nbox > 65536) return set_err(CNS_EINVAL, "nbox must be in [1, 65536]");
+    if (!grids || !phys || !dt || !offsets) return set_err(CNS_EINVAL, "null argument");
+    if (precision != CNS_FP64 && precision != CNS_MIXED) return set_err(CNS_EINVAL, "unknown precision %d", precision);
+    if (!u_packed || !aligned(u_packed)) return set_err(CNS_EINVAL, "u_packed must be non-null and 256-byte aligned");
+    const size_t esz = precision == CNS_FP64 ? sizeof(double) : sizeof(float);
+    cns_ensemble *e = new (std::nothrow) cns_ensemble();
+    if (!e) return set_err(CNS_EINVAL, "out of host memory");
+    e->c.prec = precision;
+    e->c.esz = esz;
+    e->c.stream = (hipStream_t)stream;
+    for (int i = 0; i < nbox; ++i) {
+        int rc = validate(&grids[i], &phys[i]);
+        if (!rc && (!(dt[i] > 0.0) || !std::isfinite(dt[i]))) rc = set_err(CNS_EINVAL, "dt[%d] must be positive", i);
+        if (!rc && offsets[i] < 0) rc = set_err(CNS_EINVAL, "offsets[%d] is negative", i);
+        void *u = (char *)u_packed + (size_t)offsets[i] * esz;
+        if (!rc && !aligned(u)) rc = set_err(CNS_EINVAL, "box %d state is not 256-byte aligned", i);
+        if (rc) {
+            delete e;
+            return rc;
+        }
+        e->c.add_box(grids[i], phys[i], dt[i], u);
+    }
+    e->c.layout();
+    *out = e;
+    return CNS_OK;
+}
+
+int cns_ensemble_destroy(cns_ensemble *ens) {
+    delete ens;
+    return CNS_OK;
+}
+
+size_t cns_ensemble_workspace_bytes(const cns_ensemble *ens) { return ens ? ens->c.need : 0; }
+
+int cns_ensemble_set_workspace(cns_ensemble *ens, void *ws, size_t bytes) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    if (!ws || !aligned(ws)) return set_err(CNS_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if (bytes < ens->c.need)
+        return set_err(CNS_EWORKSPACE, "workspace of %zu bytes required (got %zu)", ens->c.need, bytes);
+    ens->c.ws = (char *)ws;
+    ens->c.ws_bytes = bytes;
+    ens->c.dirty = true;
+    return ens->c.sync_table();
+}
+
+int cns_ensemble_set_tiles(cns_ensemble *ens, int32_t box, int32_t sx, int32_t sy, int32_t sz, int32_t block) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    if (box < -1 || box >= ens->c.nbox()) return set_err(CNS_EINVAL, "box index out of range");
+    if (sx < 0 || sy < 0 || sz < 0) return set_err(CNS_EINVAL, "segment length must be >= 0");
+    if (block != 0 && (block < 64 || block > 256 || (block % 64) != 0))
+        return set_err(CNS_EINVAL, "block must be 64, 128, 192 or 256");
+    for (int i = 0; i < ens->c.nbox(); ++i) {
+        if (box >= 0 && i != box) continue;
+        if (sx) ens->c.boxes[i].seg[0] = sx;
+        if (sy) ens->c.boxes[i].seg[1] = sy;
+        if (sz) ens->c.boxes[i].seg[2] = sz;
+    }
+    if (block) ens->c.block = block;
+    ens->c.dirty = true;
+    return ens->c.ws ? ens->c.sync_table() : CNS_OK;
+}
+
+int cns_ensemble_get_tiles(const cns_ensemble *ens, int32_t box, int32_t *seg3, int32_t *block) {
+    if (!ens || !seg3 || !block) return set_err(CNS_EINVAL, "null argument");
+    if (box < 0 || box >= ens->c.nbox()) return set_err(CNS_EINVAL, "box index out of range");
+    for (int d = 0; d < 3; ++d) seg3[d] = ens->c.boxes[box].seg[d];
+    *block = ens->c.block;
+    return CNS_OK;
+}
+
+int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    if (!ens->c.ws) return set_err(CNS_EWORKSPACE, "no workspace bound");
+    return autotune(ens->c, cache_path);
+}
+
+int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag, int32_t use_graph) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    if (!ens->c.ws) return set_err(CNS_EWORKSPACE, "no workspace bound");
+    if (nsteps < 0) return set_err(CNS_EINVAL, "nsteps must be >= 0");
+    if (diag && ((uintptr_t)diag & 7u)) return set_err(CNS_EINVAL, "diag must be 8-byte aligned");
+    if (use_graph && !ens->c.stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
+    ens->c.use_graph = use_graph != 0;
+    return ens->c.rk4(nullptr, 0.0, nsteps, diag);
+}
+
+int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    return ens->c.profile_enable(enable);
+}
+
+int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t *count_host) {
+    if (!ens || !ms_host || !count_host) return set_err(CNS_EINVAL, "null argument");
+    for (int k = 0; k < K_NKIND; ++k) {
+        ms_host[k] = ens->c.prof.ms[k];
+        count_host[k] = ens->c.prof.count[k];
     }
     return CNS_OK;
 }

@@ -1,34 +1,69 @@
-// cns_internal.h -- host-side internals shared by the kernel launchers and the C-ABI.
+// cns_internal.h -- internals shared by the kernels (cns_kernels.hip) and the C-ABI
+// (cns_api.hip).
+//
+// Every launch works on a *batch* of periodic boxes described by a device table of
+// BoxDesc entries.  A kernel's blocks are virtual: for each kernel family a prefix
+// array off[0..nbox] gives the first virtual block of every box; a block finds its
+// box by binary search and runs the single-box code on its local block index.  A
+// single-box plan is a batch of one, so a box advanced inside an ensemble executes
+// exactly the machine code of its single-box run.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
-#include <string>
+#include <vector>
 
 #include "cns.h"
 #include "cns_device.h"
 
 namespace cns {
 
-// workspace layout of a plan (byte offsets into the caller's buffer)
-struct Workspace {
-    size_t W, G, rhs, stA, stB, acc, part, dhost, total;
+constexpr int kPointThreads = 256;    // threads per block of point-wise kernels
+constexpr int kDiagThreads = 256;
+constexpr int kDiagBlocksMax = 1024;  // partial-sum blocks per box of the diagnostics
+constexpr int kRowThreads = 256;      // threads per block of the x rows kernel
+constexpr int kRowLdsMax = 64 * 1024;
+
+// buffer roles of a box
+enum Buf { BUF_U = 0, BUF_A = 1, BUF_B = 2 };
+
+struct BoxDesc {
+    int nx, ny, nz;
+    int seg[3];  // marching-sweep segment length per direction
+    int xrows;   // 1: x sweep by the rows kernel, 0: by the marching kernel
+    int rows;    // rows per block of the x rows kernel
+    size_t n3;
+    double inv_h[3];  // 1/dx, 1/dy, 1/dz
+    double gamma, prandtl, mu, eps, delta, dt;
+    void *u, *A, *B, *rhs, *W, *G;  // state and scratch (element type of the plan)
+    double *acc, *part;             // RK4 accumulator [5][n3], diagnostics partials
 };
 
-constexpr int kDiagBlocks = 1024;  // partial-sum blocks of the diagnostics reduction
-constexpr int kDiagThreads = 256;
+// kernel families with their own virtual-block prefix
+enum Family { F_POINT = 0, F_XROWS, F_SWEEP_X, F_SWEEP_Y, F_SWEEP_Z, F_DIAG, F_BOX, F_N };
 
-struct Box {
-    int nx, ny, nz;
-    double lx, ly, lz;
-    PhysT ph;
-    size_t n3() const { return (size_t)nx * ny * nz; }
+// per-launch arguments
+struct Launch {
+    const BoxDesc *boxes;
+    const long long *off;  // this family's prefix [nbox + 1]
+    int nbox;
+    long long total;  // off[nbox]
+    int in;           // Buf of the state read by the kernel
+    int out;          // Buf written by the fused RK4 stage update
+    int stage;        // RK4 stage 1..4 (fused update) or 0
+    int step;         // diagnostics record index
+    // single-box overrides (used when non-null / positive)
+    const void *u_ov;  // replaces the box's state u
+    void *out_ov;      // replaces rhs as the output of WRITE/ACCUM sweeps and viscous kernels
+    double dt_ov;      // replaces the box's dt
+    double *diag;      // diagnostics output base (may be null)
+    long long diag_box_stride;  // records between consecutive boxes in `diag`
 };
 
 // optional per-kernel timing with HIP events on the plan's stream
 enum KernelKind { K_PRIM = 0, K_VISC_FLUX, K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_DIAG, K_NKIND };
-constexpr int kMaxProfLaunch = 32;
+constexpr int kMaxProfLaunch = 48;
 
 struct Prof {
     bool on = false;
@@ -40,7 +75,6 @@ struct Prof {
     hipStream_t s = nullptr;
 };
 
-// brackets one launch with a pair of events when profiling is on
 struct ProfScope {
     Prof *p;
     int slot = -1;
@@ -48,36 +82,49 @@ struct ProfScope {
         if (p && p->on && p->n < kMaxProfLaunch) {
             slot = p->n++;
             p->kind[slot] = kind;
-            hipEventRecord(p->ev[2 * slot], s);
+            (void)hipEventRecord(p->ev[2 * slot], s);
             p->s = s;
         }
     }
     ~ProfScope() {
-        if (slot >= 0) hipEventRecord(p->ev[2 * slot + 1], p->s);
+        if (slot >= 0) (void)hipEventRecord(p->ev[2 * slot + 1], p->s);
     }
 };
-// wait for the recorded events and add their durations to the totals
 void prof_flush(Prof *p);
 
-struct Tiles {
-    int seg[3] = {16, 16, 16};
-    int block = 256;
+// host view of a batch: what the launchers need
+struct Batch {
+    int nbox = 0;
+    int prec = CNS_FP64;
+    int block = 256;  // threads per block of the marching sweeps
+    bool any_visc = false;
+    const BoxDesc *d_boxes = nullptr;  // device table
+    const long long *d_off[F_N] = {};  // device prefixes
+    long long total[F_N] = {};
+    int rowP = 1;       // points per thread of the rows kernel (max over boxes)
+    size_t rowLds = 0;  // LDS bytes of the rows kernel (max over boxes)
+    hipStream_t stream = nullptr;
+    Prof *prof = nullptr;
 };
 
-// kernel launchers (cns_kernels.hip); T = double or float
-template <typename T>
-void launch_init_state(const Box &b, const double *rho, const double *vel, const double *p, T *u, hipStream_t s);
-// full RHS, or RK stage (stage 1..4) when stage > 0: see cns_kernels.hip
-template <typename T>
-void launch_rhs(const Box &b, const Tiles &t, const T *u, T *rhs, T *W, T *G, hipStream_t s);
-template <typename T>
-void launch_rhs_dir(const Box &b, const Tiles &t, const T *u, int dir, T *out, hipStream_t s);
-template <typename T>
-void launch_viscous(const Box &b, const T *u, T *out, T *W, T *G, hipStream_t s);
-template <typename T>
-void launch_rk4_stage(const Box &b, const Tiles &t, int stage, const T *ustage, T *un, T *unext, double *acc,
-                      double dt, T *rhs, T *W, T *G, hipStream_t s, Prof *pf = nullptr);
-template <typename T>
-void launch_diag(const Box &b, const T *u, double *part, double *out, hipStream_t s, Prof *pf = nullptr);
+// host-side helpers (cns_kernels.hip)
+int rows_for(int nx);
+bool rows_fits(int nx, size_t esz, int *P);
+long long family_blocks(const BoxDesc &b, int fam, int block);
+
+// launchers (cns_kernels.hip); all enqueue on bt.stream
+void launch_init_state(int prec, size_t n3, double gamma, const double *rho, const double *vel, const double *p,
+                       void *u, hipStream_t s);
+void launch_fill(int prec, size_t n, void *out, hipStream_t s);
+// full RHS of every box into `out_ov` (single box) or each box's rhs buffer
+void launch_rhs(const Batch &bt, const void *u_ov, void *out_ov);
+void launch_rhs_dir(const Batch &bt, const void *u_ov, int dir, void *out_ov);
+void launch_viscous(const Batch &bt, const void *u_ov, void *out_ov);
+// one RK4 step of every box (4 stages with fused updates), then diagnostics if diag
+void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long diag_box_stride,
+                     int step);
+void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag_box_stride, int step);
+// time the y and z marching sweeps over the batch (autotuning); milliseconds per launch pair
+float time_sweeps_yz(const Batch &bt, int reps);
 
 }  // namespace cns

@@ -1,20 +1,27 @@
 // cns_kernels.hip -- gfx950 kernels of the WENO5-Roe / central-viscous RHS and RK4.
 //
-// Data layout in HBM: SoA state u[v][k][j][i] (x fastest).  One RHS evaluation is
-//   1. k_prim       : u -> W = (u, v, w, T)                          [4][N3]
+// Data layout in HBM: SoA state u[v][k][j][i] (x fastest) per box.  One RHS
+// evaluation of a batch of boxes is
+//   1. k_prim       : u -> W = (u, v, w, T)                              [4][N3]
 //   2. k_visc_flux  : W -> viscous fluxes G = (tau_xx, tau_yy, tau_zz, tau_xy,
-//                     tau_xz, tau_yz, E_x, E_y, E_z), E_d = v.tau_d - q_d   [9][N3]
-//   3. k_sweep<x>   : u, G -> rhs  (write)
-//   4. k_sweep<y>   : u, G -> rhs  (accumulate)
-//   5. k_sweep<z>   : u, G -> rhs  (accumulate), or the fused RK4 stage update
-// Each sweep thread owns a segment of one grid line along the sweep direction and
-// marches along it with a six-point register window: every point's flux is
-// computed once, every interface flux once per segment, and the flux difference
-// is formed in registers.  The viscous term along d enters the same difference as
-// the interface flux (-G_{j-1} + 7 G_j + 7 G_{j+1} - G_{j+2}) / 12, whose
-// difference is the 5-point central derivative of G.  Periodic boundaries wrap
-// the line index; there are no ghost cells.
+//                     tau_xz, tau_yz, E_x, E_y, E_z), E_d = v.tau_d - q_d       [9][N3]
+//   3. x sweep      : u, G -> rhs (write).  Whole periodic rows staged in LDS, one
+//                     thread per interface (k_sweep_x_rows); the marching kernel
+//                     when a row does not fit.
+//   4. k_sweep<y>   : u, G -> rhs (accumulate)
+//   5. k_sweep<z>   : u, G -> rhs (accumulate), or the fused RK4 stage update.
+// A marching thread owns a segment of one grid line and walks along it with a
+// six-point register window: every point flux is computed once, every interface
+// flux once per segment, the flux difference is formed in registers.  The viscous
+// term along d enters through the interface flux (-G_{j-1} + 7 G_j + 7 G_{j+1} -
+// G_{j+2}) / 12, whose difference is the 5-point central derivative of G.
+// Periodic boundaries wrap the line index; there are no ghost cells.
+//
+// Every kernel takes a Launch over a batch of boxes (see cns_internal.h) and loops
+// over virtual blocks, so one launch advances every box of an ensemble.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "cns_internal.h"
 
@@ -22,8 +29,23 @@ namespace cns {
 
 __device__ __forceinline__ int wrapi(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
 
+// box owning virtual block vb: the last i with off[i] <= vb
+__device__ __forceinline__ int find_box(const long long *off, int nbox, long long vb) {
+    int lo = 0, hi = nbox;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= vb) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
+    return which == BUF_U ? (L.u_ov ? L.u_ov : b.u) : (which == BUF_A ? b.A : b.B);
+}
+
 // ----------------------------------------------------------------------------
-// state from primitives (Sec. 2.1 equation of state)
+// state from primitives (Sec. 2.1 equation of state); single box
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ void k_init_state(size_t n3, double gm1, const double *rho, const double *vel, const double *p, T *u) {
@@ -38,74 +60,88 @@ __global__ void k_init_state(size_t n3, double gm1, const double *rho, const dou
 }
 
 template <typename T>
-__global__ void k_fill(size_t n, T v, T *out) {
+__global__ void k_fill(size_t n, T *out) {
     size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = v;
+    if (i < n) out[i] = T(0);
 }
 
 // ----------------------------------------------------------------------------
 // viscous terms: primitives, then viscous fluxes at points
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ void k_prim(size_t n3, T gamma, const T *__restrict__ u, T *__restrict__ W) {
-    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i >= n3) return;
-    T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
-    T inv = T(1) / r;
-    T vx = mx * inv, vy = my * inv, vz = mz * inv;
-    T p = (gamma - T(1)) * (e - T(0.5) * (mx * vx + my * vy + mz * vz));
-    W[i] = vx;
-    W[n3 + i] = vy;
-    W[2 * n3 + i] = vz;
-    W[3 * n3 + i] = gamma * p * inv;  // T = gamma p / rho
+__global__ __launch_bounds__(kPointThreads) void k_prim(Launch L) {
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &b = L.boxes[bi];
+        const size_t n3 = b.n3;
+        const size_t i = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
+        if (i >= n3) continue;
+        const T *u = (const T *)state_ptr(b, L, L.in);
+        T *W = (T *)b.W;
+        const T gamma = T(b.gamma);
+        T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
+        T inv = T(1) / r;
+        T vx = mx * inv, vy = my * inv, vz = mz * inv;
+        T p = (gamma - T(1)) * (e - T(0.5) * (mx * vx + my * vy + mz * vz));
+        W[i] = vx;
+        W[n3 + i] = vy;
+        W[2 * n3 + i] = vz;
+        W[3 * n3 + i] = gamma * p * inv;  // T = gamma p / rho
+    }
 }
 
 template <typename T>
-__global__ void k_visc_flux(int nx, int ny, int nz, T ihx, T ihy, T ihz, T mu, T kcond, const T *__restrict__ W,
-                            T *__restrict__ G) {
-    size_t n3 = (size_t)nx * ny * nz;
-    size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (idx >= n3) return;
-    int i = (int)(idx % nx);
-    int j = (int)((idx / nx) % ny);
-    int k = (int)(idx / ((size_t)nx * ny));
-    const size_t sy = nx, sz = (size_t)nx * ny;
-    size_t row = idx - i;
-    size_t xm2 = row + wrapi(i - 2, nx), xm1 = row + wrapi(i - 1, nx), xp1 = row + wrapi(i + 1, nx),
-           xp2 = row + wrapi(i + 2, nx);
-    size_t col = idx - j * sy;
-    size_t ym2 = col + wrapi(j - 2, ny) * sy, ym1 = col + wrapi(j - 1, ny) * sy, yp1 = col + wrapi(j + 1, ny) * sy,
-           yp2 = col + wrapi(j + 2, ny) * sy;
-    size_t pil = idx - k * sz;
-    size_t zm2 = pil + wrapi(k - 2, nz) * sz, zm1 = pil + wrapi(k - 1, nz) * sz, zp1 = pil + wrapi(k + 1, nz) * sz,
-           zp2 = pil + wrapi(k + 2, nz) * sz;
-    T g[4][3];  // g[a][b] = d W_a / d x_b
+__global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &b = L.boxes[bi];
+        const int nx = b.nx, ny = b.ny, nz = b.nz;
+        const size_t n3 = b.n3;
+        const size_t idx = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
+        if (idx >= n3) continue;
+        const T *W = (const T *)b.W;
+        T *G = (T *)b.G;
+        const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
+        const T mu = T(b.mu), kcond = T(b.mu / ((b.gamma - 1.0) * b.prandtl));
+        const int i = (int)(idx % nx);
+        const int j = (int)((idx / nx) % ny);
+        const int k = (int)(idx / ((size_t)nx * ny));
+        const size_t sy = nx, sz = (size_t)nx * ny;
+        const size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
+        const size_t xm2 = row + wrapi(i - 2, nx), xm1 = row + wrapi(i - 1, nx), xp1 = row + wrapi(i + 1, nx),
+                     xp2 = row + wrapi(i + 2, nx);
+        const size_t ym2 = col + wrapi(j - 2, ny) * sy, ym1 = col + wrapi(j - 1, ny) * sy,
+                     yp1 = col + wrapi(j + 1, ny) * sy, yp2 = col + wrapi(j + 2, ny) * sy;
+        const size_t zm2 = pil + wrapi(k - 2, nz) * sz, zm1 = pil + wrapi(k - 1, nz) * sz,
+                     zp1 = pil + wrapi(k + 1, nz) * sz, zp2 = pil + wrapi(k + 2, nz) * sz;
+        T g[4][3];  // g[a][c] = d W_a / d x_c
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const T *f = W + a * n3;
-        g[a][0] = dcen(f[xm2], f[xm1], f[xp1], f[xp2]) * ihx;
-        g[a][1] = dcen(f[ym2], f[ym1], f[yp1], f[yp2]) * ihy;
-        g[a][2] = dcen(f[zm2], f[zm1], f[zp1], f[zp2]) * ihz;
+        for (int a = 0; a < 4; ++a) {
+            const T *f = W + a * n3;
+            g[a][0] = dcen(f[xm2], f[xm1], f[xp1], f[xp2]) * ihx;
+            g[a][1] = dcen(f[ym2], f[ym1], f[yp1], f[yp2]) * ihy;
+            g[a][2] = dcen(f[zm2], f[zm1], f[zp1], f[zp2]) * ihz;
+        }
+        T div = g[0][0] + g[1][1] + g[2][2];
+        T tdiv = T(2) / T(3) * div;
+        T txx = mu * (T(2) * g[0][0] - tdiv);
+        T tyy = mu * (T(2) * g[1][1] - tdiv);
+        T tzz = mu * (T(2) * g[2][2] - tdiv);
+        T txy = mu * (g[0][1] + g[1][0]);
+        T txz = mu * (g[0][2] + g[2][0]);
+        T tyz = mu * (g[1][2] + g[2][1]);
+        T vx = W[idx], vy = W[n3 + idx], vz = W[2 * n3 + idx];
+        G[idx] = txx;
+        G[n3 + idx] = tyy;
+        G[2 * n3 + idx] = tzz;
+        G[3 * n3 + idx] = txy;
+        G[4 * n3 + idx] = txz;
+        G[5 * n3 + idx] = tyz;
+        // E_d = v . tau_d - q_d,  q_d = -kcond dT/dx_d
+        G[6 * n3 + idx] = vx * txx + vy * txy + vz * txz + kcond * g[3][0];
+        G[7 * n3 + idx] = vx * txy + vy * tyy + vz * tyz + kcond * g[3][1];
+        G[8 * n3 + idx] = vx * txz + vy * tyz + vz * tzz + kcond * g[3][2];
     }
-    T div = g[0][0] + g[1][1] + g[2][2];
-    T tdiv = T(2) / T(3) * div;
-    T txx = mu * (T(2) * g[0][0] - tdiv);
-    T tyy = mu * (T(2) * g[1][1] - tdiv);
-    T tzz = mu * (T(2) * g[2][2] - tdiv);
-    T txy = mu * (g[0][1] + g[1][0]);
-    T txz = mu * (g[0][2] + g[2][0]);
-    T tyz = mu * (g[1][2] + g[2][1]);
-    T vx = W[idx], vy = W[n3 + idx], vz = W[2 * n3 + idx];
-    G[idx] = txx;
-    G[n3 + idx] = tyy;
-    G[2 * n3 + idx] = tzz;
-    G[3 * n3 + idx] = txy;
-    G[4 * n3 + idx] = txz;
-    G[5 * n3 + idx] = tyz;
-    // E_d = v . tau_d - q_d,  q_d = -kcond dT/dx_d
-    G[6 * n3 + idx] = vx * txx + vy * txy + vz * txz + kcond * g[3][0];
-    G[7 * n3 + idx] = vx * txy + vy * tyy + vz * tyz + kcond * g[3][1];
-    G[8 * n3 + idx] = vx * txz + vy * tyz + vz * tzz + kcond * g[3][2];
 }
 
 // which G field holds component (momentum x, y, z, energy) of the viscous flux along DIR
@@ -115,162 +151,292 @@ __device__ __forceinline__ constexpr int gcomp(int c) {
                     : (DIR == 1 ? (c == 0 ? 3 : c == 1 ? 1 : c == 2 ? 5 : 7) : (c == 0 ? 4 : c == 1 ? 5 : c == 2 ? 2 : 8));
 }
 
-// viscous term alone: out = sum_d D_d G_d (used by the viscous-only entry point)
+// viscous term alone: out = sum_d D_d G_d (the viscous-only entry point)
 template <typename T>
-__global__ void k_visc_div(int nx, int ny, int nz, T ihx, T ihy, T ihz, const T *__restrict__ G, T *__restrict__ out) {
-    size_t n3 = (size_t)nx * ny * nz;
-    size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (idx >= n3) return;
-    int i = (int)(idx % nx);
-    int j = (int)((idx / nx) % ny);
-    int k = (int)(idx / ((size_t)nx * ny));
-    const size_t sy = nx, sz = (size_t)nx * ny;
-    size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
-    size_t x[4] = {row + wrapi(i - 2, nx), row + wrapi(i - 1, nx), row + wrapi(i + 1, nx), row + wrapi(i + 2, nx)};
-    size_t y[4] = {col + wrapi(j - 2, ny) * sy, col + wrapi(j - 1, ny) * sy, col + wrapi(j + 1, ny) * sy,
-                   col + wrapi(j + 2, ny) * sy};
-    size_t z[4] = {pil + wrapi(k - 2, nz) * sz, pil + wrapi(k - 1, nz) * sz, pil + wrapi(k + 1, nz) * sz,
-                   pil + wrapi(k + 2, nz) * sz};
-    out[idx] = T(0);
+__global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &b = L.boxes[bi];
+        const int nx = b.nx, ny = b.ny, nz = b.nz;
+        const size_t n3 = b.n3;
+        const size_t idx = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
+        if (idx >= n3) continue;
+        const T *G = (const T *)b.G;
+        T *out = (T *)(L.out_ov ? L.out_ov : b.rhs);
+        const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
+        const int i = (int)(idx % nx);
+        const int j = (int)((idx / nx) % ny);
+        const int k = (int)(idx / ((size_t)nx * ny));
+        const size_t sy = nx, sz = (size_t)nx * ny;
+        const size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
+        const size_t x[4] = {row + wrapi(i - 2, nx), row + wrapi(i - 1, nx), row + wrapi(i + 1, nx),
+                             row + wrapi(i + 2, nx)};
+        const size_t y[4] = {col + wrapi(j - 2, ny) * sy, col + wrapi(j - 1, ny) * sy, col + wrapi(j + 1, ny) * sy,
+                             col + wrapi(j + 2, ny) * sy};
+        const size_t z[4] = {pil + wrapi(k - 2, nz) * sz, pil + wrapi(k - 1, nz) * sz, pil + wrapi(k + 1, nz) * sz,
+                             pil + wrapi(k + 2, nz) * sz};
+        out[idx] = T(0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const T *gx = G + gcomp<0>(c) * n3;
-        const T *gy = G + gcomp<1>(c) * n3;
-        const T *gz = G + gcomp<2>(c) * n3;
-        T s = dcen(gx[x[0]], gx[x[1]], gx[x[2]], gx[x[3]]) * ihx;
-        s += dcen(gy[y[0]], gy[y[1]], gy[y[2]], gy[y[3]]) * ihy;
-        s += dcen(gz[z[0]], gz[z[1]], gz[z[2]], gz[z[3]]) * ihz;
-        out[(1 + c) * n3 + idx] = s;
+        for (int c = 0; c < 4; ++c) {
+            const T *gx = G + gcomp<0>(c) * n3;
+            const T *gy = G + gcomp<1>(c) * n3;
+            const T *gz = G + gcomp<2>(c) * n3;
+            T s = dcen(gx[x[0]], gx[x[1]], gx[x[2]], gx[x[3]]) * ihx;
+            s += dcen(gy[y[0]], gy[y[1]], gy[y[2]], gy[y[3]]) * ihy;
+            s += dcen(gz[z[0]], gz[z[1]], gz[z[2]], gz[z[3]]) * ihz;
+            out[(1 + c) * n3 + idx] = s;
+        }
     }
 }
 
 // ----------------------------------------------------------------------------
-// the WENO5-Roe sweep along one direction
+// interface flux at j+1/2 from the states w and point fluxes f at j-2 .. j+3 and
+// (VISC) the viscous fluxes g at j-1 .. j+2:
+//   H = (f^L + f^R)/2 - |A| (u^R - u^L)/2 - (-g_{j-1} + 7 g_j + 7 g_{j+1} - g_{j+2})/12
+// ----------------------------------------------------------------------------
+template <typename T, typename B, int DIR, bool VISC>
+__device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5], const T g[4][4], T gamma, T eps,
+                                               T delta, T H[5]) {
+    T FL[5], FR[5], UL[5], UR[5], du[5], D[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        weno5_lr<T, B>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps, FL[v], FR[v]);
+        weno5_lr<T, B>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL[v], UR[v]);
+        du[v] = UR[v] - UL[v];
+    }
+    roe_dissipation<T, DIR>(w[2], w[3], du, gamma, delta, D);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) H[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * D[v];
+    if constexpr (VISC) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            H[1 + c] -= (T(7) * (g[1][c] + g[2][c]) - (g[0][c] + g[3][c])) * (T(1) / T(12));
+    }
+}
+
+// ----------------------------------------------------------------------------
+// marching WENO5-Roe sweep along one direction
 // ----------------------------------------------------------------------------
 enum { MODE_WRITE = 0, MODE_ACCUM = 1, MODE_RK = 2 };
 
-template <typename T>
-struct SweepArgs {
-    const T *u;  // state being differentiated
-    const T *G;  // viscous fluxes [9][N3] (VISC only)
-    T *rhs;      // output / accumulation buffer
-    // fused RK4 stage update (MODE_RK)
-    const T *un;
-    double *acc;
-    T *unext;
-    double dt;
-    int stage;
-    // geometry: lanes run over the plane (p fastest), threads march along the line
-    size_t n3;
-    int nline;
-    size_t lstride;
-    int np;
-    size_t pstride, qstride;
-    int npq, seg, nseg;
-    T inv_dx;
-    T gamma, eps, delta;
+// geometry of a sweep along DIR: lanes run over the plane normal to DIR (p fastest)
+struct SweepGeom {
+    int nline, np, npq;
+    size_t lstride, pstride, qstride;
 };
+template <int DIR>
+__host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz) {
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    if (DIR == 0) return SweepGeom{nx, ny, ny * nz, 1, sy, sz};
+    if (DIR == 1) return SweepGeom{ny, nx, nx * nz, sy, 1, sz};
+    return SweepGeom{nz, nx, nx * ny, sz, 1, sy};
+}
 
 template <typename T, typename B, int DIR, int MODE, bool VISC>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= (size_t)a.npq * a.nseg) return;
-    const int pq = (int)(t % a.npq);
-    const int sg = (int)(t / a.npq);
-    const int p = pq % a.np, q = pq / a.np;
-    const size_t base = p * a.pstride + q * a.qstride;
-    const int n = a.nline;
-    const int j0 = sg * a.seg;
-    const int j1 = min(j0 + a.seg, n);
-    const size_t n3 = a.n3;
-    const T gm1 = a.gamma - T(1);
+__global__ __launch_bounds__(256) void k_sweep(Launch L) {
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &bx = L.boxes[bi];
+        const SweepGeom sg = sweep_geom<DIR>(bx.nx, bx.ny, bx.nz);
+        const int n = sg.nline;
+        const int seg = bx.seg[DIR];
+        const int nseg = (n + seg - 1) / seg;
+        const size_t t = (size_t)(vb - L.off[bi]) * blockDim.x + threadIdx.x;
+        if (t >= (size_t)sg.npq * nseg) continue;
+        const int pq = (int)(t % sg.npq);
+        const int sgi = (int)(t / sg.npq);
+        const int p = pq % sg.np, q = pq / sg.np;
+        const size_t base = p * sg.pstride + q * sg.qstride;
+        const int j0 = sgi * seg;
+        const int j1 = min(j0 + seg, n);
+        const size_t n3 = bx.n3;
+        const T *u = (const T *)state_ptr(bx, L, L.in);
+        const T *G = (const T *)bx.G;
+        const T gamma = T(bx.gamma), eps = T(bx.eps), delta = T(bx.delta);
+        const T gm1 = gamma - T(1);
+        const T inv_dx = T(bx.inv_h[DIR]);
 
-    T w[6][5], f[6][5], g[4][4], Hp[5];
-    // One loop computes everything, so every point flux and every interface flux
-    // runs the same machine code wherever a segment starts: results are bitwise
-    // independent of the segment length.  Iteration j loads point j+3 (and the
-    // viscous fluxes of point j+2); from j = j0-1 on it forms the interface flux at
-    // j+1/2 and from j = j0 on the flux difference at point j.
+        T w[6][5], f[6][5], g[4][4], Hp[5];
+        // One loop computes everything, so every point flux and every interface flux
+        // runs the same machine code wherever a segment starts: results are bitwise
+        // independent of the segment length.  Iteration j loads point j+3 (and the
+        // viscous fluxes of point j+2); from j = j0-1 on it forms the interface flux
+        // at j+1/2 and from j = j0 on the flux difference at point j.
 #pragma nounroll
-    for (int j = j0 - 6; j < j1; ++j) {
+        for (int j = j0 - 6; j < j1; ++j) {
 #pragma unroll
-        for (int m = 0; m < 5; ++m)
+            for (int m = 0; m < 5; ++m)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                w[m][v] = w[m + 1][v];
-                f[m][v] = f[m + 1][v];
+                for (int v = 0; v < 5; ++v) {
+                    w[m][v] = w[m + 1][v];
+                    f[m][v] = f[m + 1][v];
+                }
+            {
+                const size_t o = base + wrapi(j + 3, n) * sg.lstride;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) w[5][v] = u[v * n3 + o];
+                euler_flux<T, DIR>(w[5], gm1, f[5]);
             }
-        {
-            const size_t o = base + wrapi(j + 3, n) * a.lstride;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) w[5][v] = a.u[v * n3 + o];
-            euler_flux<T, DIR>(w[5], gm1, f[5]);
-        }
-        if constexpr (VISC) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) g[m][c] = g[m + 1][c];
-            const size_t o = base + wrapi(j + 2, n) * a.lstride;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) g[3][c] = a.G[gcomp<DIR>(c) * n3 + o];
-        }
-        if (j < j0 - 1) continue;
-
-        // interface flux at j+1/2 from the window j-2 .. j+3
-        T H[5];
-        {
-            T FL[5], FR[5], UL[5], UR[5], du[5], D[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                weno5_lr<T, B>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], a.eps, FL[v], FR[v]);
-                weno5_lr<T, B>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], a.eps, UL[v], UR[v]);
-                du[v] = UR[v] - UL[v];
-            }
-            roe_dissipation<T, DIR>(w[2], w[3], du, a.gamma, a.delta, D);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) H[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * D[v];
             if constexpr (VISC) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    H[1 + c] -= (T(7) * (g[1][c] + g[2][c]) - (g[0][c] + g[3][c])) * (T(1) / T(12));
-            }
-        }
-        if (j >= j0) {
-            const size_t o = base + (size_t)j * a.lstride;
+                for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const T r = -(H[v] - Hp[v]) * a.inv_dx;
-                const size_t e = v * n3 + o;
-                if constexpr (MODE == MODE_WRITE) {
-                    a.rhs[e] = r;
-                } else if constexpr (MODE == MODE_ACCUM) {
-                    a.rhs[e] += r;
+                    for (int c = 0; c < 4; ++c) g[m][c] = g[m + 1][c];
+                const size_t o = base + wrapi(j + 2, n) * sg.lstride;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + o];
+            }
+            if (j < j0 - 1) continue;
+
+            T H[5];
+            interface_flux<T, B, DIR, VISC>(w, f, g, gamma, eps, delta, H);
+            if (j >= j0) {
+                const size_t o = base + (size_t)j * sg.lstride;
+                if constexpr (MODE == MODE_RK) {
+                    const T *rhs = (const T *)bx.rhs;
+                    const T *un = (const T *)state_ptr(bx, L, BUF_U);
+                    T *unext = (T *)state_ptr(bx, L, L.out);
+                    double *acc = bx.acc;
+                    const double dt = L.dt_ov > 0.0 ? L.dt_ov : bx.dt;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        const T r = -(H[v] - Hp[v]) * inv_dx;
+                        const size_t e = v * n3 + o;
+                        const double k = double(rhs[e] + r);
+                        const double uo = double(un[e]);
+                        if (L.stage == 1) {
+                            acc[e] = uo + (dt / 6.0) * k;
+                            unext[e] = T(uo + (0.5 * dt) * k);
+                        } else if (L.stage == 2) {
+                            acc[e] += (dt / 3.0) * k;
+                            unext[e] = T(uo + (0.5 * dt) * k);
+                        } else if (L.stage == 3) {
+                            acc[e] += (dt / 3.0) * k;
+                            unext[e] = T(uo + dt * k);
+                        } else {
+                            unext[e] = T(acc[e] + (dt / 6.0) * k);
+                        }
+                    }
                 } else {
-                    const double k = double(a.rhs[e] + r);
-                    const double un = double(a.un[e]);
-                    if (a.stage == 1) {
-                        a.acc[e] = un + (a.dt / 6.0) * k;
-                        a.unext[e] = T(un + (0.5 * a.dt) * k);
-                    } else if (a.stage == 2) {
-                        a.acc[e] += (a.dt / 3.0) * k;
-                        a.unext[e] = T(un + (0.5 * a.dt) * k);
-                    } else if (a.stage == 3) {
-                        a.acc[e] += (a.dt / 3.0) * k;
-                        a.unext[e] = T(un + a.dt * k);
-                    } else {
-                        a.unext[e] = T(a.acc[e] + (a.dt / 6.0) * k);
+                    T *rhs = (T *)(L.out_ov ? L.out_ov : bx.rhs);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        const T r = -(H[v] - Hp[v]) * inv_dx;
+                        if constexpr (MODE == MODE_WRITE) rhs[v * n3 + o] = r;
+                        else rhs[v * n3 + o] += r;
                     }
                 }
             }
-        }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Hp[v] = H[v];
+            for (int v = 0; v < 5; ++v) Hp[v] = H[v];
+        }
     }
 }
 
 // ----------------------------------------------------------------------------
-// diagnostics: deterministic two-pass reduction
+// x sweep with whole periodic rows staged in LDS: one thread per point and per
+// interface, lanes along x (coalesced loads and stores), `rows` rows per block of
+// 256 threads, each thread handling up to P points.  Every interface of a row is
+// computed once; the periodic wrap happens in LDS.
+// ----------------------------------------------------------------------------
+template <typename T, typename B, bool VISC, int P>
+__global__ __launch_bounds__(kRowThreads) void k_sweep_x_rows(Launch L) {
+    extern __shared__ unsigned char lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &bx = L.boxes[bi];
+        const int nx = bx.nx;
+        const int per = bx.rows * nx;  // points of the block
+        T *su = lds;                   // [5][per] states, later the interface fluxes
+        T *sf = su + 5 * per;          // [5][per] point fluxes
+        T *sg = sf + 5 * per;          // [4][per] viscous fluxes (VISC)
+        const size_t n3 = bx.n3;
+        const T gamma = T(bx.gamma), eps = T(bx.eps), delta = T(bx.delta);
+        const T gm1 = gamma - T(1);
+        const T inv_dx = T(bx.inv_h[0]);
+        const long long nrows = (long long)bx.ny * bx.nz;
+        const long long row0 = (vb - L.off[bi]) * bx.rows;
+        const int nact = (int)min((long long)bx.rows, nrows - row0) * nx;  // active points
+        const size_t obase = (size_t)row0 * nx;
+        const T *u = (const T *)state_ptr(bx, L, L.in);
+        const T *G = (const T *)bx.G;
+        T *out = (T *)(L.out_ov ? L.out_ov : bx.rhs);
+
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = threadIdx.x + k * kRowThreads;
+            if (t < nact) {
+                const size_t o = obase + t;
+                T w[5], f[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) w[v] = u[v * n3 + o];
+                euler_flux<T, 0>(w, gm1, f);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    su[v * per + t] = w[v];
+                    sf[v * per + t] = f[v];
+                }
+                if constexpr (VISC) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) sg[c * per + t] = G[gcomp<0>(c) * n3 + o];
+                }
+            }
+        }
+        __syncthreads();
+        T H[P][5];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = threadIdx.x + k * kRowThreads;
+            if (t < nact) {
+                const int r = t / nx, i = t - r * nx, rb = r * nx;
+                T w[6][5], f[6][5], g[4][4];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int q = rb + wrapi(i - 2 + m, nx);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        w[m][v] = su[v * per + q];
+                        f[m][v] = sf[v * per + q];
+                    }
+                }
+                if constexpr (VISC) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int q = rb + wrapi(i - 1 + m, nx);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) g[m][c] = sg[c * per + q];
+                    }
+                }
+                interface_flux<T, B, 0, VISC>(w, f, g, gamma, eps, delta, H[k]);  // at i+1/2
+            }
+        }
+        __syncthreads();  // every thread has read the staged states
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = threadIdx.x + k * kRowThreads;
+            if (t < nact)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) su[v * per + t] = H[k][v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = threadIdx.x + k * kRowThreads;
+            if (t < nact) {
+                const int r = t / nx, i = t - r * nx;
+                const int qm = r * nx + wrapi(i - 1, nx);
+                const size_t o = obase + t;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) out[v * n3 + o] = -(H[k][v] - su[v * per + qm]) * inv_dx;
+            }
+        }
+        __syncthreads();  // LDS is reused by the next virtual block
+    }
+}
+
+// ----------------------------------------------------------------------------
+// diagnostics: deterministic two-pass reduction per box
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -282,57 +448,14 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
+__host__ __device__ __forceinline__ int diag_blocks(size_t n3) {
+    size_t b = (n3 + kDiagThreads - 1) / kDiagThreads;
+    return (int)(b < (size_t)kDiagBlocksMax ? b : (size_t)kDiagBlocksMax);
+}
 
-template <typename T>
-__global__ __launch_bounds__(kDiagThreads) void k_diag_partial(int nx, int ny, int nz, double gamma, double ihx,
-                                                               double ihy, double ihz, const T *__restrict__ u,
-                                                               double *__restrict__ part) {
-    const size_t n3 = (size_t)nx * ny * nz;
-    double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const size_t sy = nx, sz = (size_t)nx * ny;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n3; idx += (size_t)gridDim.x * blockDim.x) {
-        double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]), mz = double(u[3 * n3 + idx]),
-               e = double(u[4 * n3 + idx]);
-        double inv = 1.0 / r;
-        double vx = mx * inv, vy = my * inv, vz = mz * inv;
-        double ke = 0.5 * (mx * vx + my * vy + mz * vz);
-        double p = (gamma - 1.0) * (e - ke);
-        bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
-        if (!finite || !(r > 0.0) || !(p > 0.0)) {
-            acc[8] += 1.0;
-            continue;
-        }
-        acc[0] += ke;
-        acc[2] += r;
-        acc[3] += mx;
-        acc[4] += my;
-        acc[5] += mz;
-        acc[6] += e;
-        double c = sqrt(gamma * p * inv);
-        acc[7] = fmax(acc[7], fmax(fabs(vx), fmax(fabs(vy), fabs(vz))) + c);
-        // vorticity with the 4th-order central derivative
-        int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / sz);
-        size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
-        const int off[4] = {-2, -1, 1, 2};
-        double vyx[4], vzx[4], vxy[4], vzy[4], vxz[4], vyz[4];
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            size_t px = row + wrapi(i + off[o], nx), py = col + wrapi(j + off[o], ny) * sy,
-                   pz = pil + wrapi(k + off[o], nz) * sz;
-            double rx = 1.0 / double(u[px]), ry = 1.0 / double(u[py]), rz = 1.0 / double(u[pz]);
-            vyx[o] = double(u[2 * n3 + px]) * rx;
-            vzx[o] = double(u[3 * n3 + px]) * rx;
-            vxy[o] = double(u[n3 + py]) * ry;
-            vzy[o] = double(u[3 * n3 + py]) * ry;
-            vxz[o] = double(u[n3 + pz]) * rz;
-            vyz[o] = double(u[2 * n3 + pz]) * rz;
-        }
-        double ox = dcen(vzy[0], vzy[1], vzy[2], vzy[3]) * ihy - dcen(vyz[0], vyz[1], vyz[2], vyz[3]) * ihz;
-        double oy = dcen(vxz[0], vxz[1], vxz[2], vxz[3]) * ihz - dcen(vzx[0], vzx[1], vzx[2], vzx[3]) * ihx;
-        double oz = dcen(vyx[0], vyx[1], vyx[2], vyx[3]) * ihx - dcen(vxy[0], vxy[1], vxy[2], vxy[3]) * ihy;
-        if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
-    }
-    __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
+// block reduction of CNS_NDIAG values (slot 7 a max, the others sums) in a fixed order
+__device__ __forceinline__ void block_reduce_diag(const double acc[CNS_NDIAG], double (*red)[CNS_NDIAG], double *dst,
+                                                  const double scale[CNS_NDIAG]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int d = 0; d < CNS_NDIAG; ++d) {
@@ -344,161 +467,347 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(int nx, int ny, i
         const int d = threadIdx.x;
         double v = red[0][d];
         for (int w2 = 1; w2 < kDiagThreads / 64; ++w2) v = (d == 7) ? fmax(v, red[w2][d]) : v + red[w2][d];
-        part[(size_t)blockIdx.x * CNS_NDIAG + d] = v;
-    }
-}
-
-__global__ __launch_bounds__(kDiagThreads) void k_diag_final(int nblk, double inv_n3, const double *__restrict__ part,
-                                                            double *__restrict__ out) {
-    double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-        for (int d = 0; d < CNS_NDIAG; ++d)
-            acc[d] = (d == 7) ? fmax(acc[d], part[(size_t)b * CNS_NDIAG + d]) : acc[d] + part[(size_t)b * CNS_NDIAG + d];
-    __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 0; d < CNS_NDIAG; ++d) {
-        double v = (d == 7) ? wave_max(acc[d]) : wave_sum(acc[d]);
-        if (lane == 0) red[wid][d] = v;
+        if (dst) dst[d] = v * scale[d];
     }
     __syncthreads();
-    if (threadIdx.x < CNS_NDIAG) {
-        const int d = threadIdx.x;
-        double v = red[0][d];
-        for (int w2 = 1; w2 < kDiagThreads / 64; ++w2) v = (d == 7) ? fmax(v, red[w2][d]) : v + red[w2][d];
-        out[d] = (d == 7 || d == 8) ? v : v * inv_n3;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
+    __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
+    const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &bx = L.boxes[bi];
+        const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+        const size_t n3 = bx.n3;
+        const int nblk = diag_blocks(n3);
+        const int lb = (int)(vb - L.off[bi]);
+        const T *u = (const T *)state_ptr(bx, L, BUF_U);
+        const double gamma = bx.gamma, ihx = bx.inv_h[0], ihy = bx.inv_h[1], ihz = bx.inv_h[2];
+        double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const size_t sy = nx, sz = (size_t)nx * ny;
+        for (size_t idx = (size_t)lb * kDiagThreads + threadIdx.x; idx < n3; idx += (size_t)nblk * kDiagThreads) {
+            double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]),
+                   mz = double(u[3 * n3 + idx]), e = double(u[4 * n3 + idx]);
+            double inv = 1.0 / r;
+            double vx = mx * inv, vy = my * inv, vz = mz * inv;
+            double ke = 0.5 * (mx * vx + my * vy + mz * vz);
+            double p = (gamma - 1.0) * (e - ke);
+            bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
+            if (!finite || !(r > 0.0) || !(p > 0.0)) {
+                acc[8] += 1.0;
+                continue;
+            }
+            acc[0] += ke;
+            acc[2] += r;
+            acc[3] += mx;
+            acc[4] += my;
+            acc[5] += mz;
+            acc[6] += e;
+            double c = sqrt(gamma * p * inv);
+            acc[7] = fmax(acc[7], fmax(fabs(vx), fmax(fabs(vy), fabs(vz))) + c);
+            // vorticity with the 4th-order central derivative
+            int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / sz);
+            size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
+            const int off[4] = {-2, -1, 1, 2};
+            double vyx[4], vzx[4], vxy[4], vzy[4], vxz[4], vyz[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                size_t px = row + wrapi(i + off[o], nx), py = col + wrapi(j + off[o], ny) * sy,
+                       pz = pil + wrapi(k + off[o], nz) * sz;
+                double rx = 1.0 / double(u[px]), ry = 1.0 / double(u[py]), rz = 1.0 / double(u[pz]);
+                vyx[o] = double(u[2 * n3 + px]) * rx;
+                vzx[o] = double(u[3 * n3 + px]) * rx;
+                vxy[o] = double(u[n3 + py]) * ry;
+                vzy[o] = double(u[3 * n3 + py]) * ry;
+                vxz[o] = double(u[n3 + pz]) * rz;
+                vyz[o] = double(u[2 * n3 + pz]) * rz;
+            }
+            double ox = dcen(vzy[0], vzy[1], vzy[2], vzy[3]) * ihy - dcen(vyz[0], vyz[1], vyz[2], vyz[3]) * ihz;
+            double oy = dcen(vxz[0], vxz[1], vxz[2], vxz[3]) * ihz - dcen(vzx[0], vzx[1], vzx[2], vzx[3]) * ihx;
+            double oz = dcen(vyx[0], vyx[1], vyx[2], vyx[3]) * ihx - dcen(vxy[0], vxy[1], vxy[2], vxy[3]) * ihy;
+            if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
+        }
+        block_reduce_diag(acc, red, bx.part + (size_t)lb * CNS_NDIAG, one);
+    }
+}
+
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L) {
+    __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = (int)vb;  // one virtual block per box
+        const BoxDesc &bx = L.boxes[bi];
+        const int nblk = diag_blocks(bx.n3);
+        double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b = threadIdx.x; b < nblk; b += kDiagThreads)
+#pragma unroll
+            for (int d = 0; d < CNS_NDIAG; ++d) {
+                const double v = bx.part[(size_t)b * CNS_NDIAG + d];
+                acc[d] = (d == 7) ? fmax(acc[d], v) : acc[d] + v;
+            }
+        const double inv = 1.0 / (double)bx.n3;
+        const double scale[CNS_NDIAG] = {inv, inv, inv, inv, inv, inv, inv, 1.0, 1.0};
+        double *dst = L.diag ? L.diag + ((size_t)bi * L.diag_box_stride + L.step) * CNS_NDIAG : nullptr;
+        block_reduce_diag(acc, red, dst, scale);
     }
 }
 
 // ----------------------------------------------------------------------------
-// launchers
+// host side: shapes, block counts, launchers
 // ----------------------------------------------------------------------------
-static inline unsigned blocks_for(size_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+int rows_for(int nx) {
+    int g = 1;
+    while (nx * g * 2 <= kRowThreads) g *= 2;
+    return g;
+}
 
-template <typename T>
-void launch_init_state(const Box &b, const double *rho, const double *vel, const double *p, T *u, hipStream_t s) {
-    size_t n3 = b.n3();
-    hipLaunchKernelGGL(k_init_state<T>, dim3(blocks_for(n3, 256)), dim3(256), 0, s, n3, b.ph.gamma - 1.0, rho, vel, p,
-                       u);
+bool rows_fits(int nx, size_t esz, int *P) {
+    const int per = rows_for(nx) * nx;
+    const int p = (per + kRowThreads - 1) / kRowThreads;
+    if (P) *P = p;
+    return p <= 4 && (size_t)14 * per * esz <= (size_t)kRowLdsMax;
+}
+
+static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+long long family_blocks(const BoxDesc &b, int fam, int block) {
+    switch (fam) {
+        case F_POINT: return cdiv((long long)b.n3, kPointThreads);
+        case F_XROWS: return b.xrows ? cdiv((long long)b.ny * b.nz, b.rows) : 0;
+        case F_SWEEP_X:
+        case F_SWEEP_Y:
+        case F_SWEEP_Z: {
+            const int d = fam - F_SWEEP_X;
+            if (d == 0 && b.xrows) return 0;
+            const SweepGeom g = d == 0 ? sweep_geom<0>(b.nx, b.ny, b.nz)
+                                       : (d == 1 ? sweep_geom<1>(b.nx, b.ny, b.nz) : sweep_geom<2>(b.nx, b.ny, b.nz));
+            return cdiv((long long)g.npq * cdiv(g.nline, b.seg[d]), block);
+        }
+        case F_DIAG: return diag_blocks(b.n3);
+        case F_BOX: return 1;
+    }
+    return 0;
+}
+
+static Launch make_launch(const Batch &bt, int fam) {
+    Launch L{};
+    L.boxes = bt.d_boxes;
+    L.off = bt.d_off[fam];
+    L.nbox = bt.nbox;
+    L.total = bt.total[fam];
+    return L;
+}
+
+static Launch with_family(const Batch &bt, Launch L, int fam) {
+    L.off = bt.d_off[fam];
+    L.total = bt.total[fam];
+    return L;
+}
+
+static inline unsigned grid_for(long long total) {
+    const long long cap = 1ll << 30;
+    return (unsigned)(total < cap ? total : cap);
+}
+
+void launch_init_state(int prec, size_t n3, double gamma, const double *rho, const double *vel, const double *p,
+                       void *u, hipStream_t s) {
+    const unsigned g = (unsigned)((n3 + 255) / 256);
+    if (prec == CNS_FP64)
+        hipLaunchKernelGGL(k_init_state<double>, dim3(g), dim3(256), 0, s, n3, gamma - 1.0, rho, vel, p, (double *)u);
+    else
+        hipLaunchKernelGGL(k_init_state<float>, dim3(g), dim3(256), 0, s, n3, gamma - 1.0, rho, vel, p, (float *)u);
+}
+
+void launch_fill(int prec, size_t n, void *out, hipStream_t s) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (prec == CNS_FP64) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, s, n, (double *)out);
+    else hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, s, n, (float *)out);
 }
 
 template <typename T>
-static void launch_visc_fields(const Box &b, const T *u, T *W, T *G, hipStream_t s, Prof *pf = nullptr) {
-    size_t n3 = b.n3();
+static void visc_fields(const Batch &bt, Launch L) {
+    L = with_family(bt, L, F_POINT);
+    if (!L.total) return;
     {
-        ProfScope ps(pf, K_PRIM, s);
-        hipLaunchKernelGGL(k_prim<T>, dim3(blocks_for(n3, 256)), dim3(256), 0, s, n3, T(b.ph.gamma), u, W);
+        ProfScope ps(bt.prof, K_PRIM, bt.stream);
+        hipLaunchKernelGGL(k_prim<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);
     }
-    T mu = T(b.ph.mu_eff);
-    T kc = T(b.ph.mu_eff / ((b.ph.gamma - 1.0) * b.ph.prandtl));
-    ProfScope ps(pf, K_VISC_FLUX, s);
-    hipLaunchKernelGGL(k_visc_flux<T>, dim3(blocks_for(n3, 256)), dim3(256), 0, s, b.nx, b.ny, b.nz,
-                       T(b.nx / b.lx), T(b.ny / b.ly), T(b.nz / b.lz), mu, kc, (const T *)W, G);
-}
-
-template <typename T>
-static SweepArgs<T> sweep_args(const Box &b, const Tiles &t, int dir, const T *u, const T *G, T *rhs) {
-    SweepArgs<T> a{};
-    a.u = u;
-    a.G = G;
-    a.rhs = rhs;
-    a.n3 = b.n3();
-    const size_t sx = 1, sy = (size_t)b.nx, sz = (size_t)b.nx * b.ny;
-    if (dir == 0) {
-        a.nline = b.nx, a.lstride = sx, a.np = b.ny, a.pstride = sy, a.qstride = sz, a.npq = b.ny * b.nz;
-        a.inv_dx = T(b.nx / b.lx);
-    } else if (dir == 1) {
-        a.nline = b.ny, a.lstride = sy, a.np = b.nx, a.pstride = sx, a.qstride = sz, a.npq = b.nx * b.nz;
-        a.inv_dx = T(b.ny / b.ly);
-    } else {
-        a.nline = b.nz, a.lstride = sz, a.np = b.nx, a.pstride = sx, a.qstride = sy, a.npq = b.nx * b.ny;
-        a.inv_dx = T(b.nz / b.lz);
-    }
-    a.seg = t.seg[dir] > 0 ? t.seg[dir] : a.nline;
-    a.nseg = (a.nline + a.seg - 1) / a.seg;
-    a.gamma = T(b.ph.gamma);
-    a.eps = T(b.ph.eps);
-    a.delta = T(b.ph.delta);
-    return a;
+    ProfScope ps(bt.prof, K_VISC_FLUX, bt.stream);
+    hipLaunchKernelGGL(k_visc_flux<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);
 }
 
 template <typename T, int DIR, int MODE, bool VISC>
-static void launch_sweep_t(const SweepArgs<T> &a, int block, hipStream_t s) {
-    size_t total = (size_t)a.npq * a.nseg;
-    hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC>), dim3(blocks_for(total, block)), dim3(block), 0, s, a);
+static void sweep_t(const Batch &bt, const Launch &L) {
+    hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC>), dim3(grid_for(L.total)), dim3(bt.block), 0, bt.stream,
+                       L);
 }
 
 template <typename T, int MODE>
-static void launch_sweep(const SweepArgs<T> &a, int dir, bool visc, int block, hipStream_t s, Prof *pf = nullptr) {
-    ProfScope ps(pf, K_SWEEP_X + dir, s);
+static void sweep(const Batch &bt, Launch L, int dir, bool visc) {
+    L = with_family(bt, L, F_SWEEP_X + dir);
+    if (!L.total) return;
     if (visc) {
-        if (dir == 0) launch_sweep_t<T, 0, MODE, true>(a, block, s);
-        else if (dir == 1) launch_sweep_t<T, 1, MODE, true>(a, block, s);
-        else launch_sweep_t<T, 2, MODE, true>(a, block, s);
+        if (dir == 0) sweep_t<T, 0, MODE, true>(bt, L);
+        else if (dir == 1) sweep_t<T, 1, MODE, true>(bt, L);
+        else sweep_t<T, 2, MODE, true>(bt, L);
     } else {
-        if (dir == 0) launch_sweep_t<T, 0, MODE, false>(a, block, s);
-        else if (dir == 1) launch_sweep_t<T, 1, MODE, false>(a, block, s);
-        else launch_sweep_t<T, 2, MODE, false>(a, block, s);
+        if (dir == 0) sweep_t<T, 0, MODE, false>(bt, L);
+        else if (dir == 1) sweep_t<T, 1, MODE, false>(bt, L);
+        else sweep_t<T, 2, MODE, false>(bt, L);
     }
 }
 
-template <typename T>
-void launch_rhs(const Box &b, const Tiles &t, const T *u, T *rhs, T *W, T *G, hipStream_t s) {
-    const bool visc = b.ph.mu_eff > 0.0;
-    if (visc) launch_visc_fields<T>(b, u, W, G, s);
-    launch_sweep<T, MODE_WRITE>(sweep_args<T>(b, t, 0, u, G, rhs), 0, visc, t.block, s);
-    launch_sweep<T, MODE_ACCUM>(sweep_args<T>(b, t, 1, u, G, rhs), 1, visc, t.block, s);
-    launch_sweep<T, MODE_ACCUM>(sweep_args<T>(b, t, 2, u, G, rhs), 2, visc, t.block, s);
-}
-
-template <typename T>
-void launch_rhs_dir(const Box &b, const Tiles &t, const T *u, int dir, T *out, hipStream_t s) {
-    launch_sweep<T, MODE_WRITE>(sweep_args<T>(b, t, dir, u, (const T *)nullptr, out), dir, false, t.block, s);
-}
-
-template <typename T>
-void launch_viscous(const Box &b, const T *u, T *out, T *W, T *G, hipStream_t s) {
-    size_t n3 = b.n3();
-    if (!(b.ph.mu_eff > 0.0)) {
-        hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(5 * n3, 256)), dim3(256), 0, s, 5 * n3, T(0), out);
-        return;
+template <typename T, bool VISC>
+static void xrows_t(const Batch &bt, const Launch &L) {
+    const dim3 g(grid_for(L.total)), b(kRowThreads);
+    switch (bt.rowP) {
+        case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1>), g, b, bt.rowLds, bt.stream, L); break;
+        case 2: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 2>), g, b, bt.rowLds, bt.stream, L); break;
+        case 3: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 3>), g, b, bt.rowLds, bt.stream, L); break;
+        default: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 4>), g, b, bt.rowLds, bt.stream, L); break;
     }
-    launch_visc_fields<T>(b, u, W, G, s);
-    hipLaunchKernelGGL(k_visc_div<T>, dim3(blocks_for(n3, 256)), dim3(256), 0, s, b.nx, b.ny, b.nz, T(b.nx / b.lx),
-                       T(b.ny / b.ly), T(b.nz / b.lz), (const T *)G, out);
+}
+
+// x sweep (always the first, writing sweep): the rows kernel for boxes whose rows fit
+// in LDS, the marching kernel for the others
+template <typename T>
+static void sweep_x(const Batch &bt, const Launch &L, bool visc) {
+    ProfScope ps(bt.prof, K_SWEEP_X, bt.stream);
+    const Launch R = with_family(bt, L, F_XROWS);
+    if (R.total) {
+        if (visc) xrows_t<T, true>(bt, R);
+        else xrows_t<T, false>(bt, R);
+    }
+    sweep<T, MODE_WRITE>(bt, L, 0, visc);
 }
 
 template <typename T>
-void launch_rk4_stage(const Box &b, const Tiles &t, int stage, const T *ustage, T *un, T *unext, double *acc,
-                      double dt, T *rhs, T *W, T *G, hipStream_t s, Prof *pf) {
-    const bool visc = b.ph.mu_eff > 0.0;
-    if (visc) launch_visc_fields<T>(b, ustage, W, G, s, pf);
-    launch_sweep<T, MODE_WRITE>(sweep_args<T>(b, t, 0, ustage, G, rhs), 0, visc, t.block, s, pf);
-    launch_sweep<T, MODE_ACCUM>(sweep_args<T>(b, t, 1, ustage, G, rhs), 1, visc, t.block, s, pf);
-    SweepArgs<T> a = sweep_args<T>(b, t, 2, ustage, G, rhs);
-    a.un = un;
-    a.acc = acc;
-    a.unext = unext;
-    a.dt = dt;
-    a.stage = stage;
-    launch_sweep<T, MODE_RK>(a, 2, visc, t.block, s, pf);
+static void rhs_t(const Batch &bt, const void *u_ov, void *out_ov) {
+    Launch L = make_launch(bt, F_POINT);
+    L.in = BUF_U;
+    L.u_ov = u_ov;
+    L.out_ov = out_ov;
+    if (bt.any_visc) visc_fields<T>(bt, L);
+    sweep_x<T>(bt, L, bt.any_visc);
+    {
+        ProfScope ps(bt.prof, K_SWEEP_Y, bt.stream);
+        sweep<T, MODE_ACCUM>(bt, L, 1, bt.any_visc);
+    }
+    ProfScope ps(bt.prof, K_SWEEP_Z, bt.stream);
+    sweep<T, MODE_ACCUM>(bt, L, 2, bt.any_visc);
+}
+
+void launch_rhs(const Batch &bt, const void *u_ov, void *out_ov) {
+    if (bt.prec == CNS_FP64) rhs_t<double>(bt, u_ov, out_ov);
+    else rhs_t<float>(bt, u_ov, out_ov);
 }
 
 template <typename T>
-void launch_diag(const Box &b, const T *u, double *part, double *out, hipStream_t s, Prof *pf) {
-    ProfScope ps(pf, K_DIAG, s);
-    size_t n3 = b.n3();
-    int nblk = (int)std::min<size_t>(kDiagBlocks, blocks_for(n3, kDiagThreads));
-    hipLaunchKernelGGL(k_diag_partial<T>, dim3(nblk), dim3(kDiagThreads), 0, s, b.nx, b.ny, b.nz, b.ph.gamma,
-                       b.nx / b.lx, b.ny / b.ly, b.nz / b.lz, u, part);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, s, nblk, 1.0 / (double)n3, (const double *)part,
-                       out);
+static void rhs_dir_t(const Batch &bt, const void *u_ov, int dir, void *out_ov) {
+    Launch L = make_launch(bt, F_POINT);
+    L.in = BUF_U;
+    L.u_ov = u_ov;
+    L.out_ov = out_ov;
+    if (dir == 0) sweep_x<T>(bt, L, false);
+    else sweep<T, MODE_WRITE>(bt, L, dir, false);
+}
+
+void launch_rhs_dir(const Batch &bt, const void *u_ov, int dir, void *out_ov) {
+    if (bt.prec == CNS_FP64) rhs_dir_t<double>(bt, u_ov, dir, out_ov);
+    else rhs_dir_t<float>(bt, u_ov, dir, out_ov);
+}
+
+template <typename T>
+static void viscous_t(const Batch &bt, const void *u_ov, void *out_ov) {
+    Launch L = make_launch(bt, F_POINT);
+    L.in = BUF_U;
+    L.u_ov = u_ov;
+    L.out_ov = out_ov;
+    visc_fields<T>(bt, L);
+    hipLaunchKernelGGL(k_visc_div<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);
+}
+
+void launch_viscous(const Batch &bt, const void *u_ov, void *out_ov) {
+    if (bt.prec == CNS_FP64) viscous_t<double>(bt, u_ov, out_ov);
+    else viscous_t<float>(bt, u_ov, out_ov);
+}
+
+template <typename T>
+static void diag_t(const Batch &bt, const void *u_ov, double *diag, long long stride, int step) {
+    ProfScope ps(bt.prof, K_DIAG, bt.stream);
+    Launch L = make_launch(bt, F_DIAG);
+    L.u_ov = u_ov;
+    L.diag = diag;
+    L.diag_box_stride = stride;
+    L.step = step;
+    hipLaunchKernelGGL(k_diag_partial<T>, dim3(grid_for(L.total)), dim3(kDiagThreads), 0, bt.stream, L);
+    const Launch F = with_family(bt, L, F_BOX);
+    hipLaunchKernelGGL(k_diag_final, dim3(grid_for(F.total)), dim3(kDiagThreads), 0, bt.stream, F);
+}
+
+void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long stride, int step) {
+    if (bt.prec == CNS_FP64) diag_t<double>(bt, u_ov, diag, stride, step);
+    else diag_t<float>(bt, u_ov, diag, stride, step);
+}
+
+template <typename T>
+static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step) {
+    // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, U_4 -> A, u^{n+1} -> u
+    const int in_of[4] = {BUF_U, BUF_A, BUF_B, BUF_A};
+    const int out_of[4] = {BUF_A, BUF_B, BUF_A, BUF_U};
+    for (int s = 0; s < 4; ++s) {
+        Launch L = make_launch(bt, F_POINT);
+        L.in = in_of[s];
+        L.out = out_of[s];
+        L.stage = s + 1;
+        L.u_ov = u_ov;
+        L.dt_ov = dt_ov;
+        if (bt.any_visc) visc_fields<T>(bt, L);
+        sweep_x<T>(bt, L, bt.any_visc);
+        {
+            ProfScope ps(bt.prof, K_SWEEP_Y, bt.stream);
+            sweep<T, MODE_ACCUM>(bt, L, 1, bt.any_visc);
+        }
+        ProfScope ps(bt.prof, K_SWEEP_Z, bt.stream);
+        sweep<T, MODE_RK>(bt, L, 2, bt.any_visc);
+    }
+    if (diag) diag_t<T>(bt, u_ov, diag, stride, step);
+}
+
+void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step) {
+    if (bt.prec == CNS_FP64) rk4_step_t<double>(bt, u_ov, dt_ov, diag, stride, step);
+    else rk4_step_t<float>(bt, u_ov, dt_ov, diag, stride, step);
+}
+
+float time_sweeps_yz(const Batch &bt, int reps) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    Launch L = make_launch(bt, F_POINT);
+    L.in = BUF_U;
+    (void)hipEventRecord(a, bt.stream);
+    for (int r = 0; r < reps; ++r) {
+        if (bt.prec == CNS_FP64) {
+            sweep<double, MODE_WRITE>(bt, L, 1, bt.any_visc);
+            sweep<double, MODE_WRITE>(bt, L, 2, bt.any_visc);
+        } else {
+            sweep<float, MODE_WRITE>(bt, L, 1, bt.any_visc);
+            sweep<float, MODE_WRITE>(bt, L, 2, bt.any_visc);
+        }
+    }
+    (void)hipEventRecord(b, bt.stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / (float)(reps > 0 ? reps : 1);
 }
 
 void prof_flush(Prof *p) {
     if (!p || !p->on || p->n == 0) return;
-    hipEventSynchronize(p->ev[2 * p->n - 1]);
+    (void)hipEventSynchronize(p->ev[2 * p->n - 1]);
     for (int i = 0; i < p->n; ++i) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) == hipSuccess) {
@@ -508,17 +817,5 @@ void prof_flush(Prof *p) {
     }
     p->n = 0;
 }
-
-// explicit instantiations
-#define CNS_INSTANTIATE(T)                                                                                            \
-    template void launch_init_state<T>(const Box &, const double *, const double *, const double *, T *, hipStream_t); \
-    template void launch_rhs<T>(const Box &, const Tiles &, const T *, T *, T *, T *, hipStream_t);                   \
-    template void launch_rhs_dir<T>(const Box &, const Tiles &, const T *, int, T *, hipStream_t);                    \
-    template void launch_viscous<T>(const Box &, const T *, T *, T *, T *, hipStream_t);                              \
-    template void launch_rk4_stage<T>(const Box &, const Tiles &, int, const T *, T *, T *, double *, double, T *, T *, \
-                                      T *, hipStream_t, Prof *);                                                      \
-    template void launch_diag<T>(const Box &, const T *, double *, double *, hipStream_t, Prof *);
-CNS_INSTANTIATE(double)
-CNS_INSTANTIATE(float)
 
 }  // namespace cns

@@ -53,11 +53,12 @@ def test_init_state_matches_oracle(orc, shape):
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("direction", [0, 1, 2])
-def test_convective_term_per_direction(orc, shape, direction):
-    case(f"rhs_dir d={direction} {shape}")
+@pytest.mark.parametrize("direction,xkernel", [(0, "rows"), (0, "march"), (1, "rows"), (2, "rows")])
+def test_convective_term_per_direction(orc, shape, direction, xkernel):
+    case(f"rhs_dir d={direction} {shape} x-kernel={xkernel}")
     plan, ph, rho, vel, p = setup(orc, shape)
     plan.set_tiles(seg=(7, 5, 16))  # ragged segment tails
+    plan.set_x_kernel(xkernel)
     u_ref = orc.init_state(rho, vel, p)
     u = plan.init_state(rho, vel, p)
     got = plan.rhs_dir(u, direction).cpu().numpy()
@@ -117,6 +118,7 @@ def test_rk4_ragged_grid(orc):
     case("rk4 ragged 20x12x36 x3")
     plan, ph, rho, vel, p = setup(orc, (20, 12, 36), mu=0.02)
     plan.set_tiles(seg=(5, 7, 3))
+    plan.set_x_kernel("march")
     u_ref = orc.init_state(rho, vel, p)
     dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], 36)
     u = plan.init_state(rho, vel, p)
@@ -150,6 +152,11 @@ def test_shift_equivariance_and_tile_invariance_bitwise(orc):
     for seg, block in [((1, 1, 1), 64), ((24, 24, 24), 128), ((5, 9, 11), 192)]:
         plan.set_tiles(seg=seg, block=block)
         assert torch.equal(plan.rhs(u), r)
+    # the marching x kernel computes the same operator (round-off level)
+    plan.set_x_kernel("march")
+    r3 = plan.rhs(u)
+    assert rel_max(r3.cpu().numpy(), r.cpu().numpy()) <= 1e-14
+    plan.set_x_kernel("rows")
 
 
 def test_conservation_on_gpu(orc):

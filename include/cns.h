@@ -168,6 +168,27 @@ int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag_dev, int32_
 int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable);
 int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t *count_host);
 
+/* ---- adjoint (FP64 plans; CNS_EUNSUPPORTED otherwise) ----
+ * Reverse-mode derivatives of the discrete operator of Sec. 2.2, hand-written:
+ * vector-Jacobian products of the WENO5 reconstructions, the Roe flux with Harten's
+ * fix, the Euler fluxes and the central viscous terms.  Extension beyond the paper.
+ * adj_ws: caller-owned device scratch of cns_adjoint_workspace_bytes bytes. */
+size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t ckpt_every);
+/* ubar = (dR/du)^T rbar at u (all [5][N3] device arrays, FP64); needs
+ * cns_adjoint_workspace_bytes(plan, 0, 1) bytes of adj_ws. */
+int cns_rhs_vjp(const cns_plan *plan, const void *u_dev, const void *rbar_dev, void *ubar_dev, void *adj_ws,
+                size_t bytes);
+/* J = K(u^N) after nsteps RK4 steps of size dt from u0 (K = <|m|^2/(2 rho)>), and
+ * u0_bar = dJ/du0.  Checkpoints every ckpt_every steps; each segment is recomputed
+ * from its checkpoint, each step's stage states from its start state.  J_dev (may
+ * be NULL): one device double. */
+int cns_adjoint_rk4(cns_plan *plan, const void *u0_dev, double dt, int32_t nsteps, int32_t ckpt_every,
+                    void *adj_ws, size_t bytes, double *J_dev, void *u0_bar_dev);
+/* Transpose of the initial-state map at fixed rho and p:
+ * vbar_i = rho (mbar_i + ebar v_i); rho[N3], vel[3][N3], ubar[5][N3] -> vbar[3][N3]. */
+int cns_ic_vjp(const cns_plan *plan, const double *rho_dev, const double *vel_dev, const double *ubar_dev,
+               double *vbar_dev);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *cns_last_error(void);
 

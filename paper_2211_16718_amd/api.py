@@ -131,6 +131,40 @@ class Plan:
             check(rc, "cns_diagnostics_host")
         return out
 
+    # ---- adjoint (FP64) -----------------------------------------------------
+    def _adj_ws(self, nsteps, ckpt_every):
+        n = int(self.lib.cns_adjoint_workspace_bytes(self.h, int(nsteps), int(ckpt_every)))
+        ws = getattr(self, "_adj_buf", None)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+            self._adj_buf = ws
+        return ws, n
+
+    def rhs_vjp(self, u, rbar, out=None):
+        """``(dR/du)^T rbar`` at ``u``."""
+        self._state(u)
+        self._state(rbar, "rbar")
+        out = self.empty_state() if out is None else self._state(out, "out")
+        ws, n = self._adj_ws(0, 1)
+        check(self.lib.cns_rhs_vjp(self.h, _ptr(u), _ptr(rbar), _ptr(out), _ptr(ws), n), "cns_rhs_vjp")
+        return out
+
+    def adjoint_rk4(self, u0, dt, nsteps, ckpt_every):
+        """``(J, dJ/du0)`` for J = mean kinetic energy after ``nsteps`` RK4 steps."""
+        self._state(u0)
+        ws, n = self._adj_ws(nsteps, ckpt_every)
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = self.empty_state()
+        check(self.lib.cns_adjoint_rk4(self.h, _ptr(u0), float(dt), int(nsteps), int(ckpt_every), _ptr(ws), n,
+                                       _ptr(J), _ptr(g)), "cns_adjoint_rk4")
+        return J, g
+
+    def ic_vjp(self, rho, vel, ubar):
+        """Transpose of the initial-state map at fixed density and pressure."""
+        out = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.cns_ic_vjp(self.h, _ptr(rho), _ptr(vel), _ptr(ubar), _ptr(out)), "cns_ic_vjp")
+        return out
+
     # ---- per-kernel timing -------------------------------------------------
     def profile(self, enable=True):
         check(self.lib.cns_profile_enable(self.h, 1 if enable else 0), "cns_profile_enable")

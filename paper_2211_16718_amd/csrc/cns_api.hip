@@ -88,9 +88,9 @@ struct Core {
     int g_nsteps = -1;
 
     ~Core() {
-        if (gexec) hipGraphExecDestroy(gexec);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         if (prof.ev[0])
-            for (auto &e : prof.ev) hipEventDestroy(e);
+            for (auto &e : prof.ev) (void)hipEventDestroy(e);
     }
 
     int nbox() const { return (int)boxes.size(); }
@@ -222,7 +222,7 @@ struct Core {
     }
 
     void drop_graph() {
-        if (gexec) hipGraphExecDestroy(gexec);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         gexec = nullptr;
         g_nsteps = -1;
     }
@@ -252,7 +252,7 @@ struct Core {
             e = hipStreamEndCapture(stream, &graph);
             if (e != hipSuccess) return set_err(CNS_EHIP, "end capture: %s", hipGetErrorString(e));
             e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             if (e != hipSuccess) {
                 gexec = nullptr;
                 return set_err(CNS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
@@ -691,6 +691,167 @@ int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t 
         count_host[k] = ens->c.prof.count[k];
     }
     return CNS_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// adjoint (FP64, single box): workspace layout and the checkpointed reverse RK4
+// ----------------------------------------------------------------------------
+struct AdjLayout {
+    size_t ck, seg, st, X, ub, kb, Ub, S, W, C, Gb, rec, total;
+    int nck, K;
+};
+
+static AdjLayout adj_layout(size_t n3, int nsteps, int K) {
+    AdjLayout L{};
+    const size_t st = align256(5 * n3 * sizeof(double));
+    L.K = K > 0 ? K : 1;
+    L.nck = nsteps > 0 ? (nsteps + L.K - 1) / L.K : 0;
+    size_t off = 0;
+    L.ck = off;                      // checkpoints: state at steps 0, K, 2K, ...
+    off += (size_t)L.nck * st;
+    L.seg = off;                     // step-start states of one segment
+    off += (size_t)(nsteps > 0 ? std::min(L.K, nsteps) : 0) * st;
+    L.st = off;                      // stage states U2, U3, U4
+    off += 3 * st;
+    L.X = off;                       // running state
+    off += st;
+    L.ub = off;                      // running adjoint
+    off += st;
+    L.kb = off;                      // stage-rate adjoint (and forward stage rates)
+    off += st;
+    L.Ub = off;                      // adjoint of the current stage state
+    off += st;
+    L.S = off;                       // sum of the stage adjoints
+    off += st;
+    L.W = off;                       // primitives at the linearisation point
+    off += align256(4 * n3 * sizeof(double));
+    L.C = off;                       // per-interface contributions [30][n3]
+    off += align256(30 * n3 * sizeof(double));
+    L.Gb = off;                      // viscous adjoint fields [15][n3]
+    off += align256(15 * n3 * sizeof(double));
+    L.rec = off;                     // a diagnostics record
+    off += align256(CNS_NDIAG * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+static int adj_check(const cns_plan *plan) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (plan->c.prec != CNS_FP64) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for FP64 plans only");
+    return CNS_OK;
+}
+
+extern "C" {
+
+size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t ckpt_every) {
+    if (!plan || nsteps < 0) return 0;
+    return adj_layout(plan->c.boxes[0].n3, nsteps, ckpt_every).total;
+}
+
+int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *ubar, void *adj_ws, size_t bytes) {
+    int rc = adj_check(plan);
+    if (!rc) rc = check_ptr(u, "u");
+    if (!rc) rc = check_ptr(rbar, "rbar");
+    if (!rc) rc = check_ptr(ubar, "ubar");
+    if (!rc) rc = check_ptr(adj_ws, "adj_ws");
+    if (rc) return rc;
+    if (ubar == u || ubar == rbar) return set_err(CNS_EINVAL, "ubar must not alias u or rbar");
+    const BoxDesc &b = plan->c.boxes[0];
+    const AdjLayout L = adj_layout(b.n3, 0, 1);
+    if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
+    char *w = (char *)adj_ws;
+    adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.W),
+                (double *)(w + L.C), (double *)(w + L.Gb));
+    return check_hip("rhs_vjp");
+}
+
+int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
+                    size_t bytes, double *J_dev, void *u0_bar) {
+    int rc = adj_check(plan);
+    if (!rc) rc = check_ptr(u0, "u0");
+    if (!rc) rc = check_ptr(adj_ws, "adj_ws");
+    if (!rc) rc = check_ptr(u0_bar, "u0_bar");
+    if (rc) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(CNS_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0 || ckpt_every < 1) return set_err(CNS_EINVAL, "need nsteps >= 0 and ckpt_every >= 1");
+    if (J_dev && ((uintptr_t)J_dev & 7u)) return set_err(CNS_EINVAL, "J must be 8-byte aligned");
+    Core &c = plan->c;
+    if ((rc = c.sync_table())) return rc;
+    const BoxDesc &b = c.boxes[0];
+    const size_t n3 = b.n3, n5 = 5 * n3;
+    const AdjLayout L = adj_layout(n3, nsteps, ckpt_every);
+    if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
+    char *w = (char *)adj_ws;
+    const size_t st = align256(n5 * sizeof(double));
+    auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
+    double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
+    double *U2 = state(L.st, 0), *U3 = state(L.st, 1), *U4 = state(L.st, 2);
+    double *W = (double *)(w + L.W), *C = (double *)(w + L.C), *Gb = (double *)(w + L.Gb), *rec = (double *)(w + L.rec);
+    hipStream_t s = c.stream;
+    Batch bt = c.batch();
+    bt.prof = nullptr;
+    const int K = L.K;
+
+    // forward with checkpoints (the fused RK4 path, as cns_rk4)
+    adj_copy(n5, (const double *)u0, X, s);
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % K == 0) adj_copy(n5, X, state(L.ck, n / K), s);
+        launch_rk4_step(bt, X, dt, nullptr, 0, 0);
+    }
+    launch_diag(bt, X, rec, 0, 0);
+    if (J_dev) adj_copy(1, rec, J_dev, s);
+    adj_ke_seed(n3, X, ub, s);
+
+    // reverse, one checkpoint segment at a time (last first)
+    for (int sg = L.nck - 1; sg >= 0; --sg) {
+        const int n0 = sg * K, n1 = std::min(nsteps, n0 + K);
+        adj_copy(n5, state(L.ck, sg), X, s);
+        for (int n = n0; n < n1; ++n) {
+            adj_copy(n5, X, state(L.seg, n - n0), s);
+            if (n + 1 < n1) launch_rk4_step(bt, X, dt, nullptr, 0, 0);
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const double *Y = state(L.seg, n - n0);
+            // stage states of step n
+            launch_rhs(bt, Y, kb);
+            adj_stage(n5, 0.5 * dt, Y, kb, U2, s);
+            launch_rhs(bt, U2, kb);
+            adj_stage(n5, 0.5 * dt, Y, kb, U3, s);
+            launch_rhs(bt, U3, kb);
+            adj_stage(n5, dt, Y, kb, U4, s);
+            // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
+            // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s
+            adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
+            adj_rhs_vjp(b, s, U4, kb, Ub, W, C, Gb);
+            adj_copy(n5, Ub, S, s);
+            adj_lincomb(n5, dt / 3.0, ub, dt, Ub, kb, s);
+            adj_rhs_vjp(b, s, U3, kb, Ub, W, C, Gb);
+            adj_accum(n5, Ub, S, s);
+            adj_lincomb(n5, dt / 3.0, ub, 0.5 * dt, Ub, kb, s);
+            adj_rhs_vjp(b, s, U2, kb, Ub, W, C, Gb);
+            adj_accum(n5, Ub, S, s);
+            adj_lincomb(n5, dt / 6.0, ub, 0.5 * dt, Ub, kb, s);
+            adj_rhs_vjp(b, s, Y, kb, Ub, W, C, Gb);
+            adj_accum(n5, Ub, S, s);
+            adj_accum(n5, S, ub, s);
+        }
+    }
+    adj_copy(n5, ub, (double *)u0_bar, s);
+    return check_hip("adjoint_rk4");
+}
+
+int cns_ic_vjp(const cns_plan *plan, const double *rho, const double *vel, const double *ubar, double *vbar) {
+    int rc = adj_check(plan);
+    if (!rc) rc = check_ptr(rho, "rho");
+    if (!rc) rc = check_ptr(vel, "vel");
+    if (!rc) rc = check_ptr(ubar, "ubar");
+    if (!rc) rc = check_ptr(vbar, "vbar");
+    if (rc) return rc;
+    adj_ic_vjp(plan->c.boxes[0].n3, rho, vel, ubar, vbar, plan->c.stream);
+    return check_hip("ic_vjp");
 }
 
 }  // extern "C"

@@ -1,0 +1,340 @@
+// cns_device_adj.h -- hand-written reverse-mode (vector-Jacobian) products of the
+// device arithmetic in cns_device.h, FP64.  Each *_vjp function recomputes the
+// forward values it needs and ADDS the input adjoints to its outputs.
+#pragma once
+#include "cns_device.h"
+
+namespace cns {
+
+// d|lam|_H / d lam of Harten's fix (0 at lam = 0 when delta = 0)
+__device__ __forceinline__ double harten_dabs(double lam, double delta) {
+    const double a = fabs(lam);
+    if (a >= delta) return lam > 0.0 ? 1.0 : (lam < 0.0 ? -1.0 : 0.0);
+    return lam / delta;
+}
+
+// ---------------------------------------------------------------------------
+// WENO5 pair (weno5_lr): given the adjoints Lb, Rb of the left- and right-biased
+// values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5] (q = j-2 .. j+3).
+// Weight derivative: with alpha_k = c_k/(eps+beta_k)^2 and W = sum w_k fhat_k,
+// dW/dbeta_k = -2 w_k (fhat_k - W) / (eps + beta_k).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, double Lb, double Rb, double qb[6]) {
+    const double m2 = q[0], m1 = q[1], c0 = q[2], p1 = q[3], p2 = q[4], p3 = q[5];
+    const double r6 = 1.0 / 6.0, k13 = 13.0 / 12.0;
+    const double L1 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0) * r6;
+    const double L2 = (-m1 + 5.0 * c0 + 2.0 * p1) * r6;
+    const double L3 = (2.0 * c0 + 5.0 * p1 - p2) * r6;
+    const double R1 = (2.0 * p3 - 7.0 * p2 + 11.0 * p1) * r6;
+    const double da = m2 - 2.0 * m1 + c0, db = m1 - 2.0 * c0 + p1, dc = c0 - 2.0 * p1 + p2, dd = p1 - 2.0 * p2 + p3;
+    const double ea = m2 - 4.0 * m1 + 3.0 * c0, eb = m1 - p1, ec = 3.0 * c0 - 4.0 * p1 + p2;
+    const double fa = p3 - 4.0 * p2 + 3.0 * p1, fb = p2 - c0, fc = 3.0 * p1 - 4.0 * c0 + m1;
+    const double s1 = eps + (k13 * da * da + 0.25 * ea * ea);
+    const double s2 = eps + (k13 * db * db + 0.25 * eb * eb);
+    const double s3 = eps + (k13 * dc * dc + 0.25 * ec * ec);
+    const double t1 = eps + (k13 * dd * dd + 0.25 * fa * fa);
+    const double t2 = eps + (k13 * dc * dc + 0.25 * fb * fb);
+    const double t3 = eps + (k13 * db * db + 0.25 * fc * fc);
+    // left weights and value
+    double d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+    double a1 = 0.1 * (d2 * d3), a2 = 0.6 * (d1 * d3), a3 = 0.3 * (d1 * d2);
+    double iS = 1.0 / (a1 + a2 + a3);
+    const double w1 = a1 * iS, w2 = a2 * iS, w3 = a3 * iS;
+    const double L = w1 * L1 + w2 * L2 + w3 * L3;
+    // right weights and value
+    d1 = t1 * t1, d2 = t2 * t2, d3 = t3 * t3;
+    a1 = 0.1 * (d2 * d3), a2 = 0.6 * (d1 * d3), a3 = 0.3 * (d1 * d2);
+    iS = 1.0 / (a1 + a2 + a3);
+    const double v1 = a1 * iS, v2 = a2 * iS, v3 = a3 * iS;
+    const double R = v1 * R1 + v2 * L3 + v3 * L2;
+
+    // candidates
+    const double cL1 = Lb * w1, cL2 = Lb * w2 + Rb * v3, cL3 = Lb * w3 + Rb * v2, cR1 = Rb * v1;
+    // indicators
+    const double bL1 = -2.0 * Lb * w1 * (L1 - L) / s1;
+    const double bL2 = -2.0 * Lb * w2 * (L2 - L) / s2;
+    const double bL3 = -2.0 * Lb * w3 * (L3 - L) / s3;
+    const double bR1 = -2.0 * Rb * v1 * (R1 - R) / t1;
+    const double bR2 = -2.0 * Rb * v2 * (L3 - R) / t2;
+    const double bR3 = -2.0 * Rb * v3 * (L2 - R) / t3;
+    const double dab = 2.0 * k13 * da * bL1, eab = 0.5 * ea * bL1;
+    const double dbb = 2.0 * k13 * db * (bL2 + bR3), ebb = 0.5 * eb * bL2, fcb = 0.5 * fc * bR3;
+    const double dcb = 2.0 * k13 * dc * (bL3 + bR2), ecb = 0.5 * ec * bL3, fbb = 0.5 * fb * bR2;
+    const double ddb = 2.0 * k13 * dd * bR1, fab = 0.5 * fa * bR1;
+    qb[0] += 2.0 * r6 * cL1 + dab + eab;
+    qb[1] += -7.0 * r6 * cL1 - r6 * cL2 - 2.0 * dab + dbb - 4.0 * eab + ebb + fcb;
+    qb[2] += 11.0 * r6 * cL1 + 5.0 * r6 * cL2 + 2.0 * r6 * cL3 + dab - 2.0 * dbb + dcb + 3.0 * eab + 3.0 * ecb -
+             fbb - 4.0 * fcb;
+    qb[3] += 2.0 * r6 * cL2 + 5.0 * r6 * cL3 + 11.0 * r6 * cR1 + dbb - 2.0 * dcb + ddb - ebb - 4.0 * ecb + 3.0 * fab +
+             3.0 * fcb;
+    qb[4] += -r6 * cL3 - 7.0 * r6 * cR1 + dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb;
+    qb[5] += 2.0 * r6 * cR1 + ddb + fab;
+}
+
+// component v of the convective flux along DIR
+template <int DIR>
+__device__ __forceinline__ double euler_flux_comp(const double w[5], double gm1, int v) {
+    const double inv = 1.0 / w[0];
+    const double vn = w[1 + DIR] * inv;
+    if (v == 0) return w[1 + DIR];
+    const double p = gm1 * (w[4] - 0.5 * (w[1] * (w[1] * inv) + w[2] * (w[2] * inv) + w[3] * (w[3] * inv)));
+    if (v == 4) return (w[4] + p) * vn;
+    return w[v] * vn + (v == 1 + DIR ? p : 0.0);
+}
+
+// wb += (df/dw)^T fb for the convective flux along DIR (the Euler flux Jacobian)
+template <int DIR>
+__device__ __forceinline__ void euler_flux_vjp(const double w[5], double gm1, const double fb[5], double wb[5]) {
+    const double inv = 1.0 / w[0];
+    const double v[3] = {w[1] * inv, w[2] * inv, w[3] * inv};
+    const double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double p = gm1 * (w[4] - 0.5 * w[0] * q2);
+    const double H = (w[4] + p) * inv;
+    const double vn = v[DIR];
+    // dp/drho = gm1 q2/2, dp/dm_k = -gm1 v_k, dp/de = gm1;  dvn/drho = -vn/rho, dvn/dm_n = 1/rho
+    double rb = 0.0, mb[3] = {0.0, 0.0, 0.0}, eb = 0.0;
+    // f0 = m_n
+    mb[DIR] += fb[0];
+    // f_{1+k} = m_k vn + delta_kn p
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double g = fb[1 + k];
+        rb += g * (-v[k] * vn);
+        mb[k] += g * vn;
+        mb[DIR] += g * v[k];
+        if (k == DIR) {
+            rb += g * (0.5 * gm1 * q2);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) mb[j] += g * (-gm1 * v[j]);
+            eb += g * gm1;
+        }
+    }
+    // f4 = (e + p) vn = rho H vn
+    {
+        const double g = fb[4];
+        rb += g * vn * (0.5 * gm1 * q2 - H);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) mb[j] += g * (-gm1 * v[j] * vn);
+        mb[DIR] += g * H;
+        eb += g * (1.0 + gm1) * vn;
+    }
+    wb[0] += rb;
+    wb[1] += mb[0];
+    wb[2] += mb[1];
+    wb[3] += mb[2];
+    wb[4] += eb;
+}
+
+// ---------------------------------------------------------------------------
+// Roe dissipation (roe_dissipation, wave-strength form): given Db, add the
+// adjoints of the cell states a, b and of the jump du.
+// ---------------------------------------------------------------------------
+template <int DIR>
+__device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const double b[5], const double du[5],
+                                                    double gamma, double delta, const double Db[5], double ab[5],
+                                                    double bb[5], double dub[5]) {
+    constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+    const double gm1 = gamma - 1.0;
+    // ---- forward recompute
+    const double ia = 1.0 / a[0], ib = 1.0 / b[0];
+    const double va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
+    const double vb[3] = {b[1] * ib, b[2] * ib, b[3] * ib};
+    const double qa = a[1] * va[0] + a[2] * va[1] + a[3] * va[2];
+    const double qb = b[1] * vb[0] + b[2] * vb[1] + b[3] * vb[2];
+    const double pa = gm1 * (a[4] - 0.5 * qa), pb = gm1 * (b[4] - 0.5 * qb);
+    const double Ha = (a[4] + pa) * ia, Hb = (b[4] + pb) * ib;
+    const double sa = sqrt(a[0]), sb = sqrt(b[0]);
+    const double iw = 1.0 / (sa + sb);
+    const double wa = sa * iw, wb = sb * iw;
+    double v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wa * va[k] + wb * vb[k];
+    const double H = wa * Ha + wb * Hb;
+    const double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double c2 = gm1 * (H - 0.5 * q2);
+    const double c = sqrt(c2);
+    const double vn = v[N];
+    const double at1 = du[1 + T1] - v[T1] * du[0];
+    const double at2 = du[1 + T2] - v[T2] * du[0];
+    const double dEb = du[4] - at1 * v[T1] - at2 * v[T2];
+    const double X = du[0] * (H - vn * vn) + vn * du[1 + N] - dEb;
+    const double a2 = gm1 / c2 * X;
+    const double num = du[0] * (vn + c) - du[1 + N] - c * a2;
+    const double a1 = num / (2.0 * c);
+    const double a5 = du[0] - (a1 + a2);
+    const double l1 = harten_abs(vn - c, delta), l2 = harten_abs(vn, delta), l5 = harten_abs(vn + c, delta);
+    const double s1 = l1 * a1, s2 = l2 * a2, s5 = l5 * a5, st1 = l2 * at1, st2 = l2 * at2;
+    const double ssum = s1 + s2 + s5;
+
+    // ---- reverse
+    double s1b = 0, s2b = 0, s5b = 0, st1b = 0, st2b = 0, ssumb = 0, Hbar = 0, vnb = 0, cb = 0, q2b = 0;
+    double vbar[3] = {0, 0, 0};
+    // D4 = s1 (H - vn c) + s2 q2/2 + s5 (H + vn c) + st1 v_t1 + st2 v_t2
+    s1b += Db[4] * (H - vn * c);
+    s5b += Db[4] * (H + vn * c);
+    Hbar += Db[4] * (s1 + s5);
+    vnb += Db[4] * (s5 - s1) * c;
+    cb += Db[4] * (s5 - s1) * vn;
+    s2b += Db[4] * 0.5 * q2;
+    q2b += Db[4] * 0.5 * s2;
+    st1b += Db[4] * v[T1];
+    vbar[T1] += Db[4] * st1;
+    st2b += Db[4] * v[T2];
+    vbar[T2] += Db[4] * st2;
+    // D[1+T1] += st1, D[1+T2] += st2, D[1+N] += c (s5 - s1)
+    st1b += Db[1 + T1];
+    st2b += Db[1 + T2];
+    cb += Db[1 + N] * (s5 - s1);
+    s5b += Db[1 + N] * c;
+    s1b -= Db[1 + N] * c;
+    // D0 = ssum, D[1+k] = ssum v_k (before the additions above)
+    ssumb += Db[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ssumb += Db[1 + k] * v[k];
+        vbar[k] += Db[1 + k] * ssum;
+    }
+    s1b += ssumb;
+    s2b += ssumb;
+    s5b += ssumb;
+    // s = |lam| alpha
+    const double l1b = s1b * a1, l2b = s2b * a2 + st1b * at1 + st2b * at2, l5b = s5b * a5;
+    double a1b = s1b * l1, a2b = s2b * l2, a5b = s5b * l5, at1b = st1b * l2, at2b = st2b * l2;
+    {
+        const double x1 = l1b * harten_dabs(vn - c, delta);
+        const double x5 = l5b * harten_dabs(vn + c, delta);
+        vnb += x1 + l2b * harten_dabs(vn, delta) + x5;
+        cb += x5 - x1;
+    }
+    // a5 = du0 - (a1 + a2)
+    dub[0] += a5b;
+    a1b -= a5b;
+    a2b -= a5b;
+    // a1 = num / (2c)
+    const double numb = a1b / (2.0 * c);
+    cb -= a1b * a1 / c;
+    dub[0] += numb * (vn + c);
+    vnb += numb * du[0];
+    cb += numb * du[0];
+    dub[1 + N] -= numb;
+    cb -= numb * a2;
+    a2b -= numb * c;
+    // a2 = gm1/c2 X
+    const double Xb = a2b * gm1 / c2;
+    double c2b = -a2b * a2 / c2;
+    // X = du0 (H - vn^2) + vn du_n - dEb
+    dub[0] += Xb * (H - vn * vn);
+    Hbar += Xb * du[0];
+    vnb += Xb * (du[1 + N] - 2.0 * vn * du[0]);
+    dub[1 + N] += Xb * vn;
+    const double dEbb = -Xb;
+    // dEb = du4 - at1 v_t1 - at2 v_t2
+    dub[4] += dEbb;
+    at1b -= dEbb * v[T1];
+    vbar[T1] -= dEbb * at1;
+    at2b -= dEbb * v[T2];
+    vbar[T2] -= dEbb * at2;
+    // at = du_t - v_t du0
+    dub[1 + T1] += at1b;
+    vbar[T1] -= at1b * du[0];
+    dub[0] -= at1b * v[T1];
+    dub[1 + T2] += at2b;
+    vbar[T2] -= at2b * du[0];
+    dub[0] -= at2b * v[T2];
+    vbar[N] += vnb;
+    // c = sqrt(c2); c2 = gm1 (H - q2/2); q2 = |v|^2
+    c2b += cb / (2.0 * c);
+    Hbar += c2b * gm1;
+    q2b -= 0.5 * gm1 * c2b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vbar[k] += 2.0 * v[k] * q2b;
+    // H = wa Ha + wb Hb;  v = wa va + wb vb
+    double wab = Hbar * Ha, wbb = Hbar * Hb;
+    const double Hab = Hbar * wa, Hbb = Hbar * wb;
+    double vab[3], vbb[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        wab += vbar[k] * va[k];
+        wbb += vbar[k] * vb[k];
+        vab[k] = vbar[k] * wa;
+        vbb[k] = vbar[k] * wb;
+    }
+    // wa = sa iw, wb = sb iw, iw = 1/(sa + sb)
+    const double iwb = wab * sa + wbb * sb;
+    const double sab = wab * iw - iwb * iw * iw;
+    const double sbb = wbb * iw - iwb * iw * iw;
+    // Ha = (a4 + pa) ia; pa = gm1 (a4 - qa/2); qa = sum a_k va_k; va = a_k ia; ia = 1/a0
+    {
+        const double pab = Hab * ia;
+        double iab = Hab * (a[4] + pa);
+        ab[4] += Hab * ia + pab * gm1;
+        const double qab = -0.5 * gm1 * pab;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double vk = vab[k] + qab * a[1 + k];
+            ab[1 + k] += qab * va[k] + vk * ia;
+            iab += vk * a[1 + k];
+        }
+        ab[0] += -iab * ia * ia + sab / (2.0 * sa);
+    }
+    {
+        const double pbb = Hbb * ib;
+        double ibb = Hbb * (b[4] + pb);
+        bb[4] += Hbb * ib + pbb * gm1;
+        const double qbb = -0.5 * gm1 * pbb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double vk = vbb[k] + qbb * b[1 + k];
+            bb[1 + k] += qbb * vb[k] + vk * ib;
+            ibb += vk * b[1 + k];
+        }
+        bb[0] += -ibb * ib * ib + sbb / (2.0 * sb);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// convective interface flux H (interface_flux without the viscous part): given
+// Hb, add the adjoints of the six cell states w[0..5] (j-2 .. j+3) to wb.
+// ---------------------------------------------------------------------------
+template <int DIR>
+__device__ __forceinline__ void interface_flux_vjp(const double w[6][5], const double Hb[5], double gamma,
+                                                   double eps, double delta, double wb[6][5]) {
+    const double gm1 = gamma - 1.0;
+    // forward: jump of the reconstructed states
+    double du[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double UL, UR;
+        weno5_lr<double, double>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL, UR);
+        du[v] = UR - UL;
+    }
+    // H = (FL + FR)/2 - D/2
+    double Db[5], dub[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Db[v] = -0.5 * Hb[v];
+    roe_dissipation_vjp<DIR>(w[2], w[3], du, gamma, delta, Db, wb[2], wb[3], dub);
+    // reconstructed states: du = UR - UL
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double q[6] = {w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v]};
+        double qb[6] = {0, 0, 0, 0, 0, 0};
+        weno5_lr_vjp(q, eps, -dub[v], dub[v], qb);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) wb[m][v] += qb[m];
+    }
+    // reconstructed fluxes, then the point fluxes
+    double fb[6][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < 6; ++m) q[m] = euler_flux_comp<DIR>(w[m], gm1, v);
+        weno5_lr_vjp(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) fb[m][v] = qb[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) euler_flux_vjp<DIR>(w[m], gm1, fb[m], wb[m]);
+}
+
+}  // namespace cns

@@ -127,4 +127,15 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag
 // time the y and z marching sweeps over the batch (autotuning); milliseconds per launch pair
 float time_sweeps_yz(const Batch &bt, int reps);
 
+// adjoint launchers (cns_adjoint.hip), FP64, one box
+// ubar = (dR/du)^T rbar at u; scratch W [4][n3], C [30][n3], Gb [15][n3]
+void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *W,
+                 double *C, double *Gb);
+void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
+void adj_accum(size_t n, const double *x, double *out, hipStream_t s);
+void adj_stage(size_t n, double c, const double *u, const double *k, double *out, hipStream_t s);
+void adj_copy(size_t n, const double *x, double *out, hipStream_t s);
+void adj_ke_seed(size_t n3, const double *u, double *ubar, hipStream_t s);
+void adj_ic_vjp(size_t n3, const double *rho, const double *vel, const double *ubar, double *vbar, hipStream_t s);
+
 }  // namespace cns

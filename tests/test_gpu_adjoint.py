@@ -1,0 +1,151 @@
+"""GPU adjoint (hand-written vector-Jacobian products, checkpointed reverse RK4)
+against reverse-mode AD of the PyTorch restatement of the oracle
+(oracle/torch_ref.py, itself pinned to the C oracle and its central differences),
+against a dot-product test, and against central differences of the GPU forward."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_max
+from paper_2211_16718_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2211_16718_amd.adjoint import FinalKineticEnergy  # noqa: E402
+from paper_2211_16718_amd.api import Plan  # noqa: E402
+from oracle import torch_ref as tr  # noqa: E402
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def state(shape, seed=0, mt=0.3):
+    n = max(shape)
+    rho, vel, p = I.hit_primitives(n, seed, mt)
+    nz, ny, nx = shape
+    return tuple(np.ascontiguousarray(a[..., :nz, :ny, :nx]) for a in (rho, vel, p))
+
+
+@pytest.mark.parametrize("shape,mu,delta", [((16, 16, 16), 0.02, 1e-6), ((12, 10, 14), 0.01, 1e-6),
+                                            ((16, 16, 16), 0.0, 1e-6), ((12, 12, 12), 0.02, 0.5)])
+def test_rhs_vjp_matches_reverse_mode_reference(orc, shape, mu, delta):
+    case(f"rhs_vjp {shape} mu={mu} delta={delta}")
+    rho, vel, p = state(shape, seed=3)
+    plan = Plan(shape, mu_eff=mu, harten_delta=delta)
+    u = plan.init_state(rho, vel, p)
+    rng = np.random.default_rng(1)
+    rbar = rng.standard_normal((5,) + shape)
+    got = plan.rhs_vjp(u, torch.from_numpy(rbar).cuda()).cpu().numpy()
+    ref = tr.rhs_vjp(torch.from_numpy(orc.init_state(rho, vel, p)), torch.from_numpy(rbar),
+                     tr.make_phys(mu=mu, delta=delta)).numpy()
+    err = rel_max(got, ref)
+    print(f"rhs_vjp rel err {err:.3e}")
+    assert err <= 1e-11
+
+
+def test_dot_product_against_gpu_forward_differences():
+    # <(dR/du)^T rbar, d> = <rbar, (dR/du) d>, the right side by central
+    # differences of the GPU forward RHS
+    case("dot-product test")
+    shape = (16, 16, 16)
+    rho, vel, p = state(shape, seed=5)
+    plan = Plan(shape, mu_eff=0.02)
+    u = plan.init_state(rho, vel, p)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    rbar = torch.randn((5,) + shape, generator=g, dtype=torch.float64).cuda()
+    vjp = plan.rhs_vjp(u, rbar)
+    for k in range(3):
+        d = I.hit_velocity(16, seed=200 + k)
+        dd = torch.zeros_like(u)
+        dd[1:4] = torch.from_numpy(d).cuda()
+        h = 1e-6
+        fd = (plan.rhs((u + h * dd).contiguous()) - plan.rhs((u - h * dd).contiguous())) / (2 * h)
+        lhs = float((vjp * dd).sum())
+        rhs = float((rbar * fd).sum())
+        print(f"dot-product: {lhs:.12e} vs {rhs:.12e}")
+        assert lhs == pytest.approx(rhs, rel=1e-7)
+
+
+@pytest.mark.parametrize("nsteps,ckpt", [(7, 3), (4, 4), (5, 1)])
+def test_adjoint_rk4_matches_reverse_mode_reference(orc, nsteps, ckpt):
+    case(f"adjoint rk4 16^3 nsteps={nsteps} ckpt={ckpt}")
+    shape = (16, 16, 16)
+    mu = 0.02
+    rho, vel, p = state(shape, seed=2)
+    plan = Plan(shape, mu_eff=mu)
+    u0 = plan.init_state(rho, vel, p)
+    u0h = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u0h, orc.make_phys(mu_eff=mu))[7], 16)
+    J, g = plan.adjoint_rk4(u0, dt, nsteps, ckpt)
+    # reference: reverse-mode AD through nsteps RK4 steps, seeded with dK/du at u^N
+    uN, _ = orc.rk4(u0h, dt, nsteps, orc.make_phys(mu_eff=mu), with_diag=False)
+    uNt = torch.from_numpy(uN).requires_grad_(True)
+    (seed,) = torch.autograd.grad(tr.kinetic_energy(uNt), uNt)
+    ref = tr.rk4_vjp(torch.from_numpy(u0h), seed, dt, nsteps, tr.make_phys(mu=mu)).numpy()
+    assert float(J[0]) == pytest.approx(orc.diag(uN, orc.make_phys(mu_eff=mu))[0], rel=1e-13)
+    err = rel_max(g.cpu().numpy(), ref)
+    print(f"adjoint rk4 rel err {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_autograd_function_gradient_16(orc):
+    # the CPU FP64 reference gradient at 16^3 (same physics as the 128^3 workload)
+    case("autograd Function 16^3")
+    n, mu, nsteps = 16, 1.0 / 400, 10
+    rho, vel, p = I.hit_primitives(n, 0, 0.3)
+    plan = Plan((n, n, n), mu_eff=mu)
+    dt = I.dt_from_speed(orc.diag(orc.init_state(rho, vel, p), orc.make_phys(mu_eff=mu))[7], n)
+    v0 = torch.from_numpy(vel).cuda().requires_grad_(True)
+    J = FinalKineticEnergy.apply(v0, torch.from_numpy(rho).cuda(), torch.from_numpy(p).cuda(), plan, dt, nsteps, 4)
+    J.backward()
+    Jr, gr = tr.final_ke_and_grad(torch.from_numpy(rho), torch.from_numpy(vel), torch.from_numpy(p), dt, nsteps,
+                                  tr.make_phys(mu=mu))
+    assert float(J) == pytest.approx(Jr, rel=1e-13)
+    err = rel_max(v0.grad.cpu().numpy(), gr.numpy())
+    print(f"dJ/dv0 rel err vs CPU reference {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_adjoint_128_against_central_differences():
+    # 128^3, Re = 400, 200 RK4 steps, checkpoints every 20; 32 smooth random
+    # directions (HIT-spectrum fields, seeds 1000..1031), h = 1e-6
+    case("adjoint 128^3 x200 vs central differences (32 directions)")
+    n, mu, nsteps, ckpt = 128, 1.0 / 400, 200, 20
+    rho, vel, p = I.hit_primitives(n, 0, 0.3)
+    plan = Plan((n, n, n), mu_eff=mu)
+    rho_d, vel_d, p_d = (torch.from_numpy(a).cuda() for a in (rho, vel, p))
+    u0 = plan.init_state(rho_d, vel_d, p_d)
+    dt = I.dt_from_speed(plan.diagnostics_host(u0)[7], n)
+    v0 = vel_d.clone().requires_grad_(True)
+    J = FinalKineticEnergy.apply(v0, rho_d, p_d, plan, dt, nsteps, ckpt)
+    J.backward()
+    grad = v0.grad
+
+    def J_of(v):
+        u = plan.init_state(rho_d, v.contiguous(), p_d)
+        d = plan.rk4(u, dt, nsteps, diag=False)
+        return float(plan.diagnostics_host(u)[0])
+
+    h = 1e-6
+    ads, fds = [], []
+    for k in range(32):
+        d = torch.from_numpy(I.hit_velocity(n, seed=1000 + k)).cuda()
+        fds.append((J_of(vel_d + h * d) - J_of(vel_d - h * d)) / (2 * h))
+        ads.append(float((grad * d).sum()))
+    ads, fds = np.array(ads), np.array(fds)
+    rel = np.abs(ads - fds) / np.abs(fds)
+    # the central difference carries the forward run's round-off divided by 2h
+    # (~1e-13 / 2e-6 in absolute terms), which dominates directions whose
+    # derivative is small; normalise by the rms directional derivative too
+    norm = np.abs(ads - fds) / np.sqrt(np.mean(fds ** 2))
+    print(f"adjoint vs FD: J = {float(J):.12f}; relative errors max {rel.max():.3e} median {np.median(rel):.3e}; "
+          f"rms-normalised max {norm.max():.3e}")
+    for k in range(32):
+        print(f"  dir {k}: adjoint {ads[k]:+.12e}  fd {fds[k]:+.12e}  rel {rel[k]:.2e}")
+    assert np.median(rel) <= 1e-6 and norm.max() <= 1e-6

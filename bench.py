@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="grid points per direction (128 = the named workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="RK4 steps of the oracle sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision 512^3, ensemble and adjoint measurements")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the workload, copy a buffer of this many MiB device-to-device once "
                          "(a known-size reference for hardware byte counters)")
@@ -184,6 +186,17 @@ def main():
                "sample": f"{args.cpu_steps} RK4 steps (with diagnostics) of the same {n}^3 workload, "
                          f"{ct:.1f} s, OpenMP over grid points"}
 
+    extras = {}
+    if not args.no_extras:
+        del plan
+        torch.cuda.empty_cache()
+        for name, fn in (("mixed_512", bench_mixed), ("ensemble_64", bench_ensemble), ("adjoint_128", bench_adjoint)):
+            try:
+                extras[name] = fn()
+            except Exception as e:  # report, keep the main line
+                extras[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+
     out = {
         "metric": "grid-point RHS evaluations per second (FP64 WENO5-Roe + central viscous, RK4)",
         "value": value,
@@ -205,7 +218,125 @@ def main():
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def _timed(stream, fn):
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    r = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, r
+
+
+def bench_mixed(n=512, steps=20):
+    """512^3, Re = 1600: mixed precision against the FP64 path at the same size."""
+    import numpy as np
+    import torch
+
+    from paper_2211_16718_amd import inputs as I
+    from paper_2211_16718_amd.api import Plan
+
+    wl = I.WORKLOADS["hit512"]
+    rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)
+    out = {"config": {"workload": f"hit{n}_re1600_rk4x{steps}", "grid": [n, n, n], "steps": steps}}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        plan = Plan((n, n, n), mu_eff=1.0 / wl.re, precision=prec)
+        u = plan.init_state(rho, vel, p)
+        if prec == "fp64":
+            dt = I.dt_from_speed(plan.diagnostics_host(u)[7], n)
+        plan.rk4(plan.empty_state().copy_(u), dt, 1, diag=False)  # warm
+        sec, diag = _timed(plan.stream, lambda: plan.rk4(u, dt, steps))
+        res[prec] = (u, diag.cpu().numpy(), sec)
+        out[prec] = {"value": 4.0 * n ** 3 * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps,
+                     "bytes_per_state": int(u.numel() * u.element_size())}
+        del plan
+    u64, d64, _ = res["fp64"]
+    u32, d32, _ = res["mixed"]
+    per_var = [float((u32[v].double() - u64[v]).abs().max() / u64[v].abs().max()) for v in range(5)]
+    out["mixed_vs_fp64"] = {"max_norm_rel_err_per_variable": per_var,
+                            "ke_rel_err_final": float(abs(d32[-1, 0] - d64[-1, 0]) / d64[-1, 0]),
+                            "enstrophy_rel_err_final": float(abs(d32[-1, 1] - d64[-1, 1]) / d64[-1, 1])}
+    out["speedup_mixed_over_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def bench_ensemble(nbox=64, steps=50):
+    """64 boxes of sizes drawn from {32,48,64,96}, 50 RK4 steps, one captured graph."""
+    import torch
+
+    from paper_2211_16718_amd import inputs as I
+    from paper_2211_16718_amd.api import Ensemble, Plan
+
+    stream = torch.cuda.Stream()
+    boxes, prims = [], []
+    for i in range(nbox):
+        box, rho, vel, p = I.ensemble_box_primitives(i)
+        boxes.append(dict(shape=(box.n,) * 3, mu_eff=1.0 / box.re, dt=1.0))
+        prims.append((rho, vel, p))
+    # dt per box from the GPU diagnostics of its initial state
+    for b, pr in zip(boxes, prims):
+        pl = Plan(b["shape"], mu_eff=b["mu_eff"], stream=stream)
+        with torch.cuda.stream(stream):
+            smax = pl.diagnostics_host(pl.init_state(*pr))[7]
+        b["dt"] = I.dt_from_speed(smax, b["shape"][0])
+    ens = Ensemble(boxes, stream=stream)
+    for i, (b, pr) in enumerate(zip(boxes, prims)):
+        pl = Plan(b["shape"], mu_eff=b["mu_eff"], stream=stream)
+        with torch.cuda.stream(stream):
+            pl.init_state(*pr, out=ens.state(i))
+    stream.synchronize()
+    t0 = time.perf_counter()
+    ens.autotune(None)
+    tune_s = time.perf_counter() - t0
+    u_start = ens.u.clone()
+    with torch.cuda.stream(stream):
+        ens.run(2, graph=True)  # capture + warm
+    stream.synchronize()
+    ens.u.copy_(u_start)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        sec, diag = _timed(stream, lambda: ens.run(steps, graph=True))
+    pts = sum(b["shape"][0] ** 3 for b in boxes)
+    return {"config": {"workload": f"ensemble{nbox}_rk4x{steps}", "boxes": nbox, "points": pts,
+                       "sizes": sorted({b["shape"][0] for b in boxes})},
+            "value": 4.0 * pts * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps,
+            "autotune_s": tune_s, "graph": True,
+            "bad_points": int((diag[..., 8] > 0).sum().item())}
+
+
+def bench_adjoint(n=128, steps=200, ckpt=20):
+    """128^3, Re = 400: J = final kinetic energy after 200 steps and dJ/dv0."""
+    import torch
+
+    from paper_2211_16718_amd import inputs as I
+    from paper_2211_16718_amd.adjoint import FinalKineticEnergy
+    from paper_2211_16718_amd.api import Plan
+
+    rho, vel, p = (torch.from_numpy(a).cuda() for a in I.hit_primitives(n, 0, 0.3))
+    plan = Plan((n, n, n), mu_eff=1.0 / 400)
+    u0 = plan.init_state(rho, vel, p)
+    dt = I.dt_from_speed(plan.diagnostics_host(u0)[7], n)
+    fsec, _ = _timed(plan.stream, lambda: plan.rk4(u0, dt, steps, diag=False))
+
+    def grad():
+        v0 = vel.clone().requires_grad_(True)
+        J = FinalKineticEnergy.apply(v0, rho, p, plan, dt, steps, ckpt)
+        J.backward()
+        return J, v0.grad
+
+    gsec, (J, g) = _timed(plan.stream, grad)
+    return {"config": {"workload": f"hit{n}_re400_rk4x{steps}_adjoint", "ckpt_every": ckpt},
+            "forward_s": fsec, "gradient_s": gsec, "gradient_over_forward": gsec / fsec,
+            "value": 4.0 * n ** 3 * steps / gsec, "unit": "point-RHS/s (forward-step equivalents of the gradient)",
+            "J": float(J), "grad_norm": float(g.norm())}
 
 
 if __name__ == "__main__":

@@ -596,6 +596,43 @@ int oracle_rk4(const orc_grid *g, const orc_phys *ph, double *u, double dt, int 
     return rc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* third-order TVD Runge-Kutta (Shu-Osher), the paper's production scheme    */
+/* ------------------------------------------------------------------------- */
+int oracle_tvdrk3(const orc_grid *g, const orc_phys *ph, double *u, double dt, int nsteps, double *diag) {
+    int rc = check_grid(g, ph);
+    if (rc) return rc;
+    if (!u || !(dt > 0.0) || nsteps < 0) return ORC_EINVAL;
+    size_t n5 = 5 * npts(g);
+    double *k = (double *)malloc(n5 * sizeof(double));
+    double *U1 = (double *)malloc(n5 * sizeof(double));
+    double *U2 = (double *)malloc(n5 * sizeof(double));
+    if (!k || !U1 || !U2) {
+        free(k), free(U1), free(U2);
+        return ORC_EINVAL;
+    }
+    for (int n = 0; n < nsteps && !rc; ++n) {
+        /* U1 = u + dt R(u) */
+        rc = oracle_rhs(g, ph, u, k);
+        if (rc) break;
+        for (size_t q = 0; q < n5; ++q) U1[q] = u[q] + dt * k[q];
+        /* U2 = 3/4 u + 1/4 (U1 + dt R(U1)) */
+        rc = oracle_rhs(g, ph, U1, k);
+        if (rc) break;
+        for (size_t q = 0; q < n5; ++q) U2[q] = 0.75 * u[q] + 0.25 * (U1[q] + dt * k[q]);
+        /* u^{n+1} = 1/3 u + 2/3 (U2 + dt R(U2)) */
+        rc = oracle_rhs(g, ph, U2, k);
+        if (rc) break;
+        for (size_t q = 0; q < n5; ++q) u[q] = (1.0 / 3.0) * u[q] + (2.0 / 3.0) * (U2[q] + dt * k[q]);
+        if (diag) {
+            rc = oracle_diag(g, ph, u, diag + (size_t)n * ORC_NDIAG);
+            if (!rc && diag[(size_t)n * ORC_NDIAG + 8] > 0) rc = ORC_ENONFINITE;
+        }
+    }
+    free(k), free(U1), free(U2);
+    return rc;
+}
+
 int oracle_init_state(const orc_grid *g, double gamma, const double *rho, const double *vel, const double *p,
                       double *u) {
     int rc = check_grid(g, NULL);

@@ -82,6 +82,8 @@ int oracle_rhs_point(const orc_grid *g, const orc_phys *ph, const double *u, int
 /* nsteps classical RK4 steps in place; diag (may be NULL) receives
  * [nsteps][ORC_NDIAG] diagnostics of the state after each step. */
 int oracle_rk4(const orc_grid *g, const orc_phys *ph, double *u, double dt, int nsteps, double *diag);
+/* nsteps third-order TVD Runge-Kutta (Shu-Osher) steps in place; diag as oracle_rk4. */
+int oracle_tvdrk3(const orc_grid *g, const orc_phys *ph, double *u, double dt, int nsteps, double *diag);
 /* diagnostics of u: see ORC_NDIAG. */
 int oracle_diag(const orc_grid *g, const orc_phys *ph, const double *u, double *out);
 /* conserved state from primitives rho[N3], vel[3][N3], p[N3]. */

@@ -57,6 +57,7 @@ def lib():
         L.oracle_rhs_hyp_dir.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, C.c_int, _dp]
         L.oracle_rhs_point.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, C.c_int, C.c_int, C.c_int, _dp]
         L.oracle_rk4.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, C.c_double, C.c_int, _dp]
+        L.oracle_tvdrk3.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, C.c_double, C.c_int, _dp]
         L.oracle_init_state.argtypes = [C.POINTER(Grid), C.c_double, _dp, _dp, _dp, _dp]
         L.oracle_num_threads.restype = C.c_int
         _LIB = L
@@ -176,6 +177,17 @@ def rk4(u, dt, nsteps, phys: Phys, length=(2 * math.pi,) * 3, with_diag=True):
     rc = lib().oracle_rk4(C.byref(g), C.byref(phys), _ptr(u), float(dt), int(nsteps),
                           _ptr(diag) if with_diag else None)
     _chk(rc, "rk4")
+    return u, diag[:nsteps]
+
+
+def tvdrk3(u, dt, nsteps, phys: Phys, length=(2 * math.pi,) * 3, with_diag=True):
+    """Third-order TVD Runge-Kutta; returns ``(u_final, diag[nsteps][9])``."""
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    g = _grid_of(u, length)
+    diag = np.zeros((max(nsteps, 1), NDIAG))
+    rc = lib().oracle_tvdrk3(C.byref(g), C.byref(phys), _ptr(u), float(dt), int(nsteps),
+                             _ptr(diag) if with_diag else None)
+    _chk(rc, "tvdrk3")
     return u, diag[:nsteps]
 
 

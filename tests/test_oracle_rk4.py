@@ -35,6 +35,39 @@ def test_rk4_amplification_on_the_linear_shear_wave(orc):
     assert abs(R ** steps - math.exp(steps * z)) > 100 * 1e-8
 
 
+def test_tvdrk3_amplification_on_the_linear_shear_wave(orc):
+    # Shu-Osher TVD-RK3 on d(rho u)/dt = z/dt (rho u): R3(z) = 1 + z + z^2/2 + z^3/6
+    n, mu, A = 8, 0.5, 1e-5
+    h = 2 * math.pi / n
+    y = I.grid_coords(n)[None, :, None] * np.ones((n, n, n))
+    vel = np.zeros((3, n, n, n))
+    vel[0] = A * np.sin(y)
+    u = orc.init_state(np.ones((n, n, n)), vel, np.full((n, n, n), 1.0))
+    dt, steps = 0.5, 6
+    z = -mu * kstar(1, h) ** 2 * dt
+    R3 = 1 + z + z * z / 2 + z ** 3 / 6
+    uf, _ = orc.tvdrk3(u, dt, steps, orc.make_phys(mu_eff=mu), with_diag=False)
+    assert np.abs(uf[1] - R3 ** steps * A * np.sin(y)).max() <= 1e-8 * A
+    R4 = R3 + z ** 4 / 24
+    assert abs(R3 ** steps - R4 ** steps) > 100 * 1e-8  # distinguishable from RK4
+
+
+def test_tvdrk3_conserves_and_matches_rk4_to_third_order(orc):
+    rho, vel, p = I.hit_primitives(12, 3, 0.3)
+    u = orc.init_state(rho, vel, p)
+    ph = orc.make_phys(mu_eff=0.01)
+    d0 = orc.diag(u, ph)
+    errs = []
+    for dt in (0.004, 0.002):
+        steps = int(round(0.008 / dt))
+        u3, dg = orc.tvdrk3(u, dt, steps, ph)
+        u4, _ = orc.rk4(u, dt, steps, ph, with_diag=False)
+        errs.append(np.abs(u3 - u4).max())
+        assert abs(dg[-1][2] - d0[2]) <= 1e-14 and abs(dg[-1][6] - d0[6]) <= 1e-14 * d0[6]
+    # global error of a third-order scheme: halving dt divides the difference by ~8
+    assert 6.0 < errs[0] / errs[1] < 10.0, errs
+
+
 def test_rk4_keeps_a_free_stream_bitwise(orc):
     rho, vel, p = I.uniform_primitives(0, rho=0.9, vel=(0.5, 0.1, -0.3), p=1.7, shape=(8, 9, 10))
     u = orc.init_state(rho, vel, p)

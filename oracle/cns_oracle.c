@@ -63,6 +63,7 @@ static int check_grid(const orc_grid *g, const orc_phys *ph) {
     if (!(g->lx > 0 && g->ly > 0 && g->lz > 0)) return ORC_EINVAL;
     if (ph && !(ph->gamma > 1.0 && ph->mu_eff >= 0.0 && ph->weno_eps > 0.0 && ph->harten_delta >= 0.0))
         return ORC_EINVAL;
+    if (ph && ph->weno_weights != ORC_WENO_JS && ph->weno_weights != ORC_WENO_Z) return ORC_EINVAL;
     if (ph && ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return ORC_EINVAL;
     return ORC_OK;
 }
@@ -105,6 +106,45 @@ double oracle_weno5(double a, double b, double c, double d, double e, double eps
     double alpha1 = 0.1 / ((eps + beta1) * (eps + beta1));
     double alpha2 = 0.6 / ((eps + beta2) * (eps + beta2));
     double alpha3 = 0.3 / ((eps + beta3) * (eps + beta3));
+    double asum = alpha1 + alpha2 + alpha3;
+    double w1 = alpha1 / asum, w2 = alpha2 / asum, w3 = alpha3 / asum;
+
+    if (parts) {
+        parts[0] = beta1;
+        parts[1] = beta2;
+        parts[2] = beta3;
+        parts[3] = w1;
+        parts[4] = w2;
+        parts[5] = w3;
+        parts[6] = fhat1;
+        parts[7] = fhat2;
+        parts[8] = fhat3;
+    }
+    return w1 * fhat1 + w2 * fhat2 + w3 * fhat3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* WENO-Z weights (Borges, Carmona, Costa & Don, J. Comput. Phys. 227, 2008), */
+/* one of the low-dissipation successors the paper names: the same candidates */
+/* and smoothness indicators, alpha_k = c_k (1 + (tau5/(eps+beta_k))^2) with  */
+/* the global indicator tau5 = |beta_1 - beta_3|.                             */
+/* ------------------------------------------------------------------------- */
+double oracle_weno5z(double a, double b, double c, double d, double e, double eps, double *parts) {
+    double fhat1 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+    double fhat2 = -(1.0 / 6.0) * b + (5.0 / 6.0) * c + (1.0 / 3.0) * d;
+    double fhat3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+
+    double beta1 = (13.0 / 12.0) * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
+                   0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
+    double beta2 = (13.0 / 12.0) * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
+    double beta3 = (13.0 / 12.0) * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
+                   0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
+    double tau5 = fabs(beta1 - beta3);
+
+    double r1 = tau5 / (eps + beta1), r2 = tau5 / (eps + beta2), r3 = tau5 / (eps + beta3);
+    double alpha1 = 0.1 * (1.0 + r1 * r1);
+    double alpha2 = 0.6 * (1.0 + r2 * r2);
+    double alpha3 = 0.3 * (1.0 + r3 * r3);
     double asum = alpha1 + alpha2 + alpha3;
     double w1 = alpha1 / asum, w2 = alpha2 / asum, w3 = alpha3 / asum;
 
@@ -232,16 +272,18 @@ double oracle_harten(double lam, double delta) {
 /* ------------------------------------------------------------------------- */
 int oracle_interface_flux(const double *s, int dir, const orc_phys *ph, double *F) {
     const double gamma = ph->gamma, eps = ph->weno_eps;
+    double (*W)(double, double, double, double, double, double, double *) =
+        ph->weno_weights == ORC_WENO_Z ? oracle_weno5z : oracle_weno5;
     double f[6][5];
     for (int m = 0; m < 6; ++m) oracle_flux(s + 5 * m, dir, gamma, f[m]);
 
     /* component-wise WENO5: left-biased from j-2..j+2, right-biased = mirror (j+3..j-1) */
     double fL[5], fR[5], uL[5], uR[5];
     for (int v = 0; v < 5; ++v) {
-        fL[v] = oracle_weno5(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], eps, NULL);
-        fR[v] = oracle_weno5(f[5][v], f[4][v], f[3][v], f[2][v], f[1][v], eps, NULL);
-        uL[v] = oracle_weno5(s[0 * 5 + v], s[1 * 5 + v], s[2 * 5 + v], s[3 * 5 + v], s[4 * 5 + v], eps, NULL);
-        uR[v] = oracle_weno5(s[5 * 5 + v], s[4 * 5 + v], s[3 * 5 + v], s[2 * 5 + v], s[1 * 5 + v], eps, NULL);
+        fL[v] = W(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], eps, NULL);
+        fR[v] = W(f[5][v], f[4][v], f[3][v], f[2][v], f[1][v], eps, NULL);
+        uL[v] = W(s[0 * 5 + v], s[1 * 5 + v], s[2 * 5 + v], s[3 * 5 + v], s[4 * 5 + v], eps, NULL);
+        uR[v] = W(s[5 * 5 + v], s[4 * 5 + v], s[3 * 5 + v], s[2 * 5 + v], s[1 * 5 + v], eps, NULL);
     }
 
     /* eigensystem at the Roe average of the cell states u_j (m=2) and u_{j+1} (m=3) */

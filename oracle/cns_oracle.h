@@ -45,7 +45,11 @@ typedef struct {
     double mu_eff;       /* mu * M_inf / Re_inf; 0 disables the viscous terms */
     double weno_eps;     /* epsilon of the WENO weights (paper: 1e-6) */
     double harten_delta; /* Harten entropy-fix threshold; 0 gives the plain |lambda| */
+    int weno_weights;    /* ORC_WENO_JS (the paper's Jiang-Shu weights) or ORC_WENO_Z */
 } orc_phys;
+
+#define ORC_WENO_JS 0
+#define ORC_WENO_Z 1
 
 /* ---- building blocks (exported so tests can pin each one) ---- */
 
@@ -53,6 +57,10 @@ typedef struct {
  * (a,b,c,d,e) = (f_{j-2}, f_{j-1}, f_j, f_{j+1}, f_{j+2}).  parts (may be NULL)
  * receives beta1..3, omega1..3, fhat1..3. */
 double oracle_weno5(double a, double b, double c, double d, double e, double eps, double *parts);
+
+/* Same with the WENO-Z weights of Borges et al. (2008), exponent 2:
+ * alpha_k = c_k (1 + (|beta1 - beta3| / (eps + beta_k))^2). */
+double oracle_weno5z(double a, double b, double c, double d, double e, double eps, double *parts);
 
 /* Euler flux along dir (0=x,1=y,2=z) of the conserved state u[5]. */
 void oracle_flux(const double *u, int dir, double gamma, double *f);

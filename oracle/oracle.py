@@ -32,7 +32,7 @@ class Grid(C.Structure):
 
 class Phys(C.Structure):
     _fields_ = [("gamma", C.c_double), ("prandtl", C.c_double), ("mu_eff", C.c_double),
-                ("weno_eps", C.c_double), ("harten_delta", C.c_double)]
+                ("weno_eps", C.c_double), ("harten_delta", C.c_double), ("weno_weights", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -46,6 +46,8 @@ def lib():
         L = C.CDLL(build_oracle.LIB)
         L.oracle_weno5.restype = C.c_double
         L.oracle_weno5.argtypes = [C.c_double] * 6 + [_dp]
+        L.oracle_weno5z.restype = C.c_double
+        L.oracle_weno5z.argtypes = [C.c_double] * 6 + [_dp]
         L.oracle_flux.restype = None
         L.oracle_flux.argtypes = [_dp, C.c_int, C.c_double, _dp]
         L.oracle_roe_eigensystem.argtypes = [_dp, _dp, C.c_int, C.c_double, _dp, _dp, _dp]
@@ -80,13 +82,17 @@ def make_grid(shape, length=(2 * math.pi,) * 3) -> Grid:
     return Grid(nx, ny, nz, length[0], length[1], length[2])
 
 
-def make_phys(gamma=1.4, prandtl=0.72, mu_eff=0.01, weno_eps=1e-6, harten_delta=1e-6) -> Phys:
-    return Phys(gamma, prandtl, mu_eff, weno_eps, harten_delta)
+WENO_JS, WENO_Z = 0, 1
 
 
-def weno5(a, b, c, d, e, eps=1e-6, parts=False):
+def make_phys(gamma=1.4, prandtl=0.72, mu_eff=0.01, weno_eps=1e-6, harten_delta=1e-6, weno_weights=WENO_JS) -> Phys:
+    return Phys(gamma, prandtl, mu_eff, weno_eps, harten_delta, weno_weights)
+
+
+def weno5(a, b, c, d, e, eps=1e-6, parts=False, weights=WENO_JS):
     buf = (C.c_double * 9)()
-    r = lib().oracle_weno5(a, b, c, d, e, eps, buf)
+    fn = lib().oracle_weno5z if weights == WENO_Z else lib().oracle_weno5
+    r = fn(a, b, c, d, e, eps, buf)
     if parts:
         return r, np.array(buf[:])
     return r

@@ -144,3 +144,32 @@ def test_errors_are_reported(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.rhs(u, orc.make_phys())
     assert e.value.code in (-3, -4)
+
+
+def test_wenoz_rhs_invariants_and_convergence(orc):
+    # the WENO-Z operator keeps the exact invariants of the scheme and converges
+    # to the continuous equations at fifth order
+    phz = orc.make_phys(mu_eff=0.0, weno_weights=orc.WENO_Z)
+    rho, vel, p = I.uniform_primitives(0, rho=1.3, vel=(0.7, -0.4, 0.2), p=2.1, shape=(9, 12, 10))
+    np.testing.assert_array_equal(orc.rhs(orc.init_state(rho, vel, p), phz), 0.0)
+    u = hit_state(orc, 16)
+    r = orc.rhs(u, phz)
+    for v in range(5):
+        assert abs(r[v].sum()) <= 1e-13 * np.abs(r[v]).sum()
+    assert np.abs(r - orc.rhs(u, orc.make_phys(mu_eff=0.0))).max() > 1e-3 * np.abs(r).max()
+    errs, spec = [], None
+    for n in (16, 32, 64):
+        if spec is None:
+            rho, vel, p, spec = I.smooth_primitives((n, n, n), seed=7, amp=0.4, kmax=1, mean_vel=(0.3, -0.2, 0.1))
+        else:
+            rho, vel, p = I.smooth_eval((n, n, n), spec)
+        r = orc.rhs(orc.init_state(rho, vel, p), phz)
+        ex = continuous_rhs(rho, vel, p, 0.0)
+        errs.append(np.abs(r - ex).max() / np.abs(ex).max())
+    assert math.log2(errs[-2] / errs[-1]) > 4.5, errs
+
+
+def test_unknown_weno_weights_are_rejected(orc):
+    u = hit_state(orc, 8)
+    with pytest.raises(orc.OracleError):
+        orc.rhs(u, orc.make_phys(weno_weights=5))

@@ -145,3 +145,58 @@ def test_fifth_order_convergence_on_smooth_data(orc):
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     # Jiang-Shu weights keep fifth order on sin (no critical-point degeneracy)
     assert min(orders) > 4.8 and max(orders) < 5.5, (errs, orders)
+
+
+# ---- WENO-Z weights (Borges et al. 2008, exponent 2) -------------------------
+def test_wenoz_reduces_to_the_linear_scheme_when_beta1_equals_beta3(orc):
+    # tau5 = |beta1 - beta3| = 0 gives alpha_k = c_k exactly, whatever beta2 is:
+    # data symmetric about f_j (a = e, b = d) has beta1 = beta3.  The JS weights
+    # on the same data are far from c (beta2 = 0 << beta1 in the first case).
+    rng = np.random.default_rng(11)
+    cases = [(1.0, 0.0, 0.0, 0.0, 1.0)] + [tuple(rng.uniform(-2, 2, size=3)) for _ in range(10)]
+    for cs in cases:
+        f = cs if len(cs) == 5 else (cs[0], cs[1], cs[2], cs[1], cs[0])
+        r, parts = orc.weno5(*f, eps=1e-6, parts=True, weights=orc.WENO_Z)
+        assert parts[0] == pytest.approx(parts[2], rel=1e-14)
+        np.testing.assert_allclose(parts[3:6], [0.1, 0.6, 0.3], rtol=1e-14)
+        printed = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60.0
+        assert r == pytest.approx(printed, rel=1e-13, abs=1e-13)
+    _, pj = orc.weno5(1.0, 0.0, 0.0, 0.0, 1.0, eps=1e-6, parts=True)
+    assert pj[4] > 0.99  # JS puts nearly all weight on the smooth central stencil
+
+
+def test_wenoz_shares_candidates_and_indicators_and_is_convex(orc):
+    rng = np.random.default_rng(12)
+    for _ in range(50):
+        f = rng.normal(size=5)
+        _, pz = orc.weno5(*f, eps=1e-6, parts=True, weights=orc.WENO_Z)
+        _, pj = orc.weno5(*f, eps=1e-6, parts=True)
+        np.testing.assert_array_equal(pz[[0, 1, 2, 6, 7, 8]], pj[[0, 1, 2, 6, 7, 8]])
+        assert pz[3:6].sum() == pytest.approx(1.0, rel=1e-15) and np.all(pz[3:6] > 0)
+
+
+def test_wenoz_rejects_a_discontinuous_stencil(orc):
+    r, parts = orc.weno5(0.0, 0.0, 0.0, 0.0, 1.0, eps=1e-6, parts=True, weights=orc.WENO_Z)
+    assert parts[5] < 1e-10 and abs(r) < 1e-10
+
+
+def test_wenoz_keeps_fifth_order_at_critical_points(orc):
+    # f(x) = sin(x - sin(x)/pi) has points with f' = 0 and f''' != 0 (Henrick et
+    # al. 2005).  With eps negligible the JS weights drop to about third order
+    # there; the Z weights with exponent 2 keep fifth (exponent 1 gives about 4).
+    def orders(weights):
+        errs = []
+        for n in (64, 128, 256, 512):
+            h = 2 * math.pi / n
+            x = np.arange(n) * h + 0.1
+            f = np.sin(x - np.sin(x) / math.pi)
+            W = np.array([orc.weno5(f[(j - 2) % n], f[(j - 1) % n], f[j], f[(j + 1) % n], f[(j + 2) % n],
+                                    1e-40, weights=weights) for j in range(n)])
+            d = (W - np.roll(W, 1)) / h
+            ex = np.cos(x - np.sin(x) / math.pi) * (1 - np.cos(x) / math.pi)
+            errs.append(np.abs(d - ex).max())
+        return [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+
+    oz, oj = orders(orc.WENO_Z), orders(orc.WENO_JS)
+    assert min(oz[1:]) > 4.6, oz
+    assert max(oj[1:]) < 3.4, oj

@@ -64,7 +64,11 @@ typedef struct {
     double mu_eff;       /* mu * M_inf / Re_inf (Sec. 2.1 scaling); 0 = Euler (viscous terms skipped) */
     double weno_eps;     /* epsilon of the WENO weights, > 0 (paper: 1e-6) */
     double harten_delta; /* Harten threshold delta >= 0; 0 = plain |lambda| */
+    int32_t weno_weights; /* CNS_WENO_JS (Sec. 2.2: Jiang-Shu) or CNS_WENO_Z (Borges et al. 2008,
+                             exponent 2; one of the low-dissipation successors the paper names) */
 } cns_physics;
+
+enum { CNS_WENO_JS = 0, CNS_WENO_Z = 1 };
 
 enum { CNS_FP64 = 0, CNS_MIXED = 1 };
 
@@ -112,6 +116,30 @@ int cns_viscous(const cns_plan *plan, const void *u_dev, void *out_dev);
  * receives [nsteps][CNS_NDIAG] diagnostics of the state after each step.
  * Bad points are reported in the diagnostics (the call does not synchronise). */
 int cns_rk4(cns_plan *plan, void *u_dev, double dt, int32_t nsteps, double *diag_dev);
+
+/* Time integrators.  CNS_RK4: the classical four-stage scheme.  CNS_TVDRK3: the
+ * three-stage third-order TVD scheme of Shu and Osher, the integrator of the
+ * paper's production runs (Sec. 2.2 names both; Sec. 5 times TVD-RK3 steps). */
+#define CNS_RK4 0
+#define CNS_TVDRK3 1
+/* nsteps TVD-RK3 steps of size dt, in place on u:
+ *   U1 = u + dt R(u);  U2 = 3/4 u + 1/4 (U1 + dt R(U1));  u <- 1/3 u + 2/3 (U2 + dt R(U2)).
+ * Arguments, diagnostics and errors as cns_rk4.  In the mixed form each convex
+ * combination is formed in FP64 from the FP32 states and rounded once. */
+int cns_tvdrk3(cns_plan *plan, void *u_dev, double dt, int32_t nsteps, double *diag_dev);
+
+/* Kinetic-energy spectrum (Sec. 2.3 and Sec. 5 characterise the turbulence by E(k) and the
+ * Taylor microscale).  With v = m/rho, v_hat(k) = (1/N) sum_x v(x) exp(-i k.x) (N points) and the
+ * physical wavenumber k_d = 2 pi n_d / L_d:
+ *   E_dev[s]      = sum over modes with round(|k|) = s of |v_hat|^2 / 2,  s = 0..nshell-1;
+ *   moments_dev[0] = sum_s E[s] (= <|v|^2>/2), moments_dev[1] = sum over modes of |k|^2 |v_hat|^2 / 2,
+ * so the Taylor microscale is sqrt(5 moments[0] / moments[1]).  FP64 for either precision.
+ * Uses the plan's stage buffers as scratch (ordered with other calls on the plan's
+ * stream).  nshell must equal cns_spectrum_shells(plan) (round(|k|max) + 1), else
+ * CNS_EINVAL; grids with a dimension above 2047 or more than 4096 shells give CNS_EUNSUPPORTED.  Shell sums use
+ * LDS atomics, so their last bits may differ between runs. */
+int cns_spectrum_shells(const cns_plan *plan);
+int cns_spectrum(const cns_plan *plan, const void *u_dev, double *E_dev, int32_t nshell, double *moments_dev);
 
 /* Diagnostics of u into device memory out_dev[CNS_NDIAG]. */
 int cns_diagnostics(const cns_plan *plan, const void *u_dev, double *out_dev);
@@ -161,10 +189,12 @@ int cns_ensemble_get_tiles(const cns_ensemble *ens, int32_t box, int32_t *seg3_h
  * read first (known sizes are not re-timed) and rewritten with new choices.
  * Synchronises the ensemble's stream.  Tiles never change results. */
 int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path);
-/* nsteps RK4 steps of every box with its own dt; diag_dev (may be NULL) receives
+/* nsteps steps (RK4 unless cns_ensemble_set_integrator chose TVD-RK3) of every box with its own dt; diag_dev (may be NULL) receives
  * [nbox][nsteps][CNS_NDIAG].  use_graph != 0 captures the whole run once and
  * replays it (non-default stream required). */
 int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag_dev, int32_t use_graph);
+/* Integrator of cns_ensemble_run: CNS_RK4 (default) or CNS_TVDRK3 (else CNS_EINVAL). */
+int cns_ensemble_set_integrator(cns_ensemble *ens, int32_t scheme);
 int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable);
 int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t *count_host);
 

@@ -1,8 +1,9 @@
 """Kinetic-energy spectrum E(k) and the Taylor microscale (test infrastructure only).
 
 The paper characterises its decaying-turbulence runs by the energy spectrum
-E(k) (Sec. 3, the initial spectrum and the spectra at t/tau = 3) and by the
-Taylor microscale lambda that sets Re_lambda and tau = lambda/u0.  Written
+E(k) (Sec. 2.3: the model initial spectrum and the spectrum at t/tau = 3;
+Sec. 5: spectra per grid size and in time) and by the Taylor microscale lambda
+that sets Re_lambda and tau = lambda/u0.  Written
 from those definitions with numpy's FFT as the transform:
 
   v_hat(k) = (1/N) sum_x v(x) exp(-i k.x)      (N = nx ny nz points)

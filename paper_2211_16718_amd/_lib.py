@@ -9,12 +9,17 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcns.so")
+# CNS_LIBRARY may name another build of the same library (same C-ABI)
+LIB_PATH = os.environ.get("CNS_LIBRARY") or os.path.join(HERE, "libcns.so")
 
 CNS_OK = 0
 CNS_NDIAG = 9
 CNS_FP64 = 0
 CNS_MIXED = 1
+CNS_RK4 = 0
+CNS_WENO_JS = 0
+CNS_WENO_Z = 1
+CNS_TVDRK3 = 1
 CNS_NKERNEL = 6
 KERNEL_NAMES = ("visc_prim", "visc_flux", "sweep_x", "sweep_y", "sweep_z_rk4", "diagnostics")
 ERRORS = {0: "CNS_OK", -1: "CNS_EINVAL", -2: "CNS_EHIP", -3: "CNS_ENONFINITE", -4: "CNS_ENONPHYSICAL",
@@ -34,7 +39,7 @@ class Grid(C.Structure):
 
 class Physics(C.Structure):
     _fields_ = [("gamma", C.c_double), ("prandtl", C.c_double), ("mu_eff", C.c_double),
-                ("weno_eps", C.c_double), ("harten_delta", C.c_double)]
+                ("weno_eps", C.c_double), ("harten_delta", C.c_double), ("weno_weights", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -52,7 +57,10 @@ SIGNATURES = {
     "cns_rhs_dir": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
     "cns_viscous": (C.c_int, [_vp, _vp, _vp]),
     "cns_rk4": (C.c_int, [_vp, _vp, C.c_double, C.c_int32, _vp]),
+    "cns_tvdrk3": (C.c_int, [_vp, _vp, C.c_double, C.c_int32, _vp]),
     "cns_diagnostics": (C.c_int, [_vp, _vp, _vp]),
+    "cns_spectrum_shells": (C.c_int, [_vp]),
+    "cns_spectrum": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp]),
     "cns_diagnostics_host": (C.c_int, [_vp, _vp, _dp]),
     "cns_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "cns_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
@@ -66,6 +74,7 @@ SIGNATURES = {
     "cns_ensemble_get_tiles": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "cns_ensemble_autotune": (C.c_int, [_vp, C.c_char_p]),
     "cns_ensemble_run": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32]),
+    "cns_ensemble_set_integrator": (C.c_int, [_vp, C.c_int32]),
     "cns_ensemble_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "cns_ensemble_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
     "cns_adjoint_workspace_bytes": (C.c_size_t, [_vp, C.c_int32, C.c_int32]),

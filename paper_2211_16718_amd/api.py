@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import CNS_NDIAG, check
+from ._lib import CNS_NDIAG, CNS_RK4, CNS_TVDRK3, check
 
 TWO_PI = 2.0 * math.pi
 
@@ -23,11 +23,16 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def _weno_code(weno):
+    """``"js"``: Jiang-Shu weights (the paper's); ``"z"``: WENO-Z weights."""
+    return {"js": _lib.CNS_WENO_JS, "z": _lib.CNS_WENO_Z}[weno]
+
+
 class Plan:
     """One periodic box: grid, physics, precision, stream and workspace."""
 
     def __init__(self, shape, length=(TWO_PI, TWO_PI, TWO_PI), gamma=1.4, prandtl=0.72, mu_eff=0.01,
-                 weno_eps=1e-6, harten_delta=1e-6, precision="fp64", device="cuda:0", stream=None):
+                 weno_eps=1e-6, harten_delta=1e-6, precision="fp64", device="cuda:0", stream=None, weno="js"):
         self.lib = _lib.load()
         nz, ny, nx = (int(s) for s in shape)
         self.shape = (nz, ny, nx)
@@ -39,7 +44,7 @@ class Plan:
         prec = _lib.CNS_FP64 if precision == "fp64" else _lib.CNS_MIXED
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.grid = _lib.Grid(nx, ny, nz, *length)
-        self.phys = _lib.Physics(gamma, prandtl, mu_eff, weno_eps, harten_delta)
+        self.phys = _lib.Physics(gamma, prandtl, mu_eff, weno_eps, harten_delta, _weno_code(weno))
         h = C.c_void_p()
         check(self.lib.cns_plan_create(C.byref(h), C.byref(self.grid), C.byref(self.phys), prec,
                                        C.c_void_p(self.stream.cuda_stream)), "cns_plan_create")
@@ -109,13 +114,38 @@ class Plan:
         return out
 
     def rk4(self, u, dt, nsteps, diag=True):
-        """Advance ``u`` in place; returns the per-step diagnostics tensor
-        ``[nsteps][9]`` (float64, device) or None."""
+        """Advance ``u`` in place by classical RK4; returns the per-step diagnostics
+        tensor ``[nsteps][9]`` (float64, device) or None."""
+        return self._steps("cns_rk4", u, dt, nsteps, diag)
+
+    def tvdrk3(self, u, dt, nsteps, diag=True):
+        """Advance ``u`` in place by third-order TVD Runge-Kutta (Shu-Osher); returns
+        the per-step diagnostics as :meth:`rk4`."""
+        return self._steps("cns_tvdrk3", u, dt, nsteps, diag)
+
+    def _steps(self, fn, u, dt, nsteps, diag):
         self._state(u)
         d = torch.empty((max(int(nsteps), 1), CNS_NDIAG), dtype=torch.float64, device=self.device) if diag else None
-        check(self.lib.cns_rk4(self.h, _ptr(u), float(dt), int(nsteps), _ptr(d) if d is not None else None),
-              "cns_rk4")
+        check(getattr(self.lib, fn)(self.h, _ptr(u), float(dt), int(nsteps), _ptr(d) if d is not None else None), fn)
         return d[:nsteps] if d is not None else None
+
+    def spectrum(self, u):
+        """Kinetic-energy spectrum of the velocity m/rho: ``(E, moments)``, device float64
+        tensors ``[nshell]`` and ``[2]`` = (sum E, sum |k|^2 |v_hat|^2 / 2)."""
+        self._state(u)
+        ns = int(self.lib.cns_spectrum_shells(self.h))
+        if ns < 1:
+            check(ns, "cns_spectrum_shells")
+        E = torch.empty(ns, dtype=torch.float64, device=self.device)
+        mom = torch.empty(2, dtype=torch.float64, device=self.device)
+        check(self.lib.cns_spectrum(self.h, _ptr(u), _ptr(E), ns, _ptr(mom)), "cns_spectrum")
+        return E, mom
+
+    @staticmethod
+    def taylor_microscale(moments):
+        """lambda = sqrt(5 sum E / M2) from :meth:`spectrum`'s moments (isotropic relation)."""
+        m = [float(x) for x in moments]
+        return math.sqrt(5.0 * m[0] / m[1])
 
     def diagnostics(self, u, out=None):
         self._state(u)
@@ -186,7 +216,8 @@ class Ensemble:
     """Independent periodic boxes of uneven sizes advanced together.
 
     ``boxes``: list of dicts with ``shape`` (nz, ny, nx), ``mu_eff``, ``dt`` and
-    optionally ``length``, ``gamma``, ``prandtl``, ``weno_eps``, ``harten_delta``.
+    optionally ``length``, ``gamma``, ``prandtl``, ``weno_eps``, ``harten_delta``, ``weno``
+    (``"js"`` or ``"z"``, the same for every box).
     The states live in one packed device buffer; ``state(i)`` is box i's view.
     """
 
@@ -215,7 +246,8 @@ class Ensemble:
             L = b.get("length", (TWO_PI, TWO_PI, TWO_PI))
             grids[i] = _lib.Grid(nx, ny, nz, *L)
             phys[i] = _lib.Physics(b.get("gamma", 1.4), b.get("prandtl", 0.72), b["mu_eff"],
-                                   b.get("weno_eps", 1e-6), b.get("harten_delta", 1e-6))
+                                   b.get("weno_eps", 1e-6), b.get("harten_delta", 1e-6),
+                                   _weno_code(b.get("weno", "js")))
             dts[i] = float(b["dt"])
         coffs = (C.c_int64 * nb)(*offs)
         h = C.c_void_p()
@@ -253,8 +285,13 @@ class Ensemble:
         check(self.lib.cns_ensemble_autotune(self.h, cache_path.encode() if cache_path else None),
               "cns_ensemble_autotune")
 
+    def set_integrator(self, scheme):
+        """``"rk4"`` (default) or ``"tvdrk3"`` for :meth:`run`."""
+        code = {"rk4": CNS_RK4, "tvdrk3": CNS_TVDRK3}[scheme]
+        check(self.lib.cns_ensemble_set_integrator(self.h, code), "cns_ensemble_set_integrator")
+
     def run(self, nsteps, diag=True, graph=True):
-        """nsteps RK4 steps of every box; returns diagnostics ``[nbox][nsteps][9]`` or None."""
+        """nsteps steps of every box; returns diagnostics ``[nbox][nsteps][9]`` or None."""
         d = torch.empty((self.nbox, max(int(nsteps), 1), CNS_NDIAG), dtype=torch.float64,
                         device=self.device) if diag else None
         check(self.lib.cns_ensemble_run(self.h, int(nsteps), _ptr(d) if d is not None else None,

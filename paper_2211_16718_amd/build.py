@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcns.so")
-SOURCES = ["cns_kernels.hip", "cns_adjoint.hip", "cns_api.hip"]
+SOURCES = ["cns_kernels.hip", "cns_adjoint.hip", "cns_spectrum.hip", "cns_api.hip"]
 ARCH = os.environ.get("CNS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -54,6 +54,8 @@ static int validate(const cns_grid *g, const cns_physics *ph) {
     if (ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return set_err(CNS_EINVAL, "prandtl must be > 0");
     if (!(ph->weno_eps > 0.0)) return set_err(CNS_EINVAL, "weno_eps must be > 0");
     if (!(ph->harten_delta >= 0.0)) return set_err(CNS_EINVAL, "harten_delta must be >= 0");
+    if (ph->weno_weights != CNS_WENO_JS && ph->weno_weights != CNS_WENO_Z)
+        return set_err(CNS_EINVAL, "unknown weno_weights %d", ph->weno_weights);
     return CNS_OK;
 }
 
@@ -80,12 +82,14 @@ struct Core {
     int rowP = 1;
     size_t rowLds = 0;
     bool any_visc = false;
+    bool wz = false;
     Prof prof;
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;
     const void *g_u = nullptr;
     double g_dt = 0, *g_diag = nullptr;
-    int g_nsteps = -1;
+    int g_nsteps = -1, g_scheme = -1;
+    int scheme = CNS_RK4;  // integrator of cns_ensemble_run
 
     ~Core() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -138,6 +142,7 @@ struct Core {
         b.eps = ph.weno_eps;
         b.delta = ph.harten_delta;
         b.dt = dt;
+        wz = ph.weno_weights == CNS_WENO_Z;
         boxes.push_back(b);
         ustate.push_back(u);
         active.push_back(1);
@@ -208,6 +213,7 @@ struct Core {
         bt.prec = prec;
         bt.block = block;
         bt.any_visc = any_visc;
+        bt.wz = wz;
         bt.d_boxes = (const BoxDesc *)(ws + table_off);
         const long long *offs = (const long long *)(ws + table_off + nbox() * sizeof(BoxDesc));
         for (int f = 0; f < F_N; ++f) {
@@ -227,14 +233,14 @@ struct Core {
         g_nsteps = -1;
     }
 
-    // nsteps RK4 steps; diag layout [nbox][nsteps][CNS_NDIAG]
-    int rk4(const void *u_ov, double dt_ov, int nsteps, double *diag) {
+    // nsteps steps of the integrator `sch`; diag layout [nbox][nsteps][CNS_NDIAG]
+    int run(int sch, const void *u_ov, double dt_ov, int nsteps, double *diag) {
         int rc = sync_table();
         if (rc) return rc;
         Batch bt = batch();
         auto enqueue = [&]() {
             for (int n = 0; n < nsteps; ++n) {
-                launch_rk4_step(bt, u_ov, dt_ov, diag, nsteps, n);
+                launch_step(bt, sch, u_ov, dt_ov, diag, nsteps, n);
                 prof_flush(bt.prof);
             }
         };
@@ -243,7 +249,7 @@ struct Core {
             return check_hip("rk4");
         }
         if (!stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
-        if (!(gexec && g_u == u_ov && g_dt == dt_ov && g_diag == diag && g_nsteps == nsteps)) {
+        if (!(gexec && g_u == u_ov && g_dt == dt_ov && g_diag == diag && g_nsteps == nsteps && g_scheme == sch)) {
             drop_graph();
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
@@ -258,6 +264,7 @@ struct Core {
                 return set_err(CNS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
             }
             g_u = u_ov;
+            g_scheme = sch;
             g_dt = dt_ov;
             g_diag = diag;
             g_nsteps = nsteps;
@@ -544,7 +551,39 @@ int cns_rk4(cns_plan *plan, void *u, double dt, int32_t nsteps, double *diag) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(CNS_EINVAL, "dt must be positive and finite");
     if (nsteps < 0) return set_err(CNS_EINVAL, "nsteps must be >= 0");
     if (diag && ((uintptr_t)diag & 7u)) return set_err(CNS_EINVAL, "diag must be 8-byte aligned");
-    return plan->c.rk4(u, dt, nsteps, diag);
+    return plan->c.run(CNS_RK4, u, dt, nsteps, diag);
+}
+
+int cns_tvdrk3(cns_plan *plan, void *u, double dt, int32_t nsteps, double *diag) {
+    int rc = check_plan(plan);
+    if (!rc) rc = check_ptr(u, "u");
+    if (rc) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(CNS_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0) return set_err(CNS_EINVAL, "nsteps must be >= 0");
+    if (diag && ((uintptr_t)diag & 7u)) return set_err(CNS_EINVAL, "diag must be 8-byte aligned");
+    return plan->c.run(CNS_TVDRK3, u, dt, nsteps, diag);
+}
+
+int cns_spectrum_shells(const cns_plan *plan) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    return spectrum_shells(plan->c.boxes[0]);
+}
+
+int cns_spectrum(const cns_plan *plan, const void *u, double *E, int32_t nshell, double *mom) {
+    int rc = check_plan(plan);
+    if (!rc) rc = check_ptr(u, "u");
+    if (rc) return rc;
+    if (!E || !mom || ((uintptr_t)E & 7u) || ((uintptr_t)mom & 7u))
+        return set_err(CNS_EINVAL, "E and moments must be non-null and 8-byte aligned");
+    cns_plan *p = const_cast<cns_plan *>(plan);
+    if ((rc = p->c.sync_table())) return rc;
+    const BoxDesc &b = p->c.boxes[0];
+    if (nshell != spectrum_shells(b))
+        return set_err(CNS_EINVAL, "nshell must be %d for this grid (got %d)", spectrum_shells(b), nshell);
+    if (!spectrum_supported(b)) return set_err(CNS_EUNSUPPORTED, "spectrum needs every grid dimension <= 2047 and at most 4096 shells");
+    launch_spectrum(b, p->c.prec, p->c.stream, u, E, nshell, mom);
+    return check_hip("spectrum");
 }
 
 int cns_diagnostics(const cns_plan *plan, const void *u, double *out) {
@@ -607,6 +646,8 @@ int cns_ensemble_create(cns_ensemble **out, int32_t nbox, const cns_grid *grids,
         int rc = validate(&grids[i], &phys[i]);
         if (!rc && (!(dt[i] > 0.0) || !std::isfinite(dt[i]))) rc = set_err(CNS_EINVAL, "dt[%d] must be positive", i);
         if (!rc && offsets[i] < 0) rc = set_err(CNS_EINVAL, "offsets[%d] is negative", i);
+        if (!rc && phys[i].weno_weights != phys[0].weno_weights)
+            rc = set_err(CNS_EUNSUPPORTED, "every box of an ensemble must use the same WENO weights");
         void *u = (char *)u_packed + (size_t)offsets[i] * esz;
         if (!rc && !aligned(u)) rc = set_err(CNS_EINVAL, "box %d state is not 256-byte aligned", i);
         if (rc) {
@@ -676,7 +717,14 @@ int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag, int32_t us
     if (diag && ((uintptr_t)diag & 7u)) return set_err(CNS_EINVAL, "diag must be 8-byte aligned");
     if (use_graph && !ens->c.stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
     ens->c.use_graph = use_graph != 0;
-    return ens->c.rk4(nullptr, 0.0, nsteps, diag);
+    return ens->c.run(ens->c.scheme, nullptr, 0.0, nsteps, diag);
+}
+
+int cns_ensemble_set_integrator(cns_ensemble *ens, int32_t scheme) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    if (scheme != CNS_RK4 && scheme != CNS_TVDRK3) return set_err(CNS_EINVAL, "unknown integrator %d", scheme);
+    ens->c.scheme = scheme;
+    return CNS_OK;
 }
 
 int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable) {
@@ -741,6 +789,7 @@ static int adj_check(const cns_plan *plan) {
     int rc = check_plan(plan);
     if (rc) return rc;
     if (plan->c.prec != CNS_FP64) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for FP64 plans only");
+    if (plan->c.wz) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for the Jiang-Shu weights only");
     return CNS_OK;
 }
 

@@ -22,6 +22,22 @@ struct PhysT {
     double gamma, prandtl, mu_eff, eps, delta;
 };
 
+// Reciprocal: the hardware estimate refined by Newton-Raphson steps r <- r + r (1 - b r)
+// (two steps in FP64, one in FP32), about half the instructions of the IEEE division
+// sequence and within an ulp or two of it.
+__device__ __forceinline__ double rcp(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float b) {
+    float r = __builtin_amdgcn_rcpf(b);
+    float e = fmaf(-b, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
 template <typename T>
 __device__ __forceinline__ T harten_abs(T lam, T delta) {
     // |lam| if |lam| >= delta, else (lam^2 + delta^2) / (2 delta)  (Harten's entropy fix)
@@ -32,7 +48,36 @@ __device__ __forceinline__ T harten_abs(T lam, T delta) {
 // ---------------------------------------------------------------------------
 // WENO5, left- and right-biased values at j+1/2 from q_{j-2} .. q_{j+3}
 // ---------------------------------------------------------------------------
-template <typename T, typename B>
+// Nonlinear weights of one reconstruction from its three indicators b1..b3 (in B) and
+// candidates c1..c3: Jiang-Shu alpha_k = c_k / s_k^2, s_k = eps + b_k, or (WZ) the
+// WENO-Z weights of Borges et al. (2008), alpha_k = c_k (1 + (tau5/s_k)^2) with
+// tau5 = |b1 - b3|.  Both are scaled by s_1^2 s_2^2 s_3^2 so one reciprocal serves the
+// three weights.  The Z weights carry one more factor s^2, so they are formed in B
+// (FP64) and normalised before any narrowing.
+template <typename T, typename B, bool WZ>
+__device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, T c3) {
+    if constexpr (!WZ) {
+        T s1 = eps + T(b1), s2 = eps + T(b2), s3 = eps + T(b3);
+        T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+        T a1 = T(0.1) * (d2 * d3), a2 = T(0.6) * (d1 * d3), a3 = T(0.3) * (d1 * d2);
+        return (a1 * c1 + a2 * c2 + a3 * c3) * rcp(a1 + a2 + a3);
+    } else {
+        const B e = B(eps);
+        B t = fabs(b1 - b3);
+        B t2 = t * t;
+        B s1 = e + b1, s2 = e + b2, s3 = e + b3;
+        B d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+        B a1 = B(0.1) * (d1 + t2) * (d2 * d3), a2 = B(0.6) * (d2 + t2) * (d1 * d3), a3 = B(0.3) * (d3 + t2) * (d1 * d2);
+        if constexpr (sizeof(T) == sizeof(B)) {
+            return (a1 * c1 + a2 * c2 + a3 * c3) * rcp(a1 + a2 + a3);
+        } else {
+            B ia = rcp(a1 + a2 + a3);
+            return T(a1 * ia) * c1 + T(a2 * ia) * c2 + T(a3 * ia) * c3;
+        }
+    }
+}
+
+template <typename T, typename B, bool WZ = false>
 __device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T eps, T &L, T &R) {
     const T r6 = T(1) / T(6);
     // third-order candidates; the mirror reconstruction reuses L2 and L3
@@ -61,15 +106,8 @@ __device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T e
     B bR2 = k13 * dc * dc + B(0.25) * fb * fb;
     B bR3 = k13 * db * db + B(0.25) * fc * fc;
 
-    T s1 = eps + T(bL1), s2 = eps + T(bL2), s3 = eps + T(bL3);
-    T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
-    T a1 = T(0.1) * (d2 * d3), a2 = T(0.6) * (d1 * d3), a3 = T(0.3) * (d1 * d2);
-    L = (a1 * L1 + a2 * L2 + a3 * L3) / (a1 + a2 + a3);
-
-    T t1 = eps + T(bR1), t2 = eps + T(bR2), t3 = eps + T(bR3);
-    T e1 = t1 * t1, e2 = t2 * t2, e3 = t3 * t3;
-    T b1 = T(0.1) * (e2 * e3), b2 = T(0.6) * (e1 * e3), b3 = T(0.3) * (e1 * e2);
-    R = (b1 * R1 + b2 * L3 + b3 * L2) / (b1 + b2 + b3);
+    L = weno5_combine<T, B, WZ>(bL1, bL2, bL3, eps, L1, L2, L3);
+    R = weno5_combine<T, B, WZ>(bR1, bR2, bR3, eps, R1, L3, L2);
 }
 
 // ---------------------------------------------------------------------------
@@ -77,7 +115,7 @@ __device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T e
 // ---------------------------------------------------------------------------
 template <typename T, int DIR>
 __device__ __forceinline__ void euler_flux(const T w[5], T gm1, T f[5]) {
-    T inv = T(1) / w[0];
+    T inv = rcp(w[0]);
     T vx = w[1] * inv, vy = w[2] * inv, vz = w[3] * inv;
     T p = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
     T vn = DIR == 0 ? vx : (DIR == 1 ? vy : vz);
@@ -98,28 +136,29 @@ __device__ __forceinline__ void roe_dissipation(const T a[5], const T b[5], cons
                                                 T D[5]) {
     constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
     const T gm1 = gamma - T(1);
-    T ia = T(1) / a[0], ib = T(1) / b[0];
+    T ia = rcp(a[0]), ib = rcp(b[0]);
     T va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
     T vb[3] = {b[1] * ib, b[2] * ib, b[3] * ib};
     T pa = gm1 * (a[4] - T(0.5) * (a[1] * va[0] + a[2] * va[1] + a[3] * va[2]));
     T pb = gm1 * (b[4] - T(0.5) * (b[1] * vb[0] + b[2] * vb[1] + b[3] * vb[2]));
     T Ha = (a[4] + pa) * ia, Hb = (b[4] + pb) * ib;
     T sa = sqrt(a[0]), sb = sqrt(b[0]);
-    T iw = T(1) / (sa + sb);
+    T iw = rcp(sa + sb);
     T wa = sa * iw, wb = sb * iw;
     T v[3] = {wa * va[0] + wb * vb[0], wa * va[1] + wb * vb[1], wa * va[2] + wb * vb[2]};
     T H = wa * Ha + wb * Hb;
     T q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     T c2 = gm1 * (H - T(0.5) * q2);
     T c = sqrt(c2);
+    T ic = rcp(c);
     T vn = v[N];
 
     // wave strengths alpha = X^-1 du
     T at1 = du[1 + T1] - v[T1] * du[0];
     T at2 = du[1 + T2] - v[T2] * du[0];
     T dEb = du[4] - at1 * v[T1] - at2 * v[T2];
-    T a2 = gm1 / c2 * (du[0] * (H - vn * vn) + vn * du[1 + N] - dEb);
-    T a1 = (du[0] * (vn + c) - du[1 + N] - c * a2) / (T(2) * c);
+    T a2 = gm1 * (ic * ic) * (du[0] * (H - vn * vn) + vn * du[1 + N] - dEb);
+    T a1 = (du[0] * (vn + c) - du[1 + N] - c * a2) * (T(0.5) * ic);
     T a5 = du[0] - (a1 + a2);
 
     T l1 = harten_abs(vn - c, delta), l2 = harten_abs(vn, delta), l5 = harten_abs(vn + c, delta);

@@ -51,7 +51,8 @@ struct Launch {
     long long total;  // off[nbox]
     int in;           // Buf of the state read by the kernel
     int out;          // Buf written by the fused RK4 stage update
-    int stage;        // RK4 stage 1..4 (fused update) or 0
+    int stage;        // Runge-Kutta stage 1..4 (fused update) or 0
+    int scheme;       // CNS_RK4 or CNS_TVDRK3 for the fused update
     int step;         // diagnostics record index
     // single-box overrides (used when non-null / positive)
     const void *u_ov;  // replaces the box's state u
@@ -98,6 +99,7 @@ struct Batch {
     int prec = CNS_FP64;
     int block = 256;  // threads per block of the marching sweeps
     bool any_visc = false;
+    bool wz = false;  // WENO-Z weights (every box of a batch uses the same weights)
     const BoxDesc *d_boxes = nullptr;  // device table
     const long long *d_off[F_N] = {};  // device prefixes
     long long total[F_N] = {};
@@ -123,9 +125,18 @@ void launch_viscous(const Batch &bt, const void *u_ov, void *out_ov);
 // one RK4 step of every box (4 stages with fused updates), then diagnostics if diag
 void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long diag_box_stride,
                      int step);
+// one step of the integrator `scheme` (CNS_RK4 or CNS_TVDRK3), then diagnostics if diag
+void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag,
+                 long long diag_box_stride, int step);
 void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag_box_stride, int step);
 // time the y and z marching sweeps over the batch (autotuning); milliseconds per launch pair
 float time_sweeps_yz(const Batch &bt, int reps);
+
+// kinetic-energy spectrum (cns_spectrum.hip), one box: E[nshell] and mom = {sum E, M2};
+// scratch: the box's A, B and rhs buffers
+int spectrum_shells(const BoxDesc &b);
+bool spectrum_supported(const BoxDesc &b);
+void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, double *E, int nshell, double *mom);
 
 // adjoint launchers (cns_adjoint.hip), FP64, one box
 // ubar = (dR/du)^T rbar at u; scratch W [4][n3], C [30][n3], Gb [15][n3]

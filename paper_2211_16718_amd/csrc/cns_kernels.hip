@@ -40,6 +40,17 @@ __device__ __forceinline__ int find_box(const long long *off, int nbox, long lon
     return lo;
 }
 
+// Workgroups are dispatched to the 8 XCDs of the chip round-robin, and each XCD has
+// its own L2.  Renumbering so that XCD x runs a contiguous range of blocks keeps
+// blocks that touch neighbouring data (stencil halos) on the same L2.  A bijection
+// of [0, n) for any n.
+__device__ __forceinline__ long long xcd_block(long long b, long long n) {
+    constexpr int kXcd = 8;
+    const long long q = n / kXcd, r = n % kXcd;
+    const long long x = b % kXcd, i = b / kXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
 __device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
     return which == BUF_U ? (L.u_ov ? L.u_ov : b.u) : (which == BUF_A ? b.A : b.B);
 }
@@ -70,7 +81,8 @@ __global__ void k_fill(size_t n, T *out) {
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_prim(Launch L) {
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
+    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &b = L.boxes[bi];
         const size_t n3 = b.n3;
@@ -80,7 +92,7 @@ __global__ __launch_bounds__(kPointThreads) void k_prim(Launch L) {
         T *W = (T *)b.W;
         const T gamma = T(b.gamma);
         T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
-        T inv = T(1) / r;
+        T inv = rcp(r);
         T vx = mx * inv, vy = my * inv, vz = mz * inv;
         T p = (gamma - T(1)) * (e - T(0.5) * (mx * vx + my * vy + mz * vz));
         W[i] = vx;
@@ -92,7 +104,8 @@ __global__ __launch_bounds__(kPointThreads) void k_prim(Launch L) {
 
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
+    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &b = L.boxes[bi];
         const int nx = b.nx, ny = b.ny, nz = b.nz;
@@ -154,7 +167,8 @@ __device__ __forceinline__ constexpr int gcomp(int c) {
 // viscous term alone: out = sum_d D_d G_d (the viscous-only entry point)
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
+    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &b = L.boxes[bi];
         const int nx = b.nx, ny = b.ny, nz = b.nz;
@@ -194,14 +208,14 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
 // (VISC) the viscous fluxes g at j-1 .. j+2:
 //   H = (f^L + f^R)/2 - |A| (u^R - u^L)/2 - (-g_{j-1} + 7 g_j + 7 g_{j+1} - g_{j+2})/12
 // ----------------------------------------------------------------------------
-template <typename T, typename B, int DIR, bool VISC>
+template <typename T, typename B, int DIR, bool VISC, bool WZ>
 __device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5], const T g[4][4], T gamma, T eps,
                                                T delta, T H[5]) {
     T FL[5], FR[5], UL[5], UR[5], du[5], D[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        weno5_lr<T, B>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps, FL[v], FR[v]);
-        weno5_lr<T, B>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL[v], UR[v]);
+        weno5_lr<T, B, WZ>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps, FL[v], FR[v]);
+        weno5_lr<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL[v], UR[v]);
         du[v] = UR[v] - UL[v];
     }
     roe_dissipation<T, DIR>(w[2], w[3], du, gamma, delta, D);
@@ -232,19 +246,34 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
     return SweepGeom{nz, nx, nx * ny, sz, 1, sy};
 }
 
-template <typename T, typename B, int DIR, int MODE, bool VISC>
-__global__ __launch_bounds__(256) void k_sweep(Launch L) {
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+// Lanes run over consecutive lines of the plane (coalesced).  For y, a block of W
+// waves covers 64 lines times W consecutive segments, so neighbouring segments share
+// their six-point halos in the CU's cache; for x and z a block covers 64 W lines of one
+// segment (stacking z segments spreads a block over planes far apart in memory).
+template <typename T, typename B, int DIR, int MODE, bool VISC, bool WZ>
+__global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
+    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
+    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const SweepGeom sg = sweep_geom<DIR>(bx.nx, bx.ny, bx.nz);
         const int n = sg.nline;
         const int seg = bx.seg[DIR];
         const int nseg = (n + seg - 1) / seg;
-        const size_t t = (size_t)(vb - L.off[bi]) * blockDim.x + threadIdx.x;
-        if (t >= (size_t)sg.npq * nseg) continue;
-        const int pq = (int)(t % sg.npq);
-        const int sgi = (int)(t / sg.npq);
+        const long long lb = vb - L.off[bi];
+        int pq, sgi;
+        if constexpr (DIR == 1) {
+            const int wpb = blockDim.x >> 6;
+            const long long ncg = (sg.npq + 63) >> 6;
+            pq = (int)((lb % ncg) << 6) + (int)(threadIdx.x & 63);
+            sgi = (int)(lb / ncg) * wpb + (int)(threadIdx.x >> 6);
+            if (pq >= sg.npq || sgi >= nseg) continue;
+        } else {
+            const size_t t = (size_t)lb * blockDim.x + threadIdx.x;
+            if (t >= (size_t)sg.npq * nseg) continue;
+            pq = (int)(t % sg.npq);
+            sgi = (int)(t / sg.npq);
+        }
         const int p = pq % sg.np, q = pq / sg.np;
         const size_t base = p * sg.pstride + q * sg.qstride;
         const int j0 = sgi * seg;
@@ -256,12 +285,18 @@ __global__ __launch_bounds__(256) void k_sweep(Launch L) {
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
 
-        T w[6][5], f[6][5], g[4][4], Hp[5];
+        T w[6][5], f[6][5], g[4][4], Hp[5], nw[5];
         // One loop computes everything, so every point flux and every interface flux
         // runs the same machine code wherever a segment starts: results are bitwise
-        // independent of the segment length.  Iteration j loads point j+3 (and the
-        // viscous fluxes of point j+2); from j = j0-1 on it forms the interface flux
-        // at j+1/2 and from j = j0 on the flux difference at point j.
+        // independent of the segment length.  Iteration j takes point j+3, loaded one
+        // iteration ahead so the loads overlap the arithmetic, and the viscous fluxes
+        // of point j+2; from j = j0-1 on it forms the interface flux at j+1/2 and from
+        // j = j0 on the flux difference at point j.
+        {
+            const size_t o = base + wrapi(j0 - 3, n) * sg.lstride;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
+        }
 #pragma nounroll
         for (int j = j0 - 6; j < j1; ++j) {
 #pragma unroll
@@ -271,25 +306,27 @@ __global__ __launch_bounds__(256) void k_sweep(Launch L) {
                     w[m][v] = w[m + 1][v];
                     f[m][v] = f[m + 1][v];
                 }
-            {
-                const size_t o = base + wrapi(j + 3, n) * sg.lstride;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) w[5][v] = u[v * n3 + o];
-                euler_flux<T, DIR>(w[5], gm1, f[5]);
-            }
+            for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
             if constexpr (VISC) {
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) g[m][c] = g[m + 1][c];
-                const size_t o = base + wrapi(j + 2, n) * sg.lstride;
+                const size_t og = base + wrapi(j + 2, n) * sg.lstride;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + o];
+                for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + og];
             }
+            {  // next iteration's point j+4
+                const size_t o = base + wrapi(j + 4, n) * sg.lstride;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
+            }
+            euler_flux<T, DIR>(w[5], gm1, f[5]);
             if (j < j0 - 1) continue;
 
             T H[5];
-            interface_flux<T, B, DIR, VISC>(w, f, g, gamma, eps, delta, H);
+            interface_flux<T, B, DIR, VISC, WZ>(w, f, g, gamma, eps, delta, H);
             if (j >= j0) {
                 const size_t o = base + (size_t)j * sg.lstride;
                 if constexpr (MODE == MODE_RK) {
@@ -304,7 +341,14 @@ __global__ __launch_bounds__(256) void k_sweep(Launch L) {
                         const size_t e = v * n3 + o;
                         const double k = double(rhs[e] + r);
                         const double uo = double(un[e]);
-                        if (L.stage == 1) {
+                        if (L.scheme == CNS_TVDRK3) {
+                            // Shu-Osher: U1 = u + dt k; U2 = 3/4 u + 1/4 (U1 + dt k);
+                            // u^{n+1} = 1/3 u + 2/3 (U2 + dt k); w[2] holds the stage state at j
+                            const double us = double(w[2][v]);
+                            if (L.stage == 1) unext[e] = T(uo + dt * k);
+                            else if (L.stage == 2) unext[e] = T(0.75 * uo + 0.25 * (us + dt * k));
+                            else unext[e] = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
+                        } else if (L.stage == 1) {
                             acc[e] = uo + (dt / 6.0) * k;
                             unext[e] = T(uo + (0.5 * dt) * k);
                         } else if (L.stage == 2) {
@@ -339,7 +383,7 @@ __global__ __launch_bounds__(256) void k_sweep(Launch L) {
 // 256 threads, each thread handling up to P points.  Every interface of a row is
 // computed once; the periodic wrap happens in LDS.
 // ----------------------------------------------------------------------------
-template <typename T, typename B, bool VISC, int P>
+template <typename T, typename B, bool VISC, int P, bool WZ>
 __global__ __launch_bounds__(kRowThreads) void k_sweep_x_rows(Launch L) {
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
@@ -408,7 +452,7 @@ __global__ __launch_bounds__(kRowThreads) void k_sweep_x_rows(Launch L) {
                         for (int c = 0; c < 4; ++c) g[m][c] = sg[c * per + q];
                     }
                 }
-                interface_flux<T, B, 0, VISC>(w, f, g, gamma, eps, delta, H[k]);  // at i+1/2
+                interface_flux<T, B, 0, VISC, WZ>(w, f, g, gamma, eps, delta, H[k]);  // at i+1/2
             }
         }
         __syncthreads();  // every thread has read the staged states
@@ -476,7 +520,8 @@ template <typename T>
 __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
     __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
     const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
+    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
@@ -582,6 +627,8 @@ long long family_blocks(const BoxDesc &b, int fam, int block) {
             if (d == 0 && b.xrows) return 0;
             const SweepGeom g = d == 0 ? sweep_geom<0>(b.nx, b.ny, b.nz)
                                        : (d == 1 ? sweep_geom<1>(b.nx, b.ny, b.nz) : sweep_geom<2>(b.nx, b.ny, b.nz));
+            if (d == 1)  // blocks of 64 lines x (block/64) segments
+                return cdiv(g.npq, 64) * cdiv(cdiv(g.nline, b.seg[d]), block / 64);
             return cdiv((long long)g.npq * cdiv(g.nline, b.seg[d]), block);
         }
         case F_DIAG: return diag_blocks(b.n3);
@@ -639,8 +686,9 @@ static void visc_fields(const Batch &bt, Launch L) {
 
 template <typename T, int DIR, int MODE, bool VISC>
 static void sweep_t(const Batch &bt, const Launch &L) {
-    hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC>), dim3(grid_for(L.total)), dim3(bt.block), 0, bt.stream,
-                       L);
+    const dim3 g(grid_for(L.total)), b(bt.block);
+    if (bt.wz) hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, true>), g, b, 0, bt.stream, L);
+    else hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, false>), g, b, 0, bt.stream, L);
 }
 
 template <typename T, int MODE>
@@ -658,15 +706,21 @@ static void sweep(const Batch &bt, Launch L, int dir, bool visc) {
     }
 }
 
-template <typename T, bool VISC>
-static void xrows_t(const Batch &bt, const Launch &L) {
+template <typename T, bool VISC, bool WZ>
+static void xrows_tw(const Batch &bt, const Launch &L) {
     const dim3 g(grid_for(L.total)), b(kRowThreads);
     switch (bt.rowP) {
-        case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1>), g, b, bt.rowLds, bt.stream, L); break;
-        case 2: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 2>), g, b, bt.rowLds, bt.stream, L); break;
-        case 3: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 3>), g, b, bt.rowLds, bt.stream, L); break;
-        default: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 4>), g, b, bt.rowLds, bt.stream, L); break;
+        case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1, WZ>), g, b, bt.rowLds, bt.stream, L); break;
+        case 2: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 2, WZ>), g, b, bt.rowLds, bt.stream, L); break;
+        case 3: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 3, WZ>), g, b, bt.rowLds, bt.stream, L); break;
+        default: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 4, WZ>), g, b, bt.rowLds, bt.stream, L); break;
     }
+}
+
+template <typename T, bool VISC>
+static void xrows_t(const Batch &bt, const Launch &L) {
+    if (bt.wz) xrows_tw<T, VISC, true>(bt, L);
+    else xrows_tw<T, VISC, false>(bt, L);
 }
 
 // x sweep (always the first, writing sweep): the rows kernel for boxes whose rows fit
@@ -778,6 +832,39 @@ static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *
 void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step) {
     if (bt.prec == CNS_FP64) rk4_step_t<double>(bt, u_ov, dt_ov, diag, stride, step);
     else rk4_step_t<float>(bt, u_ov, dt_ov, diag, stride, step);
+}
+
+template <typename T>
+static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride,
+                          int step) {
+    // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, u^{n+1} -> u
+    const int in_of[3] = {BUF_U, BUF_A, BUF_B};
+    const int out_of[3] = {BUF_A, BUF_B, BUF_U};
+    for (int s = 0; s < 3; ++s) {
+        Launch L = make_launch(bt, F_POINT);
+        L.in = in_of[s];
+        L.out = out_of[s];
+        L.stage = s + 1;
+        L.scheme = CNS_TVDRK3;
+        L.u_ov = u_ov;
+        L.dt_ov = dt_ov;
+        if (bt.any_visc) visc_fields<T>(bt, L);
+        sweep_x<T>(bt, L, bt.any_visc);
+        {
+            ProfScope ps(bt.prof, K_SWEEP_Y, bt.stream);
+            sweep<T, MODE_ACCUM>(bt, L, 1, bt.any_visc);
+        }
+        ProfScope ps(bt.prof, K_SWEEP_Z, bt.stream);
+        sweep<T, MODE_RK>(bt, L, 2, bt.any_visc);
+    }
+    if (diag) diag_t<T>(bt, u_ov, diag, stride, step);
+}
+
+void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag, long long stride,
+                 int step) {
+    if (scheme == CNS_RK4) return launch_rk4_step(bt, u_ov, dt_ov, diag, stride, step);
+    if (bt.prec == CNS_FP64) tvdrk3_step_t<double>(bt, u_ov, dt_ov, diag, stride, step);
+    else tvdrk3_step_t<float>(bt, u_ov, dt_ov, diag, stride, step);
 }
 
 float time_sweeps_yz(const Batch &bt, int reps) {

@@ -1,0 +1,85 @@
+"""WENO-Z weights on the GPU against the oracle's WENO-Z (same bars as the
+Jiang-Shu parity tests: 1e-12 per RHS evaluation, 1e-10 after RK4 steps)."""
+import numpy as np
+import pytest
+
+from conftest import rel_max
+from paper_2211_16718_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2211_16718_amd._lib import CnsError  # noqa: E402
+from paper_2211_16718_amd.api import Ensemble, Plan  # noqa: E402
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def prims(shape, seed=0, mt=0.3):
+    nz, ny, nx = shape
+    rho, vel, p = I.hit_primitives(max(shape), seed, mt)
+    return tuple(np.ascontiguousarray(a) for a in (rho[:nz, :ny, :nx], vel[:, :nz, :ny, :nx], p[:nz, :ny, :nx]))
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (20, 12, 36), (9, 17, 8)])
+@pytest.mark.parametrize("mu", [0.0, 0.02])
+def test_wenoz_rhs_matches_oracle(orc, shape, mu):
+    case(f"wenoz rhs {shape} mu={mu}")
+    rho, vel, p = prims(shape, 3)
+    ph = orc.make_phys(mu_eff=mu, weno_weights=orc.WENO_Z)
+    u_ref = orc.init_state(rho, vel, p)
+    r_ref = orc.rhs(u_ref, ph)
+    plan = Plan(shape, mu_eff=mu, weno="z")
+    u = plan.init_state(rho, vel, p)
+    r = plan.rhs(u).cpu().numpy()
+    err = rel_max(r, r_ref)
+    print(f"wenoz rhs rel err {err:.3e}")
+    assert err <= 1e-12
+    for d in range(3):
+        rd = plan.rhs_dir(u, d).cpu().numpy()
+        assert rel_max(rd, orc.rhs_hyp_dir(u_ref, d, ph)) <= 1e-12
+    # and it is not the Jiang-Shu operator
+    assert rel_max(r, orc.rhs(u_ref, orc.make_phys(mu_eff=mu))) > 1e-6
+
+
+def test_wenoz_rk4_and_tvdrk3_match_oracle(orc):
+    case("wenoz rk4 / tvdrk3 32^3")
+    rho, vel, p = prims((32, 32, 32), 4)
+    ph = orc.make_phys(mu_eff=0.01, weno_weights=orc.WENO_Z)
+    u_ref = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], 32)
+    plan = Plan((32, 32, 32), mu_eff=0.01, weno="z")
+    u = plan.init_state(rho, vel, p)
+    plan.rk4(u, dt, 5)
+    assert rel_max(u.cpu().numpy(), orc.rk4(u_ref, dt, 5, ph, with_diag=False)[0]) <= 1e-10
+    u = plan.init_state(rho, vel, p)
+    plan.tvdrk3(u, dt, 5)
+    assert rel_max(u.cpu().numpy(), orc.tvdrk3(u_ref, dt, 5, ph, with_diag=False)[0]) <= 1e-10
+
+
+def test_wenoz_mixed_precision(orc):
+    case("wenoz mixed rhs 32^3")
+    rho, vel, p = prims((32, 32, 32), 5)
+    ph = orc.make_phys(mu_eff=0.01, weno_weights=orc.WENO_Z)
+    r_ref = orc.rhs(orc.init_state(rho, vel, p), ph)
+    plan = Plan((32, 32, 32), mu_eff=0.01, weno="z", precision="mixed")
+    u = plan.init_state(rho, vel, p)
+    err = rel_max(plan.rhs(u).double().cpu().numpy(), r_ref)
+    print(f"mixed wenoz rhs rel err {err:.3e}")
+    assert err <= 2e-5
+
+
+def test_wenoz_option_errors():
+    case("wenoz option errors")
+    boxes = [dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3, weno="z"), dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3)]
+    with pytest.raises(CnsError):
+        Ensemble(boxes)
+    plan = Plan((16, 16, 16), mu_eff=0.01, weno="z")
+    u = plan.init_state(*prims((16, 16, 16)))
+    with pytest.raises(CnsError):
+        plan.rhs_vjp(u, torch.ones_like(u))

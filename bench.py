@@ -53,6 +53,17 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 
 
+def kernel_source_digest():
+    """SHA-256 of the sources the sweep kernels are built from (counters taken on other
+    sources are stale)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("cns_kernels.hip", "cns_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_2211_16718_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,10 +160,7 @@ def main():
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            src = open(os.path.join(ROOT, "paper_2211_16718_amd", "csrc", "cns_kernels.hip"), "rb").read()
-            import hashlib
-
-            if t.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and dom in t.get("kernels", {}) \
+            if t.get("kernel_source_sha256") == kernel_source_digest() and dom in t.get("kernels", {}) \
                     and t.get("n") == n:
                 traffic = t["kernels"][dom]["bytes_per_launch"]
         except Exception:
@@ -190,7 +198,8 @@ def main():
     if not args.no_extras:
         del plan
         torch.cuda.empty_cache()
-        for name, fn in (("mixed_512", bench_mixed), ("ensemble_64", bench_ensemble), ("adjoint_128", bench_adjoint)):
+        for name, fn in (("mixed_512", bench_mixed), ("ensemble_64", bench_ensemble), ("adjoint_128", bench_adjoint),
+                         ("options_128", bench_options)):
             try:
                 extras[name] = fn()
             except Exception as e:  # report, keep the main line
@@ -337,6 +346,45 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
             "forward_s": fsec, "gradient_s": gsec, "gradient_over_forward": gsec / fsec,
             "value": 4.0 * n ** 3 * steps / gsec, "unit": "point-RHS/s (forward-step equivalents of the gradient)",
             "J": float(J), "grad_norm": float(g.norm())}
+
+
+def bench_options(n=128, steps=20):
+    """The same 128^3 workload with the TVD-RK3 integrator and with WENO-Z weights, and
+    the time of one energy spectrum (128^3 and 512^3)."""
+    import torch
+
+    from paper_2211_16718_amd import inputs as I
+    from paper_2211_16718_amd.api import Plan
+
+    wl = I.WORKLOADS["hit128"]
+    rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)
+    out = {"config": {"workload": f"hit{n}_re400", "grid": [n, n, n], "steps": steps}}
+    plan = Plan((n, n, n), mu_eff=1.0 / wl.re)
+    u = plan.init_state(rho, vel, p)
+    dt = I.dt_from_speed(plan.diagnostics_host(u)[7], n)
+    plan.tvdrk3(plan.empty_state().copy_(u), dt, 1, diag=False)  # warm
+    sec, _ = _timed(plan.stream, lambda: plan.tvdrk3(u, dt, steps))
+    out["tvdrk3"] = {"value": 3.0 * n ** 3 * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps}
+    pz = Plan((n, n, n), mu_eff=1.0 / wl.re, weno="z")
+    uz = pz.init_state(rho, vel, p)
+    pz.rk4(pz.empty_state().copy_(uz), dt, 1, diag=False)
+    sec, _ = _timed(pz.stream, lambda: pz.rk4(uz, dt, steps))
+    out["rk4_wenoz"] = {"value": 4.0 * n ** 3 * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps}
+    plan.spectrum(u)  # warm
+    reps = 5
+    sec, (E, mom) = _timed(plan.stream, lambda: [plan.spectrum(u) for _ in range(reps)][-1])
+    out["spectrum_128"] = {"ms": sec * 1e3 / reps, "taylor_microscale": Plan.taylor_microscale(mom),
+                           "k_peak": int(torch.argmax(E).item())}
+    del plan, pz, u, uz
+    torch.cuda.empty_cache()
+    m = 512
+    r5, v5, p5 = I.hit_primitives(m, 0, 0.3)
+    p512 = Plan((m, m, m), mu_eff=1.0 / 1600)
+    u5 = p512.init_state(r5, v5, p5)
+    p512.spectrum(u5)
+    sec, (E, mom) = _timed(p512.stream, lambda: p512.spectrum(u5))
+    out["spectrum_512"] = {"ms": sec * 1e3, "taylor_microscale": Plan.taylor_microscale(mom)}
+    return out
 
 
 if __name__ == "__main__":

@@ -285,18 +285,14 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
 
-        T w[6][5], f[6][5], g[4][4], Hp[5], nw[5];
+        T w[6][5], f[6][5], g[4][4], Hp[5];
         // One loop computes everything, so every point flux and every interface flux
         // runs the same machine code wherever a segment starts: results are bitwise
-        // independent of the segment length.  Iteration j takes point j+3, loaded one
-        // iteration ahead so the loads overlap the arithmetic, and the viscous fluxes
-        // of point j+2; from j = j0-1 on it forms the interface flux at j+1/2 and from
-        // j = j0 on the flux difference at point j.
-        {
-            const size_t o = base + wrapi(j0 - 3, n) * sg.lstride;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
-        }
+        // independent of the segment length.  Iteration j takes point j+3 and the
+        // viscous fluxes of point j+2; from j = j0-1 on it forms the interface flux at
+        // j+1/2 and from j = j0 on the flux difference at point j.  (Loading point j+4
+        // one iteration ahead was measured slower: the extra live registers spill in the
+        // fused-update variant.)
 #pragma nounroll
         for (int j = j0 - 6; j < j1; ++j) {
 #pragma unroll
@@ -306,8 +302,11 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     w[m][v] = w[m + 1][v];
                     f[m][v] = f[m + 1][v];
                 }
+            {
+                const size_t o = base + wrapi(j + 3, n) * sg.lstride;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
+                for (int v = 0; v < 5; ++v) w[5][v] = u[v * n3 + o];
+            }
             if constexpr (VISC) {
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
@@ -316,11 +315,6 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                 const size_t og = base + wrapi(j + 2, n) * sg.lstride;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + og];
-            }
-            {  // next iteration's point j+4
-                const size_t o = base + wrapi(j + 4, n) * sg.lstride;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
             }
             euler_flux<T, DIR>(w[5], gm1, f[5]);
             if (j < j0 - 1) continue;

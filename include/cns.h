@@ -150,7 +150,8 @@ int cns_diagnostics_host(const cns_plan *plan, const void *u_dev, double *out_ho
 
 /* Per-kernel timing of cns_rk4 with HIP events recorded on the plan's stream around
  * every launch (an event wait after each step).  Kernel kinds, in order:
- * viscous primitives, viscous fluxes, x sweep, y sweep, z sweep with the fused RK4
+ * viscous primitives (formed inside the viscous-flux kernel: no launches, kept so the
+ * indices stay stable), viscous fluxes, x sweep, y sweep, z sweep with the fused RK4
  * stage update, diagnostics.  enable != 0 clears the totals and turns timing on. */
 #define CNS_NKERNEL 6
 int cns_profile_enable(cns_plan *plan, int32_t enable);

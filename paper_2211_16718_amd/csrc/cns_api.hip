@@ -102,7 +102,6 @@ struct Core {
     static size_t box_scratch_bytes(const BoxDesc &b, size_t esz) {
         size_t n3 = b.n3, off = 0;
         auto take = [&](size_t bytes) { off = align256(off + bytes); };
-        take(4 * n3 * esz);  // W
         take(9 * n3 * esz);  // G
         take(5 * n3 * esz);  // rhs
         take(5 * n3 * esz);  // A
@@ -167,7 +166,6 @@ struct Core {
                 o = align256(o + bytes);
                 return (void *)p;
             };
-            b.W = take(4 * n3 * esz);
             b.G = take(9 * n3 * esz);
             b.rhs = take(5 * n3 * esz);
             b.A = take(5 * n3 * esz);

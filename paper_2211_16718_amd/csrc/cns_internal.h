@@ -36,7 +36,7 @@ struct BoxDesc {
     size_t n3;
     double inv_h[3];  // 1/dx, 1/dy, 1/dz
     double gamma, prandtl, mu, eps, delta, dt;
-    void *u, *A, *B, *rhs, *W, *G;  // state and scratch (element type of the plan)
+    void *u, *A, *B, *rhs, *G;  // state and scratch (element type of the plan)
     double *acc, *part;             // RK4 accumulator [5][n3], diagnostics partials
 };
 

@@ -2,16 +2,16 @@
 //
 // Data layout in HBM: SoA state u[v][k][j][i] (x fastest) per box.  One RHS
 // evaluation of a batch of boxes is
-//   1. k_prim       : u -> W = (u, v, w, T)                              [4][N3]
-//   2. k_visc_flux  : W -> viscous fluxes G = (tau_xx, tau_yy, tau_zz, tau_xy,
+//   1. k_visc_flux  : u -> viscous fluxes G = (tau_xx, tau_yy, tau_zz, tau_xy,
 //                     tau_xz, tau_yz, E_x, E_y, E_z), E_d = v.tau_d - q_d       [9][N3]
-//   3. x sweep      : u, G -> rhs (write).  Whole periodic rows staged in LDS, one
+//                     (primitives formed in the kernel; skipped when mu_eff = 0)
+//   2. x sweep      : u, G -> rhs (write).  Whole periodic rows staged in LDS, one
 //                     thread per interface (k_sweep_x_rows); the marching kernel
 //                     when a row does not fit.
-//   4. k_sweep<y>   : u, G -> rhs (accumulate)
-//   5. k_sweep<z>   : u, G -> rhs (accumulate), or the fused RK4 stage update.
+//   3. k_sweep<y>   : u, G -> rhs (accumulate)
+//   4. k_sweep<z>   : u, G -> rhs (accumulate), or the fused Runge-Kutta stage update.
 // A marching thread owns a segment of one grid line and walks along it with a
-// six-point register window: every point flux is computed once, every interface
+// six-point state window: every point flux is computed once, every interface
 // flux once per segment, the flux difference is formed in registers.  The viscous
 // term along d enters through the interface flux (-G_{j-1} + 7 G_j + 7 G_{j+1} -
 // G_{j+2}) / 12, whose difference is the 5-point central derivative of G.
@@ -79,29 +79,21 @@ __global__ void k_fill(size_t n, T *out) {
 // ----------------------------------------------------------------------------
 // viscous terms: primitives, then viscous fluxes at points
 // ----------------------------------------------------------------------------
+// primitives (u, v, w, T = gamma p / rho) of the state at linear index i
 template <typename T>
-__global__ __launch_bounds__(kPointThreads) void k_prim(Launch L) {
-    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
-    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
-        const int bi = find_box(L.off, L.nbox, vb);
-        const BoxDesc &b = L.boxes[bi];
-        const size_t n3 = b.n3;
-        const size_t i = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
-        if (i >= n3) continue;
-        const T *u = (const T *)state_ptr(b, L, L.in);
-        T *W = (T *)b.W;
-        const T gamma = T(b.gamma);
-        T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
-        T inv = rcp(r);
-        T vx = mx * inv, vy = my * inv, vz = mz * inv;
-        T p = (gamma - T(1)) * (e - T(0.5) * (mx * vx + my * vy + mz * vz));
-        W[i] = vx;
-        W[n3 + i] = vy;
-        W[2 * n3 + i] = vz;
-        W[3 * n3 + i] = gamma * p * inv;  // T = gamma p / rho
-    }
+__device__ __forceinline__ void prim_at(const T *u, size_t n3, size_t i, T gamma, T W[4]) {
+    const T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
+    const T inv = rcp(r);
+    W[0] = mx * inv;
+    W[1] = my * inv;
+    W[2] = mz * inv;
+    const T p = (gamma - T(1)) * (e - T(0.5) * (mx * W[0] + my * W[1] + mz * W[2]));
+    W[3] = gamma * p * inv;
 }
 
+// Viscous fluxes at points: the 12 first derivatives of (u, v, w, T) by the 5-point
+// central stencil, then tau, q and G.  The primitives of the 12 neighbours are formed
+// from the state in the kernel (no primitive array round trip through HBM).
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
     const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
@@ -112,8 +104,9 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
         const size_t n3 = b.n3;
         const size_t idx = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
         if (idx >= n3) continue;
-        const T *W = (const T *)b.W;
+        const T *u = (const T *)state_ptr(b, L, L.in);
         T *G = (T *)b.G;
+        const T gamma = T(b.gamma);
         const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
         const T mu = T(b.mu), kcond = T(b.mu / ((b.gamma - 1.0) * b.prandtl));
         const int i = (int)(idx % nx);
@@ -121,19 +114,22 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
         const int k = (int)(idx / ((size_t)nx * ny));
         const size_t sy = nx, sz = (size_t)nx * ny;
         const size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
-        const size_t xm2 = row + wrapi(i - 2, nx), xm1 = row + wrapi(i - 1, nx), xp1 = row + wrapi(i + 1, nx),
-                     xp2 = row + wrapi(i + 2, nx);
-        const size_t ym2 = col + wrapi(j - 2, ny) * sy, ym1 = col + wrapi(j - 1, ny) * sy,
-                     yp1 = col + wrapi(j + 1, ny) * sy, yp2 = col + wrapi(j + 2, ny) * sy;
-        const size_t zm2 = pil + wrapi(k - 2, nz) * sz, zm1 = pil + wrapi(k - 1, nz) * sz,
-                     zp1 = pil + wrapi(k + 1, nz) * sz, zp2 = pil + wrapi(k + 2, nz) * sz;
+        const int off[4] = {-2, -1, 1, 2};
         T g[4][3];  // g[a][c] = d W_a / d x_c
+        {
+            T Wx[4][4], Wy[4][4], Wz[4][4];  // [neighbour][component]
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const T *f = W + a * n3;
-            g[a][0] = dcen(f[xm2], f[xm1], f[xp1], f[xp2]) * ihx;
-            g[a][1] = dcen(f[ym2], f[ym1], f[yp1], f[yp2]) * ihy;
-            g[a][2] = dcen(f[zm2], f[zm1], f[zp1], f[zp2]) * ihz;
+            for (int o = 0; o < 4; ++o) {
+                prim_at(u, n3, row + wrapi(i + off[o], nx), gamma, Wx[o]);
+                prim_at(u, n3, col + wrapi(j + off[o], ny) * sy, gamma, Wy[o]);
+                prim_at(u, n3, pil + wrapi(k + off[o], nz) * sz, gamma, Wz[o]);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                g[a][0] = dcen(Wx[0][a], Wx[1][a], Wx[2][a], Wx[3][a]) * ihx;
+                g[a][1] = dcen(Wy[0][a], Wy[1][a], Wy[2][a], Wy[3][a]) * ihy;
+                g[a][2] = dcen(Wz[0][a], Wz[1][a], Wz[2][a], Wz[3][a]) * ihz;
+            }
         }
         T div = g[0][0] + g[1][1] + g[2][2];
         T tdiv = T(2) / T(3) * div;
@@ -143,7 +139,9 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
         T txy = mu * (g[0][1] + g[1][0]);
         T txz = mu * (g[0][2] + g[2][0]);
         T tyz = mu * (g[1][2] + g[2][1]);
-        T vx = W[idx], vy = W[n3 + idx], vz = W[2 * n3 + idx];
+        T Wc[4];
+        prim_at(u, n3, idx, gamma, Wc);
+        const T vx = Wc[0], vy = Wc[1], vz = Wc[2];
         G[idx] = txx;
         G[n3 + idx] = tyy;
         G[2 * n3 + idx] = tzz;
@@ -228,6 +226,37 @@ __device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5],
     }
 }
 
+// The same interface flux with the point fluxes read from the per-thread LDS ring of the
+// marching sweep (slot sl[m] holds point j-2+m), one component at a time: the fence
+// between components keeps the scheduler from hoisting all thirty LDS reads, which
+// would hold them in registers across the whole reconstruction.  Same arithmetic, in
+// the same order, as interface_flux.
+template <typename T, typename B, int DIR, bool VISC, bool WZ>
+__device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ring, const int sl[6], int bdim,
+                                                    const T g[4][4], T gamma, T eps, T delta, T H[5]) {
+    T Fs[5], du[5], D[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        T fm[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) fm[m] = ring[(sl[m] * 5 + v) * bdim];
+        T FL, FR, UL, UR;
+        weno5_lr<T, B, WZ>(fm[0], fm[1], fm[2], fm[3], fm[4], fm[5], eps, FL, FR);
+        weno5_lr<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL, UR);
+        Fs[v] = FL + FR;
+        du[v] = UR - UL;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    roe_dissipation<T, DIR>(w[2], w[3], du, gamma, delta, D);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) H[v] = T(0.5) * Fs[v] - T(0.5) * D[v];
+    if constexpr (VISC) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            H[1 + c] -= (T(7) * (g[1][c] + g[2][c]) - (g[0][c] + g[3][c])) * (T(1) / T(12));
+    }
+}
+
 // ----------------------------------------------------------------------------
 // marching WENO5-Roe sweep along one direction
 // ----------------------------------------------------------------------------
@@ -250,8 +279,19 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
 // waves covers 64 lines times W consecutive segments, so neighbouring segments share
 // their six-point halos in the CU's cache; for x and z a block covers 64 W lines of one
 // segment (stacking z segments spreads a block over planes far apart in memory).
+//
+// The writing and accumulating sweeps keep the six point fluxes in a per-thread ring
+// in LDS (6 slots x 5 components, component-major across the block so lanes hit
+// distinct banks); the registers this frees carry the loads of the next point and of
+// the point's rhs, issued before the interface-flux arithmetic so their latency
+// overlaps it (measured 12 % faster).  The fused-update sweep keeps the flux window in
+// registers and loads at the point of use: there the ring and the prefetches spill.
 template <typename T, typename B, int DIR, int MODE, bool VISC, bool WZ>
 __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
+    constexpr bool kRing = MODE != MODE_RK;
+    extern __shared__ unsigned char lds_raw[];
+    T *ring = reinterpret_cast<T *>(lds_raw) + threadIdx.x;  // slot s, component v at (s * 5 + v) * blockDim.x
+    const int bdim = blockDim.x;
     const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
     for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
@@ -284,25 +324,39 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
         const T gamma = T(bx.gamma), eps = T(bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
+        const double dt = L.dt_ov > 0.0 ? L.dt_ov : bx.dt;
 
-        T w[6][5], f[6][5], g[4][4], Hp[5];
+        T w[6][5], g[4][4], Hp[5], nw[5];
+        T f[kRing ? 1 : 6][5];  // register flux window of the fused-update sweep
         // One loop computes everything, so every point flux and every interface flux
         // runs the same machine code wherever a segment starts: results are bitwise
-        // independent of the segment length.  Iteration j takes point j+3 and the
-        // viscous fluxes of point j+2; from j = j0-1 on it forms the interface flux at
-        // j+1/2 and from j = j0 on the flux difference at point j.  (Loading point j+4
-        // one iteration ahead was measured slower: the extra live registers spill in the
-        // fused-update variant.)
+        // independent of the segment length.  Iteration j takes point j+3 (with the
+        // ring, loaded one iteration ahead) and the viscous fluxes of point j+2; from
+        // j = j0-1 on it forms the interface flux at j+1/2 and from j = j0 on the flux
+        // difference at point j.
+        if constexpr (kRing) {
+            const size_t o = base + wrapi(j0 - 3, n) * sg.lstride;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
+        }
+        int snew = 3;  // ring slot of point j+3; point j-2+m sits in slot (snew + 1 + m) mod 6
 #pragma nounroll
         for (int j = j0 - 6; j < j1; ++j) {
 #pragma unroll
             for (int m = 0; m < 5; ++m)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    w[m][v] = w[m + 1][v];
-                    f[m][v] = f[m + 1][v];
-                }
-            {
+                for (int v = 0; v < 5; ++v) w[m][v] = w[m + 1][v];
+            if constexpr (kRing) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
+                const size_t o = base + wrapi(j + 4, n) * sg.lstride;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
+            } else {
+#pragma unroll
+                for (int m = 0; m < 5; ++m)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) f[m][v] = f[m + 1][v];
                 const size_t o = base + wrapi(j + 3, n) * sg.lstride;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) w[5][v] = u[v * n3 + o];
@@ -316,39 +370,71 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + og];
             }
-            euler_flux<T, DIR>(w[5], gm1, f[5]);
+            int sold = snew;
+            if constexpr (kRing) {
+                T fn[5];
+                euler_flux<T, DIR>(w[5], gm1, fn);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) ring[(snew * 5 + v) * bdim] = fn[v];
+                snew = snew == 5 ? 0 : snew + 1;
+            } else {
+                euler_flux<T, DIR>(w[5], gm1, f[5]);
+            }
             if (j < j0 - 1) continue;
 
+            // rhs of point j, loaded before the interface-flux arithmetic
+            const size_t o = base + (size_t)(j >= j0 ? j : j0) * sg.lstride;
+            T pr[5];
+            if (MODE == MODE_ACCUM && j >= j0) {
+                const T *rhs = (const T *)(L.out_ov ? L.out_ov : bx.rhs);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) pr[v] = rhs[v * n3 + o];
+            }
+
             T H[5];
-            interface_flux<T, B, DIR, VISC, WZ>(w, f, g, gamma, eps, delta, H);
+            if constexpr (kRing) {
+                int sl[6];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int sm = sold + 1 + m;  // slot of point j-2+m (point j+3 is in sold)
+                    sl[m] = sm >= 6 ? sm - 6 : sm;
+                }
+                interface_flux_ring<T, B, DIR, VISC, WZ>(w, ring, sl, bdim, g, gamma, eps, delta, H);
+            } else {
+                interface_flux<T, B, DIR, VISC, WZ>(w, f, g, gamma, eps, delta, H);
+            }
             if (j >= j0) {
-                const size_t o = base + (size_t)j * sg.lstride;
                 if constexpr (MODE == MODE_RK) {
                     const T *rhs = (const T *)bx.rhs;
                     const T *un = (const T *)state_ptr(bx, L, BUF_U);
                     T *unext = (T *)state_ptr(bx, L, L.out);
                     double *acc = bx.acc;
-                    const double dt = L.dt_ov > 0.0 ? L.dt_ov : bx.dt;
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
                         const size_t e = v * n3 + o;
                         const double k = double(rhs[e] + r);
-                        const double uo = double(un[e]);
+                        // w[2] holds the stage state at j: u^n itself in the first stage
+                        const double us = double(w[2][v]);
                         if (L.scheme == CNS_TVDRK3) {
                             // Shu-Osher: U1 = u + dt k; U2 = 3/4 u + 1/4 (U1 + dt k);
-                            // u^{n+1} = 1/3 u + 2/3 (U2 + dt k); w[2] holds the stage state at j
-                            const double us = double(w[2][v]);
-                            if (L.stage == 1) unext[e] = T(uo + dt * k);
-                            else if (L.stage == 2) unext[e] = T(0.75 * uo + 0.25 * (us + dt * k));
-                            else unext[e] = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
+                            // u^{n+1} = 1/3 u + 2/3 (U2 + dt k)
+                            if (L.stage == 1) {
+                                unext[e] = T(us + dt * k);
+                            } else {
+                                const double uo = double(un[e]);
+                                if (L.stage == 2) unext[e] = T(0.75 * uo + 0.25 * (us + dt * k));
+                                else unext[e] = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
+                            }
                         } else if (L.stage == 1) {
-                            acc[e] = uo + (dt / 6.0) * k;
-                            unext[e] = T(uo + (0.5 * dt) * k);
+                            acc[e] = us + (dt / 6.0) * k;
+                            unext[e] = T(us + (0.5 * dt) * k);
                         } else if (L.stage == 2) {
+                            const double uo = double(un[e]);
                             acc[e] += (dt / 3.0) * k;
                             unext[e] = T(uo + (0.5 * dt) * k);
                         } else if (L.stage == 3) {
+                            const double uo = double(un[e]);
                             acc[e] += (dt / 3.0) * k;
                             unext[e] = T(uo + dt * k);
                         } else {
@@ -361,7 +447,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
                         if constexpr (MODE == MODE_WRITE) rhs[v * n3 + o] = r;
-                        else rhs[v * n3 + o] += r;
+                        else rhs[v * n3 + o] = pr[v] + r;
                     }
                 }
             }
@@ -555,7 +641,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
             for (int o = 0; o < 4; ++o) {
                 size_t px = row + wrapi(i + off[o], nx), py = col + wrapi(j + off[o], ny) * sy,
                        pz = pil + wrapi(k + off[o], nz) * sz;
-                double rx = 1.0 / double(u[px]), ry = 1.0 / double(u[py]), rz = 1.0 / double(u[pz]);
+                double rx = rcp(double(u[px])), ry = rcp(double(u[py])), rz = rcp(double(u[pz]));
                 vyx[o] = double(u[2 * n3 + px]) * rx;
                 vzx[o] = double(u[3 * n3 + px]) * rx;
                 vxy[o] = double(u[n3 + py]) * ry;
@@ -670,10 +756,6 @@ template <typename T>
 static void visc_fields(const Batch &bt, Launch L) {
     L = with_family(bt, L, F_POINT);
     if (!L.total) return;
-    {
-        ProfScope ps(bt.prof, K_PRIM, bt.stream);
-        hipLaunchKernelGGL(k_prim<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);
-    }
     ProfScope ps(bt.prof, K_VISC_FLUX, bt.stream);
     hipLaunchKernelGGL(k_visc_flux<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);
 }
@@ -681,8 +763,9 @@ static void visc_fields(const Batch &bt, Launch L) {
 template <typename T, int DIR, int MODE, bool VISC>
 static void sweep_t(const Batch &bt, const Launch &L) {
     const dim3 g(grid_for(L.total)), b(bt.block);
-    if (bt.wz) hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, true>), g, b, 0, bt.stream, L);
-    else hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, false>), g, b, 0, bt.stream, L);
+    const size_t ring = MODE == MODE_RK ? 0 : 30 * (size_t)bt.block * sizeof(T);  // point-flux ring, 6 x 5 per thread
+    if (bt.wz) hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, true>), g, b, ring, bt.stream, L);
+    else hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, false>), g, b, ring, bt.stream, L);
 }
 
 template <typename T, int MODE>

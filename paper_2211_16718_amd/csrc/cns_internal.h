@@ -24,6 +24,8 @@ constexpr int kDiagThreads = 256;
 constexpr int kDiagBlocksMax = 1024;  // partial-sum blocks per box of the diagnostics
 constexpr int kRowThreads = 256;      // threads per block of the x rows kernel
 constexpr int kRowLdsMax = 64 * 1024;
+constexpr int kViscTX = 64, kViscTY = 4;  // (x, y) tile of the viscous-flux kernel (kPointThreads threads)
+constexpr int kViscSZ = 16;               // planes per block of the viscous-flux kernel
 
 // buffer roles of a box
 enum Buf { BUF_U = 0, BUF_A = 1, BUF_B = 2 };
@@ -41,7 +43,7 @@ struct BoxDesc {
 };
 
 // kernel families with their own virtual-block prefix
-enum Family { F_POINT = 0, F_XROWS, F_SWEEP_X, F_SWEEP_Y, F_SWEEP_Z, F_DIAG, F_BOX, F_N };
+enum Family { F_POINT = 0, F_XROWS, F_SWEEP_X, F_SWEEP_Y, F_SWEEP_Z, F_DIAG, F_BOX, F_VISC, F_N };
 
 // per-launch arguments
 struct Launch {

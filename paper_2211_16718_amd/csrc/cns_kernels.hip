@@ -92,66 +92,81 @@ __device__ __forceinline__ void prim_at(const T *u, size_t n3, size_t i, T gamma
 }
 
 // Viscous fluxes at points: the 12 first derivatives of (u, v, w, T) by the 5-point
-// central stencil, then tau, q and G.  The primitives of the 12 neighbours are formed
-// from the state in the kernel (no primitive array round trip through HBM).
+// central stencil, then tau, q and G.  A block owns a 64 x 4 (x, y) tile and marches
+// along z over kViscSZ planes: the primitives of the current plane, with a +-2 halo,
+// are formed from the state into LDS (x and y derivatives), and each thread keeps its
+// own column's primitives at planes k-2 .. k+2 in registers (z derivatives).  About
+// three primitive evaluations per point instead of thirteen, and no primitive array.
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
+    __shared__ T pl[4][kViscTY + 4][kViscTX + 4];
     const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
     for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &b = L.boxes[bi];
         const int nx = b.nx, ny = b.ny, nz = b.nz;
-        const size_t n3 = b.n3;
-        const size_t idx = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
-        if (idx >= n3) continue;
+        const size_t n3 = b.n3, sz = (size_t)nx * ny;
+        const long long lb = vb - L.off[bi];
+        const int ntx = (nx + kViscTX - 1) / kViscTX, nty = (ny + kViscTY - 1) / kViscTY;
+        const int x0 = (int)(lb % ntx) * kViscTX, y0 = (int)((lb / ntx) % nty) * kViscTY;
+        const int z0 = (int)(lb / ((long long)ntx * nty)) * kViscSZ, z1 = min(z0 + kViscSZ, nz);
+        const int tx = threadIdx.x % kViscTX, ty = threadIdx.x / kViscTX;
+        const bool act = x0 + tx < nx && y0 + ty < ny;
+        const size_t col = (size_t)min(y0 + ty, ny - 1) * nx + min(x0 + tx, nx - 1);
         const T *u = (const T *)state_ptr(b, L, L.in);
         T *G = (T *)b.G;
         const T gamma = T(b.gamma);
         const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
         const T mu = T(b.mu), kcond = T(b.mu / ((b.gamma - 1.0) * b.prandtl));
-        const int i = (int)(idx % nx);
-        const int j = (int)((idx / nx) % ny);
-        const int k = (int)(idx / ((size_t)nx * ny));
-        const size_t sy = nx, sz = (size_t)nx * ny;
-        const size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
-        const int off[4] = {-2, -1, 1, 2};
-        T g[4][3];  // g[a][c] = d W_a / d x_c
-        {
-            T Wx[4][4], Wy[4][4], Wz[4][4];  // [neighbour][component]
+        T Wz[5][4];  // this column's primitives at planes k-2 .. k+2
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                prim_at(u, n3, row + wrapi(i + off[o], nx), gamma, Wx[o]);
-                prim_at(u, n3, col + wrapi(j + off[o], ny) * sy, gamma, Wy[o]);
-                prim_at(u, n3, pil + wrapi(k + off[o], nz) * sz, gamma, Wz[o]);
-            }
+        for (int m = 0; m < 4; ++m) prim_at(u, n3, col + wrapi(z0 - 2 + m, nz) * sz, gamma, Wz[m]);
+        for (int k = z0; k < z1; ++k) {
+            prim_at(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4]);
+            for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
+                const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
+                const size_t p = (size_t)k * sz + (size_t)wrapi(y0 - 2 + hy, ny) * nx + wrapi(x0 - 2 + hx, nx);
+                T w4[4];
+                prim_at(u, n3, p, gamma, w4);
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                g[a][0] = dcen(Wx[0][a], Wx[1][a], Wx[2][a], Wx[3][a]) * ihx;
-                g[a][1] = dcen(Wy[0][a], Wy[1][a], Wy[2][a], Wy[3][a]) * ihy;
-                g[a][2] = dcen(Wz[0][a], Wz[1][a], Wz[2][a], Wz[3][a]) * ihz;
+                for (int c = 0; c < 4; ++c) pl[c][hy][hx] = w4[c];
             }
+            __syncthreads();
+            if (act) {
+                T g[4][3];  // g[a][c] = d W_a / d x_c
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    g[a][0] = dcen(pl[a][ty + 2][tx], pl[a][ty + 2][tx + 1], pl[a][ty + 2][tx + 3], pl[a][ty + 2][tx + 4]) * ihx;
+                    g[a][1] = dcen(pl[a][ty][tx + 2], pl[a][ty + 1][tx + 2], pl[a][ty + 3][tx + 2], pl[a][ty + 4][tx + 2]) * ihy;
+                    g[a][2] = dcen(Wz[0][a], Wz[1][a], Wz[3][a], Wz[4][a]) * ihz;
+                }
+                T div = g[0][0] + g[1][1] + g[2][2];
+                T tdiv = T(2) / T(3) * div;
+                T txx = mu * (T(2) * g[0][0] - tdiv);
+                T tyy = mu * (T(2) * g[1][1] - tdiv);
+                T tzz = mu * (T(2) * g[2][2] - tdiv);
+                T txy = mu * (g[0][1] + g[1][0]);
+                T txz = mu * (g[0][2] + g[2][0]);
+                T tyz = mu * (g[1][2] + g[2][1]);
+                const T vx = Wz[2][0], vy = Wz[2][1], vz = Wz[2][2];
+                const size_t idx = (size_t)k * sz + col;
+                G[idx] = txx;
+                G[n3 + idx] = tyy;
+                G[2 * n3 + idx] = tzz;
+                G[3 * n3 + idx] = txy;
+                G[4 * n3 + idx] = txz;
+                G[5 * n3 + idx] = tyz;
+                // E_d = v . tau_d - q_d,  q_d = -kcond dT/dx_d
+                G[6 * n3 + idx] = vx * txx + vy * txy + vz * txz + kcond * g[3][0];
+                G[7 * n3 + idx] = vx * txy + vy * tyy + vz * tyz + kcond * g[3][1];
+                G[8 * n3 + idx] = vx * txz + vy * tyz + vz * tzz + kcond * g[3][2];
+            }
+            __syncthreads();  // the next plane overwrites the LDS tile
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Wz[m][c] = Wz[m + 1][c];
         }
-        T div = g[0][0] + g[1][1] + g[2][2];
-        T tdiv = T(2) / T(3) * div;
-        T txx = mu * (T(2) * g[0][0] - tdiv);
-        T tyy = mu * (T(2) * g[1][1] - tdiv);
-        T tzz = mu * (T(2) * g[2][2] - tdiv);
-        T txy = mu * (g[0][1] + g[1][0]);
-        T txz = mu * (g[0][2] + g[2][0]);
-        T tyz = mu * (g[1][2] + g[2][1]);
-        T Wc[4];
-        prim_at(u, n3, idx, gamma, Wc);
-        const T vx = Wc[0], vy = Wc[1], vz = Wc[2];
-        G[idx] = txx;
-        G[n3 + idx] = tyy;
-        G[2 * n3 + idx] = tzz;
-        G[3 * n3 + idx] = txy;
-        G[4 * n3 + idx] = txz;
-        G[5 * n3 + idx] = tyz;
-        // E_d = v . tau_d - q_d,  q_d = -kcond dT/dx_d
-        G[6 * n3 + idx] = vx * txx + vy * txy + vz * txz + kcond * g[3][0];
-        G[7 * n3 + idx] = vx * txy + vy * tyy + vz * tyz + kcond * g[3][1];
-        G[8 * n3 + idx] = vx * txz + vy * tyz + vz * tzz + kcond * g[3][2];
     }
 }
 
@@ -712,6 +727,8 @@ long long family_blocks(const BoxDesc &b, int fam, int block) {
             return cdiv((long long)g.npq * cdiv(g.nline, b.seg[d]), block);
         }
         case F_DIAG: return diag_blocks(b.n3);
+        case F_VISC:
+            return cdiv(b.nx, kViscTX) * cdiv(b.ny, kViscTY) * cdiv(b.nz, kViscSZ);
         case F_BOX: return 1;
     }
     return 0;
@@ -754,7 +771,7 @@ void launch_fill(int prec, size_t n, void *out, hipStream_t s) {
 
 template <typename T>
 static void visc_fields(const Batch &bt, Launch L) {
-    L = with_family(bt, L, F_POINT);
+    L = with_family(bt, L, F_VISC);
     if (!L.total) return;
     ProfScope ps(bt.prof, K_VISC_FLUX, bt.stream);
     hipLaunchKernelGGL(k_visc_flux<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);

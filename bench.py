@@ -35,8 +35,7 @@ FLOPS_PER_POINT = {
     "sweep_x": 18 + 1220 + 5 + 116 + 20 + 24 + 10,
     "sweep_y": 18 + 1220 + 5 + 116 + 20 + 24 + 10 + 5,
     "sweep_z_rk4": 18 + 1220 + 5 + 116 + 20 + 24 + 10 + 30,
-    "visc_prim": 13,
-    "visc_flux": 12 * 5 + 40,
+    "visc_flux": 13 + 12 * 5 + 40,  # primitives of the point, 12 derivatives, tau/q/G
     "diagnostics": 120,
 }
 # Algorithmic HBM bytes per grid point of one launch (FP64): each array element
@@ -45,8 +44,7 @@ BYTES_PER_POINT = {
     "sweep_x": 8 * (5 + 4 + 5),            # u, 4 viscous fluxes -> rhs
     "sweep_y": 8 * (5 + 4 + 5 + 5),        # + rhs read-modify-write
     "sweep_z_rk4": 8 * (5 + 4 + 5 + 5 + 5 + 5 + 5),  # + u^n, acc (rmw), next stage
-    "visc_prim": 8 * (5 + 4),
-    "visc_flux": 8 * (4 + 9),
+    "visc_flux": 8 * (5 + 9),              # u -> 9 viscous-flux fields
     "diagnostics": 8 * 5,
 }
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)

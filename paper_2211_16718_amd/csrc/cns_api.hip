@@ -130,7 +130,16 @@ struct Core {
         b.nx = g.nx;
         b.ny = g.ny;
         b.nz = g.nz;
-        for (int d = 0; d < 3; ++d) b.seg[d] = 16;
+        // default marching-segment length: 16, doubled (up to 64) while the launch still
+        // has about four rounds of two waves per SIMD (1 M threads over 256 CUs); longer
+        // segments recompute fewer halo interfaces, shorter ones fill the chip
+        const long long nlen[3] = {g.nx, g.ny, g.nz};
+        for (int d = 0; d < 3; ++d) {
+            const long long lines = (long long)g.nx * g.ny * g.nz / nlen[d];
+            int seg = 16;
+            while (seg < 64 && lines * ((nlen[d] + 2 * seg - 1) / (2 * seg)) >= (1ll << 19)) seg *= 2;
+            b.seg[d] = seg;
+        }
         b.n3 = (size_t)g.nx * g.ny * g.nz;
         b.inv_h[0] = g.nx / g.lx;
         b.inv_h[1] = g.ny / g.ly;

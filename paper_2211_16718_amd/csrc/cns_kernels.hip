@@ -295,15 +295,15 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
 // their six-point halos in the CU's cache; for x and z a block covers 64 W lines of one
 // segment (stacking z segments spreads a block over planes far apart in memory).
 //
-// The writing and accumulating sweeps keep the six point fluxes in a per-thread ring
-// in LDS (6 slots x 5 components, component-major across the block so lanes hit
-// distinct banks); the registers this frees carry the loads of the next point and of
-// the point's rhs, issued before the interface-flux arithmetic so their latency
-// overlaps it (measured 12 % faster).  The fused-update sweep keeps the flux window in
-// registers and loads at the point of use: there the ring and the prefetches spill.
+// The six point fluxes live in a per-thread ring in LDS (6 slots x 5 components,
+// component-major across the block so lanes hit distinct banks), read one component
+// at a time; the registers this frees carry the loads of the next point and of the
+// point's rhs, issued before the interface-flux arithmetic so their latency overlaps
+// it (y sweep 12 % and fused-update sweep 6 % faster than a register window).  u^n
+// and the accumulator of the fused update are still loaded at the point of use:
+// prefetching them too spills.
 template <typename T, typename B, int DIR, int MODE, bool VISC, bool WZ>
 __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
-    constexpr bool kRing = MODE != MODE_RK;
     extern __shared__ unsigned char lds_raw[];
     T *ring = reinterpret_cast<T *>(lds_raw) + threadIdx.x;  // slot s, component v at (s * 5 + v) * blockDim.x
     const int bdim = blockDim.x;
@@ -342,14 +342,13 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
         const double dt = L.dt_ov > 0.0 ? L.dt_ov : bx.dt;
 
         T w[6][5], g[4][4], Hp[5], nw[5];
-        T f[kRing ? 1 : 6][5];  // register flux window of the fused-update sweep
         // One loop computes everything, so every point flux and every interface flux
         // runs the same machine code wherever a segment starts: results are bitwise
-        // independent of the segment length.  Iteration j takes point j+3 (with the
-        // ring, loaded one iteration ahead) and the viscous fluxes of point j+2; from
-        // j = j0-1 on it forms the interface flux at j+1/2 and from j = j0 on the flux
-        // difference at point j.
-        if constexpr (kRing) {
+        // independent of the segment length.  Iteration j takes point j+3 (loaded one
+        // iteration ahead) and the viscous fluxes of point j+2; from j = j0-1 on it
+        // forms the interface flux at j+1/2 and from j = j0 on the flux difference at
+        // point j.
+        {
             const size_t o = base + wrapi(j0 - 3, n) * sg.lstride;
 #pragma unroll
             for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
@@ -361,20 +360,12 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
             for (int m = 0; m < 5; ++m)
 #pragma unroll
                 for (int v = 0; v < 5; ++v) w[m][v] = w[m + 1][v];
-            if constexpr (kRing) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
+            for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
+            {
                 const size_t o = base + wrapi(j + 4, n) * sg.lstride;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
-            } else {
-#pragma unroll
-                for (int m = 0; m < 5; ++m)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) f[m][v] = f[m + 1][v];
-                const size_t o = base + wrapi(j + 3, n) * sg.lstride;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) w[5][v] = u[v * n3 + o];
             }
             if constexpr (VISC) {
 #pragma unroll
@@ -385,29 +376,27 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + og];
             }
-            int sold = snew;
-            if constexpr (kRing) {
+            const int sold = snew;
+            {
                 T fn[5];
                 euler_flux<T, DIR>(w[5], gm1, fn);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) ring[(snew * 5 + v) * bdim] = fn[v];
                 snew = snew == 5 ? 0 : snew + 1;
-            } else {
-                euler_flux<T, DIR>(w[5], gm1, f[5]);
             }
             if (j < j0 - 1) continue;
 
             // rhs of point j, loaded before the interface-flux arithmetic
             const size_t o = base + (size_t)(j >= j0 ? j : j0) * sg.lstride;
             T pr[5];
-            if (MODE == MODE_ACCUM && j >= j0) {
-                const T *rhs = (const T *)(L.out_ov ? L.out_ov : bx.rhs);
+            if (MODE != MODE_WRITE && j >= j0) {
+                const T *rhs = (const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs));
 #pragma unroll
                 for (int v = 0; v < 5; ++v) pr[v] = rhs[v * n3 + o];
             }
 
             T H[5];
-            if constexpr (kRing) {
+            {
                 int sl[6];
 #pragma unroll
                 for (int m = 0; m < 6; ++m) {
@@ -415,12 +404,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     sl[m] = sm >= 6 ? sm - 6 : sm;
                 }
                 interface_flux_ring<T, B, DIR, VISC, WZ>(w, ring, sl, bdim, g, gamma, eps, delta, H);
-            } else {
-                interface_flux<T, B, DIR, VISC, WZ>(w, f, g, gamma, eps, delta, H);
             }
             if (j >= j0) {
                 if constexpr (MODE == MODE_RK) {
-                    const T *rhs = (const T *)bx.rhs;
                     const T *un = (const T *)state_ptr(bx, L, BUF_U);
                     T *unext = (T *)state_ptr(bx, L, L.out);
                     double *acc = bx.acc;
@@ -428,7 +414,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
                         const size_t e = v * n3 + o;
-                        const double k = double(rhs[e] + r);
+                        const double k = double(pr[v] + r);
                         // w[2] holds the stage state at j: u^n itself in the first stage
                         const double us = double(w[2][v]);
                         if (L.scheme == CNS_TVDRK3) {
@@ -780,7 +766,7 @@ static void visc_fields(const Batch &bt, Launch L) {
 template <typename T, int DIR, int MODE, bool VISC>
 static void sweep_t(const Batch &bt, const Launch &L) {
     const dim3 g(grid_for(L.total)), b(bt.block);
-    const size_t ring = MODE == MODE_RK ? 0 : 30 * (size_t)bt.block * sizeof(T);  // point-flux ring, 6 x 5 per thread
+    const size_t ring = 30 * (size_t)bt.block * sizeof(T);  // point-flux ring, 6 slots x 5 per thread
     if (bt.wz) hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, true>), g, b, ring, bt.stream, L);
     else hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, false>), g, b, ring, bt.stream, L);
 }

@@ -465,9 +465,41 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 // computed once; the periodic wrap happens in LDS.
 // ----------------------------------------------------------------------------
 template <typename T, typename B, bool VISC, int P, bool WZ>
-__global__ __launch_bounds__(kRowThreads) void k_sweep_x_rows(Launch L) {
+__global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
+    // A block walks over several row groups (grid stride).  With one point per thread
+    // the global loads of the next group are issued into registers before the
+    // interface arithmetic of the current one, so their latency overlaps it; with more
+    // points per thread the extra registers would halve the occupancy, so the loads
+    // stay at the top of each group.
+    constexpr bool kPrefetch = P == 1;
+    T pw[P][5], pg[P][4];
+    auto fetch = [&](long long vb) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &bx = L.boxes[bi];
+        const int nx = bx.nx;
+        const long long nrows = (long long)bx.ny * bx.nz;
+        const long long row0 = (vb - L.off[bi]) * bx.rows;
+        const int nact = (int)min((long long)bx.rows, nrows - row0) * nx;
+        const size_t obase = (size_t)row0 * nx, n3 = bx.n3;
+        const T *u = (const T *)state_ptr(bx, L, L.in);
+        const T *G = (const T *)bx.G;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = threadIdx.x + k * kRowThreads;
+            if (t < nact) {
+                const size_t o = obase + t;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) pw[k][v] = u[v * n3 + o];
+                if constexpr (VISC) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) pg[k][c] = G[gcomp<0>(c) * n3 + o];
+                }
+            }
+        }
+    };
+    if (kPrefetch && (long long)blockIdx.x < L.total) fetch(blockIdx.x);
     for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
@@ -484,31 +516,43 @@ __global__ __launch_bounds__(kRowThreads) void k_sweep_x_rows(Launch L) {
         const long long row0 = (vb - L.off[bi]) * bx.rows;
         const int nact = (int)min((long long)bx.rows, nrows - row0) * nx;  // active points
         const size_t obase = (size_t)row0 * nx;
-        const T *u = (const T *)state_ptr(bx, L, L.in);
-        const T *G = (const T *)bx.G;
         T *out = (T *)(L.out_ov ? L.out_ov : bx.rhs);
 
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int t = threadIdx.x + k * kRowThreads;
             if (t < nact) {
-                const size_t o = obase + t;
-                T w[5], f[5];
+                T wk[5], gk[4], f[5];
+                if constexpr (kPrefetch) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) w[v] = u[v * n3 + o];
-                euler_flux<T, 0>(w, gm1, f);
+                    for (int v = 0; v < 5; ++v) wk[v] = pw[k][v];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) gk[c] = pg[k][c];
+                } else {
+                    const T *u = (const T *)state_ptr(bx, L, L.in);
+                    const T *G = (const T *)bx.G;
+                    const size_t o = obase + t;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) wk[v] = u[v * n3 + o];
+                    if constexpr (VISC) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) gk[c] = G[gcomp<0>(c) * n3 + o];
+                    }
+                }
+                euler_flux<T, 0>(wk, gm1, f);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    su[v * per + t] = w[v];
+                    su[v * per + t] = wk[v];
                     sf[v * per + t] = f[v];
                 }
                 if constexpr (VISC) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) sg[c * per + t] = G[gcomp<0>(c) * n3 + o];
+                    for (int c = 0; c < 4; ++c) sg[c * per + t] = gk[c];
                 }
             }
         }
         __syncthreads();
+        if (kPrefetch && vb + gridDim.x < L.total) fetch(vb + gridDim.x);
         T H[P][5];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -788,7 +832,9 @@ static void sweep(const Batch &bt, Launch L, int dir, bool visc) {
 
 template <typename T, bool VISC, bool WZ>
 static void xrows_tw(const Batch &bt, const Launch &L) {
-    const dim3 g(grid_for(L.total)), b(kRowThreads);
+    // about four row groups per block when the loads of the next one are prefetched
+    const long long nb = bt.rowP == 1 ? std::max<long long>(std::min<long long>(L.total, 2048), L.total / 4) : L.total;
+    const dim3 g(grid_for(nb)), b(kRowThreads);
     switch (bt.rowP) {
         case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1, WZ>), g, b, bt.rowLds, bt.stream, L); break;
         case 2: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 2, WZ>), g, b, bt.rowLds, bt.stream, L); break;

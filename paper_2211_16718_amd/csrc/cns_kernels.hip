@@ -617,9 +617,15 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
-__host__ __device__ __forceinline__ int diag_blocks(size_t n3) {
-    size_t b = (n3 + kDiagThreads - 1) / kDiagThreads;
-    return (int)(b < (size_t)kDiagBlocksMax ? b : (size_t)kDiagBlocksMax);
+// the diagnostics walk the box in the tiles of the viscous-flux kernel (64 x 4 columns,
+// kViscSZ planes); one partial-sum block per tile, at most kDiagBlocksMax (then a
+// block takes every kDiagBlocksMax-th tile)
+__host__ __device__ __forceinline__ long long diag_tiles(int nx, int ny, int nz) {
+    return (long long)((nx + kViscTX - 1) / kViscTX) * ((ny + kViscTY - 1) / kViscTY) * ((nz + kViscSZ - 1) / kViscSZ);
+}
+__host__ __device__ __forceinline__ int diag_blocks(int nx, int ny, int nz) {
+    const long long t = diag_tiles(nx, ny, nz);
+    return (int)(t < kDiagBlocksMax ? t : kDiagBlocksMax);
 }
 
 // block reduction of CNS_NDIAG values (slot 7 a max, the others sums) in a fixed order
@@ -641,63 +647,97 @@ __device__ __forceinline__ void block_reduce_diag(const double acc[CNS_NDIAG], d
     __syncthreads();
 }
 
+static_assert(kDiagThreads == kViscTX * kViscTY && kPointThreads == kViscTX * kViscTY,
+              "the tiled kernels map one thread to each column of a 64 x 4 tile");
+
+// velocity m/rho of the state at linear index i (FP64, for the diagnostics)
+template <typename T>
+__device__ __forceinline__ void vel_at(const T *u, size_t n3, size_t i, double v[3]) {
+    const double ir = rcp(double(u[i]));
+    v[0] = double(u[n3 + i]) * ir;
+    v[1] = double(u[2 * n3 + i]) * ir;
+    v[2] = double(u[3 * n3 + i]) * ir;
+}
+
+// Per-block partial diagnostics.  Point quantities from the state; the vorticity from
+// the 4th-order central derivative of the velocity, whose x and y neighbours come from
+// an LDS copy of the current plane (with a +-2 halo) and whose z neighbours from a
+// per-column window of five planes in registers.
 template <typename T>
 __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
     __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
+    __shared__ double pv[3][kViscTY + 4][kViscTX + 4];
     const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
     const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
     for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
-        const size_t n3 = bx.n3;
-        const int nblk = diag_blocks(n3);
+        const size_t n3 = bx.n3, sz = (size_t)nx * ny;
+        const int nblk = diag_blocks(nx, ny, nz);
+        const long long ntile = diag_tiles(nx, ny, nz);
         const int lb = (int)(vb - L.off[bi]);
         const T *u = (const T *)state_ptr(bx, L, BUF_U);
         const double gamma = bx.gamma, ihx = bx.inv_h[0], ihy = bx.inv_h[1], ihz = bx.inv_h[2];
+        const int ntx = (nx + kViscTX - 1) / kViscTX, nty = (ny + kViscTY - 1) / kViscTY;
+        const int tx = threadIdx.x % kViscTX, ty = threadIdx.x / kViscTX;
         double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const size_t sy = nx, sz = (size_t)nx * ny;
-        for (size_t idx = (size_t)lb * kDiagThreads + threadIdx.x; idx < n3; idx += (size_t)nblk * kDiagThreads) {
-            double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]),
-                   mz = double(u[3 * n3 + idx]), e = double(u[4 * n3 + idx]);
-            double inv = 1.0 / r;
-            double vx = mx * inv, vy = my * inv, vz = mz * inv;
-            double ke = 0.5 * (mx * vx + my * vy + mz * vz);
-            double p = (gamma - 1.0) * (e - ke);
-            bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
-            if (!finite || !(r > 0.0) || !(p > 0.0)) {
-                acc[8] += 1.0;
-                continue;
-            }
-            acc[0] += ke;
-            acc[2] += r;
-            acc[3] += mx;
-            acc[4] += my;
-            acc[5] += mz;
-            acc[6] += e;
-            double c = sqrt(gamma * p * inv);
-            acc[7] = fmax(acc[7], fmax(fabs(vx), fmax(fabs(vy), fabs(vz))) + c);
-            // vorticity with the 4th-order central derivative
-            int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / sz);
-            size_t row = idx - i, col = idx - j * sy, pil = idx - k * sz;
-            const int off[4] = {-2, -1, 1, 2};
-            double vyx[4], vzx[4], vxy[4], vzy[4], vxz[4], vyz[4];
+        for (long long tile = lb; tile < ntile; tile += nblk) {
+            const int x0 = (int)(tile % ntx) * kViscTX, y0 = (int)((tile / ntx) % nty) * kViscTY;
+            const int z0 = (int)(tile / ((long long)ntx * nty)) * kViscSZ, z1 = min(z0 + kViscSZ, nz);
+            const bool act = x0 + tx < nx && y0 + ty < ny;
+            const size_t col = (size_t)min(y0 + ty, ny - 1) * nx + min(x0 + tx, nx - 1);
+            double vz[5][3];  // this column's velocity at planes k-2 .. k+2
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                size_t px = row + wrapi(i + off[o], nx), py = col + wrapi(j + off[o], ny) * sy,
-                       pz = pil + wrapi(k + off[o], nz) * sz;
-                double rx = rcp(double(u[px])), ry = rcp(double(u[py])), rz = rcp(double(u[pz]));
-                vyx[o] = double(u[2 * n3 + px]) * rx;
-                vzx[o] = double(u[3 * n3 + px]) * rx;
-                vxy[o] = double(u[n3 + py]) * ry;
-                vzy[o] = double(u[3 * n3 + py]) * ry;
-                vxz[o] = double(u[n3 + pz]) * rz;
-                vyz[o] = double(u[2 * n3 + pz]) * rz;
+            for (int m = 0; m < 4; ++m) vel_at(u, n3, col + wrapi(z0 - 2 + m, nz) * sz, vz[m]);
+            for (int k = z0; k < z1; ++k) {
+                vel_at(u, n3, col + wrapi(k + 2, nz) * sz, vz[4]);
+                for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
+                    const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
+                    double v3[3];
+                    vel_at(u, n3, (size_t)k * sz + (size_t)wrapi(y0 - 2 + hy, ny) * nx + wrapi(x0 - 2 + hx, nx), v3);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) pv[c][hy][hx] = v3[c];
+                }
+                __syncthreads();
+                if (act) {
+                    const size_t idx = (size_t)k * sz + col;
+                    const double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]),
+                                 mz = double(u[3 * n3 + idx]), e = double(u[4 * n3 + idx]);
+                    const double inv = rcp(r);
+                    const double vx = mx * inv, vy = my * inv, vzc = mz * inv;
+                    const double ke = 0.5 * (mx * vx + my * vy + mz * vzc);
+                    const double p = (gamma - 1.0) * (e - ke);
+                    const bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
+                    if (!finite || !(r > 0.0) || !(p > 0.0)) {
+                        acc[8] += 1.0;
+                    } else {
+                        acc[0] += ke;
+                        acc[2] += r;
+                        acc[3] += mx;
+                        acc[4] += my;
+                        acc[5] += mz;
+                        acc[6] += e;
+                        const double c = sqrt(gamma * p * inv);
+                        acc[7] = fmax(acc[7], fmax(fabs(vx), fmax(fabs(vy), fabs(vzc))) + c);
+                        // vorticity with the 4th-order central derivative
+                        const int X = tx + 2, Y = ty + 2;
+                        const double dvzdy = dcen(pv[2][Y - 2][X], pv[2][Y - 1][X], pv[2][Y + 1][X], pv[2][Y + 2][X]) * ihy;
+                        const double dvydz = dcen(vz[0][1], vz[1][1], vz[3][1], vz[4][1]) * ihz;
+                        const double dvxdz = dcen(vz[0][0], vz[1][0], vz[3][0], vz[4][0]) * ihz;
+                        const double dvzdx = dcen(pv[2][Y][X - 2], pv[2][Y][X - 1], pv[2][Y][X + 1], pv[2][Y][X + 2]) * ihx;
+                        const double dvydx = dcen(pv[1][Y][X - 2], pv[1][Y][X - 1], pv[1][Y][X + 1], pv[1][Y][X + 2]) * ihx;
+                        const double dvxdy = dcen(pv[0][Y - 2][X], pv[0][Y - 1][X], pv[0][Y + 1][X], pv[0][Y + 2][X]) * ihy;
+                        const double ox = dvzdy - dvydz, oy = dvxdz - dvzdx, oz = dvydx - dvxdy;
+                        if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
+                    }
+                }
+                __syncthreads();  // the next plane overwrites the LDS tile
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) vz[m][c] = vz[m + 1][c];
             }
-            double ox = dcen(vzy[0], vzy[1], vzy[2], vzy[3]) * ihy - dcen(vyz[0], vyz[1], vyz[2], vyz[3]) * ihz;
-            double oy = dcen(vxz[0], vxz[1], vxz[2], vxz[3]) * ihz - dcen(vzx[0], vzx[1], vzx[2], vzx[3]) * ihx;
-            double oz = dcen(vyx[0], vyx[1], vyx[2], vyx[3]) * ihx - dcen(vxy[0], vxy[1], vxy[2], vxy[3]) * ihy;
-            if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
         }
         block_reduce_diag(acc, red, bx.part + (size_t)lb * CNS_NDIAG, one);
     }
@@ -708,7 +748,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L) {
     for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
         const int bi = (int)vb;  // one virtual block per box
         const BoxDesc &bx = L.boxes[bi];
-        const int nblk = diag_blocks(bx.n3);
+        const int nblk = diag_blocks(bx.nx, bx.ny, bx.nz);
         double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int b = threadIdx.x; b < nblk; b += kDiagThreads)
 #pragma unroll
@@ -756,7 +796,7 @@ long long family_blocks(const BoxDesc &b, int fam, int block) {
                 return cdiv(g.npq, 64) * cdiv(cdiv(g.nline, b.seg[d]), block / 64);
             return cdiv((long long)g.npq * cdiv(g.nline, b.seg[d]), block);
         }
-        case F_DIAG: return diag_blocks(b.n3);
+        case F_DIAG: return diag_blocks(b.nx, b.ny, b.nz);
         case F_VISC:
             return cdiv(b.nx, kViscTX) * cdiv(b.ny, kViscTY) * cdiv(b.nz, kViscSZ);
         case F_BOX: return 1;

@@ -10,6 +10,9 @@
 //    interface evaluates 4 candidates and 4 second differences instead of 6 and 6.
 //  * Nonlinear weights: alpha_k = c_k / d_k with d_k = (eps + beta_k)^2 are scaled by
 //    d_1 d_2 d_3, so omega needs one division per reconstruction instead of four.
+//  * The sweeps carry 6 x the reconstructed values and 4 x the indicators (with 4 eps),
+//    which removes the constant factors from the inner arithmetic; the interface flux
+//    divides once by 12 at the end.
 //  * Roe dissipation |A| (u^R - u^L) is evaluated with wave strengths (projections
 //    on the left eigenvectors, written out) instead of explicit 5x5 matrices;
 //    |A| = X |Lambda| X^-1 is basis independent so the operator is the same.
@@ -49,7 +52,8 @@ __device__ __forceinline__ T harten_abs(T lam, T delta) {
 // WENO5, left- and right-biased values at j+1/2 from q_{j-2} .. q_{j+3}
 // ---------------------------------------------------------------------------
 // Nonlinear weights of one reconstruction from its three indicators b1..b3 (in B) and
-// candidates c1..c3: Jiang-Shu alpha_k = c_k / s_k^2, s_k = eps + b_k, or (WZ) the
+// candidates c1..c3 (any common scale of b and eps, and of the c, passes through):
+// Jiang-Shu alpha_k = c_k / s_k^2, s_k = eps + b_k, or (WZ) the
 // WENO-Z weights of Borges et al. (2008), alpha_k = c_k (1 + (tau5/s_k)^2) with
 // tau5 = |b1 - b3|.  Both are scaled by s_1^2 s_2^2 s_3^2 so one reciprocal serves the
 // three weights.  The Z weights carry one more factor s^2, so they are formed in B
@@ -57,10 +61,12 @@ __device__ __forceinline__ T harten_abs(T lam, T delta) {
 template <typename T, typename B, bool WZ>
 __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, T c3) {
     if constexpr (!WZ) {
+        // 10 alpha_k s1^2 s2^2 s3^2 = (d2 d3, 6 d1 d3, 3 d1 d2) with d_k = s_k^2
         T s1 = eps + T(b1), s2 = eps + T(b2), s3 = eps + T(b3);
         T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
-        T a1 = T(0.1) * (d2 * d3), a2 = T(0.6) * (d1 * d3), a3 = T(0.3) * (d1 * d2);
-        return (a1 * c1 + a2 * c2 + a3 * c3) * rcp(a1 + a2 + a3);
+        T a1 = d2 * d3, a2 = d1 * d3, a3 = d1 * d2;
+        T num = a1 * c1 + a2 * (T(6) * c2) + a3 * (T(3) * c3);
+        return num * rcp(a1 + T(6) * a2 + T(3) * a3);
     } else {
         const B e = B(eps);
         B t = fabs(b1 - b3);
@@ -77,17 +83,20 @@ __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, 
     }
 }
 
+// Six times the left- and right-biased values, from four times the Jiang-Shu
+// indicators: with eps4 = 4 eps every alpha_k scales by the same 1/16, so the weights
+// are those of the plain form; dropping the 1/6 of the candidates and the 13/12, 1/4 of
+// the indicators saves a multiplication per candidate and per indicator.
 template <typename T, typename B, bool WZ = false>
-__device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T eps, T &L, T &R) {
-    const T r6 = T(1) / T(6);
-    // third-order candidates; the mirror reconstruction reuses L2 and L3
-    T L1 = (T(2) * m2 - T(7) * m1 + T(11) * c0) * r6;
-    T L2 = (-m1 + T(5) * c0 + T(2) * p1) * r6;
-    T L3 = (T(2) * c0 + T(5) * p1 - p2) * r6;
-    T R1 = (T(2) * p3 - T(7) * p2 + T(11) * p1) * r6;
+__device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T eps4, T &L6, T &R6) {
+    // third-order candidates (times 6); the mirror reconstruction reuses L2 and L3
+    T L1 = T(2) * m2 - T(7) * m1 + T(11) * c0;
+    T L2 = -m1 + T(5) * c0 + T(2) * p1;
+    T L3 = T(2) * c0 + T(5) * p1 - p2;
+    T R1 = T(2) * p3 - T(7) * p2 + T(11) * p1;
 
-    // Jiang-Shu smoothness indicators, accumulated in B
-    const B k13 = B(13) / B(12);
+    // 4 x Jiang-Shu smoothness indicators, (13/3) D^2 + E^2, accumulated in B
+    const B k = B(13) / B(3);
     const B bm2 = B(m2), bm1 = B(m1), bc0 = B(c0), bp1 = B(p1), bp2 = B(p2), bp3 = B(p3);
     B da = bm2 - B(2) * bm1 + bc0;  // second differences centred at j-1, j, j+1, j+2
     B db = bm1 - B(2) * bc0 + bp1;
@@ -99,15 +108,25 @@ __device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T e
     B fa = bp3 - B(4) * bp2 + B(3) * bp1;
     B fb = bp2 - bc0;
     B fc = B(3) * bp1 - B(4) * bc0 + bm1;
-    B bL1 = k13 * da * da + B(0.25) * ea * ea;
-    B bL2 = k13 * db * db + B(0.25) * eb * eb;
-    B bL3 = k13 * dc * dc + B(0.25) * ec * ec;
-    B bR1 = k13 * dd * dd + B(0.25) * fa * fa;
-    B bR2 = k13 * dc * dc + B(0.25) * fb * fb;
-    B bR3 = k13 * db * db + B(0.25) * fc * fc;
+    const B qb = k * db * db, qc = k * dc * dc;  // shared by the two biases
+    B bL1 = k * da * da + ea * ea;
+    B bL2 = qb + eb * eb;
+    B bL3 = qc + ec * ec;
+    B bR1 = k * dd * dd + fa * fa;
+    B bR2 = qc + fb * fb;
+    B bR3 = qb + fc * fc;
 
-    L = weno5_combine<T, B, WZ>(bL1, bL2, bL3, eps, L1, L2, L3);
-    R = weno5_combine<T, B, WZ>(bR1, bR2, bR3, eps, R1, L3, L2);
+    L6 = weno5_combine<T, B, WZ>(bL1, bL2, bL3, eps4, L1, L2, L3);
+    R6 = weno5_combine<T, B, WZ>(bR1, bR2, bR3, eps4, R1, L3, L2);
+}
+
+// the left- and right-biased values themselves
+template <typename T, typename B, bool WZ = false>
+__device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T eps, T &L, T &R) {
+    T L6, R6;
+    weno5_lr6<T, B, WZ>(m2, m1, c0, p1, p2, p3, T(4) * eps, L6, R6);
+    L = L6 * (T(1) / T(6));
+    R = R6 * (T(1) / T(6));
 }
 
 // ---------------------------------------------------------------------------

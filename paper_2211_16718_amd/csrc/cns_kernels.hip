@@ -222,18 +222,19 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
 //   H = (f^L + f^R)/2 - |A| (u^R - u^L)/2 - (-g_{j-1} + 7 g_j + 7 g_{j+1} - g_{j+2})/12
 // ----------------------------------------------------------------------------
 template <typename T, typename B, int DIR, bool VISC, bool WZ>
-__device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5], const T g[4][4], T gamma, T eps,
+__device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5], const T g[4][4], T gamma, T eps4,
                                                T delta, T H[5]) {
+    // six-fold reconstructions (eps4 = 4 eps); D is linear in du, so H = (6 F - 6 D) / 12
     T FL[5], FR[5], UL[5], UR[5], du[5], D[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        weno5_lr<T, B, WZ>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps, FL[v], FR[v]);
-        weno5_lr<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL[v], UR[v]);
+        weno5_lr6<T, B, WZ>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps4, FL[v], FR[v]);
+        weno5_lr6<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps4, UL[v], UR[v]);
         du[v] = UR[v] - UL[v];
     }
     roe_dissipation<T, DIR>(w[2], w[3], du, gamma, delta, D);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) H[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * D[v];
+    for (int v = 0; v < 5; ++v) H[v] = (FL[v] + FR[v] - D[v]) * (T(1) / T(12));
     if constexpr (VISC) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -248,7 +249,7 @@ __device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5],
 // the same order, as interface_flux.
 template <typename T, typename B, int DIR, bool VISC, bool WZ>
 __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ring, const int sl[6], int bdim,
-                                                    const T g[4][4], T gamma, T eps, T delta, T H[5]) {
+                                                    const T g[4][4], T gamma, T eps4, T delta, T H[5]) {
     T Fs[5], du[5], D[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -256,15 +257,15 @@ __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ri
 #pragma unroll
         for (int m = 0; m < 6; ++m) fm[m] = ring[(sl[m] * 5 + v) * bdim];
         T FL, FR, UL, UR;
-        weno5_lr<T, B, WZ>(fm[0], fm[1], fm[2], fm[3], fm[4], fm[5], eps, FL, FR);
-        weno5_lr<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL, UR);
+        weno5_lr6<T, B, WZ>(fm[0], fm[1], fm[2], fm[3], fm[4], fm[5], eps4, FL, FR);
+        weno5_lr6<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps4, UL, UR);
         Fs[v] = FL + FR;
         du[v] = UR - UL;
         __builtin_amdgcn_sched_barrier(0);
     }
     roe_dissipation<T, DIR>(w[2], w[3], du, gamma, delta, D);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) H[v] = T(0.5) * Fs[v] - T(0.5) * D[v];
+    for (int v = 0; v < 5; ++v) H[v] = (Fs[v] - D[v]) * (T(1) / T(12));
     if constexpr (VISC) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
         const size_t n3 = bx.n3;
         const T *u = (const T *)state_ptr(bx, L, L.in);
         const T *G = (const T *)bx.G;
-        const T gamma = T(bx.gamma), eps = T(bx.eps), delta = T(bx.delta);
+        const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
         const double dt = L.dt_ov > 0.0 ? L.dt_ov : bx.dt;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     const int sm = sold + 1 + m;  // slot of point j-2+m (point j+3 is in sold)
                     sl[m] = sm >= 6 ? sm - 6 : sm;
                 }
-                interface_flux_ring<T, B, DIR, VISC, WZ>(w, ring, sl, bdim, g, gamma, eps, delta, H);
+                interface_flux_ring<T, B, DIR, VISC, WZ>(w, ring, sl, bdim, g, gamma, eps4, delta, H);
             }
             if (j >= j0) {
                 if constexpr (MODE == MODE_RK) {
@@ -509,7 +510,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
         T *sf = su + 5 * per;          // [5][per] point fluxes
         T *sg = sf + 5 * per;          // [4][per] viscous fluxes (VISC)
         const size_t n3 = bx.n3;
-        const T gamma = T(bx.gamma), eps = T(bx.eps), delta = T(bx.delta);
+        const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[0]);
         const long long nrows = (long long)bx.ny * bx.nz;
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
                         for (int c = 0; c < 4; ++c) g[m][c] = sg[c * per + q];
                     }
                 }
-                interface_flux<T, B, 0, VISC, WZ>(w, f, g, gamma, eps, delta, H[k]);  // at i+1/2
+                interface_flux<T, B, 0, VISC, WZ>(w, f, g, gamma, eps4, delta, H[k]);  // at i+1/2
             }
         }
         __syncthreads();  // every thread has read the staged states

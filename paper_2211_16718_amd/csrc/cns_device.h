@@ -41,11 +41,32 @@ __device__ __forceinline__ float rcp(float b) {
     return fmaf(r, e, r);
 }
 
+// Reciprocal square root: the hardware estimate refined by Newton-Raphson steps
+// y <- y + y (1 - x y^2) / 2 (two in FP64, one in FP32).
+__device__ __forceinline__ double rsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, r, y);
+}
+__device__ __forceinline__ float rsq(float x) {
+    float y = __builtin_amdgcn_rsqf(x);
+    float r = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, r, y);
+}
+
 template <typename T>
 __device__ __forceinline__ T harten_abs(T lam, T delta) {
     // |lam| if |lam| >= delta, else (lam^2 + delta^2) / (2 delta)  (Harten's entropy fix)
     T a = fabs(lam);
     return (a >= delta) ? a : (lam * lam + delta * delta) / (T(2) * delta);
+}
+// the same with h = 1 / (2 delta) given (no division inside the flux loop)
+template <typename T>
+__device__ __forceinline__ T harten_abs(T lam, T delta, T h) {
+    T a = fabs(lam);
+    return (a >= delta) ? a : (lam * lam + delta * delta) * h;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,21 +176,23 @@ __device__ __forceinline__ void roe_dissipation(const T a[5], const T b[5], cons
                                                 T D[5]) {
     constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
     const T gm1 = gamma - T(1);
-    T ia = rcp(a[0]), ib = rcp(b[0]);
+    // 1/sqrt(rho) gives both sqrt(rho) = rho / sqrt(rho) and 1/rho
+    T ra = rsq(a[0]), rb = rsq(b[0]);
+    T ia = ra * ra, ib = rb * rb;
     T va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
     T vb[3] = {b[1] * ib, b[2] * ib, b[3] * ib};
     T pa = gm1 * (a[4] - T(0.5) * (a[1] * va[0] + a[2] * va[1] + a[3] * va[2]));
     T pb = gm1 * (b[4] - T(0.5) * (b[1] * vb[0] + b[2] * vb[1] + b[3] * vb[2]));
     T Ha = (a[4] + pa) * ia, Hb = (b[4] + pb) * ib;
-    T sa = sqrt(a[0]), sb = sqrt(b[0]);
+    T sa = a[0] * ra, sb = b[0] * rb;
     T iw = rcp(sa + sb);
     T wa = sa * iw, wb = sb * iw;
     T v[3] = {wa * va[0] + wb * vb[0], wa * va[1] + wb * vb[1], wa * va[2] + wb * vb[2]};
     T H = wa * Ha + wb * Hb;
     T q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     T c2 = gm1 * (H - T(0.5) * q2);
-    T c = sqrt(c2);
-    T ic = rcp(c);
+    T ic = rsq(c2);
+    T c = c2 * ic;
     T vn = v[N];
 
     // wave strengths alpha = X^-1 du
@@ -180,7 +203,8 @@ __device__ __forceinline__ void roe_dissipation(const T a[5], const T b[5], cons
     T a1 = (du[0] * (vn + c) - du[1 + N] - c * a2) * (T(0.5) * ic);
     T a5 = du[0] - (a1 + a2);
 
-    T l1 = harten_abs(vn - c, delta), l2 = harten_abs(vn, delta), l5 = harten_abs(vn + c, delta);
+    const T hd = T(0.5) / delta;  // loop invariant
+    T l1 = harten_abs(vn - c, delta, hd), l2 = harten_abs(vn, delta, hd), l5 = harten_abs(vn + c, delta, hd);
     T s1 = l1 * a1, s2 = l2 * a2, s5 = l5 * a5, st1 = l2 * at1, st2 = l2 * at2;
 
     // D = sum_k |lam_k| alpha_k K_k with the right eigenvectors K_k

@@ -300,9 +300,8 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
 // component-major across the block so lanes hit distinct banks), read one component
 // at a time; the registers this frees carry the loads of the next point and of the
 // point's rhs, issued before the interface-flux arithmetic so their latency overlaps
-// it (y sweep 12 % and fused-update sweep 6 % faster than a register window).  u^n
-// and the accumulator of the fused update are still loaded at the point of use:
-// prefetching them too spills.
+// it (y sweep 12 % and fused-update sweep 6 % faster than a register window).  The
+// fused update's u^n and accumulator are loaded ahead in the same way.
 template <typename T, typename B, int DIR, int MODE, bool VISC, bool WZ>
 __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
     extern __shared__ unsigned char lds_raw[];
@@ -387,13 +386,23 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
             }
             if (j < j0 - 1) continue;
 
-            // rhs of point j, loaded before the interface-flux arithmetic
+            // output operands of point j, loaded before the interface-flux arithmetic
             const size_t o = base + (size_t)(j >= j0 ? j : j0) * sg.lstride;
-            T pr[5];
+            T pr[5], pu[5];
+            double pa[5];
             if (MODE != MODE_WRITE && j >= j0) {
                 const T *rhs = (const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs));
 #pragma unroll
                 for (int v = 0; v < 5; ++v) pr[v] = rhs[v * n3 + o];
+                if (MODE == MODE_RK && L.stage >= 2) {
+                    const T *un = (const T *)state_ptr(bx, L, BUF_U);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) pu[v] = un[v * n3 + o];
+                    if (L.scheme != CNS_TVDRK3) {
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) pa[v] = bx.acc[v * n3 + o];
+                    }
+                }
             }
 
             T H[5];
@@ -424,7 +433,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                             if (L.stage == 1) {
                                 unext[e] = T(us + dt * k);
                             } else {
-                                const double uo = double(un[e]);
+                                const double uo = double(pu[v]);
                                 if (L.stage == 2) unext[e] = T(0.75 * uo + 0.25 * (us + dt * k));
                                 else unext[e] = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
                             }
@@ -432,15 +441,15 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                             acc[e] = us + (dt / 6.0) * k;
                             unext[e] = T(us + (0.5 * dt) * k);
                         } else if (L.stage == 2) {
-                            const double uo = double(un[e]);
-                            acc[e] += (dt / 3.0) * k;
+                            const double uo = double(pu[v]);
+                            acc[e] = pa[v] + (dt / 3.0) * k;
                             unext[e] = T(uo + (0.5 * dt) * k);
                         } else if (L.stage == 3) {
-                            const double uo = double(un[e]);
-                            acc[e] += (dt / 3.0) * k;
+                            const double uo = double(pu[v]);
+                            acc[e] = pa[v] + (dt / 3.0) * k;
                             unext[e] = T(uo + dt * k);
                         } else {
-                            unext[e] = T(acc[e] + (dt / 6.0) * k);
+                            unext[e] = T(pa[v] + (dt / 6.0) * k);
                         }
                     }
                 } else {

@@ -254,3 +254,31 @@ def test_vortex_one_period_converges():
     order = math.log2(errs[0] / errs[1])
     print(f"vortex observed order {order:.2f}")
     assert order > 3.0 and errs[1] < 2e-3
+
+
+@pytest.mark.parametrize("shape,precision", [((8, 9, 320), "fp64"), ((8, 8, 580), "fp64"), ((8, 8, 600), "fp64"),
+                                             ((8, 9, 600), "mixed")])
+def test_long_rows(orc, shape, precision):
+    # 320- and 580-point FP64 rows: two and three points per thread in the rows kernel;
+    # 600-point FP64 rows do not fit in LDS, so the x sweep marches; 600-point FP32
+    # rows: three points per thread
+    case(f"long rows {shape} {precision}")
+    plan, ph, rho, vel, p = setup(orc, shape, mu=0.02, kind="smooth", precision=precision)
+    u_ref = orc.init_state(rho, vel, p)
+    u = plan.init_state(rho, vel, p)
+    r_ref = orc.rhs(u_ref, ph)
+    err = rel_max(plan.rhs(u).double().cpu().numpy(), r_ref)
+    if precision == "fp64":
+        tol, tol_rk = 1e-12, 1e-11
+    else:
+        # FP32 rounding of the point values, amplified by the 1/h of the differences:
+        # about 2^-24 max|u| / (h_min max|rhs|), with a factor 100 for the stencil weights
+        h = 2 * math.pi / max(shape)
+        tol = 100 * 2.0 ** -24 * np.abs(u_ref).max() / (h * np.abs(r_ref).max())
+        tol_rk = 2e-6
+    print(f"rhs rel err {err:.3e} (bound {tol:.1e})")
+    assert err <= tol
+    dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], max(shape))
+    plan.rk4(u, dt, 2)
+    uf, _ = orc.rk4(u_ref, dt, 2, ph, with_diag=False)
+    assert rel_max(u.double().cpu().numpy(), uf) <= tol_rk

@@ -273,6 +273,42 @@ __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ri
     }
 }
 
+// The same interface flux with every operand read from the rows kernel's LDS staging
+// (component-major arrays of `per` points; q[m] is the position of point i-2+m), one
+// component at a time behind a scheduling fence, so that the reconstruction holds
+// only the operands of the component in flight.
+template <typename T, typename B, bool VISC, bool WZ>
+__device__ __forceinline__ void interface_flux_lds(const T *su, const T *sf, const T *sg, int per, const int q[6],
+                                                   T gamma, T eps4, T delta, T H[5]) {
+    T Fs[5], du[5], D[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const T *fv = sf + v * per, *uv = su + v * per;
+        T FL, FR, UL, UR;
+        weno5_lr6<T, B, WZ>(fv[q[0]], fv[q[1]], fv[q[2]], fv[q[3]], fv[q[4]], fv[q[5]], eps4, FL, FR);
+        weno5_lr6<T, B, WZ>(uv[q[0]], uv[q[1]], uv[q[2]], uv[q[3]], uv[q[4]], uv[q[5]], eps4, UL, UR);
+        Fs[v] = FL + FR;
+        du[v] = UR - UL;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    T a[5], b[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        a[v] = su[v * per + q[2]];
+        b[v] = su[v * per + q[3]];
+    }
+    roe_dissipation<T, 0>(a, b, du, gamma, delta, D);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) H[v] = (Fs[v] - D[v]) * (T(1) / T(12));
+    if constexpr (VISC) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const T *gc = sg + c * per;
+            H[1 + c] -= (T(7) * (gc[q[2]] + gc[q[3]]) - (gc[q[1]] + gc[q[4]])) * (T(1) / T(12));
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // marching WENO5-Roe sweep along one direction
 // ----------------------------------------------------------------------------
@@ -569,25 +605,10 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
             const int t = threadIdx.x + k * kRowThreads;
             if (t < nact) {
                 const int r = t / nx, i = t - r * nx, rb = r * nx;
-                T w[6][5], f[6][5], g[4][4];
+                int q[6];
 #pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    const int q = rb + wrapi(i - 2 + m, nx);
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) {
-                        w[m][v] = su[v * per + q];
-                        f[m][v] = sf[v * per + q];
-                    }
-                }
-                if constexpr (VISC) {
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int q = rb + wrapi(i - 1 + m, nx);
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) g[m][c] = sg[c * per + q];
-                    }
-                }
-                interface_flux<T, B, 0, VISC, WZ>(w, f, g, gamma, eps4, delta, H[k]);  // at i+1/2
+                for (int m = 0; m < 6; ++m) q[m] = rb + wrapi(i - 2 + m, nx);
+                interface_flux_lds<T, B, VISC, WZ>(su, sf, sg, per, q, gamma, eps4, delta, H[k]);  // at i+1/2
             }
         }
         __syncthreads();  // every thread has read the staged states

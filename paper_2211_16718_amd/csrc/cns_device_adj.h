@@ -6,11 +6,11 @@
 
 namespace cns {
 
-// d|lam|_H / d lam of Harten's fix (0 at lam = 0 when delta = 0)
-__device__ __forceinline__ double harten_dabs(double lam, double delta) {
-    const double a = fabs(lam);
-    if (a >= delta) return lam > 0.0 ? 1.0 : (lam < 0.0 ? -1.0 : 0.0);
-    return lam / delta;
+// d|lam|_H / d lam of Harten's fix (0 at lam = 0 when delta = 0); idelta = 1/delta.
+// Written with selects, no branches.
+__device__ __forceinline__ double harten_dabs(double lam, double delta, double idelta) {
+    const double sgn = lam > 0.0 ? 1.0 : (lam < 0.0 ? -1.0 : 0.0);
+    return fabs(lam) >= delta ? sgn : lam * idelta;
 }
 
 // ---------------------------------------------------------------------------
@@ -35,28 +35,30 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
     const double t1 = eps + (k13 * dd * dd + 0.25 * fa * fa);
     const double t2 = eps + (k13 * dc * dc + 0.25 * fb * fb);
     const double t3 = eps + (k13 * db * db + 0.25 * fc * fc);
+    // reciprocals by refined hardware estimates (rcp), no IEEE division sequences
+    const double is1 = rcp(s1), is2 = rcp(s2), is3 = rcp(s3), it1 = rcp(t1), it2 = rcp(t2), it3 = rcp(t3);
     // left weights and value
     double d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
     double a1 = 0.1 * (d2 * d3), a2 = 0.6 * (d1 * d3), a3 = 0.3 * (d1 * d2);
-    double iS = 1.0 / (a1 + a2 + a3);
+    double iS = rcp(a1 + a2 + a3);
     const double w1 = a1 * iS, w2 = a2 * iS, w3 = a3 * iS;
     const double L = w1 * L1 + w2 * L2 + w3 * L3;
     // right weights and value
     d1 = t1 * t1, d2 = t2 * t2, d3 = t3 * t3;
     a1 = 0.1 * (d2 * d3), a2 = 0.6 * (d1 * d3), a3 = 0.3 * (d1 * d2);
-    iS = 1.0 / (a1 + a2 + a3);
+    iS = rcp(a1 + a2 + a3);
     const double v1 = a1 * iS, v2 = a2 * iS, v3 = a3 * iS;
     const double R = v1 * R1 + v2 * L3 + v3 * L2;
 
     // candidates
     const double cL1 = Lb * w1, cL2 = Lb * w2 + Rb * v3, cL3 = Lb * w3 + Rb * v2, cR1 = Rb * v1;
     // indicators
-    const double bL1 = -2.0 * Lb * w1 * (L1 - L) / s1;
-    const double bL2 = -2.0 * Lb * w2 * (L2 - L) / s2;
-    const double bL3 = -2.0 * Lb * w3 * (L3 - L) / s3;
-    const double bR1 = -2.0 * Rb * v1 * (R1 - R) / t1;
-    const double bR2 = -2.0 * Rb * v2 * (L3 - R) / t2;
-    const double bR3 = -2.0 * Rb * v3 * (L2 - R) / t3;
+    const double bL1 = -2.0 * Lb * w1 * (L1 - L) * is1;
+    const double bL2 = -2.0 * Lb * w2 * (L2 - L) * is2;
+    const double bL3 = -2.0 * Lb * w3 * (L3 - L) * is3;
+    const double bR1 = -2.0 * Rb * v1 * (R1 - R) * it1;
+    const double bR2 = -2.0 * Rb * v2 * (L3 - R) * it2;
+    const double bR3 = -2.0 * Rb * v3 * (L2 - R) * it3;
     const double dab = 2.0 * k13 * da * bL1, eab = 0.5 * ea * bL1;
     const double dbb = 2.0 * k13 * db * (bL2 + bR3), ebb = 0.5 * eb * bL2, fcb = 0.5 * fc * bR3;
     const double dcb = 2.0 * k13 * dc * (bL3 + bR2), ecb = 0.5 * ec * bL3, fbb = 0.5 * fb * bR2;
@@ -74,7 +76,7 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
 // component v of the convective flux along DIR
 template <int DIR>
 __device__ __forceinline__ double euler_flux_comp(const double w[5], double gm1, int v) {
-    const double inv = 1.0 / w[0];
+    const double inv = rcp(w[0]);
     const double vn = w[1 + DIR] * inv;
     if (v == 0) return w[1 + DIR];
     const double p = gm1 * (w[4] - 0.5 * (w[1] * (w[1] * inv) + w[2] * (w[2] * inv) + w[3] * (w[3] * inv)));
@@ -85,7 +87,7 @@ __device__ __forceinline__ double euler_flux_comp(const double w[5], double gm1,
 // wb += (df/dw)^T fb for the convective flux along DIR (the Euler flux Jacobian)
 template <int DIR>
 __device__ __forceinline__ void euler_flux_vjp(const double w[5], double gm1, const double fb[5], double wb[5]) {
-    const double inv = 1.0 / w[0];
+    const double inv = rcp(w[0]);
     const double v[3] = {w[1] * inv, w[2] * inv, w[3] * inv};
     const double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     const double p = gm1 * (w[4] - 0.5 * w[0] * q2);
@@ -136,15 +138,16 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
     const double gm1 = gamma - 1.0;
     // ---- forward recompute
-    const double ia = 1.0 / a[0], ib = 1.0 / b[0];
+    const double ra = rsq(a[0]), rb = rsq(b[0]);
+    const double ia = ra * ra, ib = rb * rb;
     const double va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
     const double vb[3] = {b[1] * ib, b[2] * ib, b[3] * ib};
     const double qa = a[1] * va[0] + a[2] * va[1] + a[3] * va[2];
     const double qb = b[1] * vb[0] + b[2] * vb[1] + b[3] * vb[2];
     const double pa = gm1 * (a[4] - 0.5 * qa), pb = gm1 * (b[4] - 0.5 * qb);
     const double Ha = (a[4] + pa) * ia, Hb = (b[4] + pb) * ib;
-    const double sa = sqrt(a[0]), sb = sqrt(b[0]);
-    const double iw = 1.0 / (sa + sb);
+    const double sa = a[0] * ra, sb = b[0] * rb;
+    const double iw = rcp(sa + sb);
     const double wa = sa * iw, wb = sb * iw;
     double v[3];
 #pragma unroll
@@ -152,17 +155,19 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     const double H = wa * Ha + wb * Hb;
     const double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     const double c2 = gm1 * (H - 0.5 * q2);
-    const double c = sqrt(c2);
+    const double ic = rsq(c2);
+    const double c = c2 * ic, ic2 = ic * ic;
     const double vn = v[N];
     const double at1 = du[1 + T1] - v[T1] * du[0];
     const double at2 = du[1 + T2] - v[T2] * du[0];
     const double dEb = du[4] - at1 * v[T1] - at2 * v[T2];
     const double X = du[0] * (H - vn * vn) + vn * du[1 + N] - dEb;
-    const double a2 = gm1 / c2 * X;
+    const double a2 = gm1 * ic2 * X;
     const double num = du[0] * (vn + c) - du[1 + N] - c * a2;
-    const double a1 = num / (2.0 * c);
+    const double a1 = num * (0.5 * ic);
     const double a5 = du[0] - (a1 + a2);
-    const double l1 = harten_abs(vn - c, delta), l2 = harten_abs(vn, delta), l5 = harten_abs(vn + c, delta);
+    const double hd = 0.5 / delta, idelta = 1.0 / delta;  // loop invariant
+    const double l1 = harten_abs(vn - c, delta, hd), l2 = harten_abs(vn, delta, hd), l5 = harten_abs(vn + c, delta, hd);
     const double s1 = l1 * a1, s2 = l2 * a2, s5 = l5 * a5, st1 = l2 * at1, st2 = l2 * at2;
     const double ssum = s1 + s2 + s5;
 
@@ -201,9 +206,9 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     const double l1b = s1b * a1, l2b = s2b * a2 + st1b * at1 + st2b * at2, l5b = s5b * a5;
     double a1b = s1b * l1, a2b = s2b * l2, a5b = s5b * l5, at1b = st1b * l2, at2b = st2b * l2;
     {
-        const double x1 = l1b * harten_dabs(vn - c, delta);
-        const double x5 = l5b * harten_dabs(vn + c, delta);
-        vnb += x1 + l2b * harten_dabs(vn, delta) + x5;
+        const double x1 = l1b * harten_dabs(vn - c, delta, idelta);
+        const double x5 = l5b * harten_dabs(vn + c, delta, idelta);
+        vnb += x1 + l2b * harten_dabs(vn, delta, idelta) + x5;
         cb += x5 - x1;
     }
     // a5 = du0 - (a1 + a2)
@@ -211,8 +216,8 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     a1b -= a5b;
     a2b -= a5b;
     // a1 = num / (2c)
-    const double numb = a1b / (2.0 * c);
-    cb -= a1b * a1 / c;
+    const double numb = a1b * (0.5 * ic);
+    cb -= a1b * a1 * ic;
     dub[0] += numb * (vn + c);
     vnb += numb * du[0];
     cb += numb * du[0];
@@ -220,8 +225,8 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     cb -= numb * a2;
     a2b -= numb * c;
     // a2 = gm1/c2 X
-    const double Xb = a2b * gm1 / c2;
-    double c2b = -a2b * a2 / c2;
+    const double Xb = a2b * gm1 * ic2;
+    double c2b = -a2b * a2 * ic2;
     // X = du0 (H - vn^2) + vn du_n - dEb
     dub[0] += Xb * (H - vn * vn);
     Hbar += Xb * du[0];
@@ -243,7 +248,7 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     dub[0] -= at2b * v[T2];
     vbar[N] += vnb;
     // c = sqrt(c2); c2 = gm1 (H - q2/2); q2 = |v|^2
-    c2b += cb / (2.0 * c);
+    c2b += cb * (0.5 * ic);
     Hbar += c2b * gm1;
     q2b -= 0.5 * gm1 * c2b;
 #pragma unroll
@@ -275,7 +280,7 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
             ab[1 + k] += qab * va[k] + vk * ia;
             iab += vk * a[1 + k];
         }
-        ab[0] += -iab * ia * ia + sab / (2.0 * sa);
+        ab[0] += -iab * ia * ia + sab * (0.5 * ra);  // d sqrt(rho)/d rho = 1/(2 sqrt(rho))
     }
     {
         const double pbb = Hbb * ib;
@@ -288,7 +293,7 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
             bb[1 + k] += qbb * vb[k] + vk * ib;
             ibb += vk * b[1 + k];
         }
-        bb[0] += -ibb * ib * ib + sbb / (2.0 * sb);
+        bb[0] += -ibb * ib * ib + sbb * (0.5 * rb);
     }
 }
 

@@ -28,6 +28,13 @@
 namespace cns {
 
 __device__ __forceinline__ int wrapi(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
+// the same for any j >= -n (tile halos can reach several periods past a short line);
+// the division only runs for lines shorter than the halo
+__device__ __forceinline__ int wrapm(int j, int n) {
+    int r = j < 0 ? j + n : j;
+    r = r >= n ? r - n : r;
+    return r >= n ? r % n : r;
+}
 
 // box owning virtual block vb: the last i with off[i] <= vb
 __device__ __forceinline__ int find_box(const long long *off, int nbox, long long vb) {
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
             prim_at(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4]);
             for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
                 const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
-                const size_t p = (size_t)k * sz + (size_t)wrapi(y0 - 2 + hy, ny) * nx + wrapi(x0 - 2 + hx, nx);
+                const size_t p = (size_t)k * sz + (size_t)wrapm(y0 - 2 + hy, ny) * nx + wrapm(x0 - 2 + hx, nx);
                 T w4[4];
                 prim_at(u, n3, p, gamma, w4);
 #pragma unroll
@@ -277,7 +284,7 @@ __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ri
 // (component-major arrays of `per` points; q[m] is the position of point i-2+m), one
 // component at a time behind a scheduling fence, so that the reconstruction holds
 // only the operands of the component in flight.
-template <typename T, typename B, bool VISC, bool WZ>
+template <typename T, typename B, int DIR, bool VISC, bool WZ>
 __device__ __forceinline__ void interface_flux_lds(const T *su, const T *sf, const T *sg, int per, const int q[6],
                                                    T gamma, T eps4, T delta, T H[5]) {
     T Fs[5], du[5], D[5];
@@ -297,7 +304,7 @@ __device__ __forceinline__ void interface_flux_lds(const T *su, const T *sf, con
         a[v] = su[v * per + q[2]];
         b[v] = su[v * per + q[3]];
     }
-    roe_dissipation<T, 0>(a, b, du, gamma, delta, D);
+    roe_dissipation<T, DIR>(a, b, du, gamma, delta, D);
 #pragma unroll
     for (int v = 0; v < 5; ++v) H[v] = (Fs[v] - D[v]) * (T(1) / T(12));
     if constexpr (VISC) {
@@ -608,7 +615,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
                 int q[6];
 #pragma unroll
                 for (int m = 0; m < 6; ++m) q[m] = rb + wrapi(i - 2 + m, nx);
-                interface_flux_lds<T, B, VISC, WZ>(su, sf, sg, per, q, gamma, eps4, delta, H[k]);  // at i+1/2
+                interface_flux_lds<T, B, 0, VISC, WZ>(su, sf, sg, per, q, gamma, eps4, delta, H[k]);  // at i+1/2
             }
         }
         __syncthreads();  // every thread has read the staged states
@@ -726,7 +733,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
                 for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
                     const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
                     double v3[3];
-                    vel_at(u, n3, (size_t)k * sz + (size_t)wrapi(y0 - 2 + hy, ny) * nx + wrapi(x0 - 2 + hx, nx), v3);
+                    vel_at(u, n3, (size_t)k * sz + (size_t)wrapm(y0 - 2 + hy, ny) * nx + wrapm(x0 - 2 + hx, nx), v3);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) pv[c][hy][hx] = v3[c];
                 }

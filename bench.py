@@ -368,6 +368,12 @@ def bench_options(n=128, steps=20):
     pz.rk4(pz.empty_state().copy_(uz), dt, 1, diag=False)
     sec, _ = _timed(pz.stream, lambda: pz.rk4(uz, dt, steps))
     out["rk4_wenoz"] = {"value": 4.0 * n ** 3 * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps}
+    # the RHS alone (cns_rhs: viscous fluxes and the three sweeps, no stage update)
+    r = plan.empty_state()
+    plan.rhs(u, r)
+    reps = 20
+    sec, _ = _timed(plan.stream, lambda: [plan.rhs(u, r) for _ in range(reps)])
+    out["rhs_only"] = {"value": n ** 3 * reps / sec, "unit": "point-RHS/s", "ms": sec * 1e3 / reps}
     plan.spectrum(u)  # warm
     reps = 5
     sec, (E, mom) = _timed(plan.stream, lambda: [plan.spectrum(u) for _ in range(reps)][-1])

@@ -4,9 +4,9 @@
 // (dR/du)^T rbar of the semi-discrete operator R(u) = -sum_d (H_{j+1/2} - H_{j-1/2})/dx_d
 // + sum_d D_d G^v_d is assembled as
 //   convective part, per direction d:  Hbar_{j+1/2} = (rbar_{j+1} - rbar_j)/dx_d;
-//     k_adj_iface<d>: one thread per interface forms the local product of the
-//     interface flux (30 contributions to the six cells it reads) into C;
-//     k_adj_gather<d>: one thread per point sums the six contributions it receives;
+//     k_adj_conv<d>: one thread per interface forms the local product of the
+//     interface flux (30 contributions to the six cells it reads) and adds them,
+//     in a fixed order, into LDS accumulators of the cells, which are then written;
 //   viscous part: the adjoint of a central difference is minus the same central
 //     difference, so Gbar_d = -D_d rbar; k_adj_visc1 maps it through the viscous
 //     fluxes to the adjoints of the velocity/temperature gradients and of the
@@ -51,54 +51,134 @@ __device__ __forceinline__ size_t shift_idx(const AdjGeom &g, int i, int j, int 
     return ((size_t)k * g.ny + j) * g.nx + i;
 }
 
-template <int DIR>
-__global__ __launch_bounds__(256) void k_adj_iface(AdjGeom g, const double *__restrict__ u,
-                                                   const double *__restrict__ rbar, double *__restrict__ C) {
-    const size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (p >= g.n3) return;
-    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
-    const size_t n3 = g.n3;
-    double w[6][5];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        const size_t q = shift_idx(g, i, j, k, DIR, m - 2);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) w[m][v] = u[v * n3 + q];
-    }
-    const size_t pn = shift_idx(g, i, j, k, DIR, 1);
-    double Hb[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Hb[v] = (rbar[v * n3 + pn] - rbar[v * n3 + p]) * g.ih[DIR];
-    double wb[6][5];
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) wb[m][v] = 0.0;
-    interface_flux_vjp<DIR>(w, Hb, g.gamma, g.eps, g.delta, wb);
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) C[(size_t)(m * 5 + v) * n3 + p] = wb[m][v];
-}
+// ---------------------------------------------------------------------------
+// Convective adjoint along DIR, fused with the gather: ubar(=|+=) sum over the six
+// interfaces that read each cell of their contributions.
+//
+// A block of TA x TB = 256 threads owns TB whole periodic lines along DIR and marches
+// along them in chunks of TA interfaces.  Each thread forms the product of one
+// interface (j+1/2, cells j-2 .. j+3), then adds its contributions to an LDS ring of
+// cell accumulators in six phases: in phase m every thread adds the contribution to
+// its cell j+m-2, so within a phase no two threads touch one cell, and the order of
+// the additions into every cell is fixed (deterministic, no atomics).
+//
+// Cells are indexed along the line without wrapping, e = -2 .. n+2; e and e+n are
+// the same grid cell.  After the chunk with interfaces I .. I+TA-1 the cells up to
+// I+TA-3 are complete: cells 3 .. n-3 are written out, and the partial sums of cells
+// -2 .. 2 are set aside ("head") until the last chunk adds the rest of those five
+// grid cells (e = n-2 .. n+2).  The ring holds RS >= 2 TA + 5 cells: the cells being
+// written out after one chunk and the cells touched by the next never share a slot,
+// so no barrier separates them, and a slot is cleared as soon as its cell is out.
+// x: TA = 64 lanes along the row, TB = 4 rows; y, z: TA = 8 along the line, TB = 32
+// lanes across x (coalesced loads and stores in every direction).
+// ---------------------------------------------------------------------------
+template <int DIR> struct AdjConvShape;
+template <> struct AdjConvShape<0> { static constexpr int TA = 64, TB = 4, RS = 256; };
+template <> struct AdjConvShape<1> { static constexpr int TA = 8, TB = 32, RS = 32; };
+template <> struct AdjConvShape<2> { static constexpr int TA = 8, TB = 32, RS = 32; };
 
-// ubar(p) (=|+=) sum_m C[m](p - (m - 2) e_d): point p is cell m of the interface at p-(m-2)
 template <int DIR>
-__global__ __launch_bounds__(256) void k_adj_gather(AdjGeom g, const double *__restrict__ C, double *__restrict__ ubar,
-                                                    int accumulate) {
-    const size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (p >= g.n3) return;
-    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
+__global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__restrict__ u,
+                                                     const double *__restrict__ rbar, double *__restrict__ ubar,
+                                                     int accumulate) {
+    using S = AdjConvShape<DIR>;
+    constexpr int TA = S::TA, TB = S::TB, RS = S::RS;
+    __shared__ double ring[TB * 5 * RS];
+    __shared__ double head[TB * 25];
+    // lane roles: ta along the line, tb across lines; lanes are consecutive in x
+    const int ta = DIR == 0 ? (int)threadIdx.x % TA : (int)threadIdx.x / TB;
+    const int tb = DIR == 0 ? (int)threadIdx.x / TA : (int)threadIdx.x % TB;
+    // ring slot of cell e for component v (conflict-free for the phase pattern)
+    auto slot = [&](int e, int v) -> int {
+        const int r = (e + 2) & (RS - 1);
+        return DIR == 0 ? (tb * 5 + v) * RS + r : (r * 5 + v) * TB + tb;
+    };
     const size_t n3 = g.n3;
-    size_t src[6];
+    int n;
+    size_t base, stride;
+    bool lane_ok;
+    if (DIR == 0) {
+        const size_t row = (size_t)blockIdx.x * TB + tb;
+        lane_ok = row < (size_t)g.ny * g.nz;
+        n = g.nx;
+        base = lane_ok ? row * g.nx : 0;
+        stride = 1;
+    } else {
+        const int ntx = (g.nx + TB - 1) / TB;
+        const int xt = (int)(blockIdx.x % ntx), o = (int)(blockIdx.x / ntx);
+        const int x = xt * TB + tb;
+        lane_ok = x < g.nx;
+        const int xs = lane_ok ? x : 0;
+        if (DIR == 1) {
+            n = g.ny;
+            base = (size_t)o * g.nx * g.ny + xs;
+            stride = (size_t)g.nx;
+        } else {
+            n = g.nz;
+            base = (size_t)o * g.nx + xs;
+            stride = (size_t)g.nx * g.ny;
+        }
+    }
+    const double ih = g.ih[DIR];
+    for (int t = threadIdx.x; t < TB * 5 * RS; t += 256) ring[t] = 0.0;
+    __syncthreads();
+    int I = 0;
+    for (;; I += TA) {
+        const int j = I + ta;
+        const bool act = lane_ok && j < n;
+        double wb[6][5];
+        if (act) {
+            size_t c[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) src[m] = shift_idx(g, i, j, k, DIR, 2 - m);
+            for (int m = 0; m < 6; ++m) c[m] = base + (size_t)wrapj(j + m - 2, n) * stride;
+            const size_t pn = base + (size_t)wrapj(j + 1, n) * stride, p = c[2];
+            double Hb[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        double s = 0.0;
+            for (int v = 0; v < 5; ++v) Hb[v] = (rbar[v * n3 + pn] - rbar[v * n3 + p]) * ih;
+            interface_flux_vjp<DIR>(u, n3, c, Hb, g.gamma, g.eps, g.delta, wb);
+        }
 #pragma unroll
-        for (int m = 0; m < 6; ++m) s += C[(size_t)(m * 5 + v) * n3 + src[m]];
-        if (accumulate) ubar[v * n3 + p] += s;
-        else ubar[v * n3 + p] = s;
+        for (int m = 0; m < 6; ++m) {
+            if (act) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) ring[slot(j + m - 2, v)] += wb[m][v];
+            }
+            __syncthreads();
+        }
+        const bool last = I + TA >= n;
+        const int e = I - 2 + ta;  // completed by this chunk (all of them unless last)
+        if (lane_ok && e <= 2) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) head[tb * 25 + (e + 2) * 5 + v] = ring[slot(e, v)];
+        } else if (lane_ok && !last && e <= n - 3) {
+            const size_t q = base + (size_t)e * stride;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double s = ring[slot(e, v)];
+                if (accumulate) ubar[v * n3 + q] += s;
+                else ubar[v * n3 + q] = s;
+            }
+        }
+        if (!last) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) ring[slot(e, v)] = 0.0;
+        } else {
+            break;
+        }
+    }
+    __syncthreads();
+    // the rest of the line: cells max(I-2, 3) .. n+2, folding e >= n-2 with the head
+    for (int e = I - 2 + ta; e <= n + 2; e += TA) {
+        if (!lane_ok || e < 3) continue;
+        const int r = e >= n ? e - n : e;
+        const size_t q = base + (size_t)r * stride;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double s = ring[slot(e, v)];
+            if (e >= n - 2) s += head[tb * 25 + (e - n + 2) * 5 + v];
+            if (accumulate) ubar[v * n3 + q] += s;
+            else ubar[v * n3 + q] = s;
+        }
     }
 }
 
@@ -263,13 +343,6 @@ __global__ void k_accum(size_t n, const double *__restrict__ x, double *__restri
     if (i < n) out[i] += x[i];
 }
 
-// out = u + c k (an RK4 stage state, same arithmetic as the fused stage update)
-__global__ void k_stage(size_t n, double c, const double *__restrict__ u, const double *__restrict__ k,
-                        double *__restrict__ out) {
-    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = u[i] + c * k[i];
-}
-
 __global__ void k_copy(size_t n, const double *__restrict__ x, double *__restrict__ out) {
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (i < n) out[i] = x[i];
@@ -305,18 +378,18 @@ __global__ void k_ic_vjp(size_t n3, const double *__restrict__ rho, const double
 static inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *W,
-                 double *C, double *Gb) {
+                 double *Gb) {
     const AdjGeom g = adj_geom(b);
     const size_t n3 = b.n3;
     const bool visc = b.mu > 0.0;
     if (visc) hipLaunchKernelGGL(k_adj_prim, grid1(n3), dim3(256), 0, s, g, u, W);
     if (visc) hipLaunchKernelGGL(k_adj_visc1, grid1(n3), dim3(256), 0, s, g, (const double *)W, rbar, Gb);
-    hipLaunchKernelGGL(k_adj_iface<0>, grid1(n3), dim3(256), 0, s, g, u, rbar, C);
-    hipLaunchKernelGGL(k_adj_gather<0>, grid1(n3), dim3(256), 0, s, g, (const double *)C, ubar, 0);
-    hipLaunchKernelGGL(k_adj_iface<1>, grid1(n3), dim3(256), 0, s, g, u, rbar, C);
-    hipLaunchKernelGGL(k_adj_gather<1>, grid1(n3), dim3(256), 0, s, g, (const double *)C, ubar, 1);
-    hipLaunchKernelGGL(k_adj_iface<2>, grid1(n3), dim3(256), 0, s, g, u, rbar, C);
-    hipLaunchKernelGGL(k_adj_gather<2>, grid1(n3), dim3(256), 0, s, g, (const double *)C, ubar, 1);
+    // blocks: x, TB = 4 rows each; y, z: one 32-wide x tile of the lines at one z (y) each
+    const unsigned bx = (unsigned)(((size_t)b.ny * b.nz + 3) / 4);
+    const unsigned ntx = (unsigned)((b.nx + 31) / 32);
+    hipLaunchKernelGGL(k_adj_conv<0>, dim3(bx), dim3(256), 0, s, g, u, rbar, ubar, 0);
+    hipLaunchKernelGGL(k_adj_conv<1>, dim3(ntx * (unsigned)b.nz), dim3(256), 0, s, g, u, rbar, ubar, 1);
+    hipLaunchKernelGGL(k_adj_conv<2>, dim3(ntx * (unsigned)b.ny), dim3(256), 0, s, g, u, rbar, ubar, 1);
     if (visc) hipLaunchKernelGGL(k_adj_visc2, grid1(n3), dim3(256), 0, s, g, u, (const double *)Gb, ubar);
 }
 
@@ -325,9 +398,6 @@ void adj_lincomb(size_t n, double a, const double *x, double b, const double *y,
 }
 void adj_accum(size_t n, const double *x, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_accum, grid1(n), dim3(256), 0, s, n, x, out);
-}
-void adj_stage(size_t n, double c, const double *u, const double *k, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage, grid1(n), dim3(256), 0, s, n, c, u, k, out);
 }
 void adj_copy(size_t n, const double *x, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, grid1(n), dim3(256), 0, s, n, x, out);

@@ -754,7 +754,7 @@ int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t 
 // adjoint (FP64, single box): workspace layout and the checkpointed reverse RK4
 // ----------------------------------------------------------------------------
 struct AdjLayout {
-    size_t ck, seg, st, X, ub, kb, Ub, S, W, C, Gb, rec, total;
+    size_t ck, seg, X, ub, kb, Ub, S, W, Gb, rec, total;
     int nck, K;
 };
 
@@ -766,10 +766,8 @@ static AdjLayout adj_layout(size_t n3, int nsteps, int K) {
     size_t off = 0;
     L.ck = off;                      // checkpoints: state at steps 0, K, 2K, ...
     off += (size_t)L.nck * st;
-    L.seg = off;                     // step-start states of one segment
-    off += (size_t)(nsteps > 0 ? std::min(L.K, nsteps) : 0) * st;
-    L.st = off;                      // stage states U2, U3, U4
-    off += 3 * st;
+    L.seg = off;                     // per step of one segment: step-start state, stage states U2, U3, U4
+    off += (size_t)(nsteps > 0 ? std::min(L.K, nsteps) : 0) * 4 * st;
     L.X = off;                       // running state
     off += st;
     L.ub = off;                      // running adjoint
@@ -782,8 +780,6 @@ static AdjLayout adj_layout(size_t n3, int nsteps, int K) {
     off += st;
     L.W = off;                       // primitives at the linearisation point
     off += align256(4 * n3 * sizeof(double));
-    L.C = off;                       // per-interface contributions [30][n3]
-    off += align256(30 * n3 * sizeof(double));
     L.Gb = off;                      // viscous adjoint fields [15][n3]
     off += align256(15 * n3 * sizeof(double));
     L.rec = off;                     // a diagnostics record
@@ -820,7 +816,7 @@ int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *uba
     if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
     char *w = (char *)adj_ws;
     adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.W),
-                (double *)(w + L.C), (double *)(w + L.Gb));
+                (double *)(w + L.Gb));
     return check_hip("rhs_vjp");
 }
 
@@ -844,8 +840,7 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
     const size_t st = align256(n5 * sizeof(double));
     auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
     double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
-    double *U2 = state(L.st, 0), *U3 = state(L.st, 1), *U4 = state(L.st, 2);
-    double *W = (double *)(w + L.W), *C = (double *)(w + L.C), *Gb = (double *)(w + L.Gb), *rec = (double *)(w + L.rec);
+    double *W = (double *)(w + L.W), *Gb = (double *)(w + L.Gb), *rec = (double *)(w + L.rec);
     hipStream_t s = c.stream;
     Batch bt = c.batch();
     bt.prof = nullptr;
@@ -864,33 +859,31 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
     // reverse, one checkpoint segment at a time (last first)
     for (int sg = L.nck - 1; sg >= 0; --sg) {
         const int n0 = sg * K, n1 = std::min(nsteps, n0 + K);
+        // recompute the segment, keeping every step-start state and the stage states
+        // U2, U3, U4 the fused step writes (the last step's result is not needed)
         adj_copy(n5, state(L.ck, sg), X, s);
         for (int n = n0; n < n1; ++n) {
-            adj_copy(n5, X, state(L.seg, n - n0), s);
-            if (n + 1 < n1) launch_rk4_step(bt, X, dt, nullptr, 0, 0);
+            adj_copy(n5, X, state(L.seg, 4 * (n - n0)), s);
+            void *const st3[3] = {state(L.seg, 4 * (n - n0) + 1), state(L.seg, 4 * (n - n0) + 2),
+                                  state(L.seg, 4 * (n - n0) + 3)};
+            launch_rk4_step(bt, X, dt, nullptr, 0, 0, st3);
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            const double *Y = state(L.seg, n - n0);
-            // stage states of step n
-            launch_rhs(bt, Y, kb);
-            adj_stage(n5, 0.5 * dt, Y, kb, U2, s);
-            launch_rhs(bt, U2, kb);
-            adj_stage(n5, 0.5 * dt, Y, kb, U3, s);
-            launch_rhs(bt, U3, kb);
-            adj_stage(n5, dt, Y, kb, U4, s);
+            const double *Y = state(L.seg, 4 * (n - n0)), *U2 = state(L.seg, 4 * (n - n0) + 1),
+                         *U3 = state(L.seg, 4 * (n - n0) + 2), *U4 = state(L.seg, 4 * (n - n0) + 3);
             // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
             // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s
             adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
-            adj_rhs_vjp(b, s, U4, kb, Ub, W, C, Gb);
+            adj_rhs_vjp(b, s, U4, kb, Ub, W, Gb);
             adj_copy(n5, Ub, S, s);
             adj_lincomb(n5, dt / 3.0, ub, dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, U3, kb, Ub, W, C, Gb);
+            adj_rhs_vjp(b, s, U3, kb, Ub, W, Gb);
             adj_accum(n5, Ub, S, s);
             adj_lincomb(n5, dt / 3.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, U2, kb, Ub, W, C, Gb);
+            adj_rhs_vjp(b, s, U2, kb, Ub, W, Gb);
             adj_accum(n5, Ub, S, s);
             adj_lincomb(n5, dt / 6.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, Y, kb, Ub, W, C, Gb);
+            adj_rhs_vjp(b, s, Y, kb, Ub, W, Gb);
             adj_accum(n5, Ub, S, s);
             adj_accum(n5, S, ub, s);
         }

@@ -32,33 +32,38 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
     const double s1 = eps + (k13 * da * da + 0.25 * ea * ea);
     const double s2 = eps + (k13 * db * db + 0.25 * eb * eb);
     const double s3 = eps + (k13 * dc * dc + 0.25 * ec * ec);
-    const double t1 = eps + (k13 * dd * dd + 0.25 * fa * fa);
-    const double t2 = eps + (k13 * dc * dc + 0.25 * fb * fb);
-    const double t3 = eps + (k13 * db * db + 0.25 * fc * fc);
-    // reciprocals by refined hardware estimates (rcp), no IEEE division sequences
-    const double is1 = rcp(s1), is2 = rcp(s2), is3 = rcp(s3), it1 = rcp(t1), it2 = rcp(t2), it3 = rcp(t3);
+    const double u1 = eps + (k13 * dd * dd + 0.25 * fa * fa);
+    const double u2 = eps + (k13 * dc * dc + 0.25 * fb * fb);
+    const double u3 = eps + (k13 * db * db + 0.25 * fc * fc);
+    // Product form of the weights, one reciprocal per side: with s_k = eps + beta_k,
+    // t_k = prod_{i != k} s_i, P = s1 s2 s3, a_k = c_k t_k^2 and A = sum a_k,
+    // w_k = a_k / A = a_k P iPA and w_k / s_k = a_k t_k iPA, where iPA = 1 / (P A).
     // left weights and value
-    double d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
-    double a1 = 0.1 * (d2 * d3), a2 = 0.6 * (d1 * d3), a3 = 0.3 * (d1 * d2);
-    double iS = rcp(a1 + a2 + a3);
-    const double w1 = a1 * iS, w2 = a2 * iS, w3 = a3 * iS;
+    double t1 = s2 * s3, t2 = s1 * s3, t3 = s1 * s2;
+    double a1 = 0.1 * (t1 * t1), a2 = 0.6 * (t2 * t2), a3 = 0.3 * (t3 * t3);
+    double iPA = rcp((t3 * s3) * (a1 + a2 + a3));
+    double iA = (t3 * s3) * iPA;
+    const double w1 = a1 * iA, w2 = a2 * iA, w3 = a3 * iA;
+    const double is1 = a1 * t1 * iPA, is2 = a2 * t2 * iPA, is3 = a3 * t3 * iPA;  // w_k / s_k
     const double L = w1 * L1 + w2 * L2 + w3 * L3;
     // right weights and value
-    d1 = t1 * t1, d2 = t2 * t2, d3 = t3 * t3;
-    a1 = 0.1 * (d2 * d3), a2 = 0.6 * (d1 * d3), a3 = 0.3 * (d1 * d2);
-    iS = rcp(a1 + a2 + a3);
-    const double v1 = a1 * iS, v2 = a2 * iS, v3 = a3 * iS;
+    t1 = u2 * u3, t2 = u1 * u3, t3 = u1 * u2;
+    a1 = 0.1 * (t1 * t1), a2 = 0.6 * (t2 * t2), a3 = 0.3 * (t3 * t3);
+    iPA = rcp((t3 * u3) * (a1 + a2 + a3));
+    iA = (t3 * u3) * iPA;
+    const double v1 = a1 * iA, v2 = a2 * iA, v3 = a3 * iA;
+    const double it1 = a1 * t1 * iPA, it2 = a2 * t2 * iPA, it3 = a3 * t3 * iPA;  // v_k / s_k
     const double R = v1 * R1 + v2 * L3 + v3 * L2;
 
     // candidates
     const double cL1 = Lb * w1, cL2 = Lb * w2 + Rb * v3, cL3 = Lb * w3 + Rb * v2, cR1 = Rb * v1;
     // indicators
-    const double bL1 = -2.0 * Lb * w1 * (L1 - L) * is1;
-    const double bL2 = -2.0 * Lb * w2 * (L2 - L) * is2;
-    const double bL3 = -2.0 * Lb * w3 * (L3 - L) * is3;
-    const double bR1 = -2.0 * Rb * v1 * (R1 - R) * it1;
-    const double bR2 = -2.0 * Rb * v2 * (L3 - R) * it2;
-    const double bR3 = -2.0 * Rb * v3 * (L2 - R) * it3;
+    const double bL1 = -2.0 * Lb * (L1 - L) * is1;
+    const double bL2 = -2.0 * Lb * (L2 - L) * is2;
+    const double bL3 = -2.0 * Lb * (L3 - L) * is3;
+    const double bR1 = -2.0 * Rb * (R1 - R) * it1;
+    const double bR2 = -2.0 * Rb * (L3 - R) * it2;
+    const double bR3 = -2.0 * Rb * (L2 - R) * it3;
     const double dab = 2.0 * k13 * da * bL1, eab = 0.5 * ea * bL1;
     const double dbb = 2.0 * k13 * db * (bL2 + bR3), ebb = 0.5 * eb * bL2, fcb = 0.5 * fc * bR3;
     const double dcb = 2.0 * k13 * dc * (bL3 + bR2), ecb = 0.5 * ec * bL3, fbb = 0.5 * fb * bR2;
@@ -299,47 +304,97 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
 
 // ---------------------------------------------------------------------------
 // convective interface flux H (interface_flux without the viscous part): given
-// Hb, add the adjoints of the six cell states w[0..5] (j-2 .. j+3) to wb.
+// Hb, ASSIGN to wb[m] the adjoints of the six cell states j-2 .. j+3, which sit
+// at offsets c[0..5] of the SoA state u (component stride n3).
+//
+// The six states and their adjoints do not fit in registers together with the
+// intermediates of the Roe and WENO products, so the states are read again from
+// memory (L1/L2) at each stage instead of being held, and the compiler barrier
+// between stages keeps it from merging the loads back into one live set.  The
+// stage with the most live values, the reconstructed point fluxes (their 30
+// values, then their 30 adjoints in place), runs first, while wb is not yet live;
+// the Roe dissipation and the reconstructed states follow.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void adj_stage_fence() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int DIR>
-__device__ __forceinline__ void interface_flux_vjp(const double w[6][5], const double Hb[5], double gamma,
-                                                   double eps, double delta, double wb[6][5]) {
+__device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u, size_t n3, const size_t c[6],
+                                                   const double Hb[5], double gamma, double eps, double delta,
+                                                   double wb[6][5]) {
     const double gm1 = gamma - 1.0;
-    // forward: jump of the reconstructed states
-    double du[5];
+    // H = (FL + FR)/2 - D/2.  Point fluxes F[m][v], then component by component the
+    // adjoints of the reconstructed fluxes FL, FR (each Hb/2), in place
+    double F[6][5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        double UL, UR;
-        weno5_lr<double, double>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, UL, UR);
-        du[v] = UR - UL;
+    for (int m = 0; m < 6; ++m) {
+        double w[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v] = u[(size_t)v * n3 + c[m]];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[m][v] = euler_flux_comp<DIR>(w, gm1, v);
+        adj_stage_fence();
     }
-    // H = (FL + FR)/2 - D/2
-    double Db[5], dub[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Db[v] = -0.5 * Hb[v];
-    roe_dissipation_vjp<DIR>(w[2], w[3], du, gamma, delta, Db, wb[2], wb[3], dub);
-    // reconstructed states: du = UR - UL
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        double q[6] = {w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v]};
-        double qb[6] = {0, 0, 0, 0, 0, 0};
-        weno5_lr_vjp(q, eps, -dub[v], dub[v], qb);
-#pragma unroll
-        for (int m = 0; m < 6; ++m) wb[m][v] += qb[m];
-    }
-    // reconstructed fluxes, then the point fluxes
-    double fb[6][5];
+    adj_stage_fence();
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int m = 0; m < 6; ++m) q[m] = euler_flux_comp<DIR>(w[m], gm1, v);
+        for (int m = 0; m < 6; ++m) q[m] = F[m][v];
         weno5_lr_vjp(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb);
 #pragma unroll
-        for (int m = 0; m < 6; ++m) fb[m][v] = qb[m];
+        for (int m = 0; m < 6; ++m) F[m][v] = qb[m];
+        adj_stage_fence();
     }
+    adj_stage_fence();
+    // through the point fluxes to the cell states
 #pragma unroll
-    for (int m = 0; m < 6; ++m) euler_flux_vjp<DIR>(w[m], gm1, fb[m], wb[m]);
+    for (int m = 0; m < 6; ++m) {
+        double w[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            w[v] = u[(size_t)v * n3 + c[m]];
+            wb[m][v] = 0.0;
+        }
+        euler_flux_vjp<DIR>(w, gm1, F[m], wb[m]);
+    }
+    adj_stage_fence();
+    // dissipation: jump of the reconstructed states, then the Roe product at cells j, j+1
+    double du[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double *f = u + (size_t)v * n3;
+        double UL, UR;
+        weno5_lr<double, double>(f[c[0]], f[c[1]], f[c[2]], f[c[3]], f[c[4]], f[c[5]], eps, UL, UR);
+        du[v] = UR - UL;
+    }
+    adj_stage_fence();
+    double dub[5] = {0, 0, 0, 0, 0};
+    {
+        double a[5], b[5], Db[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            a[v] = u[(size_t)v * n3 + c[2]];
+            b[v] = u[(size_t)v * n3 + c[3]];
+            Db[v] = -0.5 * Hb[v];
+        }
+        roe_dissipation_vjp<DIR>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
+    }
+    adj_stage_fence();
+    // reconstructed states: du = UR - UL
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double *f = u + (size_t)v * n3;
+        double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < 6; ++m) q[m] = f[c[m]];
+        weno5_lr_vjp(q, eps, -dub[v], dub[v], qb);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) wb[m][v] += qb[m];
+        adj_stage_fence();
+    }
 }
 
 }  // namespace cns

@@ -58,6 +58,7 @@ struct Launch {
     int step;         // diagnostics record index
     // single-box overrides (used when non-null / positive)
     const void *u_ov;  // replaces the box's state u
+    void *a_ov, *b_ov;  // replace the box's stage buffers A, B
     void *out_ov;      // replaces rhs as the output of WRITE/ACCUM sweeps and viscous kernels
     double dt_ov;      // replaces the box's dt
     double *diag;      // diagnostics output base (may be null)
@@ -125,8 +126,10 @@ void launch_rhs(const Batch &bt, const void *u_ov, void *out_ov);
 void launch_rhs_dir(const Batch &bt, const void *u_ov, int dir, void *out_ov);
 void launch_viscous(const Batch &bt, const void *u_ov, void *out_ov);
 // one RK4 step of every box (4 stages with fused updates), then diagnostics if diag
+// stage_states (single box, may be null): three buffers that receive the stage states
+// U2, U3, U4 of the step (they replace the stage buffers A, B)
 void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long diag_box_stride,
-                     int step);
+                     int step, void *const *stage_states = nullptr);
 // one step of the integrator `scheme` (CNS_RK4 or CNS_TVDRK3), then diagnostics if diag
 void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag,
                  long long diag_box_stride, int step);
@@ -143,10 +146,9 @@ void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, d
 // adjoint launchers (cns_adjoint.hip), FP64, one box
 // ubar = (dR/du)^T rbar at u; scratch W [4][n3], C [30][n3], Gb [15][n3]
 void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *W,
-                 double *C, double *Gb);
+                 double *Gb);
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
 void adj_accum(size_t n, const double *x, double *out, hipStream_t s);
-void adj_stage(size_t n, double c, const double *u, const double *k, double *out, hipStream_t s);
 void adj_copy(size_t n, const double *x, double *out, hipStream_t s);
 void adj_ke_seed(size_t n3, const double *u, double *ubar, hipStream_t s);
 void adj_ic_vjp(size_t n3, const double *rho, const double *vel, const double *ubar, double *vbar, hipStream_t s);

@@ -59,7 +59,9 @@ __device__ __forceinline__ long long xcd_block(long long b, long long n) {
 }
 
 __device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
-    return which == BUF_U ? (L.u_ov ? L.u_ov : b.u) : (which == BUF_A ? b.A : b.B);
+    if (which == BUF_U) return L.u_ov ? L.u_ov : b.u;
+    if (which == BUF_A) return L.a_ov ? L.a_ov : b.A;
+    return L.b_ov ? L.b_ov : b.B;
 }
 
 // ----------------------------------------------------------------------------
@@ -460,7 +462,6 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
             }
             if (j >= j0) {
                 if constexpr (MODE == MODE_RK) {
-                    const T *un = (const T *)state_ptr(bx, L, BUF_U);
                     T *unext = (T *)state_ptr(bx, L, L.out);
                     double *acc = bx.acc;
 #pragma unroll
@@ -1010,8 +1011,10 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long stri
 }
 
 template <typename T>
-static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step) {
-    // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, U_4 -> A, u^{n+1} -> u
+static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step,
+                       void *const *stage_states) {
+    // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, U_4 -> A, u^{n+1} -> u;
+    // with stage_states, A is U2's buffer for stages 1-2 and U4's for stages 3-4, B is U3's
     const int in_of[4] = {BUF_U, BUF_A, BUF_B, BUF_A};
     const int out_of[4] = {BUF_A, BUF_B, BUF_A, BUF_U};
     for (int s = 0; s < 4; ++s) {
@@ -1020,6 +1023,10 @@ static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *
         L.out = out_of[s];
         L.stage = s + 1;
         L.u_ov = u_ov;
+        if (stage_states) {
+            L.a_ov = stage_states[s < 2 ? 0 : 2];
+            L.b_ov = stage_states[1];
+        }
         L.dt_ov = dt_ov;
         if (bt.any_visc) visc_fields<T>(bt, L);
         sweep_x<T>(bt, L, bt.any_visc);
@@ -1033,9 +1040,10 @@ static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *
     if (diag) diag_t<T>(bt, u_ov, diag, stride, step);
 }
 
-void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step) {
-    if (bt.prec == CNS_FP64) rk4_step_t<double>(bt, u_ov, dt_ov, diag, stride, step);
-    else rk4_step_t<float>(bt, u_ov, dt_ov, diag, stride, step);
+void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step,
+                     void *const *stage_states) {
+    if (bt.prec == CNS_FP64) rk4_step_t<double>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
+    else rk4_step_t<float>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
 }
 
 template <typename T>

@@ -70,7 +70,10 @@ __device__ __forceinline__ size_t shift_idx(const AdjGeom &g, int i, int j, int 
 // written out after one chunk and the cells touched by the next never share a slot,
 // so no barrier separates them, and a slot is cleared as soon as its cell is out.
 // x: TA = 64 lanes along the row, TB = 4 rows; y, z: TA = 8 along the line, TB = 32
-// lanes across x (coalesced loads and stores in every direction).
+// lanes across x (coalesced loads and stores in every direction).  Before each
+// chunk the block stages the states of the cells I-2 .. I+TA+2 of its lines in
+// LDS, so the stages of the interface product, which re-read the states rather
+// than hold them, read LDS instead of the caches.
 // ---------------------------------------------------------------------------
 template <int DIR> struct AdjConvShape;
 template <> struct AdjConvShape<0> { static constexpr int TA = 64, TB = 4, RS = 256; };
@@ -83,8 +86,10 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
                                                      int accumulate) {
     using S = AdjConvShape<DIR>;
     constexpr int TA = S::TA, TB = S::TB, RS = S::RS;
+    constexpr int NC = TA + 5;  // staged cells per line
     __shared__ double ring[TB * 5 * RS];
     __shared__ double head[TB * 25];
+    __shared__ double stg[TB * 5 * NC];
     // lane roles: ta along the line, tb across lines; lanes are consecutive in x
     const int ta = DIR == 0 ? (int)threadIdx.x % TA : (int)threadIdx.x / TB;
     const int tb = DIR == 0 ? (int)threadIdx.x / TA : (int)threadIdx.x % TB;
@@ -94,48 +99,59 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
         return DIR == 0 ? (tb * 5 + v) * RS + r : (r * 5 + v) * TB + tb;
     };
     const size_t n3 = g.n3;
-    int n;
-    size_t base, stride;
-    bool lane_ok;
-    if (DIR == 0) {
-        const size_t row = (size_t)blockIdx.x * TB + tb;
-        lane_ok = row < (size_t)g.ny * g.nz;
-        n = g.nx;
-        base = lane_ok ? row * g.nx : 0;
-        stride = 1;
-    } else {
-        const int ntx = (g.nx + TB - 1) / TB;
-        const int xt = (int)(blockIdx.x % ntx), o = (int)(blockIdx.x / ntx);
-        const int x = xt * TB + tb;
-        lane_ok = x < g.nx;
-        const int xs = lane_ok ? x : 0;
-        if (DIR == 1) {
-            n = g.ny;
-            base = (size_t)o * g.nx * g.ny + xs;
-            stride = (size_t)g.nx;
-        } else {
-            n = g.nz;
-            base = (size_t)o * g.nx + xs;
-            stride = (size_t)g.nx * g.ny;
+    const int n = DIR == 0 ? g.nx : (DIR == 1 ? g.ny : g.nz);
+    const size_t stride = DIR == 0 ? 1 : (DIR == 1 ? (size_t)g.nx : (size_t)g.nx * g.ny);
+    const int ntx = (g.nx + TB - 1) / TB;
+    // the line of lane column t: whether it exists, and the offset of its cell 0
+    auto line = [&](int t, size_t &lb) -> bool {
+        if (DIR == 0) {
+            const size_t row = (size_t)blockIdx.x * TB + t;
+            lb = row * g.nx;
+            return row < (size_t)g.ny * g.nz;
         }
-    }
+        const int x = (int)(blockIdx.x % ntx) * TB + t, o = (int)(blockIdx.x / ntx);
+        lb = (DIR == 1 ? (size_t)o * g.nx * g.ny : (size_t)o * g.nx) + (size_t)x;
+        return x < g.nx;
+    };
+    size_t base;
+    const bool lane_ok = line(tb, base);
     const double ih = g.ih[DIR];
     for (int t = threadIdx.x; t < TB * 5 * RS; t += 256) ring[t] = 0.0;
     __syncthreads();
     int I = 0;
     for (;; I += TA) {
+        // stage cells I-2 .. I+TA+2 (any number of periods: short lines wrap more than once)
+        for (int t = threadIdx.x; t < TB * 5 * NC; t += 256) {
+            int k, v, l;
+            if (DIR == 0) {
+                k = t % NC;
+                v = (t / NC) % 5;
+                l = t / (5 * NC);
+            } else {
+                l = t % TB;
+                v = (t / TB) % 5;
+                k = t / (5 * TB);
+            }
+            size_t lb;
+            const bool ok = line(l, lb);
+            int cell = (I - 2 + k) % n;
+            if (cell < 0) cell += n;
+            stg[t] = ok ? u[v * n3 + lb + (size_t)cell * stride] : 0.0;
+        }
+        __syncthreads();
         const int j = I + ta;
         const bool act = lane_ok && j < n;
         double wb[6][5];
         if (act) {
-            size_t c[6];
+            // cell j-2+m is staged cell ta+m
+            int c[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) c[m] = base + (size_t)wrapj(j + m - 2, n) * stride;
-            const size_t pn = base + (size_t)wrapj(j + 1, n) * stride, p = c[2];
+            for (int m = 0; m < 6; ++m) c[m] = DIR == 0 ? tb * 5 * NC + ta + m : (ta + m) * 5 * TB + tb;
+            const size_t p = base + (size_t)j * stride, pn = base + (size_t)wrapj(j + 1, n) * stride;
             double Hb[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) Hb[v] = (rbar[v * n3 + pn] - rbar[v * n3 + p]) * ih;
-            interface_flux_vjp<DIR>(u, n3, c, Hb, g.gamma, g.eps, g.delta, wb);
+            interface_flux_vjp<DIR>(stg, DIR == 0 ? NC : TB, c, Hb, g.gamma, g.eps, g.delta, wb);
         }
 #pragma unroll
         for (int m = 0; m < 6; ++m) {

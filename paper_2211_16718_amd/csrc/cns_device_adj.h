@@ -305,12 +305,13 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
 // ---------------------------------------------------------------------------
 // convective interface flux H (interface_flux without the viscous part): given
 // Hb, ASSIGN to wb[m] the adjoints of the six cell states j-2 .. j+3, which sit
-// at offsets c[0..5] of the SoA state u (component stride n3).
+// at offsets c[0..5] of the array st (component stride cs; the caller stages
+// them in LDS).
 //
 // The six states and their adjoints do not fit in registers together with the
 // intermediates of the Roe and WENO products, so the states are read again from
-// memory (L1/L2) at each stage instead of being held, and the compiler barrier
-// between stages keeps it from merging the loads back into one live set.  The
+// st at each stage instead of being held, and the compiler barrier between
+// stages keeps it from merging the loads back into one live set.  The
 // stage with the most live values, the reconstructed point fluxes (their 30
 // values, then their 30 adjoints in place), runs first, while wb is not yet live;
 // the Roe dissipation and the reconstructed states follow.
@@ -321,9 +322,8 @@ __device__ __forceinline__ void adj_stage_fence() {
 }
 
 template <int DIR>
-__device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u, size_t n3, const size_t c[6],
-                                                   const double Hb[5], double gamma, double eps, double delta,
-                                                   double wb[6][5]) {
+__device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, const int c[6], const double Hb[5],
+                                                   double gamma, double eps, double delta, double wb[6][5]) {
     const double gm1 = gamma - 1.0;
     // H = (FL + FR)/2 - D/2.  Point fluxes F[m][v], then component by component the
     // adjoints of the reconstructed fluxes FL, FR (each Hb/2), in place
@@ -332,7 +332,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u,
     for (int m = 0; m < 6; ++m) {
         double w[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) w[v] = u[(size_t)v * n3 + c[m]];
+        for (int v = 0; v < 5; ++v) w[v] = st[v * cs + c[m]];
 #pragma unroll
         for (int v = 0; v < 5; ++v) F[m][v] = euler_flux_comp<DIR>(w, gm1, v);
         adj_stage_fence();
@@ -355,7 +355,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u,
         double w[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            w[v] = u[(size_t)v * n3 + c[m]];
+            w[v] = st[v * cs + c[m]];
             wb[m][v] = 0.0;
         }
         euler_flux_vjp<DIR>(w, gm1, F[m], wb[m]);
@@ -365,7 +365,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u,
     double du[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        const double *f = u + (size_t)v * n3;
+        const double *f = st + v * cs;
         double UL, UR;
         weno5_lr<double, double>(f[c[0]], f[c[1]], f[c[2]], f[c[3]], f[c[4]], f[c[5]], eps, UL, UR);
         du[v] = UR - UL;
@@ -376,8 +376,8 @@ __device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u,
         double a[5], b[5], Db[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            a[v] = u[(size_t)v * n3 + c[2]];
-            b[v] = u[(size_t)v * n3 + c[3]];
+            a[v] = st[v * cs + c[2]];
+            b[v] = st[v * cs + c[3]];
             Db[v] = -0.5 * Hb[v];
         }
         roe_dissipation_vjp<DIR>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
@@ -386,7 +386,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *__restrict__ u,
     // reconstructed states: du = UR - UL
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        const double *f = u + (size_t)v * n3;
+        const double *f = st + v * cs;
         double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int m = 0; m < 6; ++m) q[m] = f[c[m]];

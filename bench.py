@@ -39,11 +39,12 @@ FLOPS_PER_POINT = {
     "diagnostics": 120,
 }
 # Algorithmic HBM bytes per grid point of one launch (FP64): each array element
-# read or written once.
+# read or written once; the fused RK4 stage is averaged over the four stages
+# (u^n read in stages 2-4, the accumulator written in stage 2 and read in stage 4).
 BYTES_PER_POINT = {
     "sweep_x": 8 * (5 + 4 + 5),            # u, 4 viscous fluxes -> rhs
     "sweep_y": 8 * (5 + 4 + 5 + 5),        # + rhs read-modify-write
-    "sweep_z_rk4": 8 * (5 + 4 + 5 + 5 + 5 + 5 + 5),  # + u^n, acc (rmw), next stage
+    "sweep_z_rk4": 8 * (5 + 4 + 5 + 5) + 8 * (15 + 5 + 5) // 4,  # u, G, rhs -> next stage; + u^n, acc
     "visc_flux": 8 * (5 + 9),              # u -> 9 viscous-flux fields
     "diagnostics": 8 * 5,
 }

@@ -21,6 +21,8 @@
 // over virtual blocks, so one launch advances every box of an ensemble.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 
 #include "cns_internal.h"
@@ -57,6 +59,15 @@ __device__ __forceinline__ long long xcd_block(long long b, long long n) {
     const long long x = b % kXcd, i = b / kXcd;
     return x * q + (x < r ? x : r) + i;
 }
+
+// Classical RK4 keeps u^n, the stage state and an FP64 accumulator of
+// u^n + dt sum_s b_s k_s.  With FP64 stage states (U2 = u + dt k1/2, U4 = u + dt k3)
+// the terms of k1 and k3 are recovered from them when the accumulator is next
+// touched, so it is written in stage 2 and read in stage 4 only; FP32 stage states
+// could not give those terms back to FP64 accuracy, so the mixed form updates it in
+// every stage.
+template <typename T>
+constexpr bool kFp64Stages = std::is_same<T, double>::value;
 
 __device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
     if (which == BUF_U) return L.u_ov ? L.u_ov : b.u;
@@ -443,7 +454,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     const T *un = (const T *)state_ptr(bx, L, BUF_U);
 #pragma unroll
                     for (int v = 0; v < 5; ++v) pu[v] = un[v * n3 + o];
-                    if (L.scheme != CNS_TVDRK3) {
+                    // the FP64 form reads the accumulator in the last stage only
+                    if (L.scheme != CNS_TVDRK3 && (!kFp64Stages<T> || L.stage == 4)) {
 #pragma unroll
                         for (int v = 0; v < 5; ++v) pa[v] = bx.acc[v * n3 + o];
                     }
@@ -480,6 +492,21 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                                 const double uo = double(pu[v]);
                                 if (L.stage == 2) unext[e] = T(0.75 * uo + 0.25 * (us + dt * k));
                                 else unext[e] = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
+                            }
+                        } else if constexpr (kFp64Stages<T>) {
+                            // FP64 stage states give back dt k1 / 6 = (U2 - u) / 3 and
+                            // dt k3 / 3 = (U4 - u) / 3, so the accumulator is written in
+                            // stage 2 and read in stage 4 only
+                            if (L.stage == 1) {
+                                unext[e] = us + (0.5 * dt) * k;
+                            } else if (L.stage == 2) {
+                                const double uo = pu[v];
+                                acc[e] = (uo + (1.0 / 3.0) * (us - uo)) + (dt / 3.0) * k;
+                                unext[e] = uo + (0.5 * dt) * k;
+                            } else if (L.stage == 3) {
+                                unext[e] = pu[v] + dt * k;
+                            } else {
+                                unext[e] = (pa[v] + (1.0 / 3.0) * (us - pu[v])) + (dt / 6.0) * k;
                             }
                         } else if (L.stage == 1) {
                             acc[e] = us + (dt / 6.0) * k;

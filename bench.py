@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2, help="RK4 steps of the oracle sample")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision 512^3, ensemble and adjoint measurements")
+    ap.add_argument("--extras", default="mixed_512,ensemble_64,adjoint_128,options_128",
+                    help="comma-separated subset of the extra measurements to run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the workload, copy a buffer of this many MiB device-to-device once "
                          "(a known-size reference for hardware byte counters)")
@@ -197,8 +199,11 @@ def main():
     if not args.no_extras:
         del plan
         torch.cuda.empty_cache()
+        wanted = set(args.extras.split(","))
         for name, fn in (("mixed_512", bench_mixed), ("ensemble_64", bench_ensemble), ("adjoint_128", bench_adjoint),
                          ("options_128", bench_options)):
+            if name not in wanted:
+                continue
             try:
                 extras[name] = fn()
             except Exception as e:  # report, keep the main line
@@ -344,7 +349,7 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
     return {"config": {"workload": f"hit{n}_re400_rk4x{steps}_adjoint", "ckpt_every": ckpt},
             "forward_s": fsec, "gradient_s": gsec, "gradient_over_forward": gsec / fsec,
             "value": 4.0 * n ** 3 * steps / gsec, "unit": "point-RHS/s (forward-step equivalents of the gradient)",
-            "J": float(J), "grad_norm": float(g.norm())}
+            "J": float(J.detach()), "grad_norm": float(g.norm())}
 
 
 def bench_options(n=128, steps=20):

@@ -50,6 +50,7 @@ BYTES_PER_POINT = {
 }
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9  # VALU lane-instructions per second (3.93e13)
 
 
 def kernel_source_digest():
@@ -166,6 +167,20 @@ def main():
                 traffic = t["kernels"][dom]["bytes_per_launch"]
         except Exception:
             traffic = None
+    # VALU instructions per point of the dominant kernel (SQ_INSTS_VALU counters taken on
+    # the same kernel sources), as a fraction of the issue peak: one wave64 VALU
+    # instruction per SIMD every 4 cycles = 256 x 4 x 16 lanes x 2.4 GHz lane-instructions/s
+    valu = None
+    vfile = os.path.join(ROOT, "profiles", "valu.json")
+    if os.path.exists(vfile):
+        try:
+            v = json.load(open(vfile))
+            if v.get("kernel_source_sha256") == kernel_source_digest() and dom in v.get("kernels", {}):
+                per = v["kernels"][dom]["valu_per_point"]
+                valu = {"valu_instructions_per_point": round(per, 1),
+                        "valu_issue_frac": round(per * n ** 3 / avg_s / PEAK_VALU_LANE_INSTR, 4)}
+        except Exception:
+            valu = None
     roofline = {
         "bound": "alu",
         "kernel": dom,
@@ -179,6 +194,8 @@ def main():
         "flops_per_point": FLOPS_PER_POINT[dom],
         "avg_launch_ms": round(kernels[dom]["avg_ms"], 5),
     }
+    if valu:
+        roofline.update(valu)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -194,6 +211,10 @@ def main():
                "kind": "oracle",
                "sample": f"{args.cpu_steps} RK4 steps (with diagnostics) of the same {n}^3 workload, "
                          f"{ct:.1f} s, OpenMP over grid points"}
+        cpu1 = _oracle_one_core(n, mu)
+        if cpu1:
+            cpu["one_core"] = cpu1
+            cpu["one_core"]["gpu_over_one_core"] = value / cpu1["value"]
 
     extras = {}
     if not args.no_extras:
@@ -246,6 +267,38 @@ def _timed(stream, fn):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3, r
+
+
+def _oracle_one_core(n, mu):
+    """The oracle's RHS on one host thread (the paper's GPU-vs-one-core comparison), in a
+    child process started with OMP_NUM_THREADS=1: one RHS evaluation of the same input."""
+    import subprocess
+
+    code = (
+        "import json, sys, time\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import numpy as np\n"
+        "import oracle\n"
+        "from paper_2211_16718_amd import inputs as I\n"
+        f"n, mu = {n}, {mu!r}\n"
+        "wl = I.WORKLOADS['hit128']\n"
+        "rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)\n"
+        "ph = oracle.make_phys(mu_eff=mu)\n"
+        "uh = oracle.init_state(rho, vel, p)\n"
+        "oracle.rhs(np.ascontiguousarray(uh[:, :8, :8, :8]), ph)\n"
+        "t0 = time.perf_counter()\n"
+        "oracle.rhs(uh, ph)\n"
+        "ct = time.perf_counter() - t0\n"
+        "print(json.dumps({'value': n ** 3 / ct, 'seconds': ct, 'cores': oracle.num_threads()}))\n"
+    )
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception:
+        return None
+    return {"value": d["value"], "unit": "point-RHS/s", "cores": d["cores"], "kind": "oracle",
+            "sample": f"one RHS evaluation of the same {n}^3 state, {d['seconds']:.1f} s"}
 
 
 def bench_mixed(n=512, steps=20):

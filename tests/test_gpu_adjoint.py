@@ -49,6 +49,30 @@ def test_rhs_vjp_matches_reverse_mode_reference(orc, shape, mu, delta):
     assert err <= 1e-11
 
 
+@pytest.mark.parametrize("shape", [(9, 11, 70), (8, 8, 8), (130, 8, 9), (8, 8, 260)])
+def test_rhs_vjp_ragged_lines(orc, shape):
+    """Line lengths and counts that leave chunks, lane tiles and blocks of the fused
+    convective adjoint partly filled (70 = 64 + 6 along x, 11 and 9 along y, z; 99 rows;
+    x tiles of 32 over 70 or 9 points), lines shorter than a chunk whose staged cells
+    wrap several periods (8^3), many chunks along z (130), and x rows long enough for
+    the cell-accumulator ring to wrap (260 > 252 cells)."""
+    case(f"rhs_vjp ragged {shape}")
+    rho, vel, p, _ = I.smooth_primitives(shape, seed=5, amp=0.3, kmax=3)
+    rng = np.random.default_rng(7)  # small-scale noise: nonlinear WENO weights everywhere
+    rho = rho * (1.0 + 0.05 * rng.standard_normal(shape))
+    p = p * (1.0 + 0.05 * rng.standard_normal(shape))
+    vel = vel + 0.1 * rng.standard_normal(vel.shape)
+    plan = Plan(shape, mu_eff=0.02)
+    u = plan.init_state(rho, vel, p)
+    rbar = rng.standard_normal((5,) + shape)
+    got = plan.rhs_vjp(u, torch.from_numpy(rbar).cuda()).cpu().numpy()
+    ref = tr.rhs_vjp(torch.from_numpy(orc.init_state(rho, vel, p)), torch.from_numpy(rbar),
+                     tr.make_phys(mu=0.02, delta=1e-6)).numpy()
+    err = rel_max(got, ref)
+    print(f"rhs_vjp ragged rel err {err:.3e}")
+    assert err <= 1e-11
+
+
 def test_dot_product_against_gpu_forward_differences():
     # <(dR/du)^T rbar, d> = <rbar, (dR/du) d>, the right side by central
     # differences of the GPU forward RHS

@@ -20,6 +20,11 @@
 namespace cns {
 
 __device__ __forceinline__ int wrapj(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
+// any number of periods (the halo of a 64-wide tile over a shorter line)
+__device__ __forceinline__ int wrapn(int j, int n) {
+    const int r = j % n;
+    return r < 0 ? r + n : r;
+}
 
 struct AdjGeom {
     int nx, ny, nz;
@@ -198,151 +203,233 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
     }
 }
 
-// viscous adjoint, part 1: Gbar_d = -D_d rbar; through tau, q, E to the adjoints of the
-// 12 gradients g[a][b] = d W_a/dx_b (W = u, v, w, T) and of the point velocities.
-// Output Gb: [12] gradient adjoints (a-major), then [3] point-velocity adjoints.
-__global__ __launch_bounds__(256) void k_adj_visc1(AdjGeom g, const double *__restrict__ W,
-                                                   const double *__restrict__ rbar, double *__restrict__ Gb) {
-    const size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (p >= g.n3) return;
-    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
-    const size_t n3 = g.n3;
-    size_t nb[3][4];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        nb[d][0] = shift_idx(g, i, j, k, d, -2);
-        nb[d][1] = shift_idx(g, i, j, k, d, -1);
-        nb[d][2] = shift_idx(g, i, j, k, d, 1);
-        nb[d][3] = shift_idx(g, i, j, k, d, 2);
-    }
-    // forward at p: gradients, stresses
-    double gr[4][3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double *f = W + a * n3;
-            gr[a][d] = dcen(f[nb[d][0]], f[nb[d][1]], f[nb[d][2]], f[nb[d][3]]) * g.ih[d];
-        }
-    const double mu = g.mu, kc = g.mu / ((g.gamma - 1.0) * g.prandtl);
-    const double div = gr[0][0] + gr[1][1] + gr[2][2];
-    const double tdiv = 2.0 / 3.0 * div;
-    const double txx = mu * (2.0 * gr[0][0] - tdiv), tyy = mu * (2.0 * gr[1][1] - tdiv),
-                 tzz = mu * (2.0 * gr[2][2] - tdiv);
-    const double txy = mu * (gr[0][1] + gr[1][0]), txz = mu * (gr[0][2] + gr[2][0]),
-                 tyz = mu * (gr[1][2] + gr[2][1]);
-    const double vx = W[p], vy = W[n3 + p], vz = W[2 * n3 + p];
-    // Gbar_d[c] = -(D_d rbar_{1+c})(p), c: x-, y-, z-momentum, energy
-    double Gbar[3][4];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double *r = rbar + (1 + c) * n3;
-            Gbar[d][c] = -dcen(r[nb[d][0]], r[nb[d][1]], r[nb[d][2]], r[nb[d][3]]) * g.ih[d];
-        }
-    // G_x = [txx, txy, txz, Ex], G_y = [txy, tyy, tyz, Ey], G_z = [txz, tyz, tzz, Ez]
-    // E_x = vx txx + vy txy + vz txz + kc dT/dx, etc.
-    const double Ex = Gbar[0][3], Ey = Gbar[1][3], Ez = Gbar[2][3];
-    const double bxx = Gbar[0][0] + Ex * vx;
-    const double byy = Gbar[1][1] + Ey * vy;
-    const double bzz = Gbar[2][2] + Ez * vz;
-    const double bxy = Gbar[0][1] + Gbar[1][0] + Ex * vy + Ey * vx;
-    const double bxz = Gbar[0][2] + Gbar[2][0] + Ex * vz + Ez * vx;
-    const double byz = Gbar[1][2] + Gbar[2][1] + Ey * vz + Ez * vy;
-    const double vbx = Ex * txx + Ey * txy + Ez * txz;
-    const double vby = Ex * txy + Ey * tyy + Ez * tyz;
-    const double vbz = Ex * txz + Ey * tyz + Ez * tzz;
-    // tau_aa = mu (2 g_aa - 2/3 div), tau_ab = mu (g_ab + g_ba)
-    const double divb = -2.0 / 3.0 * mu * (bxx + byy + bzz);
-    double gb[4][3];
-    gb[0][0] = 2.0 * mu * bxx + divb;
-    gb[1][1] = 2.0 * mu * byy + divb;
-    gb[2][2] = 2.0 * mu * bzz + divb;
-    gb[0][1] = mu * bxy;
-    gb[1][0] = mu * bxy;
-    gb[0][2] = mu * bxz;
-    gb[2][0] = mu * bxz;
-    gb[1][2] = mu * byz;
-    gb[2][1] = mu * byz;
-    gb[3][0] = kc * Ex;
-    gb[3][1] = kc * Ey;
-    gb[3][2] = kc * Ez;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) Gb[(size_t)(a * 3 + d) * n3 + p] = gb[a][d];
-    Gb[12 * n3 + p] = vbx;
-    Gb[13 * n3 + p] = vby;
-    Gb[14 * n3 + p] = vbz;
-}
+// ---------------------------------------------------------------------------
+// Viscous adjoint on the tiles of the forward viscous-flux kernel: a block owns a
+// 64 x 4 (x, y) tile and marches along z over kViscSZ planes; the x and y stencil
+// operands of the current plane sit in LDS (with a +-2 halo), each thread keeps its
+// own column's z operands at planes k-2 .. k+2 in registers.
+//
+// Part 1: Gbar_d = -D_d rbar (momentum and energy rows), through tau, q and E to the
+// adjoints of the 12 gradients g[a][b] = d W_a / dx_b (W = u, v, w, T) and of the
+// point velocities.  tau is symmetric, so the 12 gradient adjoints hold 9 distinct
+// values; Gb stores gxx, gyy, gzz, gxy, gxz, gyz, kappa E_x, kappa E_y, kappa E_z,
+// then the three point-velocity adjoints: kAdjGbFields fields.
+// ---------------------------------------------------------------------------
 
-// viscous adjoint, part 2: Wbar = point adjoints - sum_b D_b gbar[.][b]; then through
-// W(u) = (m/rho, gamma p / rho) to ubar (accumulated)
-__global__ __launch_bounds__(256) void k_adj_visc2(AdjGeom g, const double *__restrict__ u,
-                                                   const double *__restrict__ Gb, double *__restrict__ ubar) {
-    const size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (p >= g.n3) return;
-    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
-    const size_t n3 = g.n3;
-    size_t nb[3][4];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        nb[d][0] = shift_idx(g, i, j, k, d, -2);
-        nb[d][1] = shift_idx(g, i, j, k, d, -1);
-        nb[d][2] = shift_idx(g, i, j, k, d, 1);
-        nb[d][3] = shift_idx(g, i, j, k, d, 2);
-    }
-    double Wb[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        double s = a < 3 ? Gb[(12 + a) * n3 + p] : 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double *f = Gb + (size_t)(a * 3 + d) * n3;
-            s -= dcen(f[nb[d][0]], f[nb[d][1]], f[nb[d][2]], f[nb[d][3]]) * g.ih[d];
-        }
-        Wb[a] = s;
-    }
-    // W = (m_k / rho, gamma p / rho), p = (gamma-1)(e - m.v/2)
-    const double gm1 = g.gamma - 1.0;
-    const double r = u[p], m[3] = {u[n3 + p], u[2 * n3 + p], u[3 * n3 + p]}, e = u[4 * n3 + p];
-    const double inv = 1.0 / r;
-    const double v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
-    const double qq = m[0] * v[0] + m[1] * v[1] + m[2] * v[2];
-    const double pr = gm1 * (e - 0.5 * qq);
-    // T = gamma pr inv
-    const double prb = g.gamma * inv * Wb[3];
-    double invb = g.gamma * pr * Wb[3];
-    const double eb = gm1 * prb;
-    const double qqb = -0.5 * gm1 * prb;
-    double mb[3], vb[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        vb[c] = Wb[c] + qqb * m[c];
-        mb[c] = qqb * v[c] + vb[c] * inv;
-        invb += vb[c] * m[c];
-    }
-    ubar[p] += -invb * inv * inv;
-    ubar[n3 + p] += mb[0];
-    ubar[2 * n3 + p] += mb[1];
-    ubar[3 * n3 + p] += mb[2];
-    ubar[4 * n3 + p] += eb;
-}
-
-// W = (u, v, w, T) at the linearisation point (same arithmetic as the forward k_prim)
-__global__ void k_adj_prim(AdjGeom g, const double *__restrict__ u, double *__restrict__ W) {
-    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i >= g.n3) return;
-    const size_t n3 = g.n3;
+// W = (u, v, w, T = gamma p / rho) of the state at linear index i: the forward's
+// primitive map, the linearisation point of the viscous terms
+__device__ __forceinline__ void adj_prim_at(const double *__restrict__ u, size_t n3, size_t i, double gamma,
+                                            double W[4]) {
     const double r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
-    const double inv = 1.0 / r;
-    const double vx = mx * inv, vy = my * inv, vz = mz * inv;
-    const double p = (g.gamma - 1.0) * (e - 0.5 * (mx * vx + my * vy + mz * vz));
-    W[i] = vx;
-    W[n3 + i] = vy;
-    W[2 * n3 + i] = vz;
-    W[3 * n3 + i] = g.gamma * p * inv;
+    const double inv = rcp(r);
+    W[0] = mx * inv;
+    W[1] = my * inv;
+    W[2] = mz * inv;
+    const double p = (gamma - 1.0) * (e - 0.5 * (mx * W[0] + my * W[1] + mz * W[2]));
+    W[3] = gamma * p * inv;
+}
+
+struct AdjTile {
+    int x0, y0, z0, z1, tx, ty;
+    bool act;
+    size_t col;
+};
+__device__ __forceinline__ AdjTile adj_tile(const AdjGeom &g) {
+    AdjTile t;
+    const int ntx = (g.nx + kViscTX - 1) / kViscTX, nty = (g.ny + kViscTY - 1) / kViscTY;
+    const long long lb = blockIdx.x;
+    t.x0 = (int)(lb % ntx) * kViscTX;
+    t.y0 = (int)((lb / ntx) % nty) * kViscTY;
+    t.z0 = (int)(lb / ((long long)ntx * nty)) * kViscSZ;
+    t.z1 = min(t.z0 + kViscSZ, g.nz);
+    t.tx = threadIdx.x % kViscTX;
+    t.ty = threadIdx.x / kViscTX;
+    t.act = t.x0 + t.tx < g.nx && t.y0 + t.ty < g.ny;
+    t.col = (size_t)min(t.y0 + t.ty, g.ny - 1) * g.nx + min(t.x0 + t.tx, g.nx - 1);
+    return t;
+}
+
+__global__ __launch_bounds__(kPointThreads) void k_adj_visc1(AdjGeom g, const double *__restrict__ u,
+                                                             const double *__restrict__ rbar, double *__restrict__ Gb) {
+    constexpr int TX = kViscTX, TY = kViscTY;
+    __shared__ double pw[4][TY + 4][TX + 4];  // W of the plane
+    __shared__ double pr[4][TY + 4][TX + 4];  // rbar rows 1..4 of the plane
+    const AdjTile t = adj_tile(g);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t n3 = g.n3, sz = (size_t)nx * ny;
+    const double *rb = rbar + n3;  // rows 1..4: momentum x, y, z, energy
+    double Wz[5][4], Rz[5][4];     // this column at planes k-2 .. k+2
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const size_t q = t.col + (size_t)wrapj(t.z0 - 2 + m, nz) * sz;
+        adj_prim_at(u, n3, q, g.gamma, Wz[m]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Rz[m][c] = rb[c * n3 + q];
+    }
+    const double mu = g.mu, kc = g.mu / ((g.gamma - 1.0) * g.prandtl);
+    for (int k = t.z0; k < t.z1; ++k) {
+        {
+            const size_t q = t.col + (size_t)wrapj(k + 2, nz) * sz;
+            adj_prim_at(u, n3, q, g.gamma, Wz[4]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Rz[4][c] = rb[c * n3 + q];
+        }
+        for (int h = threadIdx.x; h < (TX + 4) * (TY + 4); h += blockDim.x) {
+            const int hx = h % (TX + 4), hy = h / (TX + 4);
+            const size_t q = (size_t)k * sz + (size_t)wrapn(t.y0 - 2 + hy, ny) * nx + wrapn(t.x0 - 2 + hx, nx);
+            double w4[4];
+            adj_prim_at(u, n3, q, g.gamma, w4);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                pw[c][hy][hx] = w4[c];
+                pr[c][hy][hx] = rb[c * n3 + q];
+            }
+        }
+        __syncthreads();
+        if (t.act) {
+            const int X = t.tx + 2, Y = t.ty + 2;
+            // forward at the point: gradients and stresses
+            double gr[4][3];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                gr[a][0] = dcen(pw[a][Y][X - 2], pw[a][Y][X - 1], pw[a][Y][X + 1], pw[a][Y][X + 2]) * g.ih[0];
+                gr[a][1] = dcen(pw[a][Y - 2][X], pw[a][Y - 1][X], pw[a][Y + 1][X], pw[a][Y + 2][X]) * g.ih[1];
+                gr[a][2] = dcen(Wz[0][a], Wz[1][a], Wz[3][a], Wz[4][a]) * g.ih[2];
+            }
+            const double div = gr[0][0] + gr[1][1] + gr[2][2];
+            const double tdiv = 2.0 / 3.0 * div;
+            const double txx = mu * (2.0 * gr[0][0] - tdiv), tyy = mu * (2.0 * gr[1][1] - tdiv),
+                         tzz = mu * (2.0 * gr[2][2] - tdiv);
+            const double txy = mu * (gr[0][1] + gr[1][0]), txz = mu * (gr[0][2] + gr[2][0]),
+                         tyz = mu * (gr[1][2] + gr[2][1]);
+            const double vx = Wz[2][0], vy = Wz[2][1], vz = Wz[2][2];
+            // Gbar_d[c] = -(D_d rbar_{1+c}), c: x-, y-, z-momentum, energy
+            double Gbar[3][4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                Gbar[0][c] = -dcen(pr[c][Y][X - 2], pr[c][Y][X - 1], pr[c][Y][X + 1], pr[c][Y][X + 2]) * g.ih[0];
+                Gbar[1][c] = -dcen(pr[c][Y - 2][X], pr[c][Y - 1][X], pr[c][Y + 1][X], pr[c][Y + 2][X]) * g.ih[1];
+                Gbar[2][c] = -dcen(Rz[0][c], Rz[1][c], Rz[3][c], Rz[4][c]) * g.ih[2];
+            }
+            // G_x = [txx, txy, txz, Ex], G_y = [txy, tyy, tyz, Ey], G_z = [txz, tyz, tzz, Ez],
+            // E_x = vx txx + vy txy + vz txz + kc dT/dx, etc.
+            const double Ex = Gbar[0][3], Ey = Gbar[1][3], Ez = Gbar[2][3];
+            const double bxx = Gbar[0][0] + Ex * vx;
+            const double byy = Gbar[1][1] + Ey * vy;
+            const double bzz = Gbar[2][2] + Ez * vz;
+            const double bxy = Gbar[0][1] + Gbar[1][0] + Ex * vy + Ey * vx;
+            const double bxz = Gbar[0][2] + Gbar[2][0] + Ex * vz + Ez * vx;
+            const double byz = Gbar[1][2] + Gbar[2][1] + Ey * vz + Ez * vy;
+            // tau_aa = mu (2 g_aa - 2/3 div), tau_ab = mu (g_ab + g_ba)
+            const double divb = -2.0 / 3.0 * mu * (bxx + byy + bzz);
+            const size_t idx = (size_t)k * sz + t.col;
+            Gb[idx] = 2.0 * mu * bxx + divb;
+            Gb[n3 + idx] = 2.0 * mu * byy + divb;
+            Gb[2 * n3 + idx] = 2.0 * mu * bzz + divb;
+            Gb[3 * n3 + idx] = mu * bxy;
+            Gb[4 * n3 + idx] = mu * bxz;
+            Gb[5 * n3 + idx] = mu * byz;
+            Gb[6 * n3 + idx] = kc * Ex;
+            Gb[7 * n3 + idx] = kc * Ey;
+            Gb[8 * n3 + idx] = kc * Ez;
+            Gb[9 * n3 + idx] = Ex * txx + Ey * txy + Ez * txz;
+            Gb[10 * n3 + idx] = Ex * txy + Ey * tyy + Ez * tyz;
+            Gb[11 * n3 + idx] = Ex * txz + Ey * tyz + Ez * tzz;
+        }
+        __syncthreads();  // the next plane overwrites the LDS tile
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                Wz[m][c] = Wz[m + 1][c];
+                Rz[m][c] = Rz[m + 1][c];
+            }
+    }
+}
+
+// Part 2: Wbar_a = (point adjoint) - sum_b D_b gbar[a][b], then through
+// W(u) = (m/rho, gamma p / rho) to ubar (accumulated).  The x derivatives act on
+// (gxx, gxy, gxz, kappa E_x), the y derivatives on (gxy, gyy, gyz, kappa E_y), the z
+// derivatives on (gxz, gyz, gzz, kappa E_z).
+__global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const double *__restrict__ u,
+                                                             const double *__restrict__ Gb, double *__restrict__ ubar) {
+    constexpr int TX = kViscTX, TY = kViscTY;
+    constexpr int fx[4] = {0, 3, 4, 6}, fy[4] = {3, 1, 5, 7}, fz[4] = {4, 5, 2, 8};
+    __shared__ double qx[4][TY][TX + 4];  // x-differenced fields of the plane, x halo
+    __shared__ double qy[4][TY + 4][TX];  // y-differenced fields of the plane, y halo
+    const AdjTile t = adj_tile(g);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t n3 = g.n3, sz = (size_t)nx * ny;
+    double Gz[5][4];  // z-differenced fields of this column at planes k-2 .. k+2
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const size_t q = t.col + (size_t)wrapj(t.z0 - 2 + m, nz) * sz;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) Gz[m][a] = Gb[fz[a] * n3 + q];
+    }
+    const double gm1 = g.gamma - 1.0;
+    for (int k = t.z0; k < t.z1; ++k) {
+        {
+            const size_t q = t.col + (size_t)wrapj(k + 2, nz) * sz;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) Gz[4][a] = Gb[fz[a] * n3 + q];
+        }
+        const size_t plane = (size_t)k * sz;
+        for (int h = threadIdx.x; h < (TX + 4) * TY; h += blockDim.x) {
+            const int hx = h % (TX + 4), hy = h / (TX + 4);
+            const size_t q = plane + (size_t)min(t.y0 + hy, ny - 1) * nx + wrapn(t.x0 - 2 + hx, nx);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) qx[a][hy][hx] = Gb[fx[a] * n3 + q];
+        }
+        for (int h = threadIdx.x; h < TX * (TY + 4); h += blockDim.x) {
+            const int hx = h % TX, hy = h / TX;
+            const size_t q = plane + (size_t)wrapn(t.y0 - 2 + hy, ny) * nx + min(t.x0 + hx, nx - 1);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) qy[a][hy][hx] = Gb[fy[a] * n3 + q];
+        }
+        __syncthreads();
+        if (t.act) {
+            const size_t p = plane + t.col;
+            const int X = t.tx + 2, Y = t.ty + 2;
+            double Wb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double s = a < 3 ? Gb[(9 + a) * n3 + p] : 0.0;
+                s -= dcen(qx[a][t.ty][X - 2], qx[a][t.ty][X - 1], qx[a][t.ty][X + 1], qx[a][t.ty][X + 2]) * g.ih[0];
+                s -= dcen(qy[a][Y - 2][t.tx], qy[a][Y - 1][t.tx], qy[a][Y + 1][t.tx], qy[a][Y + 2][t.tx]) * g.ih[1];
+                s -= dcen(Gz[0][a], Gz[1][a], Gz[3][a], Gz[4][a]) * g.ih[2];
+                Wb[a] = s;
+            }
+            // W = (m_k / rho, gamma p / rho), p = (gamma-1)(e - m.v/2)
+            const double r = u[p], m[3] = {u[n3 + p], u[2 * n3 + p], u[3 * n3 + p]}, e = u[4 * n3 + p];
+            const double inv = rcp(r);
+            const double v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
+            const double qq = m[0] * v[0] + m[1] * v[1] + m[2] * v[2];
+            const double pr = gm1 * (e - 0.5 * qq);
+            // T = gamma pr inv
+            const double prb = g.gamma * inv * Wb[3];
+            double invb = g.gamma * pr * Wb[3];
+            const double eb = gm1 * prb;
+            const double qqb = -0.5 * gm1 * prb;
+            double mb[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double vb = Wb[c] + qqb * m[c];
+                mb[c] = qqb * v[c] + vb * inv;
+                invb += vb * m[c];
+            }
+            ubar[p] += -invb * inv * inv;
+            ubar[n3 + p] += mb[0];
+            ubar[2 * n3 + p] += mb[1];
+            ubar[3 * n3 + p] += mb[2];
+            ubar[4 * n3 + p] += eb;
+        }
+        __syncthreads();  // the next plane overwrites the LDS tiles
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) Gz[m][a] = Gz[m + 1][a];
+    }
 }
 
 // out = a x + b y (y may be null)
@@ -393,20 +480,19 @@ __global__ void k_ic_vjp(size_t n3, const double *__restrict__ rho, const double
 // ----------------------------------------------------------------------------
 static inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *W,
-                 double *Gb) {
+void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *Gb) {
     const AdjGeom g = adj_geom(b);
-    const size_t n3 = b.n3;
     const bool visc = b.mu > 0.0;
-    if (visc) hipLaunchKernelGGL(k_adj_prim, grid1(n3), dim3(256), 0, s, g, u, W);
-    if (visc) hipLaunchKernelGGL(k_adj_visc1, grid1(n3), dim3(256), 0, s, g, (const double *)W, rbar, Gb);
+    const unsigned tiles = (unsigned)(((b.nx + kViscTX - 1) / kViscTX) * (long long)((b.ny + kViscTY - 1) / kViscTY) *
+                                      ((b.nz + kViscSZ - 1) / kViscSZ));
+    if (visc) hipLaunchKernelGGL(k_adj_visc1, dim3(tiles), dim3(kPointThreads), 0, s, g, u, rbar, Gb);
     // blocks: x, TB = 4 rows each; y, z: one 32-wide x tile of the lines at one z (y) each
     const unsigned bx = (unsigned)(((size_t)b.ny * b.nz + 3) / 4);
     const unsigned ntx = (unsigned)((b.nx + 31) / 32);
     hipLaunchKernelGGL(k_adj_conv<0>, dim3(bx), dim3(256), 0, s, g, u, rbar, ubar, 0);
     hipLaunchKernelGGL(k_adj_conv<1>, dim3(ntx * (unsigned)b.nz), dim3(256), 0, s, g, u, rbar, ubar, 1);
     hipLaunchKernelGGL(k_adj_conv<2>, dim3(ntx * (unsigned)b.ny), dim3(256), 0, s, g, u, rbar, ubar, 1);
-    if (visc) hipLaunchKernelGGL(k_adj_visc2, grid1(n3), dim3(256), 0, s, g, u, (const double *)Gb, ubar);
+    if (visc) hipLaunchKernelGGL(k_adj_visc2, dim3(tiles), dim3(kPointThreads), 0, s, g, u, (const double *)Gb, ubar);
 }
 
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s) {

@@ -754,7 +754,7 @@ int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t 
 // adjoint (FP64, single box): workspace layout and the checkpointed reverse RK4
 // ----------------------------------------------------------------------------
 struct AdjLayout {
-    size_t ck, seg, X, ub, kb, Ub, S, W, Gb, rec, total;
+    size_t ck, seg, X, ub, kb, Ub, S, Gb, rec, total;
     int nck, K;
 };
 
@@ -778,10 +778,8 @@ static AdjLayout adj_layout(size_t n3, int nsteps, int K) {
     off += st;
     L.S = off;                       // sum of the stage adjoints
     off += st;
-    L.W = off;                       // primitives at the linearisation point
-    off += align256(4 * n3 * sizeof(double));
-    L.Gb = off;                      // viscous adjoint fields [15][n3]
-    off += align256(15 * n3 * sizeof(double));
+    L.Gb = off;                      // viscous adjoint fields [kAdjGbFields][n3]
+    off += align256(kAdjGbFields * n3 * sizeof(double));
     L.rec = off;                     // a diagnostics record
     off += align256(CNS_NDIAG * sizeof(double));
     L.total = off;
@@ -815,8 +813,7 @@ int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *uba
     const AdjLayout L = adj_layout(b.n3, 0, 1);
     if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
     char *w = (char *)adj_ws;
-    adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.W),
-                (double *)(w + L.Gb));
+    adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.Gb));
     return check_hip("rhs_vjp");
 }
 
@@ -840,17 +837,28 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
     const size_t st = align256(n5 * sizeof(double));
     auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
     double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
-    double *W = (double *)(w + L.W), *Gb = (double *)(w + L.Gb), *rec = (double *)(w + L.rec);
+    double *Gb = (double *)(w + L.Gb), *rec = (double *)(w + L.rec);
     hipStream_t s = c.stream;
     Batch bt = c.batch();
     bt.prof = nullptr;
     const int K = L.K;
 
-    // forward with checkpoints (the fused RK4 path, as cns_rk4)
+    // the step-start state and stage states U2, U3, U4 of step n of a segment starting at n0,
+    // kept while the fused RK4 step advances X
+    auto keep_step = [&](int n, int n0) {
+        adj_copy(n5, X, state(L.seg, 4 * (n - n0)), s);
+        void *const st3[3] = {state(L.seg, 4 * (n - n0) + 1), state(L.seg, 4 * (n - n0) + 2),
+                              state(L.seg, 4 * (n - n0) + 3)};
+        launch_rk4_step(bt, X, dt, nullptr, 0, 0, st3);
+    };
+    // forward with checkpoints (the fused RK4 path, as cns_rk4); the last segment keeps
+    // its states on the way, so the reverse sweep starts without recomputing it
+    const int last0 = (L.nck - 1) * K;
     adj_copy(n5, (const double *)u0, X, s);
     for (int n = 0; n < nsteps; ++n) {
         if (n % K == 0) adj_copy(n5, X, state(L.ck, n / K), s);
-        launch_rk4_step(bt, X, dt, nullptr, 0, 0);
+        if (n >= last0) keep_step(n, last0);
+        else launch_rk4_step(bt, X, dt, nullptr, 0, 0);
     }
     launch_diag(bt, X, rec, 0, 0);
     if (J_dev) adj_copy(1, rec, J_dev, s);
@@ -859,14 +867,11 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
     // reverse, one checkpoint segment at a time (last first)
     for (int sg = L.nck - 1; sg >= 0; --sg) {
         const int n0 = sg * K, n1 = std::min(nsteps, n0 + K);
-        // recompute the segment, keeping every step-start state and the stage states
-        // U2, U3, U4 the fused step writes (the last step's result is not needed)
-        adj_copy(n5, state(L.ck, sg), X, s);
-        for (int n = n0; n < n1; ++n) {
-            adj_copy(n5, X, state(L.seg, 4 * (n - n0)), s);
-            void *const st3[3] = {state(L.seg, 4 * (n - n0) + 1), state(L.seg, 4 * (n - n0) + 2),
-                                  state(L.seg, 4 * (n - n0) + 3)};
-            launch_rk4_step(bt, X, dt, nullptr, 0, 0, st3);
+        // recompute the segment (the last one is already kept), keeping every step-start
+        // state and the stage states U2, U3, U4 the fused step writes
+        if (sg != L.nck - 1) {
+            adj_copy(n5, state(L.ck, sg), X, s);
+            for (int n = n0; n < n1; ++n) keep_step(n, n0);
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const double *Y = state(L.seg, 4 * (n - n0)), *U2 = state(L.seg, 4 * (n - n0) + 1),
@@ -874,16 +879,16 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
             // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
             // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s
             adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
-            adj_rhs_vjp(b, s, U4, kb, Ub, W, Gb);
+            adj_rhs_vjp(b, s, U4, kb, Ub, Gb);
             adj_copy(n5, Ub, S, s);
             adj_lincomb(n5, dt / 3.0, ub, dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, U3, kb, Ub, W, Gb);
+            adj_rhs_vjp(b, s, U3, kb, Ub, Gb);
             adj_accum(n5, Ub, S, s);
             adj_lincomb(n5, dt / 3.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, U2, kb, Ub, W, Gb);
+            adj_rhs_vjp(b, s, U2, kb, Ub, Gb);
             adj_accum(n5, Ub, S, s);
             adj_lincomb(n5, dt / 6.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, Y, kb, Ub, W, Gb);
+            adj_rhs_vjp(b, s, Y, kb, Ub, Gb);
             adj_accum(n5, Ub, S, s);
             adj_accum(n5, S, ub, s);
         }

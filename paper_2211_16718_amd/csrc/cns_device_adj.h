@@ -15,11 +15,13 @@ __device__ __forceinline__ double harten_dabs(double lam, double delta, double i
 
 // ---------------------------------------------------------------------------
 // WENO5 pair (weno5_lr): given the adjoints Lb, Rb of the left- and right-biased
-// values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5] (q = j-2 .. j+3).
+// values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5] (q = j-2 .. j+3); the
+// values L and R themselves are returned in Lv, Rv.
 // Weight derivative: with alpha_k = c_k/(eps+beta_k)^2 and W = sum w_k fhat_k,
 // dW/dbeta_k = -2 w_k (fhat_k - W) / (eps + beta_k).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, double Lb, double Rb, double qb[6]) {
+__device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, double Lb, double Rb, double qb[6],
+                                             double &Lv, double &Rv) {
     const double m2 = q[0], m1 = q[1], c0 = q[2], p1 = q[3], p2 = q[4], p3 = q[5];
     const double r6 = 1.0 / 6.0, k13 = 13.0 / 12.0;
     const double L1 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0) * r6;
@@ -76,6 +78,8 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
              3.0 * fcb;
     qb[4] += -r6 * cL3 - 7.0 * r6 * cR1 + dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb;
     qb[5] += 2.0 * r6 * cR1 + ddb + fab;
+    Lv = L;
+    Rv = R;
 }
 
 // component v of the convective flux along DIR
@@ -133,16 +137,19 @@ __device__ __forceinline__ void euler_flux_vjp(const double w[5], double gm1, co
 }
 
 // ---------------------------------------------------------------------------
-// Roe dissipation (roe_dissipation, wave-strength form): given Db, add the
-// adjoints of the cell states a, b and of the jump du.
+// Roe dissipation (roe_dissipation, wave-strength form) D = M(a, b) du: linear in the
+// jump du, with M from the Roe average of the cell states a, b alone (Harten's fix
+// acts on the eigenvalues).  Given Db, the two parts of its transpose product:
+//   STATES = false: dub += M^T Db (needs no du);
+//   STATES = true:  ab, bb += the adjoints of a and b through M (needs du).
 // ---------------------------------------------------------------------------
-template <int DIR>
+template <int DIR, bool STATES>
 __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const double b[5], const double du[5],
                                                     double gamma, double delta, const double Db[5], double ab[5],
                                                     double bb[5], double dub[5]) {
     constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
     const double gm1 = gamma - 1.0;
-    // ---- forward recompute
+    // ---- forward recompute: the Roe average
     const double ra = rsq(a[0]), rb = rsq(b[0]);
     const double ia = ra * ra, ib = rb * rb;
     const double va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
@@ -163,18 +170,22 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     const double ic = rsq(c2);
     const double c = c2 * ic, ic2 = ic * ic;
     const double vn = v[N];
-    const double at1 = du[1 + T1] - v[T1] * du[0];
-    const double at2 = du[1 + T2] - v[T2] * du[0];
-    const double dEb = du[4] - at1 * v[T1] - at2 * v[T2];
-    const double X = du[0] * (H - vn * vn) + vn * du[1 + N] - dEb;
-    const double a2 = gm1 * ic2 * X;
-    const double num = du[0] * (vn + c) - du[1 + N] - c * a2;
-    const double a1 = num * (0.5 * ic);
-    const double a5 = du[0] - (a1 + a2);
     const double hd = 0.5 / delta, idelta = 1.0 / delta;  // loop invariant
     const double l1 = harten_abs(vn - c, delta, hd), l2 = harten_abs(vn, delta, hd), l5 = harten_abs(vn + c, delta, hd);
-    const double s1 = l1 * a1, s2 = l2 * a2, s5 = l5 * a5, st1 = l2 * at1, st2 = l2 * at2;
-    const double ssum = s1 + s2 + s5;
+    // ---- forward recompute: the wave strengths of du (only the state adjoints need them)
+    double at1 = 0, at2 = 0, a1 = 0, a2 = 0, a5 = 0, s1 = 0, s2 = 0, s5 = 0, st1 = 0, st2 = 0, ssum = 0;
+    if constexpr (STATES) {
+        at1 = du[1 + T1] - v[T1] * du[0];
+        at2 = du[1 + T2] - v[T2] * du[0];
+        const double dEb = du[4] - at1 * v[T1] - at2 * v[T2];
+        const double X = du[0] * (H - vn * vn) + vn * du[1 + N] - dEb;
+        a2 = gm1 * ic2 * X;
+        const double num = du[0] * (vn + c) - du[1 + N] - c * a2;
+        a1 = num * (0.5 * ic);
+        a5 = du[0] - (a1 + a2);
+        s1 = l1 * a1, s2 = l2 * a2, s5 = l5 * a5, st1 = l2 * at1, st2 = l2 * at2;
+        ssum = s1 + s2 + s5;
+    }
 
     // ---- reverse
     double s1b = 0, s2b = 0, s5b = 0, st1b = 0, st2b = 0, ssumb = 0, Hbar = 0, vnb = 0, cb = 0, q2b = 0;
@@ -182,75 +193,81 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
     // D4 = s1 (H - vn c) + s2 q2/2 + s5 (H + vn c) + st1 v_t1 + st2 v_t2
     s1b += Db[4] * (H - vn * c);
     s5b += Db[4] * (H + vn * c);
-    Hbar += Db[4] * (s1 + s5);
-    vnb += Db[4] * (s5 - s1) * c;
-    cb += Db[4] * (s5 - s1) * vn;
     s2b += Db[4] * 0.5 * q2;
-    q2b += Db[4] * 0.5 * s2;
     st1b += Db[4] * v[T1];
-    vbar[T1] += Db[4] * st1;
     st2b += Db[4] * v[T2];
-    vbar[T2] += Db[4] * st2;
+    if constexpr (STATES) {
+        Hbar += Db[4] * (s1 + s5);
+        vnb += Db[4] * (s5 - s1) * c;
+        cb += Db[4] * (s5 - s1) * vn;
+        q2b += Db[4] * 0.5 * s2;
+        vbar[T1] += Db[4] * st1;
+        vbar[T2] += Db[4] * st2;
+    }
     // D[1+T1] += st1, D[1+T2] += st2, D[1+N] += c (s5 - s1)
     st1b += Db[1 + T1];
     st2b += Db[1 + T2];
-    cb += Db[1 + N] * (s5 - s1);
     s5b += Db[1 + N] * c;
     s1b -= Db[1 + N] * c;
+    if constexpr (STATES) cb += Db[1 + N] * (s5 - s1);
     // D0 = ssum, D[1+k] = ssum v_k (before the additions above)
     ssumb += Db[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         ssumb += Db[1 + k] * v[k];
-        vbar[k] += Db[1 + k] * ssum;
+        if constexpr (STATES) vbar[k] += Db[1 + k] * ssum;
     }
     s1b += ssumb;
     s2b += ssumb;
     s5b += ssumb;
     // s = |lam| alpha
-    const double l1b = s1b * a1, l2b = s2b * a2 + st1b * at1 + st2b * at2, l5b = s5b * a5;
     double a1b = s1b * l1, a2b = s2b * l2, a5b = s5b * l5, at1b = st1b * l2, at2b = st2b * l2;
-    {
+    if constexpr (STATES) {
+        const double l1b = s1b * a1, l2b = s2b * a2 + st1b * at1 + st2b * at2, l5b = s5b * a5;
         const double x1 = l1b * harten_dabs(vn - c, delta, idelta);
         const double x5 = l5b * harten_dabs(vn + c, delta, idelta);
         vnb += x1 + l2b * harten_dabs(vn, delta, idelta) + x5;
         cb += x5 - x1;
     }
     // a5 = du0 - (a1 + a2)
-    dub[0] += a5b;
+    if constexpr (!STATES) dub[0] += a5b;
     a1b -= a5b;
     a2b -= a5b;
     // a1 = num / (2c)
     const double numb = a1b * (0.5 * ic);
-    cb -= a1b * a1 * ic;
-    dub[0] += numb * (vn + c);
-    vnb += numb * du[0];
-    cb += numb * du[0];
-    dub[1 + N] -= numb;
-    cb -= numb * a2;
+    if constexpr (STATES) {
+        cb -= a1b * a1 * ic;
+        vnb += numb * du[0];
+        cb += numb * du[0];
+        cb -= numb * a2;
+    } else {
+        dub[0] += numb * (vn + c);
+        dub[1 + N] -= numb;
+    }
     a2b -= numb * c;
     // a2 = gm1/c2 X
     const double Xb = a2b * gm1 * ic2;
+    // X = du0 (H - vn^2) + vn du_n - dEb;  dEb = du4 - at1 v_t1 - at2 v_t2;  at = du_t - v_t du0
+    const double dEbb = -Xb;
+    at1b -= dEbb * v[T1];
+    at2b -= dEbb * v[T2];
+    if constexpr (!STATES) {
+        dub[0] += Xb * (H - vn * vn);
+        dub[1 + N] += Xb * vn;
+        dub[4] += dEbb;
+        dub[1 + T1] += at1b;
+        dub[0] -= at1b * v[T1];
+        dub[1 + T2] += at2b;
+        dub[0] -= at2b * v[T2];
+        return;
+    }
     double c2b = -a2b * a2 * ic2;
-    // X = du0 (H - vn^2) + vn du_n - dEb
-    dub[0] += Xb * (H - vn * vn);
     Hbar += Xb * du[0];
     vnb += Xb * (du[1 + N] - 2.0 * vn * du[0]);
-    dub[1 + N] += Xb * vn;
-    const double dEbb = -Xb;
-    // dEb = du4 - at1 v_t1 - at2 v_t2
-    dub[4] += dEbb;
-    at1b -= dEbb * v[T1];
     vbar[T1] -= dEbb * at1;
-    at2b -= dEbb * v[T2];
     vbar[T2] -= dEbb * at2;
-    // at = du_t - v_t du0
-    dub[1 + T1] += at1b;
     vbar[T1] -= at1b * du[0];
-    dub[0] -= at1b * v[T1];
-    dub[1 + T2] += at2b;
     vbar[T2] -= at2b * du[0];
-    dub[0] -= at2b * v[T2];
     vbar[N] += vnb;
     // c = sqrt(c2); c2 = gm1 (H - q2/2); q2 = |v|^2
     c2b += cb * (0.5 * ic);
@@ -343,7 +360,8 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int m = 0; m < 6; ++m) q[m] = F[m][v];
-        weno5_lr_vjp(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb);
+        double Lv, Rv;
+        weno5_lr_vjp(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb, Lv, Rv);
 #pragma unroll
         for (int m = 0; m < 6; ++m) F[m][v] = qb[m];
         adj_stage_fence();
@@ -361,40 +379,37 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         euler_flux_vjp<DIR>(w, gm1, F[m], wb[m]);
     }
     adj_stage_fence();
-    // dissipation: jump of the reconstructed states, then the Roe product at cells j, j+1
-    double du[5];
+    // dissipation D = M(a, b) du at cells a = j, b = j+1: first dub = M^T Db, which needs
+    // no du; the reverse of the reconstructed states then yields du itself (UR - UL);
+    // last the adjoints of a and b through M
+    double a[5], b[5], Db[5], du[5], dub[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        a[v] = st[v * cs + c[2]];
+        b[v] = st[v * cs + c[3]];
+        Db[v] = -0.5 * Hb[v];
+        du[v] = 0.0;
+    }
+    roe_dissipation_vjp<DIR, false>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
+    adj_stage_fence();
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         const double *f = st + v * cs;
-        double UL, UR;
-        weno5_lr<double, double>(f[c[0]], f[c[1]], f[c[2]], f[c[3]], f[c[4]], f[c[5]], eps, UL, UR);
-        du[v] = UR - UL;
-    }
-    adj_stage_fence();
-    double dub[5] = {0, 0, 0, 0, 0};
-    {
-        double a[5], b[5], Db[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            a[v] = st[v * cs + c[2]];
-            b[v] = st[v * cs + c[3]];
-            Db[v] = -0.5 * Hb[v];
-        }
-        roe_dissipation_vjp<DIR>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
-    }
-    adj_stage_fence();
-    // reconstructed states: du = UR - UL
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        const double *f = st + v * cs;
-        double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
+        double q[6], qb[6] = {0, 0, 0, 0, 0, 0}, UL, UR;
 #pragma unroll
         for (int m = 0; m < 6; ++m) q[m] = f[c[m]];
-        weno5_lr_vjp(q, eps, -dub[v], dub[v], qb);
+        weno5_lr_vjp(q, eps, -dub[v], dub[v], qb, UL, UR);
+        du[v] = UR - UL;
 #pragma unroll
         for (int m = 0; m < 6; ++m) wb[m][v] += qb[m];
         adj_stage_fence();
     }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        a[v] = st[v * cs + c[2]];
+        b[v] = st[v * cs + c[3]];
+    }
+    roe_dissipation_vjp<DIR, true>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
 }
 
 }  // namespace cns

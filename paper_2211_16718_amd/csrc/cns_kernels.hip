@@ -758,6 +758,10 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
             for (int m = 0; m < 4; ++m) vel_at(u, n3, col + wrapi(z0 - 2 + m, nz) * sz, vz[m]);
             for (int k = z0; k < z1; ++k) {
                 vel_at(u, n3, col + wrapi(k + 2, nz) * sz, vz[4]);
+                // the point's state, loaded ahead of the plane staging and its barrier
+                const size_t idx = (size_t)k * sz + col;
+                const double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]),
+                             mz = double(u[3 * n3 + idx]), e = double(u[4 * n3 + idx]);
                 for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
                     const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
                     double v3[3];
@@ -767,9 +771,6 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
                 }
                 __syncthreads();
                 if (act) {
-                    const size_t idx = (size_t)k * sz + col;
-                    const double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]),
-                                 mz = double(u[3 * n3 + idx]), e = double(u[4 * n3 + idx]);
                     const double inv = rcp(r);
                     const double vx = mx * inv, vy = my * inv, vzc = mz * inv;
                     const double ke = 0.5 * (mx * vx + my * vy + mz * vzc);

@@ -232,6 +232,57 @@ def test_rhs_and_rk4_step_128(orc):
     np.testing.assert_allclose(diag[0, :8], diag_ref[0, :8], rtol=1e-11, atol=1e-14)
 
 
+def test_rhs_512_sampled_points(orc):
+    """The 512^3 workload in the launch configuration the benchmark times (64-point
+    segments along y and z, the rows kernel with two points per thread): the FP64 RHS
+    at sampled points, edges and corners included, against the oracle's one-point RHS;
+    the same for the mixed form within its FP32 rounding bound; and conservation and
+    one RK4 step's mass over the whole grid.  The input is the 128^3 HIT field tiled
+    4 x 4 x 4 plus seeded noise (so no 128-periodicity is left), in seconds rather
+    than the minutes of a 512^3 spectral synthesis."""
+    case("512^3 rhs at sampled points (Re=1600), fp64 and mixed")
+    n, mu = 512, 1.0 / 1600
+    rho0, vel0, p0 = I.hit_primitives(128, 0, 0.3)
+    rng = np.random.default_rng(11)
+    rho = np.tile(rho0, (4, 4, 4)) * (1.0 + 1e-3 * rng.standard_normal((n, n, n)))
+    p = np.tile(p0, (4, 4, 4)) * (1.0 + 1e-3 * rng.standard_normal((n, n, n)))
+    vel = np.tile(vel0, (1, 4, 4, 4)) + 1e-2 * rng.standard_normal((3, n, n, n))
+    ph = orc.make_phys(mu_eff=mu)
+    u_ref = orc.init_state(rho, vel, p)
+    edge = [0, 1, 2, 255, 256, 509, 510, 511]
+    pts = [(i, j, k) for i in (0, 511) for j in (0, 511) for k in (0, 511)]
+    pts += [tuple(int(x) for x in rng.choice(edge, 3)) for _ in range(64)]
+    pts += [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(192)]
+    ref = np.array([orc.rhs_point(u_ref, i, j, k, ph) for (i, j, k) in pts])  # [npts][5]
+    for precision in ("fp64", "mixed"):
+        plan = Plan((n, n, n), mu_eff=mu, precision=precision)
+        u = plan.init_state(rho, vel, p)
+        r = plan.rhs(u).double()
+        scale = float(r.abs().max())
+        # conservation: every component sums to zero up to round-off of the sum
+        sums = r.sum(dim=(1, 2, 3)).abs() / r.abs().sum(dim=(1, 2, 3))
+        ii, jj, kk = (torch.tensor([q[c] for q in pts], device=r.device) for c in range(3))
+        got = r[:, kk, jj, ii].T.cpu().numpy()  # [npts][5]
+        err = float(np.abs(got - ref).max()) / scale
+        if precision == "fp64":
+            tol = 1e-12
+        else:
+            h = 2 * math.pi / n
+            tol = 100 * 2.0 ** -24 * float(np.abs(u_ref).max()) / (h * scale)
+        print(f"512^3 {precision} rhs sampled rel err {err:.3e} (bound {tol:.1e}); "
+              f"max |sum| / sum |.| {float(sums.max()):.1e}")
+        assert err <= tol
+        assert float(sums.max()) <= (1e-12 if precision == "fp64" else 1e-5)
+        if precision == "fp64":
+            d0 = plan.diagnostics_host(u)
+            dt = I.dt_from_speed(d0[7], n)
+            d1 = plan.rk4(u, dt, 1).cpu().numpy()[0]
+            assert abs(d1[2] - d0[2]) <= 1e-12 * abs(d0[2])
+            assert d1[8] == 0
+        del plan, u, r
+        torch.cuda.empty_cache()
+
+
 def test_vortex_one_period_converges():
     # Euler, isentropic vortex advected over one full period of the box, compared
     # with the exact (translated) solution at 64^2 and 128^2 (thin slab nz = 8: the

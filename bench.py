@@ -406,8 +406,8 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
 
 
 def bench_options(n=128, steps=20):
-    """The same 128^3 workload with the TVD-RK3 integrator and with WENO-Z weights, and
-    the time of one energy spectrum (128^3 and 512^3)."""
+    """The same 128^3 workload with the TVD-RK3 integrator, with WENO-Z and with mapped
+    weights, the RHS alone, and the time of one energy spectrum (128^3 and 512^3)."""
     import torch
 
     from paper_2211_16718_amd import inputs as I
@@ -427,6 +427,12 @@ def bench_options(n=128, steps=20):
     pz.rk4(pz.empty_state().copy_(uz), dt, 1, diag=False)
     sec, _ = _timed(pz.stream, lambda: pz.rk4(uz, dt, steps))
     out["rk4_wenoz"] = {"value": 4.0 * n ** 3 * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps}
+    pm = Plan((n, n, n), mu_eff=1.0 / wl.re, weno="m")
+    um = pm.init_state(rho, vel, p)
+    pm.rk4(pm.empty_state().copy_(um), dt, 1, diag=False)
+    sec, _ = _timed(pm.stream, lambda: pm.rk4(um, dt, steps))
+    out["rk4_wenom"] = {"value": 4.0 * n ** 3 * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps}
+    del pm, um
     # the RHS alone (cns_rhs: viscous fluxes and the three sweeps, no stage update)
     r = plan.empty_state()
     plan.rhs(u, r)

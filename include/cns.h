@@ -64,11 +64,12 @@ typedef struct {
     double mu_eff;       /* mu * M_inf / Re_inf (Sec. 2.1 scaling); 0 = Euler (viscous terms skipped) */
     double weno_eps;     /* epsilon of the WENO weights, > 0 (paper: 1e-6) */
     double harten_delta; /* Harten threshold delta >= 0; 0 = plain |lambda| */
-    int32_t weno_weights; /* CNS_WENO_JS (Sec. 2.2: Jiang-Shu) or CNS_WENO_Z (Borges et al. 2008,
-                             exponent 2; one of the low-dissipation successors the paper names) */
+    int32_t weno_weights; /* CNS_WENO_JS (Sec. 2.2: Jiang-Shu), CNS_WENO_Z (Borges et al. 2008,
+                             exponent 2) or CNS_WENO_M (mapped, Henrick et al. 2005): the two
+                             improved nonlinear weights the paper cites (Sec. 1) */
 } cns_physics;
 
-enum { CNS_WENO_JS = 0, CNS_WENO_Z = 1 };
+enum { CNS_WENO_JS = 0, CNS_WENO_Z = 1, CNS_WENO_M = 2 };
 
 enum { CNS_FP64 = 0, CNS_MIXED = 1 };
 

@@ -63,7 +63,8 @@ static int check_grid(const orc_grid *g, const orc_phys *ph) {
     if (!(g->lx > 0 && g->ly > 0 && g->lz > 0)) return ORC_EINVAL;
     if (ph && !(ph->gamma > 1.0 && ph->mu_eff >= 0.0 && ph->weno_eps > 0.0 && ph->harten_delta >= 0.0))
         return ORC_EINVAL;
-    if (ph && ph->weno_weights != ORC_WENO_JS && ph->weno_weights != ORC_WENO_Z) return ORC_EINVAL;
+    if (ph && ph->weno_weights != ORC_WENO_JS && ph->weno_weights != ORC_WENO_Z && ph->weno_weights != ORC_WENO_M)
+        return ORC_EINVAL;
     if (ph && ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return ORC_EINVAL;
     return ORC_OK;
 }
@@ -160,6 +161,37 @@ double oracle_weno5z(double a, double b, double c, double d, double e, double ep
         parts[8] = fhat3;
     }
     return w1 * fhat1 + w2 * fhat2 + w3 * fhat3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Mapped WENO weights (Henrick, Aslam & Powers, J. Comput. Phys. 207, 2005),  */
+/* the other improvement of the nonlinear weights the paper cites: the Jiang-  */
+/* Shu weights w_k pass through g_k(w) = w (d_k + d_k^2 - 3 d_k w + w^2) /    */
+/* (d_k^2 + w (1 - 2 d_k)), d_k the optimal weight, and are renormalised.      */
+/* ------------------------------------------------------------------------- */
+double oracle_weno_map(double w, double d) {
+    return w * (d + d * d - 3.0 * d * w + w * w) / (d * d + w * (1.0 - 2.0 * d));
+}
+
+double oracle_weno5m(double a, double b, double c, double d, double e, double eps, double *parts) {
+    double js[9];
+    oracle_weno5(a, b, c, d, e, eps, js); /* candidates, indicators, Jiang-Shu weights */
+    const double dk[3] = {0.1, 0.6, 0.3};
+    double g[3], gsum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        g[k] = oracle_weno_map(js[3 + k], dk[k]);
+        gsum += g[k];
+    }
+    double w[3];
+    for (int k = 0; k < 3; ++k) w[k] = g[k] / gsum;
+    if (parts) {
+        for (int k = 0; k < 3; ++k) {
+            parts[k] = js[k];
+            parts[3 + k] = w[k];
+            parts[6 + k] = js[6 + k];
+        }
+    }
+    return w[0] * js[6] + w[1] * js[7] + w[2] * js[8];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -273,7 +305,7 @@ double oracle_harten(double lam, double delta) {
 int oracle_interface_flux(const double *s, int dir, const orc_phys *ph, double *F) {
     const double gamma = ph->gamma, eps = ph->weno_eps;
     double (*W)(double, double, double, double, double, double, double *) =
-        ph->weno_weights == ORC_WENO_Z ? oracle_weno5z : oracle_weno5;
+        ph->weno_weights == ORC_WENO_Z ? oracle_weno5z : (ph->weno_weights == ORC_WENO_M ? oracle_weno5m : oracle_weno5);
     double f[6][5];
     for (int m = 0; m < 6; ++m) oracle_flux(s + 5 * m, dir, gamma, f[m]);
 

@@ -45,11 +45,12 @@ typedef struct {
     double mu_eff;       /* mu * M_inf / Re_inf; 0 disables the viscous terms */
     double weno_eps;     /* epsilon of the WENO weights (paper: 1e-6) */
     double harten_delta; /* Harten entropy-fix threshold; 0 gives the plain |lambda| */
-    int weno_weights;    /* ORC_WENO_JS (the paper's Jiang-Shu weights) or ORC_WENO_Z */
+    int weno_weights;    /* ORC_WENO_JS (the paper's Jiang-Shu weights), ORC_WENO_Z or ORC_WENO_M */
 } orc_phys;
 
 #define ORC_WENO_JS 0
 #define ORC_WENO_Z 1
+#define ORC_WENO_M 2
 
 /* ---- building blocks (exported so tests can pin each one) ---- */
 
@@ -61,6 +62,12 @@ double oracle_weno5(double a, double b, double c, double d, double e, double eps
 /* Same with the WENO-Z weights of Borges et al. (2008), exponent 2:
  * alpha_k = c_k (1 + (|beta1 - beta3| / (eps + beta_k))^2). */
 double oracle_weno5z(double a, double b, double c, double d, double e, double eps, double *parts);
+
+/* Same with the mapped weights of Henrick et al. (2005): the Jiang-Shu weights w_k
+ * mapped by g_k (oracle_weno_map with d_k = 1/10, 6/10, 3/10) and renormalised. */
+double oracle_weno5m(double a, double b, double c, double d, double e, double eps, double *parts);
+/* The mapping g(w) = w (d + d^2 - 3 d w + w^2) / (d^2 + w (1 - 2 d)). */
+double oracle_weno_map(double w, double d);
 
 /* Euler flux along dir (0=x,1=y,2=z) of the conserved state u[5]. */
 void oracle_flux(const double *u, int dir, double gamma, double *f);

@@ -48,6 +48,10 @@ def lib():
         L.oracle_weno5.argtypes = [C.c_double] * 6 + [_dp]
         L.oracle_weno5z.restype = C.c_double
         L.oracle_weno5z.argtypes = [C.c_double] * 6 + [_dp]
+        L.oracle_weno5m.restype = C.c_double
+        L.oracle_weno5m.argtypes = [C.c_double] * 6 + [_dp]
+        L.oracle_weno_map.restype = C.c_double
+        L.oracle_weno_map.argtypes = [C.c_double, C.c_double]
         L.oracle_flux.restype = None
         L.oracle_flux.argtypes = [_dp, C.c_int, C.c_double, _dp]
         L.oracle_roe_eigensystem.argtypes = [_dp, _dp, C.c_int, C.c_double, _dp, _dp, _dp]
@@ -82,7 +86,7 @@ def make_grid(shape, length=(2 * math.pi,) * 3) -> Grid:
     return Grid(nx, ny, nz, length[0], length[1], length[2])
 
 
-WENO_JS, WENO_Z = 0, 1
+WENO_JS, WENO_Z, WENO_M = 0, 1, 2
 
 
 def make_phys(gamma=1.4, prandtl=0.72, mu_eff=0.01, weno_eps=1e-6, harten_delta=1e-6, weno_weights=WENO_JS) -> Phys:
@@ -91,11 +95,16 @@ def make_phys(gamma=1.4, prandtl=0.72, mu_eff=0.01, weno_eps=1e-6, harten_delta=
 
 def weno5(a, b, c, d, e, eps=1e-6, parts=False, weights=WENO_JS):
     buf = (C.c_double * 9)()
-    fn = lib().oracle_weno5z if weights == WENO_Z else lib().oracle_weno5
+    fn = {WENO_JS: lib().oracle_weno5, WENO_Z: lib().oracle_weno5z, WENO_M: lib().oracle_weno5m}[weights]
     r = fn(a, b, c, d, e, eps, buf)
     if parts:
         return r, np.array(buf[:])
     return r
+
+
+def weno_map(w, d):
+    """The weight mapping of the mapped WENO weights (Henrick et al. 2005)."""
+    return lib().oracle_weno_map(w, d)
 
 
 def flux(u, direction, gamma=1.4):

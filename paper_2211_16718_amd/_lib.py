@@ -19,6 +19,7 @@ CNS_MIXED = 1
 CNS_RK4 = 0
 CNS_WENO_JS = 0
 CNS_WENO_Z = 1
+CNS_WENO_M = 2
 CNS_TVDRK3 = 1
 CNS_NKERNEL = 6
 KERNEL_NAMES = ("visc_prim", "visc_flux", "sweep_x", "sweep_y", "sweep_z_rk4", "diagnostics")

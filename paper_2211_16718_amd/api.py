@@ -24,8 +24,9 @@ def _ptr(t: torch.Tensor) -> int:
 
 
 def _weno_code(weno):
-    """``"js"``: Jiang-Shu weights (the paper's); ``"z"``: WENO-Z weights."""
-    return {"js": _lib.CNS_WENO_JS, "z": _lib.CNS_WENO_Z}[weno]
+    """``"js"``: Jiang-Shu weights (the paper's); ``"z"``: WENO-Z weights (Borges et al.
+    2008); ``"m"``: mapped weights (Henrick et al. 2005)."""
+    return {"js": _lib.CNS_WENO_JS, "z": _lib.CNS_WENO_Z, "m": _lib.CNS_WENO_M}[weno]
 
 
 class Plan:

@@ -54,7 +54,7 @@ static int validate(const cns_grid *g, const cns_physics *ph) {
     if (ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return set_err(CNS_EINVAL, "prandtl must be > 0");
     if (!(ph->weno_eps > 0.0)) return set_err(CNS_EINVAL, "weno_eps must be > 0");
     if (!(ph->harten_delta >= 0.0)) return set_err(CNS_EINVAL, "harten_delta must be >= 0");
-    if (ph->weno_weights != CNS_WENO_JS && ph->weno_weights != CNS_WENO_Z)
+    if (ph->weno_weights != CNS_WENO_JS && ph->weno_weights != CNS_WENO_Z && ph->weno_weights != CNS_WENO_M)
         return set_err(CNS_EINVAL, "unknown weno_weights %d", ph->weno_weights);
     return CNS_OK;
 }
@@ -82,7 +82,7 @@ struct Core {
     int rowP = 1;
     size_t rowLds = 0;
     bool any_visc = false;
-    bool wz = false;
+    int weights = CNS_WENO_JS;
     Prof prof;
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;
@@ -150,7 +150,7 @@ struct Core {
         b.eps = ph.weno_eps;
         b.delta = ph.harten_delta;
         b.dt = dt;
-        wz = ph.weno_weights == CNS_WENO_Z;
+        weights = ph.weno_weights;
         boxes.push_back(b);
         ustate.push_back(u);
         active.push_back(1);
@@ -220,7 +220,7 @@ struct Core {
         bt.prec = prec;
         bt.block = block;
         bt.any_visc = any_visc;
-        bt.wz = wz;
+        bt.weights = weights;
         bt.d_boxes = (const BoxDesc *)(ws + table_off);
         const long long *offs = (const long long *)(ws + table_off + nbox() * sizeof(BoxDesc));
         for (int f = 0; f < F_N; ++f) {
@@ -790,7 +790,7 @@ static int adj_check(const cns_plan *plan) {
     int rc = check_plan(plan);
     if (rc) return rc;
     if (plan->c.prec != CNS_FP64) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for FP64 plans only");
-    if (plan->c.wz) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for the Jiang-Shu weights only");
+    if (plan->c.weights != CNS_WENO_JS) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for the Jiang-Shu weights only");
     return CNS_OK;
 }
 

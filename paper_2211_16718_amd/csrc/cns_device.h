@@ -19,6 +19,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "cns.h"
+
 namespace cns {
 
 struct PhysT {
@@ -73,22 +75,26 @@ __device__ __forceinline__ T harten_abs(T lam, T delta, T h) {
 // WENO5, left- and right-biased values at j+1/2 from q_{j-2} .. q_{j+3}
 // ---------------------------------------------------------------------------
 // Nonlinear weights of one reconstruction from its three indicators b1..b3 (in B) and
-// candidates c1..c3 (any common scale of b and eps, and of the c, passes through):
-// Jiang-Shu alpha_k = c_k / s_k^2, s_k = eps + b_k, or (WZ) the
-// WENO-Z weights of Borges et al. (2008), alpha_k = c_k (1 + (tau5/s_k)^2) with
-// tau5 = |b1 - b3|.  Both are scaled by s_1^2 s_2^2 s_3^2 so one reciprocal serves the
-// three weights.  The Z weights carry one more factor s^2, so they are formed in B
-// (FP64) and normalised before any narrowing.
-template <typename T, typename B, bool WZ>
+// candidates c1..c3 (any common scale of b and eps, and of the c, passes through).
+// WW selects the weights: CNS_WENO_JS, Jiang-Shu alpha_k = c_k / s_k^2 with
+// s_k = eps + b_k; CNS_WENO_Z, the WENO-Z weights of Borges et al. (2008),
+// alpha_k = c_k (1 + (tau5/s_k)^2) with tau5 = |b1 - b3|; CNS_WENO_M, the mapped
+// weights of Henrick et al. (2005), the Jiang-Shu weights w_k passed through
+// g_k(w) = w (c_k + c_k^2 - 3 c_k w + w^2) / (c_k^2 + w (1 - 2 c_k)) and renormalised.
+// The alpha are scaled by s_1^2 s_2^2 s_3^2, the mapped values by the product of the
+// three denominators, so one reciprocal serves the three weights of each
+// normalisation.  The Z and mapped weights are formed in B (FP64) and normalised
+// before any narrowing.
+template <typename T, typename B, int WW>
 __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, T c3) {
-    if constexpr (!WZ) {
+    if constexpr (WW == CNS_WENO_JS) {
         // 10 alpha_k s1^2 s2^2 s3^2 = (d2 d3, 6 d1 d3, 3 d1 d2) with d_k = s_k^2
         T s1 = eps + T(b1), s2 = eps + T(b2), s3 = eps + T(b3);
         T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
         T a1 = d2 * d3, a2 = d1 * d3, a3 = d1 * d2;
         T num = a1 * c1 + a2 * (T(6) * c2) + a3 * (T(3) * c3);
         return num * rcp(a1 + T(6) * a2 + T(3) * a3);
-    } else {
+    } else if constexpr (WW == CNS_WENO_Z) {
         const B e = B(eps);
         B t = fabs(b1 - b3);
         B t2 = t * t;
@@ -101,6 +107,25 @@ __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, 
             B ia = rcp(a1 + a2 + a3);
             return T(a1 * ia) * c1 + T(a2 * ia) * c2 + T(a3 * ia) * c3;
         }
+    } else {
+        static_assert(WW == CNS_WENO_M, "unknown WENO weights");
+        const B e = B(eps);
+        B s1 = e + b1, s2 = e + b2, s3 = e + b3;
+        B d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+        B a1 = B(0.1) * (d2 * d3), a2 = B(0.6) * (d1 * d3), a3 = B(0.3) * (d1 * d2);
+        B ia = rcp(a1 + a2 + a3);
+        B w1 = a1 * ia, w2 = a2 * ia, w3 = a3 * ia;  // Jiang-Shu weights
+        // g_k = N_k / D_k with c = 1/10, 6/10, 3/10
+        B N1 = w1 * (B(0.1) + B(0.1) * B(0.1) - B(0.3) * w1 + w1 * w1), D1 = B(0.1) * B(0.1) + w1 * B(0.8);
+        B N2 = w2 * (B(0.6) + B(0.6) * B(0.6) - B(1.8) * w2 + w2 * w2), D2 = B(0.6) * B(0.6) + w2 * B(-0.2);
+        B N3 = w3 * (B(0.3) + B(0.3) * B(0.3) - B(0.9) * w3 + w3 * w3), D3 = B(0.3) * B(0.3) + w3 * B(0.4);
+        B g1 = N1 * (D2 * D3), g2 = N2 * (D1 * D3), g3 = N3 * (D1 * D2);
+        B ig = rcp(g1 + g2 + g3);
+        if constexpr (sizeof(T) == sizeof(B)) {
+            return (g1 * c1 + g2 * c2 + g3 * c3) * ig;
+        } else {
+            return T(g1 * ig) * c1 + T(g2 * ig) * c2 + T(g3 * ig) * c3;
+        }
     }
 }
 
@@ -108,7 +133,7 @@ __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, 
 // indicators: with eps4 = 4 eps every alpha_k scales by the same 1/16, so the weights
 // are those of the plain form; dropping the 1/6 of the candidates and the 13/12, 1/4 of
 // the indicators saves a multiplication per candidate and per indicator.
-template <typename T, typename B, bool WZ = false>
+template <typename T, typename B, int WW = CNS_WENO_JS>
 __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T eps4, T &L6, T &R6) {
     // third-order candidates (times 6); the mirror reconstruction reuses L2 and L3
     T L1 = T(2) * m2 - T(7) * m1 + T(11) * c0;
@@ -137,15 +162,15 @@ __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T 
     B bR2 = qc + fb * fb;
     B bR3 = qb + fc * fc;
 
-    L6 = weno5_combine<T, B, WZ>(bL1, bL2, bL3, eps4, L1, L2, L3);
-    R6 = weno5_combine<T, B, WZ>(bR1, bR2, bR3, eps4, R1, L3, L2);
+    L6 = weno5_combine<T, B, WW>(bL1, bL2, bL3, eps4, L1, L2, L3);
+    R6 = weno5_combine<T, B, WW>(bR1, bR2, bR3, eps4, R1, L3, L2);
 }
 
 // the left- and right-biased values themselves
-template <typename T, typename B, bool WZ = false>
+template <typename T, typename B, int WW = CNS_WENO_JS>
 __device__ __forceinline__ void weno5_lr(T m2, T m1, T c0, T p1, T p2, T p3, T eps, T &L, T &R) {
     T L6, R6;
-    weno5_lr6<T, B, WZ>(m2, m1, c0, p1, p2, p3, T(4) * eps, L6, R6);
+    weno5_lr6<T, B, WW>(m2, m1, c0, p1, p2, p3, T(4) * eps, L6, R6);
     L = L6 * (T(1) / T(6));
     R = R6 * (T(1) / T(6));
 }

@@ -102,7 +102,7 @@ struct Batch {
     int prec = CNS_FP64;
     int block = 256;  // threads per block of the marching sweeps
     bool any_visc = false;
-    bool wz = false;  // WENO-Z weights (every box of a batch uses the same weights)
+    int weights = CNS_WENO_JS;  // WENO weights (every box of a batch uses the same)
     const BoxDesc *d_boxes = nullptr;  // device table
     const long long *d_off[F_N] = {};  // device prefixes
     long long total[F_N] = {};

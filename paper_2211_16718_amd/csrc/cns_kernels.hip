@@ -241,15 +241,15 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
 // (VISC) the viscous fluxes g at j-1 .. j+2:
 //   H = (f^L + f^R)/2 - |A| (u^R - u^L)/2 - (-g_{j-1} + 7 g_j + 7 g_{j+1} - g_{j+2})/12
 // ----------------------------------------------------------------------------
-template <typename T, typename B, int DIR, bool VISC, bool WZ>
+template <typename T, typename B, int DIR, bool VISC, int WW>
 __device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5], const T g[4][4], T gamma, T eps4,
                                                T delta, T H[5]) {
     // six-fold reconstructions (eps4 = 4 eps); D is linear in du, so H = (6 F - 6 D) / 12
     T FL[5], FR[5], UL[5], UR[5], du[5], D[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        weno5_lr6<T, B, WZ>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps4, FL[v], FR[v]);
-        weno5_lr6<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps4, UL[v], UR[v]);
+        weno5_lr6<T, B, WW>(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], f[5][v], eps4, FL[v], FR[v]);
+        weno5_lr6<T, B, WW>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps4, UL[v], UR[v]);
         du[v] = UR[v] - UL[v];
     }
     roe_dissipation<T, DIR>(w[2], w[3], du, gamma, delta, D);
@@ -267,7 +267,7 @@ __device__ __forceinline__ void interface_flux(const T w[6][5], const T f[6][5],
 // between components keeps the scheduler from hoisting all thirty LDS reads, which
 // would hold them in registers across the whole reconstruction.  Same arithmetic, in
 // the same order, as interface_flux.
-template <typename T, typename B, int DIR, bool VISC, bool WZ>
+template <typename T, typename B, int DIR, bool VISC, int WW>
 __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ring, const int sl[6], int bdim,
                                                     const T g[4][4], T gamma, T eps4, T delta, T H[5]) {
     T Fs[5], du[5], D[5];
@@ -277,8 +277,8 @@ __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ri
 #pragma unroll
         for (int m = 0; m < 6; ++m) fm[m] = ring[(sl[m] * 5 + v) * bdim];
         T FL, FR, UL, UR;
-        weno5_lr6<T, B, WZ>(fm[0], fm[1], fm[2], fm[3], fm[4], fm[5], eps4, FL, FR);
-        weno5_lr6<T, B, WZ>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps4, UL, UR);
+        weno5_lr6<T, B, WW>(fm[0], fm[1], fm[2], fm[3], fm[4], fm[5], eps4, FL, FR);
+        weno5_lr6<T, B, WW>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps4, UL, UR);
         Fs[v] = FL + FR;
         du[v] = UR - UL;
         __builtin_amdgcn_sched_barrier(0);
@@ -297,7 +297,7 @@ __device__ __forceinline__ void interface_flux_ring(const T w[6][5], const T *ri
 // (component-major arrays of `per` points; q[m] is the position of point i-2+m), one
 // component at a time behind a scheduling fence, so that the reconstruction holds
 // only the operands of the component in flight.
-template <typename T, typename B, int DIR, bool VISC, bool WZ>
+template <typename T, typename B, int DIR, bool VISC, int WW>
 __device__ __forceinline__ void interface_flux_lds(const T *su, const T *sf, const T *sg, int per, const int q[6],
                                                    T gamma, T eps4, T delta, T H[5]) {
     T Fs[5], du[5], D[5];
@@ -305,8 +305,8 @@ __device__ __forceinline__ void interface_flux_lds(const T *su, const T *sf, con
     for (int v = 0; v < 5; ++v) {
         const T *fv = sf + v * per, *uv = su + v * per;
         T FL, FR, UL, UR;
-        weno5_lr6<T, B, WZ>(fv[q[0]], fv[q[1]], fv[q[2]], fv[q[3]], fv[q[4]], fv[q[5]], eps4, FL, FR);
-        weno5_lr6<T, B, WZ>(uv[q[0]], uv[q[1]], uv[q[2]], uv[q[3]], uv[q[4]], uv[q[5]], eps4, UL, UR);
+        weno5_lr6<T, B, WW>(fv[q[0]], fv[q[1]], fv[q[2]], fv[q[3]], fv[q[4]], fv[q[5]], eps4, FL, FR);
+        weno5_lr6<T, B, WW>(uv[q[0]], uv[q[1]], uv[q[2]], uv[q[3]], uv[q[4]], uv[q[5]], eps4, UL, UR);
         Fs[v] = FL + FR;
         du[v] = UR - UL;
         __builtin_amdgcn_sched_barrier(0);
@@ -358,7 +358,7 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
 // point's rhs, issued before the interface-flux arithmetic so their latency overlaps
 // it (y sweep 12 % and fused-update sweep 6 % faster than a register window).  The
 // fused update's u^n and accumulator are loaded ahead in the same way.
-template <typename T, typename B, int DIR, int MODE, bool VISC, bool WZ>
+template <typename T, typename B, int DIR, int MODE, bool VISC, int WW>
 __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
     extern __shared__ unsigned char lds_raw[];
     T *ring = reinterpret_cast<T *>(lds_raw) + threadIdx.x;  // slot s, component v at (s * 5 + v) * blockDim.x
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     const int sm = sold + 1 + m;  // slot of point j-2+m (point j+3 is in sold)
                     sl[m] = sm >= 6 ? sm - 6 : sm;
                 }
-                interface_flux_ring<T, B, DIR, VISC, WZ>(w, ring, sl, bdim, g, gamma, eps4, delta, H);
+                interface_flux_ring<T, B, DIR, VISC, WW>(w, ring, sl, bdim, g, gamma, eps4, delta, H);
             }
             if (j >= j0) {
                 if constexpr (MODE == MODE_RK) {
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 // 256 threads, each thread handling up to P points.  Every interface of a row is
 // computed once; the periodic wrap happens in LDS.
 // ----------------------------------------------------------------------------
-template <typename T, typename B, bool VISC, int P, bool WZ>
+template <typename T, typename B, bool VISC, int P, int WW>
 __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
                 int q[6];
 #pragma unroll
                 for (int m = 0; m < 6; ++m) q[m] = rb + wrapi(i - 2 + m, nx);
-                interface_flux_lds<T, B, 0, VISC, WZ>(su, sf, sg, per, q, gamma, eps4, delta, H[k]);  // at i+1/2
+                interface_flux_lds<T, B, 0, VISC, WW>(su, sf, sg, per, q, gamma, eps4, delta, H[k]);  // at i+1/2
             }
         }
         __syncthreads();  // every thread has read the staged states
@@ -918,8 +918,12 @@ template <typename T, int DIR, int MODE, bool VISC>
 static void sweep_t(const Batch &bt, const Launch &L) {
     const dim3 g(grid_for(L.total)), b(bt.block);
     const size_t ring = 30 * (size_t)bt.block * sizeof(T);  // point-flux ring, 6 slots x 5 per thread
-    if (bt.wz) hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, true>), g, b, ring, bt.stream, L);
-    else hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, false>), g, b, ring, bt.stream, L);
+    if (bt.weights == CNS_WENO_Z)
+        hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, CNS_WENO_Z>), g, b, ring, bt.stream, L);
+    else if (bt.weights == CNS_WENO_M)
+        hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, CNS_WENO_M>), g, b, ring, bt.stream, L);
+    else
+        hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, CNS_WENO_JS>), g, b, ring, bt.stream, L);
 }
 
 template <typename T, int MODE>
@@ -937,23 +941,24 @@ static void sweep(const Batch &bt, Launch L, int dir, bool visc) {
     }
 }
 
-template <typename T, bool VISC, bool WZ>
+template <typename T, bool VISC, int WW>
 static void xrows_tw(const Batch &bt, const Launch &L) {
     // about four row groups per block when the loads of the next one are prefetched
     const long long nb = bt.rowP == 1 ? std::max<long long>(std::min<long long>(L.total, 2048), L.total / 4) : L.total;
     const dim3 g(grid_for(nb)), b(kRowThreads);
     switch (bt.rowP) {
-        case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1, WZ>), g, b, bt.rowLds, bt.stream, L); break;
-        case 2: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 2, WZ>), g, b, bt.rowLds, bt.stream, L); break;
-        case 3: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 3, WZ>), g, b, bt.rowLds, bt.stream, L); break;
-        default: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 4, WZ>), g, b, bt.rowLds, bt.stream, L); break;
+        case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1, WW>), g, b, bt.rowLds, bt.stream, L); break;
+        case 2: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 2, WW>), g, b, bt.rowLds, bt.stream, L); break;
+        case 3: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 3, WW>), g, b, bt.rowLds, bt.stream, L); break;
+        default: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 4, WW>), g, b, bt.rowLds, bt.stream, L); break;
     }
 }
 
 template <typename T, bool VISC>
 static void xrows_t(const Batch &bt, const Launch &L) {
-    if (bt.wz) xrows_tw<T, VISC, true>(bt, L);
-    else xrows_tw<T, VISC, false>(bt, L);
+    if (bt.weights == CNS_WENO_Z) xrows_tw<T, VISC, CNS_WENO_Z>(bt, L);
+    else if (bt.weights == CNS_WENO_M) xrows_tw<T, VISC, CNS_WENO_M>(bt, L);
+    else xrows_tw<T, VISC, CNS_WENO_JS>(bt, L);
 }
 
 // x sweep (always the first, writing sweep): the rows kernel for boxes whose rows fit

@@ -1,5 +1,6 @@
-"""WENO-Z weights on the GPU against the oracle's WENO-Z (same bars as the
-Jiang-Shu parity tests: 1e-12 per RHS evaluation, 1e-10 after RK4 steps)."""
+"""The improved WENO weights on the GPU against the oracle's: WENO-Z (Borges et al.
+2008) and the mapped weights (Henrick et al. 2005); same bars as the Jiang-Shu parity
+tests: 1e-12 per RHS evaluation, 1e-10 after RK4 steps."""
 import numpy as np
 import pytest
 
@@ -20,25 +21,33 @@ def case(msg):
     print(f"[case] {msg}", flush=True)
 
 
+WEIGHTS = ["z", "m"]
+
+
+def oracle_code(orc, weno):
+    return {"z": orc.WENO_Z, "m": orc.WENO_M}[weno]
+
+
 def prims(shape, seed=0, mt=0.3):
     nz, ny, nx = shape
     rho, vel, p = I.hit_primitives(max(shape), seed, mt)
     return tuple(np.ascontiguousarray(a) for a in (rho[:nz, :ny, :nx], vel[:, :nz, :ny, :nx], p[:nz, :ny, :nx]))
 
 
+@pytest.mark.parametrize("weno", WEIGHTS)
 @pytest.mark.parametrize("shape", [(32, 32, 32), (20, 12, 36), (9, 17, 8)])
 @pytest.mark.parametrize("mu", [0.0, 0.02])
-def test_wenoz_rhs_matches_oracle(orc, shape, mu):
-    case(f"wenoz rhs {shape} mu={mu}")
+def test_weights_rhs_matches_oracle(orc, weno, shape, mu):
+    case(f"weno-{weno} rhs {shape} mu={mu}")
     rho, vel, p = prims(shape, 3)
-    ph = orc.make_phys(mu_eff=mu, weno_weights=orc.WENO_Z)
+    ph = orc.make_phys(mu_eff=mu, weno_weights=oracle_code(orc, weno))
     u_ref = orc.init_state(rho, vel, p)
     r_ref = orc.rhs(u_ref, ph)
-    plan = Plan(shape, mu_eff=mu, weno="z")
+    plan = Plan(shape, mu_eff=mu, weno=weno)
     u = plan.init_state(rho, vel, p)
     r = plan.rhs(u).cpu().numpy()
     err = rel_max(r, r_ref)
-    print(f"wenoz rhs rel err {err:.3e}")
+    print(f"weno-{weno} rhs rel err {err:.3e}")
     assert err <= 1e-12
     for d in range(3):
         rd = plan.rhs_dir(u, d).cpu().numpy()
@@ -47,13 +56,14 @@ def test_wenoz_rhs_matches_oracle(orc, shape, mu):
     assert rel_max(r, orc.rhs(u_ref, orc.make_phys(mu_eff=mu))) > 1e-6
 
 
-def test_wenoz_rk4_and_tvdrk3_match_oracle(orc):
-    case("wenoz rk4 / tvdrk3 32^3")
+@pytest.mark.parametrize("weno", WEIGHTS)
+def test_weights_rk4_and_tvdrk3_match_oracle(orc, weno):
+    case(f"weno-{weno} rk4 / tvdrk3 32^3")
     rho, vel, p = prims((32, 32, 32), 4)
-    ph = orc.make_phys(mu_eff=0.01, weno_weights=orc.WENO_Z)
+    ph = orc.make_phys(mu_eff=0.01, weno_weights=oracle_code(orc, weno))
     u_ref = orc.init_state(rho, vel, p)
     dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], 32)
-    plan = Plan((32, 32, 32), mu_eff=0.01, weno="z")
+    plan = Plan((32, 32, 32), mu_eff=0.01, weno=weno)
     u = plan.init_state(rho, vel, p)
     plan.rk4(u, dt, 5)
     assert rel_max(u.cpu().numpy(), orc.rk4(u_ref, dt, 5, ph, with_diag=False)[0]) <= 1e-10
@@ -62,24 +72,26 @@ def test_wenoz_rk4_and_tvdrk3_match_oracle(orc):
     assert rel_max(u.cpu().numpy(), orc.tvdrk3(u_ref, dt, 5, ph, with_diag=False)[0]) <= 1e-10
 
 
-def test_wenoz_mixed_precision(orc):
-    case("wenoz mixed rhs 32^3")
+@pytest.mark.parametrize("weno", WEIGHTS)
+def test_weights_mixed_precision(orc, weno):
+    case(f"weno-{weno} mixed rhs 32^3")
     rho, vel, p = prims((32, 32, 32), 5)
-    ph = orc.make_phys(mu_eff=0.01, weno_weights=orc.WENO_Z)
+    ph = orc.make_phys(mu_eff=0.01, weno_weights=oracle_code(orc, weno))
     r_ref = orc.rhs(orc.init_state(rho, vel, p), ph)
-    plan = Plan((32, 32, 32), mu_eff=0.01, weno="z", precision="mixed")
+    plan = Plan((32, 32, 32), mu_eff=0.01, weno=weno, precision="mixed")
     u = plan.init_state(rho, vel, p)
     err = rel_max(plan.rhs(u).double().cpu().numpy(), r_ref)
-    print(f"mixed wenoz rhs rel err {err:.3e}")
+    print(f"mixed weno-{weno} rhs rel err {err:.3e}")
     assert err <= 2e-5
 
 
-def test_wenoz_option_errors():
-    case("wenoz option errors")
-    boxes = [dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3, weno="z"), dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3)]
+@pytest.mark.parametrize("weno", WEIGHTS)
+def test_weights_option_errors(weno):
+    case(f"weno-{weno} option errors")
+    boxes = [dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3, weno=weno), dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3)]
     with pytest.raises(CnsError):
         Ensemble(boxes)
-    plan = Plan((16, 16, 16), mu_eff=0.01, weno="z")
+    plan = Plan((16, 16, 16), mu_eff=0.01, weno=weno)
     u = plan.init_state(*prims((16, 16, 16)))
     with pytest.raises(CnsError):
         plan.rhs_vjp(u, torch.ones_like(u))

@@ -146,10 +146,11 @@ def test_errors_are_reported(orc):
     assert e.value.code in (-3, -4)
 
 
-def test_wenoz_rhs_invariants_and_convergence(orc):
-    # the WENO-Z operator keeps the exact invariants of the scheme and converges
-    # to the continuous equations at fifth order
-    phz = orc.make_phys(mu_eff=0.0, weno_weights=orc.WENO_Z)
+@pytest.mark.parametrize("weights", ["z", "m"])
+def test_improved_weights_rhs_invariants_and_convergence(orc, weights):
+    # the WENO-Z and mapped-weight operators keep the exact invariants of the scheme
+    # and converge to the continuous equations at fifth order
+    phz = orc.make_phys(mu_eff=0.0, weno_weights={"z": orc.WENO_Z, "m": orc.WENO_M}[weights])
     rho, vel, p = I.uniform_primitives(0, rho=1.3, vel=(0.7, -0.4, 0.2), p=2.1, shape=(9, 12, 10))
     np.testing.assert_array_equal(orc.rhs(orc.init_state(rho, vel, p), phz), 0.0)
     u = hit_state(orc, 16)

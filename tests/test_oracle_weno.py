@@ -200,3 +200,73 @@ def test_wenoz_keeps_fifth_order_at_critical_points(orc):
     oz, oj = orders(orc.WENO_Z), orders(orc.WENO_JS)
     assert min(oz[1:]) > 4.6, oz
     assert max(oj[1:]) < 3.4, oj
+
+
+# ---- mapped weights (Henrick, Aslam & Powers 2005) --------------------------
+def _map_factored(w, d):
+    # g(w) - d = (w - d)^3 / (d^2 + w (1 - 2 d)): the mapping's numerator minus d times
+    # its denominator is (w - d)^3, so d is a triple fixed point (g(d) = d, g' = g'' = 0)
+    return d + (w - d) ** 3 / (d * d + w * (1.0 - 2.0 * d))
+
+
+def test_wenom_mapping_closed_form_and_fixed_points(orc):
+    rng = np.random.default_rng(21)
+    for d in (0.1, 0.6, 0.3):
+        for w in rng.uniform(0.0, 1.0, size=40):
+            assert orc.weno_map(w, d) == pytest.approx(_map_factored(w, d), rel=1e-13, abs=1e-15)
+        assert orc.weno_map(0.0, d) == 0.0
+        assert orc.weno_map(d, d) == pytest.approx(d, rel=1e-15)
+        assert orc.weno_map(1.0, d) == pytest.approx(1.0, rel=1e-15)
+        # flat to second order at d: the deviation shrinks like its cube
+        for dw in (1e-2, 1e-3):
+            assert abs(orc.weno_map(d + dw, d) - d) <= 2.0 * dw ** 3 / (d * d + d * (1 - 2 * d))
+
+
+def test_wenom_weights_are_the_mapped_js_weights(orc):
+    rng = np.random.default_rng(22)
+    for _ in range(50):
+        f = rng.normal(size=5)
+        _, pm = orc.weno5(*f, eps=1e-6, parts=True, weights=orc.WENO_M)
+        _, pj = orc.weno5(*f, eps=1e-6, parts=True)
+        np.testing.assert_array_equal(pm[[0, 1, 2, 6, 7, 8]], pj[[0, 1, 2, 6, 7, 8]])
+        g = np.array([_map_factored(pj[3 + k], dk) for k, dk in enumerate((0.1, 0.6, 0.3))])
+        np.testing.assert_allclose(pm[3:6], g / g.sum(), rtol=1e-12)
+        assert pm[3:6].sum() == pytest.approx(1.0, rel=1e-15) and np.all(pm[3:6] > 0)
+
+
+def test_wenom_recovers_the_linear_weights_on_smooth_data(orc):
+    # smooth data: the JS weights deviate from c by O(h^2); mapped, by O(h^6)
+    x0, dev_j, dev_m = 0.3, [], []
+    for h in (0.1, 0.05):
+        f = [math.sin(x0 + (k - 2) * h) for k in range(5)]
+        _, pj = orc.weno5(*f, eps=1e-40, parts=True)
+        _, pm = orc.weno5(*f, eps=1e-40, parts=True, weights=orc.WENO_M)
+        dev_j.append(np.abs(pj[3:6] - [0.1, 0.6, 0.3]).max())
+        dev_m.append(np.abs(pm[3:6] - [0.1, 0.6, 0.3]).max())
+    assert dev_m[0] < 1e-2 * dev_j[0]
+    assert math.log2(dev_m[0] / dev_m[1]) > 5.0 and math.log2(dev_j[0] / dev_j[1]) < 2.5
+
+
+def test_wenom_rejects_a_discontinuous_stencil(orc):
+    r, parts = orc.weno5(0.0, 0.0, 0.0, 0.0, 1.0, eps=1e-6, parts=True, weights=orc.WENO_M)
+    assert parts[5] < 1e-10 and abs(r) < 1e-10
+
+
+def test_wenom_keeps_fifth_order_at_critical_points(orc):
+    # the test function of Henrick et al. (2005), f' = 0 with f''' != 0: the mapped
+    # weights keep fifth order where the JS weights drop to about third
+    def orders(weights):
+        errs = []
+        for n in (64, 128, 256, 512):
+            h = 2 * math.pi / n
+            x = np.arange(n) * h + 0.1
+            f = np.sin(x - np.sin(x) / math.pi)
+            W = np.array([orc.weno5(f[(j - 2) % n], f[(j - 1) % n], f[j], f[(j + 1) % n], f[(j + 2) % n],
+                                    1e-40, weights=weights) for j in range(n)])
+            d = (W - np.roll(W, 1)) / h
+            ex = np.cos(x - np.sin(x) / math.pi) * (1 - np.cos(x) / math.pi)
+            errs.append(np.abs(d - ex).max())
+        return [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+
+    om = orders(orc.WENO_M)
+    assert min(om[1:]) > 4.6, om

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
 
 // ---------------------------------------------------------------------------
 // Viscous adjoint on the tiles of the forward viscous-flux kernel: a block owns a
-// 64 x 4 (x, y) tile and marches along z over kViscSZ planes; the x and y stencil
+// 32 x 8 (x, y) tile and marches along z over kViscSZ planes; the x and y stencil
 // operands of the current plane sit in LDS (with a +-2 halo), each thread keeps its
 // own column's z operands at planes k-2 .. k+2 in registers.
 //

@@ -24,7 +24,7 @@ constexpr int kDiagThreads = 256;
 constexpr int kDiagBlocksMax = 1024;  // partial-sum blocks per box of the diagnostics
 constexpr int kRowThreads = 256;      // threads per block of the x rows kernel
 constexpr int kRowLdsMax = 64 * 1024;
-constexpr int kViscTX = 64, kViscTY = 4;  // (x, y) tile of the viscous-flux kernel (kPointThreads threads)
+constexpr int kViscTX = 32, kViscTY = 8;  // (x, y) tile of the viscous-flux kernel (kPointThreads threads)
 constexpr int kViscSZ = 16;               // planes per block of the viscous-flux kernel
 
 // buffer roles of a box

@@ -112,7 +112,7 @@ __device__ __forceinline__ void prim_at(const T *u, size_t n3, size_t i, T gamma
 }
 
 // Viscous fluxes at points: the 12 first derivatives of (u, v, w, T) by the 5-point
-// central stencil, then tau, q and G.  A block owns a 64 x 4 (x, y) tile and marches
+// central stencil, then tau, q and G.  A block owns a 32 x 8 (x, y) tile and marches
 // along z over kViscSZ planes: the primitives of the current plane, with a +-2 halo,
 // are formed from the state into LDS (x and y derivatives), and each thread keeps its
 // own column's primitives at planes k-2 .. k+2 in registers (z derivatives).  About
@@ -683,7 +683,7 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
-// the diagnostics walk the box in the tiles of the viscous-flux kernel (64 x 4 columns,
+// the diagnostics walk the box in the tiles of the viscous-flux kernel (32 x 8 columns,
 // kViscSZ planes); one partial-sum block per tile, at most kDiagBlocksMax (then a
 // block takes every kDiagBlocksMax-th tile)
 __host__ __device__ __forceinline__ long long diag_tiles(int nx, int ny, int nz) {
@@ -714,7 +714,7 @@ __device__ __forceinline__ void block_reduce_diag(const double acc[CNS_NDIAG], d
 }
 
 static_assert(kDiagThreads == kViscTX * kViscTY && kPointThreads == kViscTX * kViscTY,
-              "the tiled kernels map one thread to each column of a 64 x 4 tile");
+              "the tiled kernels map one thread to each column of a kViscTX x kViscTY tile");
 
 // velocity m/rho of the state at linear index i (FP64, for the diagnostics)
 template <typename T>

@@ -375,6 +375,16 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const do
             for (int a = 0; a < 4; ++a) Gz[4][a] = Gb[fz[a] * n3 + q];
         }
         const size_t plane = (size_t)k * sz;
+        // the point's own operands, loaded ahead of the plane staging and its barrier
+        const size_t p = plane + t.col;
+        double pa[3], us[5], ub[5];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) pa[a] = Gb[(9 + a) * n3 + p];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            us[v] = u[v * n3 + p];
+            ub[v] = ubar[v * n3 + p];
+        }
         for (int h = threadIdx.x; h < (TX + 4) * TY; h += blockDim.x) {
             const int hx = h % (TX + 4), hy = h / (TX + 4);
             const size_t q = plane + (size_t)min(t.y0 + hy, ny - 1) * nx + wrapn(t.x0 - 2 + hx, nx);
@@ -389,19 +399,18 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const do
         }
         __syncthreads();
         if (t.act) {
-            const size_t p = plane + t.col;
             const int X = t.tx + 2, Y = t.ty + 2;
             double Wb[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                double s = a < 3 ? Gb[(9 + a) * n3 + p] : 0.0;
+                double s = a < 3 ? pa[a] : 0.0;
                 s -= dcen(qx[a][t.ty][X - 2], qx[a][t.ty][X - 1], qx[a][t.ty][X + 1], qx[a][t.ty][X + 2]) * g.ih[0];
                 s -= dcen(qy[a][Y - 2][t.tx], qy[a][Y - 1][t.tx], qy[a][Y + 1][t.tx], qy[a][Y + 2][t.tx]) * g.ih[1];
                 s -= dcen(Gz[0][a], Gz[1][a], Gz[3][a], Gz[4][a]) * g.ih[2];
                 Wb[a] = s;
             }
             // W = (m_k / rho, gamma p / rho), p = (gamma-1)(e - m.v/2)
-            const double r = u[p], m[3] = {u[n3 + p], u[2 * n3 + p], u[3 * n3 + p]}, e = u[4 * n3 + p];
+            const double r = us[0], m[3] = {us[1], us[2], us[3]}, e = us[4];
             const double inv = rcp(r);
             const double v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
             const double qq = m[0] * v[0] + m[1] * v[1] + m[2] * v[2];
@@ -418,11 +427,11 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const do
                 mb[c] = qqb * v[c] + vb * inv;
                 invb += vb * m[c];
             }
-            ubar[p] += -invb * inv * inv;
-            ubar[n3 + p] += mb[0];
-            ubar[2 * n3 + p] += mb[1];
-            ubar[3 * n3 + p] += mb[2];
-            ubar[4 * n3 + p] += eb;
+            ubar[p] = ub[0] + -invb * inv * inv;
+            ubar[n3 + p] = ub[1] + mb[0];
+            ubar[2 * n3 + p] = ub[2] + mb[1];
+            ubar[3 * n3 + p] = ub[3] + mb[2];
+            ubar[4 * n3 + p] = ub[4] + eb;
         }
         __syncthreads();  // the next plane overwrites the LDS tiles
 #pragma unroll

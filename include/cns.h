@@ -211,9 +211,10 @@ size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t
 int cns_rhs_vjp(const cns_plan *plan, const void *u_dev, const void *rbar_dev, void *ubar_dev, void *adj_ws,
                 size_t bytes);
 /* J = K(u^N) after nsteps RK4 steps of size dt from u0 (K = <|m|^2/(2 rho)>), and
- * u0_bar = dJ/du0.  Checkpoints every ckpt_every steps; each segment is recomputed
- * from its checkpoint, each step's stage states from its start state.  J_dev (may
- * be NULL): one device double. */
+ * u0_bar = dJ/du0.  Checkpoints every ckpt_every steps; the reverse sweep takes one
+ * segment at a time, recomputed from its checkpoint (the last one is kept during the
+ * forward pass) with the start and stage states of each of its steps kept.  J_dev
+ * (may be NULL): one device double. */
 int cns_adjoint_rk4(cns_plan *plan, const void *u0_dev, double dt, int32_t nsteps, int32_t ckpt_every,
                     void *adj_ws, size_t bytes, double *J_dev, void *u0_bar_dev);
 /* Transpose of the initial-state map at fixed rho and p:

@@ -144,7 +144,6 @@ bool spectrum_supported(const BoxDesc &b);
 void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, double *E, int nshell, double *mom);
 
 // adjoint launchers (cns_adjoint.hip), FP64, one box
-// ubar = (dR/du)^T rbar at u; scratch W [4][n3], C [30][n3], Gb [15][n3]
 // adjoint of the full RHS at u: ubar = (dR/du)^T rbar; Gb: kAdjGbFields x n3 scratch
 constexpr int kAdjGbFields = 12;
 void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *Gb);

@@ -217,6 +217,11 @@ int cns_rhs_vjp(const cns_plan *plan, const void *u_dev, const void *rbar_dev, v
  * (may be NULL): one device double. */
 int cns_adjoint_rk4(cns_plan *plan, const void *u0_dev, double dt, int32_t nsteps, int32_t ckpt_every,
                     void *adj_ws, size_t bytes, double *J_dev, void *u0_bar_dev);
+/* The same for nsteps steps of the three-stage TVD Runge-Kutta scheme (Shu-Osher form,
+ * as cns_tvdrk3), the integrator of the paper's production runs; the same workspace
+ * (cns_adjoint_workspace_bytes covers either integrator). */
+int cns_adjoint_tvdrk3(cns_plan *plan, const void *u0_dev, double dt, int32_t nsteps, int32_t ckpt_every,
+                       void *adj_ws, size_t bytes, double *J_dev, void *u0_bar_dev);
 /* Transpose of the initial-state map at fixed rho and p:
  * vbar_i = rho (mbar_i + ebar v_i); rho[N3], vel[3][N3], ubar[5][N3] -> vbar[3][N3]. */
 int cns_ic_vjp(const cns_plan *plan, const double *rho_dev, const double *vel_dev, const double *ubar_dev,

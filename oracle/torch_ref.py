@@ -179,6 +179,13 @@ def rk4_step(u, dt, ph):
     return u + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
+def tvdrk3_step(u, dt, ph):
+    """Three-stage TVD Runge-Kutta step in Shu-Osher form (Sec. 5 integrator)."""
+    u1 = u + dt * rhs(u, ph)
+    u2 = 0.75 * u + 0.25 * (u1 + dt * rhs(u1, ph))
+    return (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + dt * rhs(u2, ph))
+
+
 def kinetic_energy(u):
     return 0.5 * ((u[1] ** 2 + u[2] ** 2 + u[3] ** 2) / u[0]).mean()
 
@@ -193,15 +200,17 @@ def make_phys(gamma=1.4, prandtl=0.72, mu=0.01, eps=1e-6, delta=1e-6, length=(2 
     return dict(gamma=gamma, prandtl=prandtl, mu=mu, eps=eps, delta=delta, length=length)
 
 
-def final_ke_and_grad(rho, vel, p, dt, nsteps, ph):
-    """J = K(u^N) after nsteps RK4 steps from the primitives, and dJ/dvel (with rho
-    and p held fixed), by reverse-mode AD with per-step recomputation."""
+def final_ke_and_grad(rho, vel, p, dt, nsteps, ph, step=None):
+    """J = K(u^N) after nsteps steps (RK4 unless ``step`` is given) from the primitives,
+    and dJ/dvel (with rho and p held fixed), by reverse-mode AD with per-step
+    recomputation."""
+    step = rk4_step if step is None else step
     vel = torch.as_tensor(vel, dtype=torch.float64).clone().requires_grad_(True)
     rho = torch.as_tensor(rho, dtype=torch.float64)
     p = torch.as_tensor(p, dtype=torch.float64)
     u = ic_state(rho, vel, p, ph["gamma"])
     for _ in range(nsteps):
-        u = tcp.checkpoint(rk4_step, u, dt, ph, use_reentrant=False)
+        u = tcp.checkpoint(step, u, dt, ph, use_reentrant=False)
     J = kinetic_energy(u)
     (gv,) = torch.autograd.grad(J, vel)
     return float(J), gv.detach()
@@ -215,11 +224,12 @@ def rhs_vjp(u, rbar, ph):
     return g.detach()
 
 
-def rk4_vjp(u, ubar, dt, nsteps, ph):
-    """(d u^N / d u^0)^T ubar for nsteps RK4 steps from u."""
+def rk4_vjp(u, ubar, dt, nsteps, ph, step=None):
+    """(d u^N / d u^0)^T ubar for nsteps RK4 steps (or ``step``) from u."""
+    step = rk4_step if step is None else step
     u0 = torch.as_tensor(u, dtype=torch.float64).clone().requires_grad_(True)
     x = u0
     for _ in range(nsteps):
-        x = tcp.checkpoint(rk4_step, x, dt, ph, use_reentrant=False)
+        x = tcp.checkpoint(step, x, dt, ph, use_reentrant=False)
     (g,) = torch.autograd.grad(x, u0, grad_outputs=torch.as_tensor(ubar, dtype=torch.float64))
     return g.detach()

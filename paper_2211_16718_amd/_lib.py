@@ -81,6 +81,7 @@ SIGNATURES = {
     "cns_adjoint_workspace_bytes": (C.c_size_t, [_vp, C.c_int32, C.c_int32]),
     "cns_rhs_vjp": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_size_t]),
     "cns_adjoint_rk4": (C.c_int, [_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, _vp]),
+    "cns_adjoint_tvdrk3": (C.c_int, [_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, _vp]),
     "cns_ic_vjp": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "cns_last_error": (C.c_char_p, []),
 }

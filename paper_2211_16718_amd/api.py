@@ -182,12 +182,19 @@ class Plan:
 
     def adjoint_rk4(self, u0, dt, nsteps, ckpt_every):
         """``(J, dJ/du0)`` for J = mean kinetic energy after ``nsteps`` RK4 steps."""
+        return self._adjoint("cns_adjoint_rk4", u0, dt, nsteps, ckpt_every)
+
+    def adjoint_tvdrk3(self, u0, dt, nsteps, ckpt_every):
+        """``(J, dJ/du0)`` for J = mean kinetic energy after ``nsteps`` TVD-RK3 steps."""
+        return self._adjoint("cns_adjoint_tvdrk3", u0, dt, nsteps, ckpt_every)
+
+    def _adjoint(self, fn, u0, dt, nsteps, ckpt_every):
         self._state(u0)
         ws, n = self._adj_ws(nsteps, ckpt_every)
         J = torch.empty(1, dtype=torch.float64, device=self.device)
         g = self.empty_state()
-        check(self.lib.cns_adjoint_rk4(self.h, _ptr(u0), float(dt), int(nsteps), int(ckpt_every), _ptr(ws), n,
-                                       _ptr(J), _ptr(g)), "cns_adjoint_rk4")
+        check(getattr(self.lib, fn)(self.h, _ptr(u0), float(dt), int(nsteps), int(ckpt_every), _ptr(ws), n,
+                                    _ptr(J), _ptr(g)), fn)
         return J, g
 
     def ic_vjp(self, rho, vel, ubar):

@@ -817,8 +817,8 @@ int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *uba
     return check_hip("rhs_vjp");
 }
 
-int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
-                    size_t bytes, double *J_dev, void *u0_bar) {
+static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every,
+                       void *adj_ws, size_t bytes, double *J_dev, void *u0_bar) {
     int rc = adj_check(plan);
     if (!rc) rc = check_ptr(u0, "u0");
     if (!rc) rc = check_ptr(adj_ws, "adj_ws");
@@ -843,22 +843,22 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
     bt.prof = nullptr;
     const int K = L.K;
 
-    // the step-start state and stage states U2, U3, U4 of step n of a segment starting at n0,
-    // kept while the fused RK4 step advances X
+    // the step-start state and the stage states of step n of a segment starting at n0 (RK4:
+    // U2, U3, U4; TVD-RK3: U1, U2), kept while the fused step advances X
     auto keep_step = [&](int n, int n0) {
         adj_copy(n5, X, state(L.seg, 4 * (n - n0)), s);
         void *const st3[3] = {state(L.seg, 4 * (n - n0) + 1), state(L.seg, 4 * (n - n0) + 2),
                               state(L.seg, 4 * (n - n0) + 3)};
-        launch_rk4_step(bt, X, dt, nullptr, 0, 0, st3);
+        launch_step(bt, scheme, X, dt, nullptr, 0, 0, st3);
     };
-    // forward with checkpoints (the fused RK4 path, as cns_rk4); the last segment keeps
+    // forward with checkpoints (the fused path, as cns_rk4 / cns_tvdrk3); the last segment keeps
     // its states on the way, so the reverse sweep starts without recomputing it
     const int last0 = (L.nck - 1) * K;
     adj_copy(n5, (const double *)u0, X, s);
     for (int n = 0; n < nsteps; ++n) {
         if (n % K == 0) adj_copy(n5, X, state(L.ck, n / K), s);
         if (n >= last0) keep_step(n, last0);
-        else launch_rk4_step(bt, X, dt, nullptr, 0, 0);
+        else launch_step(bt, scheme, X, dt, nullptr, 0, 0);
     }
     launch_diag(bt, X, rec, 0, 0);
     if (J_dev) adj_copy(1, rec, J_dev, s);
@@ -874,8 +874,30 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
             for (int n = n0; n < n1; ++n) keep_step(n, n0);
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            const double *Y = state(L.seg, 4 * (n - n0)), *U2 = state(L.seg, 4 * (n - n0) + 1),
-                         *U3 = state(L.seg, 4 * (n - n0) + 2), *U4 = state(L.seg, 4 * (n - n0) + 3);
+            const double *Y = state(L.seg, 4 * (n - n0));
+            if (scheme == CNS_TVDRK3) {
+                // Shu-Osher stages U1 = u + dt R(u), U2 = 3/4 u + 1/4 (U1 + dt R(U1)),
+                // u' = 1/3 u + 2/3 (U2 + dt R(U2)), reversed:
+                //   Ubar2 = 2/3 ub + R'(U2)^T (2/3 dt ub)
+                //   Ubar1 = 1/4 Ubar2 + R'(U1)^T (1/4 dt Ubar2)
+                //   ub   <- 1/3 ub + 3/4 Ubar2 + Ubar1 + R'(u)^T (dt Ubar1)
+                // (S holds Ubar2 and X, free during the reverse steps, holds Ubar1)
+                const double *U1 = state(L.seg, 4 * (n - n0) + 1), *U2 = state(L.seg, 4 * (n - n0) + 2);
+                adj_lincomb(n5, 2.0 / 3.0 * dt, ub, 0.0, nullptr, kb, s);
+                adj_rhs_vjp(b, s, U2, kb, Ub, Gb);
+                adj_lincomb(n5, 2.0 / 3.0, ub, 1.0, Ub, S, s);
+                adj_lincomb(n5, 0.25 * dt, S, 0.0, nullptr, kb, s);
+                adj_rhs_vjp(b, s, U1, kb, Ub, Gb);
+                adj_lincomb(n5, 0.25, S, 1.0, Ub, X, s);
+                adj_lincomb(n5, dt, X, 0.0, nullptr, kb, s);
+                adj_rhs_vjp(b, s, Y, kb, Ub, Gb);
+                adj_lincomb(n5, 1.0 / 3.0, ub, 0.75, S, ub, s);
+                adj_accum(n5, X, ub, s);
+                adj_accum(n5, Ub, ub, s);
+                continue;
+            }
+            const double *U2 = state(L.seg, 4 * (n - n0) + 1), *U3 = state(L.seg, 4 * (n - n0) + 2),
+                         *U4 = state(L.seg, 4 * (n - n0) + 3);
             // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
             // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s
             adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
@@ -895,6 +917,16 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
     }
     adj_copy(n5, ub, (double *)u0_bar, s);
     return check_hip("adjoint_rk4");
+}
+
+int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
+                    size_t bytes, double *J_dev, void *u0_bar) {
+    return adjoint_run(plan, CNS_RK4, u0, dt, nsteps, ckpt_every, adj_ws, bytes, J_dev, u0_bar);
+}
+
+int cns_adjoint_tvdrk3(cns_plan *plan, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
+                       size_t bytes, double *J_dev, void *u0_bar) {
+    return adjoint_run(plan, CNS_TVDRK3, u0, dt, nsteps, ckpt_every, adj_ws, bytes, J_dev, u0_bar);
 }
 
 int cns_ic_vjp(const cns_plan *plan, const double *rho, const double *vel, const double *ubar, double *vbar) {

@@ -132,7 +132,7 @@ void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *di
                      int step, void *const *stage_states = nullptr);
 // one step of the integrator `scheme` (CNS_RK4 or CNS_TVDRK3), then diagnostics if diag
 void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag,
-                 long long diag_box_stride, int step);
+                 long long diag_box_stride, int step, void *const *stage_states = nullptr);
 void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag_box_stride, int step);
 // time the y and z marching sweeps over the batch (autotuning); milliseconds per launch pair
 float time_sweeps_yz(const Batch &bt, int reps);

@@ -1081,8 +1081,9 @@ void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *di
 
 template <typename T>
 static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride,
-                          int step) {
-    // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, u^{n+1} -> u
+                          int step, void *const *stage_states) {
+    // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, u^{n+1} -> u;
+    // with stage_states, A is stage_states[0] and B stage_states[1]
     const int in_of[3] = {BUF_U, BUF_A, BUF_B};
     const int out_of[3] = {BUF_A, BUF_B, BUF_U};
     for (int s = 0; s < 3; ++s) {
@@ -1093,6 +1094,10 @@ static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, doubl
         L.scheme = CNS_TVDRK3;
         L.u_ov = u_ov;
         L.dt_ov = dt_ov;
+        if (stage_states) {
+            L.a_ov = stage_states[0];
+            L.b_ov = stage_states[1];
+        }
         if (bt.any_visc) visc_fields<T>(bt, L);
         sweep_x<T>(bt, L, bt.any_visc);
         {
@@ -1106,10 +1111,10 @@ static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, doubl
 }
 
 void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag, long long stride,
-                 int step) {
-    if (scheme == CNS_RK4) return launch_rk4_step(bt, u_ov, dt_ov, diag, stride, step);
-    if (bt.prec == CNS_FP64) tvdrk3_step_t<double>(bt, u_ov, dt_ov, diag, stride, step);
-    else tvdrk3_step_t<float>(bt, u_ov, dt_ov, diag, stride, step);
+                 int step, void *const *stage_states) {
+    if (scheme == CNS_RK4) return launch_rk4_step(bt, u_ov, dt_ov, diag, stride, step, stage_states);
+    if (bt.prec == CNS_FP64) tvdrk3_step_t<double>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
+    else tvdrk3_step_t<float>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
 }
 
 float time_sweeps_yz(const Batch &bt, int reps) {

@@ -136,6 +136,48 @@ def test_autograd_function_gradient_16(orc):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("nsteps,ckpt", [(7, 3), (4, 4)])
+def test_adjoint_tvdrk3_matches_reverse_mode_reference(orc, nsteps, ckpt):
+    case(f"adjoint tvdrk3 (12,10,14) nsteps={nsteps} ckpt={ckpt}")
+    shape = (12, 10, 14)
+    mu = 0.02
+    rho, vel, p = state(shape, seed=4)
+    plan = Plan(shape, mu_eff=mu)
+    u0 = plan.init_state(rho, vel, p)
+    u0h = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u0h, orc.make_phys(mu_eff=mu))[7], 14)
+    J, g = plan.adjoint_tvdrk3(u0, dt, nsteps, ckpt)
+    uN, _ = orc.tvdrk3(u0h, dt, nsteps, orc.make_phys(mu_eff=mu), with_diag=False)
+    uNt = torch.from_numpy(uN).requires_grad_(True)
+    (seed,) = torch.autograd.grad(tr.kinetic_energy(uNt), uNt)
+    ref = tr.rk4_vjp(torch.from_numpy(u0h), seed, dt, nsteps, tr.make_phys(mu=mu), step=tr.tvdrk3_step).numpy()
+    assert float(J[0]) == pytest.approx(orc.diag(uN, orc.make_phys(mu_eff=mu))[0], rel=1e-13)
+    err = rel_max(g.cpu().numpy(), ref)
+    print(f"adjoint tvdrk3 rel err {err:.3e}")
+    assert err <= 1e-10
+    # and it is not the RK4 gradient
+    _, g4 = plan.adjoint_rk4(plan.init_state(rho, vel, p), dt, nsteps, ckpt)
+    assert rel_max(g4.cpu().numpy(), ref) > 1e-8
+
+
+def test_autograd_function_tvdrk3_16(orc):
+    case("autograd Function tvdrk3 16^3")
+    n, mu, nsteps = 16, 1.0 / 400, 6
+    rho, vel, p = I.hit_primitives(n, 0, 0.3)
+    plan = Plan((n, n, n), mu_eff=mu)
+    dt = I.dt_from_speed(orc.diag(orc.init_state(rho, vel, p), orc.make_phys(mu_eff=mu))[7], n)
+    v0 = torch.from_numpy(vel).cuda().requires_grad_(True)
+    J = FinalKineticEnergy.apply(v0, torch.from_numpy(rho).cuda(), torch.from_numpy(p).cuda(), plan, dt, nsteps, 4,
+                                 "tvdrk3")
+    J.backward()
+    Jr, gr = tr.final_ke_and_grad(torch.from_numpy(rho), torch.from_numpy(vel), torch.from_numpy(p), dt, nsteps,
+                                  tr.make_phys(mu=mu), step=tr.tvdrk3_step)
+    assert float(J) == pytest.approx(Jr, rel=1e-13)
+    err = rel_max(v0.grad.cpu().numpy(), gr.numpy())
+    print(f"tvdrk3 dJ/dv0 rel err vs CPU reference {err:.3e}")
+    assert err <= 1e-10
+
+
 def test_adjoint_128_against_central_differences():
     # 128^3, Re = 400, 200 RK4 steps, checkpoints every 20; 32 smooth random
     # directions (HIT-spectrum fields, seeds 1000..1031)

@@ -91,3 +91,35 @@ def test_final_ke_gradient_matches_central_differences(orc, tr):
         h = 1e-6
         fd = (Jc(vel + h * d) - Jc(vel - h * d)) / (2 * h)
         assert float(np.sum(gv.numpy() * d)) == pytest.approx(fd, rel=1e-6)
+
+
+def test_forward_tvdrk3_matches_c_oracle(orc, tr):
+    rho, vel, p, u, ph, mu = setup(orc, n=10)
+    dt = I.dt_from_speed(orc.diag(u, ph)[7], 10)
+    uf, _ = orc.tvdrk3(u, dt, 2, ph, with_diag=False)
+    x = torch.from_numpy(u)
+    for _ in range(2):
+        x = tr.tvdrk3_step(x, dt, tr.make_phys(mu=mu))
+    np.testing.assert_allclose(x.numpy(), uf, rtol=0, atol=1e-13 * np.abs(uf).max())
+
+
+def test_final_ke_gradient_tvdrk3_matches_central_differences(orc, tr):
+    n, steps = 8, 3
+    rho, vel, p = I.hit_primitives(n, 2, 0.3)
+    mu = 0.02
+    ph = orc.make_phys(mu_eff=mu)
+    u0 = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u0, ph)[7], n)
+    J, gv = tr.final_ke_and_grad(torch.from_numpy(rho), torch.from_numpy(vel), torch.from_numpy(p), dt, steps,
+                                 tr.make_phys(mu=mu), step=tr.tvdrk3_step)
+
+    def Jc(v):
+        uf, _ = orc.tvdrk3(orc.init_state(rho, v, p), dt, steps, ph, with_diag=False)
+        return orc.diag(uf, ph)[0]
+
+    assert J == pytest.approx(Jc(vel), rel=1e-13)
+    for k in range(2):
+        d = I.hit_velocity(n, seed=200 + k)
+        h = 1e-6
+        fd = (Jc(vel + h * d) - Jc(vel - h * d)) / (2 * h)
+        assert float(np.sum(gv.numpy() * d)) == pytest.approx(fd, rel=1e-6)

@@ -403,6 +403,19 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
            "forward_s": fsec, "gradient_s": gsec, "gradient_over_forward": gsec / fsec,
            "value": 4.0 * n ** 3 * steps / gsec, "unit": "point-RHS/s (forward-step equivalents of the gradient)",
            "J": float(J.detach()), "grad_norm": float(g.norm())}
+    # the same gradient through the TVD-RK3 integrator (checkpoints every ckpt steps)
+    plan.tvdrk3(plan.init_state(rho, vel, p), dt, 1, diag=False)
+    u3 = plan.init_state(rho, vel, p)
+    f3, _ = _timed(plan.stream, lambda: plan.tvdrk3(u3, dt, steps, diag=False))
+
+    def grad3():
+        v0 = vel.clone().requires_grad_(True)
+        J = FinalKineticEnergy.apply(v0, rho, p, plan, dt, steps, ckpt, "tvdrk3")
+        J.backward()
+        return J, v0.grad
+
+    g3, (J3, _) = _timed(plan.stream, grad3)
+    out["tvdrk3"] = {"forward_s": f3, "gradient_s": g3, "gradient_over_forward": g3 / f3, "J": float(J3.detach())}
     # one segment (checkpoint interval = all steps): the forward pass keeps the start and
     # stage states of every step in HBM (4 states per step) and nothing is recomputed
     need = int(plan.lib.cns_adjoint_workspace_bytes(plan.h, steps, steps))

@@ -794,29 +794,6 @@ static int adj_check(const cns_plan *plan) {
     return CNS_OK;
 }
 
-extern "C" {
-
-size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t ckpt_every) {
-    if (!plan || nsteps < 0) return 0;
-    return adj_layout(plan->c.boxes[0].n3, nsteps, ckpt_every).total;
-}
-
-int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *ubar, void *adj_ws, size_t bytes) {
-    int rc = adj_check(plan);
-    if (!rc) rc = check_ptr(u, "u");
-    if (!rc) rc = check_ptr(rbar, "rbar");
-    if (!rc) rc = check_ptr(ubar, "ubar");
-    if (!rc) rc = check_ptr(adj_ws, "adj_ws");
-    if (rc) return rc;
-    if (ubar == u || ubar == rbar) return set_err(CNS_EINVAL, "ubar must not alias u or rbar");
-    const BoxDesc &b = plan->c.boxes[0];
-    const AdjLayout L = adj_layout(b.n3, 0, 1);
-    if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
-    char *w = (char *)adj_ws;
-    adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.Gb));
-    return check_hip("rhs_vjp");
-}
-
 static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every,
                        void *adj_ws, size_t bytes, double *J_dev, void *u0_bar) {
     int rc = adj_check(plan);
@@ -917,6 +894,29 @@ static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, in
     }
     adj_copy(n5, ub, (double *)u0_bar, s);
     return check_hip("adjoint_rk4");
+}
+
+extern "C" {
+
+size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t ckpt_every) {
+    if (!plan || nsteps < 0) return 0;
+    return adj_layout(plan->c.boxes[0].n3, nsteps, ckpt_every).total;
+}
+
+int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *ubar, void *adj_ws, size_t bytes) {
+    int rc = adj_check(plan);
+    if (!rc) rc = check_ptr(u, "u");
+    if (!rc) rc = check_ptr(rbar, "rbar");
+    if (!rc) rc = check_ptr(ubar, "ubar");
+    if (!rc) rc = check_ptr(adj_ws, "adj_ws");
+    if (rc) return rc;
+    if (ubar == u || ubar == rbar) return set_err(CNS_EINVAL, "ubar must not alias u or rbar");
+    const BoxDesc &b = plan->c.boxes[0];
+    const AdjLayout L = adj_layout(b.n3, 0, 1);
+    if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
+    char *w = (char *)adj_ws;
+    adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.Gb));
+    return check_hip("rhs_vjp");
 }
 
 int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,

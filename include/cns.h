@@ -200,10 +200,11 @@ int cns_ensemble_set_integrator(cns_ensemble *ens, int32_t scheme);
 int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable);
 int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t *count_host);
 
-/* ---- adjoint (FP64 plans; CNS_EUNSUPPORTED otherwise) ----
+/* ---- adjoint (FP64 plans, any of the WENO weights; CNS_EUNSUPPORTED for mixed) ----
  * Reverse-mode derivatives of the discrete operator of Sec. 2.2, hand-written:
- * vector-Jacobian products of the WENO5 reconstructions, the Roe flux with Harten's
- * fix, the Euler fluxes and the central viscous terms.  Extension beyond the paper.
+ * vector-Jacobian products of the WENO5 reconstructions (Jiang-Shu, Z or mapped
+ * weights), the Roe flux with Harten's fix, the Euler fluxes and the central viscous
+ * terms.  Extension beyond the paper.
  * adj_ws: caller-owned device scratch of cns_adjoint_workspace_bytes bytes. */
 size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t ckpt_every);
 /* ubar = (dR/du)^T rbar at u (all [5][N3] device arrays, FP64); needs

@@ -43,20 +43,32 @@ def flux(u, d, gamma):
     return torch.stack(f)
 
 
-def weno5(a, b, c, dd, e, eps):
+def weno5(a, b, c, dd, e, eps, weights="js"):
     """Sec. 2.2 WENO5 value at j+1/2 from f_{j-2..j+2} (candidates, optimal
-    weights 1/10, 6/10, 3/10, Jiang-Shu indicators, alpha = c/(eps+beta)^2)."""
+    weights 1/10, 6/10, 3/10, Jiang-Shu indicators, alpha = c/(eps+beta)^2);
+    weights "z": WENO-Z, alpha = c (1 + (|beta1 - beta3| / (eps+beta))^2) (Borges
+    et al. 2008); "m": the Jiang-Shu weights mapped by
+    g(w) = w (c + c^2 - 3 c w + w^2) / (c^2 + w (1 - 2 c)) and renormalised
+    (Henrick et al. 2005)."""
     f1 = a / 3.0 - 7.0 * b / 6.0 + 11.0 * c / 6.0
     f2 = -b / 6.0 + 5.0 * c / 6.0 + dd / 3.0
     f3 = c / 3.0 + 5.0 * dd / 6.0 - e / 6.0
     b1 = 13.0 / 12.0 * (a - 2 * b + c) ** 2 + 0.25 * (a - 4 * b + 3 * c) ** 2
     b2 = 13.0 / 12.0 * (b - 2 * c + dd) ** 2 + 0.25 * (b - dd) ** 2
     b3 = 13.0 / 12.0 * (c - 2 * dd + e) ** 2 + 0.25 * (3 * c - 4 * dd + e) ** 2
-    a1 = 0.1 / (eps + b1) ** 2
-    a2 = 0.6 / (eps + b2) ** 2
-    a3 = 0.3 / (eps + b3) ** 2
-    s = a1 + a2 + a3
-    return (a1 / s) * f1 + (a2 / s) * f2 + (a3 / s) * f3
+    opt = (0.1, 0.6, 0.3)
+    if weights == "z":
+        tau = torch.abs(b1 - b3)
+        al = [ck * (1.0 + (tau / (eps + bk)) ** 2) for ck, bk in zip(opt, (b1, b2, b3))]
+    else:
+        al = [ck / (eps + bk) ** 2 for ck, bk in zip(opt, (b1, b2, b3))]
+    s = al[0] + al[1] + al[2]
+    w = [ak / s for ak in al]
+    if weights == "m":
+        g = [wk * (ck + ck * ck - 3.0 * ck * wk + wk * wk) / (ck * ck + wk * (1.0 - 2.0 * ck)) for ck, wk in zip(opt, w)]
+        gs = g[0] + g[1] + g[2]
+        w = [gk / gs for gk in g]
+    return w[0] * f1 + w[1] * f2 + w[2] * f3
 
 
 def roe_eigensystem(uL, uR, d, gamma):
@@ -123,10 +135,11 @@ def interface_flux(u, d, ph):
     g, eps = ph["gamma"], ph["eps"]
     s = [at(u, m - 2, d) for m in range(6)]  # states at j-2 .. j+3
     f = [flux(sm, d, g) for sm in s]
-    fL = weno5(f[0], f[1], f[2], f[3], f[4], eps)
-    fR = weno5(f[5], f[4], f[3], f[2], f[1], eps)
-    uL = weno5(s[0], s[1], s[2], s[3], s[4], eps)
-    uR = weno5(s[5], s[4], s[3], s[2], s[1], eps)
+    wt = ph.get("weights", "js")
+    fL = weno5(f[0], f[1], f[2], f[3], f[4], eps, wt)
+    fR = weno5(f[5], f[4], f[3], f[2], f[1], eps, wt)
+    uL = weno5(s[0], s[1], s[2], s[3], s[4], eps, wt)
+    uR = weno5(s[5], s[4], s[3], s[2], s[1], eps, wt)
     X, Xi, lam = roe_eigensystem(s[2], s[3], d, g)
     du = uR - uL
     w = [harten(lam[r], ph["delta"]) * sum(Xi[r][c] * du[c] for c in range(5)) for r in range(5)]
@@ -196,8 +209,8 @@ def ic_state(rho, vel, p, gamma):
                         p / (gamma - 1.0) + 0.5 * rho * (vel * vel).sum(0)])
 
 
-def make_phys(gamma=1.4, prandtl=0.72, mu=0.01, eps=1e-6, delta=1e-6, length=(2 * math.pi,) * 3):
-    return dict(gamma=gamma, prandtl=prandtl, mu=mu, eps=eps, delta=delta, length=length)
+def make_phys(gamma=1.4, prandtl=0.72, mu=0.01, eps=1e-6, delta=1e-6, length=(2 * math.pi,) * 3, weights="js"):
+    return dict(gamma=gamma, prandtl=prandtl, mu=mu, eps=eps, delta=delta, length=length, weights=weights)
 
 
 def final_ke_and_grad(rho, vel, p, dt, nsteps, ph, step=None):

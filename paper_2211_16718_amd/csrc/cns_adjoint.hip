@@ -85,7 +85,7 @@ template <> struct AdjConvShape<0> { static constexpr int TA = 64, TB = 4, RS = 
 template <> struct AdjConvShape<1> { static constexpr int TA = 8, TB = 32, RS = 32; };
 template <> struct AdjConvShape<2> { static constexpr int TA = 8, TB = 32, RS = 32; };
 
-template <int DIR>
+template <int DIR, int WW>
 __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__restrict__ u,
                                                      const double *__restrict__ rbar, double *__restrict__ ubar,
                                                      int accumulate) {
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
             double Hb[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) Hb[v] = (rbar[v * n3 + pn] - rbar[v * n3 + p]) * ih;
-            interface_flux_vjp<DIR>(stg, DIR == 0 ? NC : TB, c, Hb, g.gamma, g.eps, g.delta, wb);
+            interface_flux_vjp<DIR, WW>(stg, DIR == 0 ? NC : TB, c, Hb, g.gamma, g.eps, g.delta, wb);
         }
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
@@ -489,18 +489,27 @@ __global__ void k_ic_vjp(size_t n3, const double *__restrict__ rho, const double
 // ----------------------------------------------------------------------------
 static inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *Gb) {
+template <int WW>
+static void adj_conv(const BoxDesc &b, hipStream_t s, const AdjGeom &g, const double *u, const double *rbar,
+                     double *ubar) {
+    // blocks: x, TB = 4 rows each; y, z: one 32-wide x tile of the lines at one z (y) each
+    const unsigned bx = (unsigned)(((size_t)b.ny * b.nz + 3) / 4);
+    const unsigned ntx = (unsigned)((b.nx + 31) / 32);
+    hipLaunchKernelGGL((k_adj_conv<0, WW>), dim3(bx), dim3(256), 0, s, g, u, rbar, ubar, 0);
+    hipLaunchKernelGGL((k_adj_conv<1, WW>), dim3(ntx * (unsigned)b.nz), dim3(256), 0, s, g, u, rbar, ubar, 1);
+    hipLaunchKernelGGL((k_adj_conv<2, WW>), dim3(ntx * (unsigned)b.ny), dim3(256), 0, s, g, u, rbar, ubar, 1);
+}
+
+void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
+                 double *Gb) {
     const AdjGeom g = adj_geom(b);
     const bool visc = b.mu > 0.0;
     const unsigned tiles = (unsigned)(((b.nx + kViscTX - 1) / kViscTX) * (long long)((b.ny + kViscTY - 1) / kViscTY) *
                                       ((b.nz + kViscSZ - 1) / kViscSZ));
     if (visc) hipLaunchKernelGGL(k_adj_visc1, dim3(tiles), dim3(kPointThreads), 0, s, g, u, rbar, Gb);
-    // blocks: x, TB = 4 rows each; y, z: one 32-wide x tile of the lines at one z (y) each
-    const unsigned bx = (unsigned)(((size_t)b.ny * b.nz + 3) / 4);
-    const unsigned ntx = (unsigned)((b.nx + 31) / 32);
-    hipLaunchKernelGGL(k_adj_conv<0>, dim3(bx), dim3(256), 0, s, g, u, rbar, ubar, 0);
-    hipLaunchKernelGGL(k_adj_conv<1>, dim3(ntx * (unsigned)b.nz), dim3(256), 0, s, g, u, rbar, ubar, 1);
-    hipLaunchKernelGGL(k_adj_conv<2>, dim3(ntx * (unsigned)b.ny), dim3(256), 0, s, g, u, rbar, ubar, 1);
+    if (weights == CNS_WENO_Z) adj_conv<CNS_WENO_Z>(b, s, g, u, rbar, ubar);
+    else if (weights == CNS_WENO_M) adj_conv<CNS_WENO_M>(b, s, g, u, rbar, ubar);
+    else adj_conv<CNS_WENO_JS>(b, s, g, u, rbar, ubar);
     if (visc) hipLaunchKernelGGL(k_adj_visc2, dim3(tiles), dim3(kPointThreads), 0, s, g, u, (const double *)Gb, ubar);
 }
 

@@ -790,7 +790,6 @@ static int adj_check(const cns_plan *plan) {
     int rc = check_plan(plan);
     if (rc) return rc;
     if (plan->c.prec != CNS_FP64) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for FP64 plans only");
-    if (plan->c.weights != CNS_WENO_JS) return set_err(CNS_EUNSUPPORTED, "the adjoint is available for the Jiang-Shu weights only");
     return CNS_OK;
 }
 
@@ -861,13 +860,13 @@ static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, in
                 // (S holds Ubar2 and X, free during the reverse steps, holds Ubar1)
                 const double *U1 = state(L.seg, 4 * (n - n0) + 1), *U2 = state(L.seg, 4 * (n - n0) + 2);
                 adj_lincomb(n5, 2.0 / 3.0 * dt, ub, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, s, U2, kb, Ub, Gb);
+                adj_rhs_vjp(b, c.weights, s, U2, kb, Ub, Gb);
                 adj_lincomb(n5, 2.0 / 3.0, ub, 1.0, Ub, S, s);
                 adj_lincomb(n5, 0.25 * dt, S, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, s, U1, kb, Ub, Gb);
+                adj_rhs_vjp(b, c.weights, s, U1, kb, Ub, Gb);
                 adj_lincomb(n5, 0.25, S, 1.0, Ub, X, s);
                 adj_lincomb(n5, dt, X, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, s, Y, kb, Ub, Gb);
+                adj_rhs_vjp(b, c.weights, s, Y, kb, Ub, Gb);
                 adj_lincomb(n5, 1.0 / 3.0, ub, 0.75, S, ub, s);
                 adj_accum(n5, X, ub, s);
                 adj_accum(n5, Ub, ub, s);
@@ -878,16 +877,16 @@ static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, in
             // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
             // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s
             adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
-            adj_rhs_vjp(b, s, U4, kb, Ub, Gb);
+            adj_rhs_vjp(b, c.weights, s, U4, kb, Ub, Gb);
             adj_copy(n5, Ub, S, s);
             adj_lincomb(n5, dt / 3.0, ub, dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, U3, kb, Ub, Gb);
+            adj_rhs_vjp(b, c.weights, s, U3, kb, Ub, Gb);
             adj_accum(n5, Ub, S, s);
             adj_lincomb(n5, dt / 3.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, U2, kb, Ub, Gb);
+            adj_rhs_vjp(b, c.weights, s, U2, kb, Ub, Gb);
             adj_accum(n5, Ub, S, s);
             adj_lincomb(n5, dt / 6.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, s, Y, kb, Ub, Gb);
+            adj_rhs_vjp(b, c.weights, s, Y, kb, Ub, Gb);
             adj_accum(n5, Ub, S, s);
             adj_accum(n5, S, ub, s);
         }
@@ -915,7 +914,8 @@ int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *uba
     const AdjLayout L = adj_layout(b.n3, 0, 1);
     if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
     char *w = (char *)adj_ws;
-    adj_rhs_vjp(b, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar, (double *)(w + L.Gb));
+    adj_rhs_vjp(b, plan->c.weights, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar,
+                (double *)(w + L.Gb));
     return check_hip("rhs_vjp");
 }
 

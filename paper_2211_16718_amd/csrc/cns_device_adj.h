@@ -14,12 +14,83 @@ __device__ __forceinline__ double harten_dabs(double lam, double delta, double i
 }
 
 // ---------------------------------------------------------------------------
-// WENO5 pair (weno5_lr): given the adjoints Lb, Rb of the left- and right-biased
-// values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5] (q = j-2 .. j+3); the
-// values L and R themselves are returned in Lv, Rv.
-// Weight derivative: with alpha_k = c_k/(eps+beta_k)^2 and W = sum w_k fhat_k,
-// dW/dbeta_k = -2 w_k (fhat_k - W) / (eps + beta_k).
+// One biased reconstruction V = sum_k w_k q_k from the plain candidates q_k and the
+// smoothness sums s_k = eps + beta_k: the value, the final weights w_k and dV/dbeta_k.
+// With w_k = alpha_k / A and A = sum alpha:  dV/dbeta_j = sum_k (q_k - V) dalpha_k/dbeta_j / A.
+//   JS: alpha_k = c_k / s_k^2, so dV/dbeta_j = -2 (q_j - V) w_j / s_j; the weights in
+//       product form, t_k = prod_{i != k} s_i, P = s1 s2 s3, a_k = c_k t_k^2,
+//       w_k = a_k P iPA and w_k / s_k = a_k t_k iPA with iPA = 1 / (P sum a).
+//   Z:  alpha_k = c_k + tau z_k with z_k = c_k tau / s_k^2, tau = |beta1 - beta3|:
+//       dV/dbeta_j = (1/A) [-2 (q_j - V) tau z_j / s_j + dtau/dbeta_j 2 sum_k (q_k - V) z_k].
+//   M:  the JS weights u_k mapped, g_k = c_k + (u_k - c_k)^3 / D_k, D_k = c_k^2 + u_k (1 - 2 c_k),
+//       w_k = g_k / G; with gamma_k = (q_k - V) g'_k / G,
+//       dV/dbeta_j = -2 (u_j / s_j) (gamma_j - sum_k gamma_k u_k).
 // ---------------------------------------------------------------------------
+template <int WW>
+__device__ __forceinline__ void weno_side_vjp(double s1, double s2, double s3, double q1, double q2, double q3,
+                                              double &V, double w[3], double dV[3]) {
+    if constexpr (WW == CNS_WENO_Z) {
+        const double tau = fabs(s1 - s3);
+        const double i1 = rcp(s1), i2 = rcp(s2), i3 = rcp(s3);
+        const double z1 = 0.1 * tau * (i1 * i1), z2 = 0.6 * tau * (i2 * i2), z3 = 0.3 * tau * (i3 * i3);
+        const double a1 = 0.1 + tau * z1, a2 = 0.6 + tau * z2, a3 = 0.3 + tau * z3;
+        const double iA = rcp(a1 + a2 + a3);
+        w[0] = a1 * iA, w[1] = a2 * iA, w[2] = a3 * iA;
+        V = w[0] * q1 + w[1] * q2 + w[2] * q3;
+        const double sg = s1 > s3 ? 1.0 : (s1 < s3 ? -1.0 : 0.0);
+        const double P = 2.0 * ((q1 - V) * z1 + (q2 - V) * z2 + (q3 - V) * z3);
+        dV[0] = iA * (-2.0 * (q1 - V) * tau * z1 * i1 + sg * P);
+        dV[1] = iA * (-2.0 * (q2 - V) * tau * z2 * i2);
+        dV[2] = iA * (-2.0 * (q3 - V) * tau * z3 * i3 - sg * P);
+    } else {
+        const double t1 = s2 * s3, t2 = s1 * s3, t3 = s1 * s2;
+        const double a1 = 0.1 * (t1 * t1), a2 = 0.6 * (t2 * t2), a3 = 0.3 * (t3 * t3);
+        const double iPA = rcp((t3 * s3) * (a1 + a2 + a3));
+        const double iA = (t3 * s3) * iPA;
+        const double u1 = a1 * iA, u2 = a2 * iA, u3 = a3 * iA;                     // Jiang-Shu weights
+        const double r1 = a1 * t1 * iPA, r2 = a2 * t2 * iPA, r3 = a3 * t3 * iPA;  // u_k / s_k
+        if constexpr (WW == CNS_WENO_JS) {
+            w[0] = u1, w[1] = u2, w[2] = u3;
+            V = u1 * q1 + u2 * q2 + u3 * q3;
+            dV[0] = -2.0 * (q1 - V) * r1;
+            dV[1] = -2.0 * (q2 - V) * r2;
+            dV[2] = -2.0 * (q3 - V) * r3;
+        } else {
+            static_assert(WW == CNS_WENO_M, "unknown WENO weights");
+            const double c[3] = {0.1, 0.6, 0.3}, u[3] = {u1, u2, u3}, r[3] = {r1, r2, r3}, q[3] = {q1, q2, q3};
+            double g[3], gp[3], G = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double e = u[k] - c[k], D = c[k] * c[k] + u[k] * (1.0 - 2.0 * c[k]), iD = rcp(D);
+                g[k] = c[k] + e * e * e * iD;
+                gp[k] = e * e * (3.0 * D - e * (1.0 - 2.0 * c[k])) * (iD * iD);
+                G += g[k];
+            }
+            const double iG = rcp(G);
+            V = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                w[k] = g[k] * iG;
+                V += w[k] * q[k];
+            }
+            double gam[3], S = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                gam[k] = (q[k] - V) * gp[k] * iG;
+                S += gam[k] * u[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dV[k] = -2.0 * r[k] * (gam[k] - S);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// WENO5 pair (weno5_lr with the weights WW): given the adjoints Lb, Rb of the left-
+// and right-biased values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5]
+// (q = j-2 .. j+3); the values L and R themselves are returned in Lv, Rv.
+// ---------------------------------------------------------------------------
+template <int WW = CNS_WENO_JS>
 __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, double Lb, double Rb, double qb[6],
                                              double &Lv, double &Rv) {
     const double m2 = q[0], m1 = q[1], c0 = q[2], p1 = q[3], p2 = q[4], p3 = q[5];
@@ -37,35 +108,15 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
     const double u1 = eps + (k13 * dd * dd + 0.25 * fa * fa);
     const double u2 = eps + (k13 * dc * dc + 0.25 * fb * fb);
     const double u3 = eps + (k13 * db * db + 0.25 * fc * fc);
-    // Product form of the weights, one reciprocal per side: with s_k = eps + beta_k,
-    // t_k = prod_{i != k} s_i, P = s1 s2 s3, a_k = c_k t_k^2 and A = sum a_k,
-    // w_k = a_k / A = a_k P iPA and w_k / s_k = a_k t_k iPA, where iPA = 1 / (P A).
-    // left weights and value
-    double t1 = s2 * s3, t2 = s1 * s3, t3 = s1 * s2;
-    double a1 = 0.1 * (t1 * t1), a2 = 0.6 * (t2 * t2), a3 = 0.3 * (t3 * t3);
-    double iPA = rcp((t3 * s3) * (a1 + a2 + a3));
-    double iA = (t3 * s3) * iPA;
-    const double w1 = a1 * iA, w2 = a2 * iA, w3 = a3 * iA;
-    const double is1 = a1 * t1 * iPA, is2 = a2 * t2 * iPA, is3 = a3 * t3 * iPA;  // w_k / s_k
-    const double L = w1 * L1 + w2 * L2 + w3 * L3;
-    // right weights and value
-    t1 = u2 * u3, t2 = u1 * u3, t3 = u1 * u2;
-    a1 = 0.1 * (t1 * t1), a2 = 0.6 * (t2 * t2), a3 = 0.3 * (t3 * t3);
-    iPA = rcp((t3 * u3) * (a1 + a2 + a3));
-    iA = (t3 * u3) * iPA;
-    const double v1 = a1 * iA, v2 = a2 * iA, v3 = a3 * iA;
-    const double it1 = a1 * t1 * iPA, it2 = a2 * t2 * iPA, it3 = a3 * t3 * iPA;  // v_k / s_k
-    const double R = v1 * R1 + v2 * L3 + v3 * L2;
+    double L, R, w[3], v[3], dL[3], dR[3];
+    weno_side_vjp<WW>(s1, s2, s3, L1, L2, L3, L, w, dL);  // left-biased
+    weno_side_vjp<WW>(u1, u2, u3, R1, L3, L2, R, v, dR);  // right-biased (mirrored stencils)
 
     // candidates
-    const double cL1 = Lb * w1, cL2 = Lb * w2 + Rb * v3, cL3 = Lb * w3 + Rb * v2, cR1 = Rb * v1;
+    const double cL1 = Lb * w[0], cL2 = Lb * w[1] + Rb * v[2], cL3 = Lb * w[2] + Rb * v[1], cR1 = Rb * v[0];
     // indicators
-    const double bL1 = -2.0 * Lb * (L1 - L) * is1;
-    const double bL2 = -2.0 * Lb * (L2 - L) * is2;
-    const double bL3 = -2.0 * Lb * (L3 - L) * is3;
-    const double bR1 = -2.0 * Rb * (R1 - R) * it1;
-    const double bR2 = -2.0 * Rb * (L3 - R) * it2;
-    const double bR3 = -2.0 * Rb * (L2 - R) * it3;
+    const double bL1 = Lb * dL[0], bL2 = Lb * dL[1], bL3 = Lb * dL[2];
+    const double bR1 = Rb * dR[0], bR2 = Rb * dR[1], bR3 = Rb * dR[2];
     const double dab = 2.0 * k13 * da * bL1, eab = 0.5 * ea * bL1;
     const double dbb = 2.0 * k13 * db * (bL2 + bR3), ebb = 0.5 * eb * bL2, fcb = 0.5 * fc * bR3;
     const double dcb = 2.0 * k13 * dc * (bL3 + bR2), ecb = 0.5 * ec * bL3, fbb = 0.5 * fb * bR2;
@@ -338,7 +389,7 @@ __device__ __forceinline__ void adj_stage_fence() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int DIR>
+template <int DIR, int WW>
 __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, const int c[6], const double Hb[5],
                                                    double gamma, double eps, double delta, double wb[6][5]) {
     const double gm1 = gamma - 1.0;
@@ -361,7 +412,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
 #pragma unroll
         for (int m = 0; m < 6; ++m) q[m] = F[m][v];
         double Lv, Rv;
-        weno5_lr_vjp(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb, Lv, Rv);
+        weno5_lr_vjp<WW>(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb, Lv, Rv);
 #pragma unroll
         for (int m = 0; m < 6; ++m) F[m][v] = qb[m];
         adj_stage_fence();
@@ -398,7 +449,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         double q[6], qb[6] = {0, 0, 0, 0, 0, 0}, UL, UR;
 #pragma unroll
         for (int m = 0; m < 6; ++m) q[m] = f[c[m]];
-        weno5_lr_vjp(q, eps, -dub[v], dub[v], qb, UL, UR);
+        weno5_lr_vjp<WW>(q, eps, -dub[v], dub[v], qb, UL, UR);
         du[v] = UR - UL;
 #pragma unroll
         for (int m = 0; m < 6; ++m) wb[m][v] += qb[m];

@@ -146,7 +146,8 @@ void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, d
 // adjoint launchers (cns_adjoint.hip), FP64, one box
 // adjoint of the full RHS at u: ubar = (dR/du)^T rbar; Gb: kAdjGbFields x n3 scratch
 constexpr int kAdjGbFields = 12;
-void adj_rhs_vjp(const BoxDesc &b, hipStream_t s, const double *u, const double *rbar, double *ubar, double *Gb);
+void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
+                 double *Gb);
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
 void adj_accum(size_t n, const double *x, double *out, hipStream_t s);
 void adj_copy(size_t n, const double *x, double *out, hipStream_t s);

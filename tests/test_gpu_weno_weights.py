@@ -1,6 +1,7 @@
 """The improved WENO weights on the GPU against the oracle's: WENO-Z (Borges et al.
 2008) and the mapped weights (Henrick et al. 2005); same bars as the Jiang-Shu parity
-tests: 1e-12 per RHS evaluation, 1e-10 after RK4 steps."""
+tests: 1e-12 per RHS evaluation, 1e-10 after RK4 steps; their adjoints against
+reverse-mode AD of the PyTorch restatement (pinned to the C oracle)."""
 import numpy as np
 import pytest
 
@@ -91,7 +92,45 @@ def test_weights_option_errors(weno):
     boxes = [dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3, weno=weno), dict(shape=(16, 16, 16), mu_eff=0.01, dt=1e-3)]
     with pytest.raises(CnsError):
         Ensemble(boxes)
-    plan = Plan((16, 16, 16), mu_eff=0.01, weno=weno)
+    # the mixed form has no adjoint, whatever the weights
+    plan = Plan((16, 16, 16), mu_eff=0.01, weno=weno, precision="mixed")
     u = plan.init_state(*prims((16, 16, 16)))
     with pytest.raises(CnsError):
         plan.rhs_vjp(u, torch.ones_like(u))
+
+
+@pytest.mark.parametrize("weno", WEIGHTS)
+def test_weights_adjoint_matches_reverse_mode_reference(orc, weno):
+    from oracle import torch_ref as tr
+
+    case(f"weno-{weno} rhs_vjp (12,10,14) and 4 RK4 steps 16^3")
+    shape, mu = (12, 10, 14), 0.02
+    rho, vel, p = prims(shape, 6)
+    plan = Plan(shape, mu_eff=mu, weno=weno)
+    u = plan.init_state(rho, vel, p)
+    rbar = np.random.default_rng(2).standard_normal((5,) + shape)
+    got = plan.rhs_vjp(u, torch.from_numpy(rbar).cuda()).cpu().numpy()
+    tph = tr.make_phys(mu=mu, weights=weno)
+    ref = tr.rhs_vjp(torch.from_numpy(orc.init_state(rho, vel, p)), torch.from_numpy(rbar), tph).numpy()
+    err = rel_max(got, ref)
+    print(f"weno-{weno} rhs_vjp rel err {err:.3e}")
+    assert err <= 1e-11
+    ref_js = tr.rhs_vjp(torch.from_numpy(orc.init_state(rho, vel, p)), torch.from_numpy(rbar),
+                        tr.make_phys(mu=mu)).numpy()
+    assert rel_max(got, ref_js) > 1e-6  # not the Jiang-Shu product
+    # checkpointed reverse RK4
+    n, nsteps = 16, 4
+    rho, vel, p = prims((n, n, n), 7)
+    ph = orc.make_phys(mu_eff=mu, weno_weights=oracle_code(orc, weno))
+    u0h = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u0h, ph)[7], n)
+    plan = Plan((n, n, n), mu_eff=mu, weno=weno)
+    J, g = plan.adjoint_rk4(plan.init_state(rho, vel, p), dt, nsteps, 3)
+    uN, _ = orc.rk4(u0h, dt, nsteps, ph, with_diag=False)
+    uNt = torch.from_numpy(uN).requires_grad_(True)
+    (seed,) = torch.autograd.grad(tr.kinetic_energy(uNt), uNt)
+    ref = tr.rk4_vjp(torch.from_numpy(u0h), seed, dt, nsteps, tr.make_phys(mu=mu, weights=weno)).numpy()
+    assert float(J[0]) == pytest.approx(orc.diag(uN, ph)[0], rel=1e-13)
+    err = rel_max(g.cpu().numpy(), ref)
+    print(f"weno-{weno} adjoint rk4 rel err {err:.3e}")
+    assert err <= 1e-10

@@ -123,3 +123,31 @@ def test_final_ke_gradient_tvdrk3_matches_central_differences(orc, tr):
         h = 1e-6
         fd = (Jc(vel + h * d) - Jc(vel - h * d)) / (2 * h)
         assert float(np.sum(gv.numpy() * d)) == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("weights", ["z", "m"])
+def test_forward_improved_weights_match_c_oracle(orc, tr, weights):
+    rho, vel, p, u, ph, mu = setup(orc, seed=7)
+    code = {"z": orc.WENO_Z, "m": orc.WENO_M}[weights]
+    phw = orc.make_phys(mu_eff=mu, weno_weights=code)
+    ut = torch.from_numpy(u)
+    tph = tr.make_phys(mu=mu, weights=weights)
+    for d in range(3):
+        ref = orc.rhs_hyp_dir(u, d, phw)
+        np.testing.assert_allclose(tr.rhs_hyp_dir(ut, d, tph).numpy(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    # and the weights differ from the Jiang-Shu ones on this state
+    assert np.abs(orc.rhs_hyp_dir(u, 0, phw) - orc.rhs_hyp_dir(u, 0, ph)).max() > 1e-6
+
+
+@pytest.mark.parametrize("weights", ["z", "m"])
+def test_rhs_vjp_improved_weights_match_central_differences(orc, tr, weights):
+    rho, vel, p, u, ph, mu = setup(orc, n=10, seed=8)
+    phw = orc.make_phys(mu_eff=mu, weno_weights={"z": orc.WENO_Z, "m": orc.WENO_M}[weights])
+    rng = np.random.default_rng(3)
+    rbar = rng.standard_normal(u.shape)
+    g = tr.rhs_vjp(torch.from_numpy(u), torch.from_numpy(rbar), tr.make_phys(mu=mu, weights=weights)).numpy()
+    for k in range(2):
+        d = rng.standard_normal(u.shape) * np.abs(u).mean(axis=(1, 2, 3), keepdims=True)
+        h = 1e-7
+        fd = (orc.rhs(u + h * d, phw) - orc.rhs(u - h * d, phw)) / (2 * h)
+        assert float(np.sum(g * d)) == pytest.approx(float(np.sum(rbar * fd)), rel=1e-7), k

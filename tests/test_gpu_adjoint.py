@@ -221,3 +221,41 @@ def test_adjoint_128_against_central_differences():
     for k in range(32):
         print(f"  dir {k}: adjoint {ads[k]:+.12e}  fd {fds[k]:+.12e}  rel {rel[k]:.2e}")
     assert np.median(rel) <= 1e-6 and norm.max() <= 3e-6
+
+
+def test_adjoint_degenerate_and_invalid_arguments(orc):
+    """Zero steps: J = K(u0) and dJ/du0 = dK/du0; a one-step run with a checkpoint
+    interval longer than the run; and the errors the entry points report."""
+    from paper_2211_16718_amd._lib import CnsError
+
+    case("adjoint degenerate and invalid arguments")
+    shape, mu = (10, 9, 12), 0.02
+    rho, vel, p = state(shape, seed=9)
+    plan = Plan(shape, mu_eff=mu)
+    u0 = plan.init_state(rho, vel, p)
+    u0h = orc.init_state(rho, vel, p)
+    for run in (plan.adjoint_rk4, plan.adjoint_tvdrk3):
+        J, g = run(u0, 1e-3, 0, 1)
+        ut = torch.from_numpy(u0h).requires_grad_(True)
+        (seed,) = torch.autograd.grad(tr.kinetic_energy(ut), ut)
+        assert float(J[0]) == pytest.approx(orc.diag(u0h, orc.make_phys(mu_eff=mu))[0], rel=1e-13)
+        assert rel_max(g.cpu().numpy(), seed.numpy()) <= 1e-14
+    dt = I.dt_from_speed(orc.diag(u0h, orc.make_phys(mu_eff=mu))[7], 12)
+    _, g1 = plan.adjoint_rk4(u0, dt, 1, 50)
+    ref = tr.rk4_vjp(torch.from_numpy(u0h), tr_seed(orc, u0h, dt, mu), dt, 1, tr.make_phys(mu=mu)).numpy()
+    assert rel_max(g1.cpu().numpy(), ref) <= 1e-10
+    for run in (plan.adjoint_rk4, plan.adjoint_tvdrk3):
+        with pytest.raises(CnsError):
+            run(u0, dt, 3, 0)  # checkpoint interval < 1
+        with pytest.raises(CnsError):
+            run(u0, -dt, 3, 1)  # non-positive step
+    mixed = Plan(shape, mu_eff=mu, precision="mixed")
+    with pytest.raises(CnsError):
+        mixed.adjoint_tvdrk3(mixed.init_state(rho, vel, p), dt, 1, 1)
+
+
+def tr_seed(orc, u0h, dt, mu):
+    uN, _ = orc.rk4(u0h, dt, 1, orc.make_phys(mu_eff=mu), with_diag=False)
+    uNt = torch.from_numpy(uN).requires_grad_(True)
+    (seed,) = torch.autograd.grad(tr.kinetic_energy(uNt), uNt)
+    return seed

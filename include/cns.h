@@ -137,8 +137,9 @@ int cns_tvdrk3(cns_plan *plan, void *u_dev, double dt, int32_t nsteps, double *d
  * so the Taylor microscale is sqrt(5 moments[0] / moments[1]).  FP64 for either precision.
  * Uses the plan's stage buffers as scratch (ordered with other calls on the plan's
  * stream).  nshell must equal cns_spectrum_shells(plan) (round(|k|max) + 1), else
- * CNS_EINVAL; grids with a dimension above 2047 or more than 4096 shells give CNS_EUNSUPPORTED.  Shell sums use
- * LDS atomics, so their last bits may differ between runs. */
+ * CNS_EINVAL; grids with a dimension above 2047, more than 4096 shells, or more than one
+ * shell per 1.2 grid points (24 bytes of scratch per shell) give CNS_EUNSUPPORTED.  Shell
+ * sums use LDS atomics, so their last bits may differ between runs. */
 int cns_spectrum_shells(const cns_plan *plan);
 int cns_spectrum(const cns_plan *plan, const void *u_dev, double *E_dev, int32_t nshell, double *moments_dev);
 

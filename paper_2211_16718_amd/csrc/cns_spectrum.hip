@@ -16,7 +16,8 @@
 //      transformed by a mixed-radix Stockham autosort FFT (radix 4, 2 and 3, 5, ... as
 //      generic small-prime butterflies), lines of the y and z passes batched along x so
 //      loads and stores stay coalesced.
-//   3. binning: per-block shell histograms in LDS, then a fixed-order sum over blocks.
+//   3. binning: per-block shell histograms in LDS, then a fixed-order sum over blocks
+//      (one block per shell) and over shells.
 //      (LDS double atomics: the last bits of a shell sum may vary between runs.)
 // Scratch: the plan's stage buffers A (X1), B (X2) and rhs (block partials).
 #include <cmath>
@@ -201,30 +202,43 @@ __global__ __launch_bounds__(kPointThreads) void k_spec_bin(const double2 *X1, c
     for (int s = threadIdx.x; s < 2 * G.nshell; s += blockDim.x) part[(size_t)blockIdx.x * 2 * G.nshell + s] = hist[s];
 }
 
-// E[s] = sum over blocks (fixed order); mom = {sum_s E[s], sum_s M2[s]}
+// E[s], M2[s] = sum over the block partials in a fixed order: one block per shell, its
+// threads striding over the partials, then a fixed-shape tree in LDS
 __global__ __launch_bounds__(kPointThreads) void k_spec_final(const double *part, int nblocks, int nshell, double *E,
-                                                              double *mom) {
-    extern __shared__ double m2s[];  // [2][nshell]
-    for (int s = threadIdx.x; s < nshell; s += blockDim.x) {
-        double e = 0.0, m = 0.0;
-        for (int b = 0; b < nblocks; ++b) {
-            e += part[(size_t)b * 2 * nshell + s];
-            m += part[(size_t)b * 2 * nshell + nshell + s];
-        }
-        E[s] = e;
-        m2s[s] = e;
-        m2s[nshell + s] = m;
+                                                              double *M2) {
+    __shared__ double re[kPointThreads], rm[kPointThreads];
+    const int s = blockIdx.x;
+    double e = 0.0, m = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        e += part[(size_t)b * 2 * nshell + s];
+        m += part[(size_t)b * 2 * nshell + nshell + s];
     }
+    re[threadIdx.x] = e;
+    rm[threadIdx.x] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double e = 0.0, m = 0.0;
-        for (int s = 0; s < nshell; ++s) {
-            e += m2s[s];
-            m += m2s[nshell + s];
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            re[threadIdx.x] += re[threadIdx.x + w];
+            rm[threadIdx.x] += rm[threadIdx.x + w];
         }
-        mom[0] = e;
-        mom[1] = m;
+        __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        E[s] = re[0];
+        M2[s] = rm[0];
+    }
+}
+
+// mom = {sum_s E[s], sum_s M2[s]} in shell order
+__global__ void k_spec_mom(const double *E, const double *M2, int nshell, double *mom) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double e = 0.0, m = 0.0;
+    for (int s = 0; s < nshell; ++s) {
+        e += E[s];
+        m += M2[s];
+    }
+    mom[0] = e;
+    mom[1] = m;
 }
 
 // ---------------------------------------------------------------------------
@@ -250,9 +264,10 @@ bool spectrum_supported(const BoxDesc &b) {
     const int n[3] = {b.nx, b.ny, b.nz};
     for (int d = 0; d < 3; ++d)
         if ((size_t)2 * (n[d] + 1) * sizeof(double2) > kFftLdsMax) return false;
-    // the shell histogram must fit in LDS and one block's partials in the rhs buffer
+    // the shell histogram must fit in LDS, one block's partials and the per-shell second
+    // moments in the rhs buffer (at least 20 bytes per point)
     const size_t hist = 2 * sizeof(double) * (size_t)spectrum_shells(b);
-    return hist <= kFftLdsMax && hist <= 20 * b.n3;
+    return hist <= kFftLdsMax && hist + sizeof(double) * (size_t)spectrum_shells(b) <= 20 * b.n3;
 }
 
 static void fft_pass(double2 *X, const BoxDesc &b, int dir, hipStream_t s) {
@@ -296,13 +311,17 @@ void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, d
     G.kuy = 2.0 * M_PI * b.inv_h[1] / b.ny;
     G.kuz = 2.0 * M_PI * b.inv_h[2] / b.nz;
     G.norm = 1.0 / ((double)b.n3 * (double)b.n3);
-    // block partials in the rhs buffer (at least 20 bytes per point)
-    const size_t cap = (b.n3 * 20) / (2 * sizeof(double) * (size_t)nshell);
+    // block partials, then the per-shell second moments, in the rhs buffer (at least 20
+    // bytes per point)
+    const size_t room = b.n3 * 20 - (size_t)nshell * sizeof(double);
+    const size_t cap = room / (2 * sizeof(double) * (size_t)nshell);
     const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>({cap, (size_t)1024, (size_t)pg}));
     double *part = (double *)b.rhs;
+    double *M2 = part + (size_t)nb * 2 * nshell;
     const size_t hist = 2 * sizeof(double) * (size_t)nshell;
     hipLaunchKernelGGL(k_spec_bin, dim3(nb), dim3(kPointThreads), hist, s, X1, X2, G, part);
-    hipLaunchKernelGGL(k_spec_final, dim3(1), dim3(kPointThreads), hist, s, part, (int)nb, nshell, E, mom);
+    hipLaunchKernelGGL(k_spec_final, dim3((unsigned)nshell), dim3(kPointThreads), 0, s, part, (int)nb, nshell, E, M2);
+    hipLaunchKernelGGL(k_spec_mom, dim3(1), dim3(64), 0, s, E, M2, nshell, mom);
 }
 
 }  // namespace cns

@@ -28,29 +28,52 @@
 namespace cns {
 
 constexpr int kFftThreads = 256;
+constexpr int kFftPerThread = 8;                           // elements a thread holds through a stage
+constexpr int kFftElems = kFftThreads * kFftPerThread;     // nl * N per block
 constexpr int kFftMaxRadix = 32;
 constexpr size_t kFftLdsMax = 64 * 1024;
+constexpr size_t kFftLineLds = 32 * 1024;                  // LDS for the lines of one block
+
+// Exact unsigned division by a divisor fixed at launch: q = (umulhi(n, M) + n) >> l with
+// l = ceil(log2 d) and M = floor(2^32 (2^l - d) / d) + 1 (the round-up multiply-shift of
+// Granlund and Montgomery), exact for every 32-bit n.
+struct FastDiv {
+    uint32_t M;
+    int l;
+};
+static FastDiv fastdiv(uint32_t d) {
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    return FastDiv{(uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1), l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+    return (uint32_t)(((uint64_t)__umulhi(n, f.M) + n) >> f.l);
+}
+// Division of small numbers: with M = ceil(2^32 / d), floor(n M / 2^32) = floor(n / d)
+// whenever n < 2^16 and d < 2^16 (the error n (M d - 2^32) / (d 2^32) stays below 1/d).
+// The in-line indexes of the stages (below 2^13) use it, with M formed on the device.
+__device__ __forceinline__ uint64_t small_magic(uint32_t d) { return (uint64_t)(0xFFFFFFFFu / d) + 1u; }
+__device__ __forceinline__ int sdiv(int n, uint64_t M) { return (int)(((uint64_t)(uint32_t)n * M) >> 32); }
 
 struct FftPlan {
     int N;            // line length
     int nr;           // number of radix stages
     int radix[kFftMaxRadix];
-    long long nlines;
-    int nl;           // lines per block
-    int ld;           // LDS stride between lines (N + 1: consecutive lines fall in different banks)
-    long long na;     // line index L -> (L % na) * sa + (L / na) * sb
+    FastDiv dN, dnl, dna;
+    int nlines;
+    int nl;           // lines per block (nl * N <= kFftElems)
+    int ld;           // LDS stride between lines
+    int swz;          // 14: XOR swizzle of the in-line index (N % 16 == 0, ld = N); 0: ld = N + 1
+    int na;           // line index L -> (L % na) * sa + (L / na) * sb
     size_t sa, sb, es;
     int contig;       // 1: elements of a line are contiguous (x pass)
+    const double2 *tw;  // tw[k] = exp(-2 pi i k / N), k < N (global; each block copies it to LDS)
 };
 
-template <typename T>
-__global__ void k_spec_pack(const T *u, size_t n3, double2 *X1, double2 *X2) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n3; i += (size_t)gridDim.x * blockDim.x) {
-        const double r = double(u[i]);
-        const double vx = double(u[n3 + i]) / r, vy = double(u[2 * n3 + i]) / r, vz = double(u[3 * n3 + i]) / r;
-        X1[i] = make_double2(vx, vy);
-        X2[i] = make_double2(vz, 0.0);
-    }
+// LDS slot of element j of line l.  Lines of the y and z passes are loaded with l
+// fastest; the swizzle (or the padding) puts the lines of one index j in different banks.
+__device__ __forceinline__ int lds_at(int l, int j, const FftPlan &P) {
+    return l * P.ld + (j ^ ((l << 1) & P.swz));
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -58,116 +81,217 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// exp(-2 pi i num / den) (forward transform)
-__device__ __forceinline__ double2 twiddle(long long num, long long den) {
-    double s, c;
-    sincospi(-2.0 * (double)num / (double)den, &s, &c);
-    return make_double2(c, s);
+
+// One Stockham stage of radix R on nl lines of length N, in place in LDS: every thread
+// reads the inputs of its butterflies into registers, the block synchronises, then the
+// outputs are written.  Butterfly j (0 <= j < N/R) reads x[j + r N/R], r = 0..R-1,
+// multiplies by the twiddles exp(-2 pi i r k/(Ns R)) with k = j mod Ns, takes a length-R
+// DFT and writes output s to x[(j/Ns) Ns R + k + s Ns].
+template <int R>
+__device__ __forceinline__ void fft_stage_small(double2 *x, const double2 *tw, const FftPlan &P, int nl, int Ns) {
+    const int N = P.N, m = N / R, tws = N / (Ns * R), nb = nl * m, tR = N / R;
+    const uint64_t Mm = small_magic(m), Mns = small_magic(Ns);
+    constexpr int NB = (kFftPerThread + R - 1) / R;
+    double2 v[NB][R];
+    int lo[NB], oo[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int t = threadIdx.x + q * kFftThreads;
+        if (t < nb) {
+            const int l = sdiv(t, Mm), j = t - l * m;
+            const int jn = sdiv(j, Mns), k = j - jn * Ns;
+            lo[q] = l;
+            oo[q] = jn * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v[q][r] = x[lds_at(l, j + r * m, P)];
+                if (r) v[q][r] = cmul(v[q][r], tw[r * k * tws]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int t = threadIdx.x + q * kFftThreads;
+        if (t < nb) {
+            const int l = lo[q], o = oo[q];
+            if constexpr (R == 2) {
+                x[lds_at(l, o, P)] = cadd(v[q][0], v[q][1]);
+                x[lds_at(l, o + Ns, P)] = csub(v[q][0], v[q][1]);
+            } else if constexpr (R == 4) {
+                const double2 s0 = cadd(v[q][0], v[q][2]), d0 = csub(v[q][0], v[q][2]);
+                const double2 s1 = cadd(v[q][1], v[q][3]), d1 = csub(v[q][1], v[q][3]);
+                const double2 md1 = make_double2(d1.y, -d1.x);  // -i * d1
+                x[lds_at(l, o, P)] = cadd(s0, s1);
+                x[lds_at(l, o + Ns, P)] = cadd(d0, md1);
+                x[lds_at(l, o + 2 * Ns, P)] = csub(s0, s1);
+                x[lds_at(l, o + 3 * Ns, P)] = csub(d0, md1);
+            } else {
+#pragma unroll
+                for (int s = 0; s < R; ++s) {
+                    double2 acc = v[q][0];
+#pragma unroll
+                    for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[q][r], tw[((r * s) % R) * tR]));
+                    x[lds_at(l, o + s * Ns, P)] = acc;
+                }
+            }
+        }
+    }
+    __syncthreads();
 }
 
-// One Stockham stage of radix R on nl lines of length N: src -> dst (LDS), Ns = product of
-// the radices of the earlier stages.  Butterfly j (0 <= j < N/R) reads src[j + r N/R],
-// r = 0..R-1, applies the twiddles exp(-2 pi i r k/(Ns R)) with k = j mod Ns, takes a
-// length-R DFT and writes output s to dst[(j/Ns) Ns R + k + s Ns].
-template <int R>
-__device__ __forceinline__ void fft_stage_small(const double2 *src, double2 *dst, int N, int ld, int nl, int Ns) {
-    const int m = N / R;
-    for (int t = threadIdx.x; t < nl * m; t += blockDim.x) {
-        const int l = t / m, j = t % m;
-        const double2 *a = src + (size_t)l * ld;
-        double2 *b = dst + (size_t)l * ld;
-        const int k = j % Ns;
-        double2 v[R];
+// generic radix R (any prime above 5): one work item per output, outputs held in
+// registers until every input has been read
+__device__ __forceinline__ void fft_stage_generic(double2 *x, const double2 *tw, const FftPlan &P, int nl, int Ns,
+                                                  int R) {
+    const int N = P.N, m = N / R, tws = N / (Ns * R), tR = N / R;
+    const uint64_t MN = small_magic(N), Mm = small_magic(m), Mns = small_magic(Ns);
+    double2 out[kFftPerThread];
+    int at[kFftPerThread];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            v[r] = a[j + r * m];
-            if (r) v[r] = cmul(v[r], twiddle((long long)r * k, (long long)Ns * R));
+    for (int q = 0; q < kFftPerThread; ++q) {
+        const int t = threadIdx.x + q * kFftThreads;
+        if (t < nl * N) {
+            const int l = sdiv(t, MN), qq = t - l * N;
+            const int s = sdiv(qq, Mm), j = qq - s * m;
+            const int jn = sdiv(j, Mns), k = j - jn * Ns;
+            double2 acc = x[lds_at(l, j, P)];
+            int rs = 0;
+            for (int r = 1; r < R; ++r) {
+                rs += s;
+                if (rs >= R) rs -= R;
+                const double2 w = cmul(x[lds_at(l, j + r * m, P)], tw[r * k * tws]);
+                acc = cadd(acc, cmul(w, tw[rs * tR]));
+            }
+            out[q] = acc;
+            at[q] = lds_at(l, jn * Ns * R + k + s * Ns, P);
         }
-        const int o = (j / Ns) * Ns * R + k;
-        if constexpr (R == 2) {
-            b[o] = cadd(v[0], v[1]);
-            b[o + Ns] = csub(v[0], v[1]);
-        } else if constexpr (R == 4) {
-            const double2 s0 = cadd(v[0], v[2]), d0 = csub(v[0], v[2]);
-            const double2 s1 = cadd(v[1], v[3]), d1 = csub(v[1], v[3]);
-            const double2 md1 = make_double2(d1.y, -d1.x);  // -i * d1
-            b[o] = cadd(s0, s1);
-            b[o + Ns] = cadd(d0, md1);
-            b[o + 2 * Ns] = csub(s0, s1);
-            b[o + 3 * Ns] = csub(d0, md1);
-        } else {
+    }
+    __syncthreads();
 #pragma unroll
-            for (int s = 0; s < R; ++s) {
-                double2 acc = v[0];
+    for (int q = 0; q < kFftPerThread; ++q) {
+        const int t = threadIdx.x + q * kFftThreads;
+        if (t < nl * N) x[at[q]] = out[q];
+    }
+    __syncthreads();
+}
+
+// Element offset of element j of line L in the field.
+__device__ __forceinline__ size_t line_elem(const FftPlan &P, int L, int j) {
+    const int hi = (int)fdiv(L, P.dna), lo = L - hi * P.na;
+    return (size_t)lo * P.sa + (size_t)hi * P.sb + (size_t)j * P.es;
+}
+
+// Line and element of slot t of a block's line group (x pass: elements of one line are
+// consecutive in t; y and z passes: lines are, so loads and stores coalesce along x).
+__device__ __forceinline__ void slot_lj(const FftPlan &P, int t, int &l, int &j) {
+    if (P.contig) {
+        l = (int)fdiv(t, P.dN);
+        j = t - l * P.N;
+    } else {
+        j = (int)fdiv(t, P.dnl);
+        l = t - j * P.nl;
+    }
+}
+
+// The thread index behind an empty asm: the slot indexes of the store phase are formed
+// again instead of being kept live through the stages.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Load the elements of the thread's slots of line group g into val (zero past the last
+// line).
+template <int SRC, typename T>
+__device__ __forceinline__ void load_group(const FftPlan &P, const double2 *X, const T *u, size_t n3, int g,
+                                           double2 (&val)[kFftPerThread]) {
+    const int nl = P.nl, ne = nl * P.N;
+    const int L0 = g * nl, nact = min(nl, P.nlines - L0);
+    const int tid = opaque_tid();
 #pragma unroll
-                for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], twiddle((long long)((r * s) % R), R)));
-                b[o + s * Ns] = acc;
+    for (int q = 0; q < kFftPerThread; ++q) {
+        const int t = tid + q * kFftThreads;
+        val[q] = make_double2(0.0, 0.0);
+        int l, j;
+        slot_lj(P, t, l, j);
+        if (t < ne && l < nact) {
+            const size_t e = line_elem(P, L0 + l, j);
+            if constexpr (SRC == 0) {
+                val[q] = X[e];
+            } else {
+                const double r = double(u[e]);
+                if constexpr (SRC == 1)
+                    val[q] = make_double2(double(u[n3 + e]) / r, double(u[2 * n3 + e]) / r);
+                else
+                    val[q] = make_double2(double(u[3 * n3 + e]) / r, 0.0);
             }
         }
     }
 }
 
-// generic radix R (any prime): one work item per output
-__device__ __forceinline__ void fft_stage_generic(const double2 *src, double2 *dst, int N, int ld, int nl, int Ns,
-                                                  int R) {
-    const int m = N / R;
-    for (int t = threadIdx.x; t < nl * N; t += blockDim.x) {
-        const int l = t / N, q = t % N;
-        const int j = q % m, s = q / m;
-        const double2 *a = src + (size_t)l * ld;
-        const int k = j % Ns;
-        double2 acc = a[j];
-        for (int r = 1; r < R; ++r) {
-            const double2 v = cmul(a[j + r * m], twiddle((long long)r * k, (long long)Ns * R));
-            acc = cadd(acc, cmul(v, twiddle((long long)((r * s) % R), R)));
-        }
-        dst[(size_t)l * ld + (j / Ns) * Ns * R + k + s * Ns] = acc;
-    }
-}
-
-__global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2 *data, FftPlan P) {
-    extern __shared__ double2 lds_c[];
-    const int N = P.N, nl = P.nl, ld = P.ld;
-    for (long long g = blockIdx.x; g * nl < P.nlines; g += gridDim.x) {
-        const long long L0 = g * nl;
-        const int nact = (int)min((long long)nl, P.nlines - L0);
-        double2 *src = lds_c, *dst = lds_c + (size_t)nl * ld;
-        for (int t = threadIdx.x; t < nl * N; t += blockDim.x) {
-            const int l = P.contig ? t / N : t % nl;
-            const int j = P.contig ? t % N : t / nl;
-            if (l < nact) {
-                const long long L = L0 + l;
-                const size_t base = (size_t)(L % P.na) * P.sa + (size_t)(L / P.na) * P.sb;
-                src[(size_t)l * ld + j] = data[base + (size_t)j * P.es];
-            } else {
-                src[(size_t)l * ld + j] = make_double2(0.0, 0.0);
+// Batched 1-D FFTs of one pass.  SRC = 0: the lines of X are transformed in place.
+// SRC = 1 or 2 (x pass only): the lines are formed from the state u, v_x + i v_y (1) or
+// v_z (2), with v = m / rho, and the transform is written to X.  POW2: the line length is
+// a power of two, so only the radix-4 and radix-2 stages are compiled in (104-120
+// VGPRs instead of the 180-195 that the odd radices bring).  One line group per block.
+template <int SRC, typename T, bool POW2>
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2 *X, const T *u, size_t n3, FftPlan P) {
+    extern __shared__ double2 lds_c[];  // [N] twiddles, then [nl][ld] lines
+    double2 *tws = lds_c, *lines = lds_c + P.N;
+    const int nl = P.nl;
+    const int ne = nl * P.N;
+    const int ngroups = (P.nlines + nl - 1) / nl;
+    for (int k = threadIdx.x; k < P.N; k += kFftThreads) tws[k] = P.tw[k];
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int L0 = g * nl;
+        const int nact = min(nl, P.nlines - L0);
+        {
+            double2 val[kFftPerThread];
+            load_group<SRC, T>(P, X, u, n3, g, val);
+            const int tid = opaque_tid();
+#pragma unroll
+            for (int q = 0; q < kFftPerThread; ++q) {
+                const int t = tid + q * kFftThreads;
+                int l, j;
+                slot_lj(P, t, l, j);
+                if (t < ne) lines[lds_at(l, j, P)] = val[q];
             }
         }
         __syncthreads();
         int Ns = 1;
         for (int st = 0; st < P.nr; ++st) {
             const int R = P.radix[st];
-            if (R == 4) fft_stage_small<4>(src, dst, N, ld, nl, Ns);
-            else if (R == 2) fft_stage_small<2>(src, dst, N, ld, nl, Ns);
-            else if (R == 3) fft_stage_small<3>(src, dst, N, ld, nl, Ns);
-            else if (R == 5) fft_stage_small<5>(src, dst, N, ld, nl, Ns);
-            else fft_stage_generic(src, dst, N, ld, nl, Ns, R);
-            __syncthreads();
-            double2 *tmp = src;
-            src = dst;
-            dst = tmp;
+            if (R == 4) {
+                fft_stage_small<4>(lines, tws, P, nl, Ns);
+            } else if (R == 2) {
+                fft_stage_small<2>(lines, tws, P, nl, Ns);
+            } else if constexpr (!POW2) {
+                if (R == 3) fft_stage_small<3>(lines, tws, P, nl, Ns);
+                else if (R == 5) fft_stage_small<5>(lines, tws, P, nl, Ns);
+                else fft_stage_generic(lines, tws, P, nl, Ns, R);
+            }
             Ns *= R;
         }
-        for (int t = threadIdx.x; t < nl * N; t += blockDim.x) {
-            const int l = P.contig ? t / N : t % nl;
-            const int j = P.contig ? t % N : t / nl;
-            if (l < nact) {
-                const long long L = L0 + l;
-                const size_t base = (size_t)(L % P.na) * P.sa + (size_t)(L / P.na) * P.sb;
-                data[base + (size_t)j * P.es] = src[(size_t)l * ld + j];
-            }
+        const int tid = opaque_tid();
+#pragma unroll
+        for (int q = 0; q < kFftPerThread; ++q) {
+            const int t = tid + q * kFftThreads;
+            int l, j;
+            slot_lj(P, t, l, j);
+            if (t < ne && l < nact) X[line_elem(P, L0 + l, j)] = lines[lds_at(l, j, P)];
         }
         __syncthreads();  // the next group reuses the LDS
+    }
+}
+
+// tw[k] = exp(-2 pi i k / N), k < N
+__global__ void k_fft_twiddles(double2 *tw, int N) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)k / (double)N, &s, &c);
+        tw[k] = make_double2(c, s);
     }
 }
 
@@ -263,48 +387,75 @@ int spectrum_shells(const BoxDesc &b) {
 bool spectrum_supported(const BoxDesc &b) {
     const int n[3] = {b.nx, b.ny, b.nz};
     for (int d = 0; d < 3; ++d)
-        if ((size_t)2 * (n[d] + 1) * sizeof(double2) > kFftLdsMax) return false;
+        if (n[d] > 2047) return false;
     // the shell histogram must fit in LDS, one block's partials and the per-shell second
     // moments in the rhs buffer (at least 20 bytes per point)
     const size_t hist = 2 * sizeof(double) * (size_t)spectrum_shells(b);
     return hist <= kFftLdsMax && hist + sizeof(double) * (size_t)spectrum_shells(b) <= 20 * b.n3;
 }
 
-static void fft_pass(double2 *X, const BoxDesc &b, int dir, hipStream_t s) {
+// One pass of batched line FFTs along direction dir.  SRC as in k_fft_lines; tw holds the
+// twiddle table of this direction's length.
+template <int SRC, typename T>
+static void fft_pass(double2 *X, const T *u, const BoxDesc &b, int dir, const double2 *tw, hipStream_t s) {
     FftPlan P{};
-    const size_t nx = b.nx, ny = b.ny, nz = b.nz;
+    const size_t nx = b.nx, ny = b.ny;
     P.N = dir == 0 ? b.nx : (dir == 1 ? b.ny : b.nz);
     P.nr = fft_factor(P.N, P.radix);
-    P.nlines = (long long)(b.n3 / P.N);
+    P.nlines = (int)(b.n3 / P.N);
     if (dir == 0) {
         P.na = P.nlines, P.sa = nx, P.sb = 0, P.es = 1, P.contig = 1;
     } else if (dir == 1) {
-        P.na = nx, P.sa = 1, P.sb = nx * ny, P.es = nx, P.contig = 0;
+        P.na = (int)nx, P.sa = 1, P.sb = nx * ny, P.es = nx, P.contig = 0;
     } else {
         P.na = P.nlines, P.sa = 1, P.sb = 0, P.es = nx * ny, P.contig = 0;
     }
-    // lines per block: fill the LDS budget (two buffers), at most 64 lines
-    P.ld = P.N + 1;
-    const int nl = (int)std::max<size_t>(1, std::min<size_t>(64, kFftLdsMax / (2 * sizeof(double2) * P.ld)));
+    // lines per block: at most kFftElems elements and the line LDS budget, at most 64 lines
+    P.swz = P.N % 16 == 0 ? 14 : 0;
+    P.ld = P.swz ? P.N : P.N + 1;
+    const int nl = std::max(1, std::min({64, kFftElems / P.N, (int)(kFftLineLds / (sizeof(double2) * P.ld))}));
     P.nl = nl;
-    const size_t lds = 2 * sizeof(double2) * (size_t)nl * P.ld;
+    P.dN = fastdiv((uint32_t)P.N);
+    P.dnl = fastdiv((uint32_t)nl);
+    P.dna = fastdiv((uint32_t)P.na);
+    P.tw = tw;
+    const size_t lds = sizeof(double2) * ((size_t)nl * P.ld + P.N);
     const long long groups = (P.nlines + nl - 1) / nl;
     const unsigned grid = (unsigned)std::min<long long>(groups, 1 << 20);
-    (void)nz;
-    hipLaunchKernelGGL(k_fft_lines, dim3(grid), dim3(kFftThreads), lds, s, X, P);
+    if ((P.N & (P.N - 1)) == 0)
+        hipLaunchKernelGGL((k_fft_lines<SRC, T, true>), dim3(grid), dim3(kFftThreads), lds, s, X, u, b.n3, P);
+    else
+        hipLaunchKernelGGL((k_fft_lines<SRC, T, false>), dim3(grid), dim3(kFftThreads), lds, s, X, u, b.n3, P);
+}
+
+template <typename T>
+static void spectrum_transforms(const BoxDesc &b, hipStream_t s, const T *u, double2 *X1, double2 *X2,
+                                double2 *tw) {
+    // twiddle tables of the three lengths at the start of the rhs buffer (free until the
+    // binning below writes its partials there)
+    const int n[3] = {b.nx, b.ny, b.nz};
+    const double2 *twd[3];
+    double2 *t = tw;
+    for (int d = 0; d < 3; ++d) {
+        hipLaunchKernelGGL(k_fft_twiddles, dim3((n[d] + 255) / 256), dim3(256), 0, s, t, n[d]);
+        twd[d] = t;
+        t += n[d];
+    }
+    fft_pass<1, T>(X1, u, b, 0, twd[0], s);
+    fft_pass<2, T>(X2, u, b, 0, twd[0], s);
+    for (int d = 1; d < 3; ++d) {
+        fft_pass<0, T>(X1, nullptr, b, d, twd[d], s);
+        fft_pass<0, T>(X2, nullptr, b, d, twd[d], s);
+    }
 }
 
 void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, double *E, int nshell, double *mom) {
     double2 *X1 = (double2 *)b.A, *X2 = (double2 *)b.B;
     const unsigned pg = (unsigned)std::min<size_t>((b.n3 + kPointThreads - 1) / kPointThreads, 65536);
     if (prec == CNS_FP64)
-        hipLaunchKernelGGL(k_spec_pack<double>, dim3(pg), dim3(kPointThreads), 0, s, (const double *)u, b.n3, X1, X2);
+        spectrum_transforms<double>(b, s, (const double *)u, X1, X2, (double2 *)b.rhs);
     else
-        hipLaunchKernelGGL(k_spec_pack<float>, dim3(pg), dim3(kPointThreads), 0, s, (const float *)u, b.n3, X1, X2);
-    for (int d = 0; d < 3; ++d) {
-        fft_pass(X1, b, d, s);
-        fft_pass(X2, b, d, s);
-    }
+        spectrum_transforms<float>(b, s, (const float *)u, X1, X2, (double2 *)b.rhs);
     SpecGeom G;
     G.nx = b.nx, G.ny = b.ny, G.nz = b.nz, G.nshell = nshell, G.n3 = b.n3;
     G.kux = 2.0 * M_PI * b.inv_h[0] / b.nx;

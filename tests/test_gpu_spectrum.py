@@ -25,6 +25,7 @@ def case(msg):
     ((24, 20, 36), (2.0, 3.0, 4.0), "fp64"),   # radix 4, 2, 3, 5 and ragged sizes
     ((9, 17, 14), None, "fp64"),               # odd sizes and a prime (17) line length
     ((8, 8, 8), None, "fp64"),
+    ((20, 12, 48), None, "fp64"),              # swizzled rows of a non-power-of-two length, ragged last line group
     ((32, 32, 32), None, "mixed"),
 ])
 def test_spectrum_matches_oracle(shape, length, precision):

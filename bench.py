@@ -211,6 +211,8 @@ def main():
                "kind": "oracle",
                "sample": f"{args.cpu_steps} RK4 steps (with diagnostics) of the same {n}^3 workload, "
                          f"{ct:.1f} s, OpenMP over grid points"}
+        cpu["host"] = _host_cpu()
+        cpu["configs"] = _oracle_configs()
         cpu1 = _oracle_one_core(n, mu)
         if cpu1:
             cpu["one_core"] = cpu1
@@ -267,6 +269,82 @@ def _timed(stream, fn):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3, r
+
+
+def _oracle_configs():
+    """The oracle beside the GPU path on the other configurations, all host threads: the
+    32^3 workload in full (10 RK4 steps), the first 32^3 and 96^3 boxes of the uneven
+    ensemble (2 RK4 steps each), and the gradient of the final kinetic energy at 16^3 (2
+    RK4 steps; the restatement runs op by op, several seconds per step) from
+    the PyTorch CPU restatement.  Each with the GPU time of the same work."""
+    import torch
+
+    import oracle
+    from oracle import torch_ref
+    from paper_2211_16718_amd import inputs as I
+    from paper_2211_16718_amd.adjoint import FinalKineticEnergy
+    from paper_2211_16718_amd.api import Plan
+
+    def both(n, rho, vel, p, mu, steps):
+        ph = oracle.make_phys(mu_eff=mu)
+        uh = oracle.init_state(rho, vel, p)
+        plan = Plan((n, n, n), mu_eff=mu)
+        u = plan.init_state(rho, vel, p)
+        dt = I.dt_from_speed(plan.diagnostics_host(u)[7], n)
+        plan.rk4(plan.empty_state().copy_(u), dt, 1)  # warm
+        gsec, _ = _timed(plan.stream, lambda: plan.rk4(u, dt, steps))
+        t0 = time.perf_counter()
+        oracle.rk4(uh, dt, steps, ph)
+        csec = time.perf_counter() - t0
+        work = 4.0 * n ** 3 * steps
+        return {"grid": n, "steps": steps, "oracle_point_rhs_per_s": work / csec, "oracle_s": csec,
+                "gpu_point_rhs_per_s": work / gsec, "gpu_s": gsec, "gpu_over_oracle": csec / gsec}
+
+    out = {"cores": oracle.num_threads()}
+    wl = I.WORKLOADS["hit32"]
+    out["hit32_rk4x10"] = both(32, *I.hit_primitives(32, wl.seed, wl.mt), 1.0 / wl.re, 10)
+    for want in (32, 96):
+        i = next(i for i in range(64) if I.ensemble_box_params(i)[0].n == want)
+        box, rho, vel, p = I.ensemble_box_primitives(i)
+        out[f"ensemble_box{i}_n{want}_rk4x2"] = both(want, rho, vel, p, 1.0 / box.re, 2)
+    n, steps, mu = 16, 2, 1.0 / 400
+    rho, vel, p = I.hit_primitives(n, 0, 0.3)
+    plan = Plan((n, n, n), mu_eff=mu)
+    dt = I.dt_from_speed(plan.diagnostics_host(plan.init_state(rho, vel, p))[7], n)
+    r, v, q = (torch.from_numpy(a).cuda() for a in (rho, vel, p))
+
+    def grad():
+        v0 = v.clone().requires_grad_(True)
+        FinalKineticEnergy.apply(v0, r, q, plan, dt, steps, 1).backward()
+        return v0.grad
+
+    grad()  # warm
+    gsec, _ = _timed(plan.stream, grad)
+    t0 = time.perf_counter()
+    torch_ref.final_ke_and_grad(rho, vel, p, dt, steps, torch_ref.make_phys(mu=mu))
+    csec = time.perf_counter() - t0
+    out[f"adjoint16_rk4x{steps}"] = {"grid": n, "steps": steps, "torch_cpu_s": csec, "torch_cpu_threads": torch.get_num_threads(),
+                               "gpu_s": gsec, "gpu_over_cpu": csec / gsec}
+    return out
+
+
+def _host_cpu():
+    """The host CPU the oracle ran on: model name, logical CPUs, sockets, OMP_NUM_THREADS."""
+    model, sockets = None, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "model name" and model is None:
+                    model = v.strip()
+                elif k == "physical id":
+                    sockets.add(v.strip())
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "sockets": len(sockets) or None,
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def _oracle_one_core(n, mu):

@@ -226,7 +226,7 @@ def final_ke_and_grad(rho, vel, p, dt, nsteps, ph, step=None):
         u = tcp.checkpoint(step, u, dt, ph, use_reentrant=False)
     J = kinetic_energy(u)
     (gv,) = torch.autograd.grad(J, vel)
-    return float(J), gv.detach()
+    return float(J.detach()), gv.detach()
 
 
 def rhs_vjp(u, rbar, ph):

@@ -169,7 +169,8 @@ int cns_set_graph(cns_plan *plan, int32_t enable);
 
 /* ---- ensembles: independent periodic boxes of uneven sizes advanced together ----
  * Every kernel launch covers all boxes (virtual blocks mapped to boxes by prefix
- * sums), so one RK4 step of the whole ensemble is 21 launches, optionally replayed
+ * sums), so one RK4 step of the whole ensemble is 18 launches (viscous fluxes and three
+ * sweeps per stage, two for the diagnostics), optionally replayed
  * from a captured hipGraph.  A box advanced in an ensemble gives bitwise the result
  * of its own single-box plan (same kernels, same arithmetic).  Extension beyond the
  * paper, which advances one domain. */

@@ -48,7 +48,18 @@ BYTES_PER_POINT = {
     "visc_flux": 8 * (5 + 9),              # u -> 9 viscous-flux fields
     "diagnostics": 8 * 5,
 }
+# The mixed form (FP32 state, G and rhs; FP64 accumulator, updated in every stage): u^n
+# read in stages 2-3, the accumulator written in stage 1, updated in stages 2-3 and read
+# in stage 4.
+BYTES_PER_POINT_MIXED = {
+    "sweep_x": 4 * (5 + 4 + 5),
+    "sweep_y": 4 * (5 + 4 + 5 + 5),
+    "sweep_z_rk4": 4 * (5 + 4 + 5 + 5) + (40 + 100 + 100 + 40) // 4,
+    "visc_flux": 4 * (5 + 9),
+    "diagnostics": 4 * 5,
+}
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (published; its 2x over FP64 needs packed FP32)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9  # VALU lane-instructions per second (3.93e13)
 
@@ -70,6 +81,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=128, help="grid points per direction (128 = the named workload)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64 (the named workload) or the mixed form, for profiling it alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="RK4 steps of the oracle sample")
     ap.add_argument("--no-extras", action="store_true",
@@ -107,7 +120,8 @@ def main():
     wl = I.WORKLOADS["hit128"]
     mu = 1.0 / wl.re
     rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)
-    plan = Plan((n, n, n), mu_eff=mu, precision="fp64", device="cuda:0")
+    fp64 = args.precision == "fp64"
+    plan = Plan((n, n, n), mu_eff=mu, precision=args.precision, device="cuda:0")
     u = plan.init_state(rho, vel, p)
     smax = plan.diagnostics_host(u)[7]
     dt = I.dt_from_speed(smax, n, cfl=I.CFL)
@@ -162,7 +176,7 @@ def main():
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            if t.get("kernel_source_sha256") == kernel_source_digest() and dom in t.get("kernels", {}) \
+            if fp64 and t.get("kernel_source_sha256") == kernel_source_digest() and dom in t.get("kernels", {}) \
                     and t.get("n") == n:
                 traffic = t["kernels"][dom]["bytes_per_launch"]
         except Exception:
@@ -175,22 +189,24 @@ def main():
     if os.path.exists(vfile):
         try:
             v = json.load(open(vfile))
-            if v.get("kernel_source_sha256") == kernel_source_digest() and dom in v.get("kernels", {}):
+            if fp64 and v.get("kernel_source_sha256") == kernel_source_digest() and dom in v.get("kernels", {}):
                 per = v["kernels"][dom]["valu_per_point"]
                 valu = {"valu_instructions_per_point": round(per, 1),
                         "valu_issue_frac": round(per * n ** 3 / avg_s / PEAK_VALU_LANE_INSTR, 4)}
         except Exception:
             valu = None
+    peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
+    bpp = (BYTES_PER_POINT if fp64 else BYTES_PER_POINT_MIXED)[dom]
     roofline = {
         "bound": "alu",
         "kernel": dom,
         "achieved": round(achieved, 3),
-        "peak": PEAK_FP64_TFLOPS,
+        "peak": peak,
         "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+        "frac": round(achieved / peak, 4),
         "traffic": traffic,
-        "algorithmic_bytes_per_launch": BYTES_PER_POINT[dom] * n ** 3,
-        "hbm_frac_algorithmic": round(BYTES_PER_POINT[dom] * n ** 3 / avg_s / 1e9 / PEAK_HBM_GBS, 4),
+        "algorithmic_bytes_per_launch": bpp * n ** 3,
+        "hbm_frac_algorithmic": round(bpp * n ** 3 / avg_s / 1e9 / PEAK_HBM_GBS, 4),
         "flops_per_point": FLOPS_PER_POINT[dom],
         "avg_launch_ms": round(kernels[dom]["avg_ms"], 5),
     }
@@ -234,7 +250,8 @@ def main():
             torch.cuda.empty_cache()
 
     out = {
-        "metric": "grid-point RHS evaluations per second (FP64 WENO5-Roe + central viscous, RK4)",
+        "metric": "grid-point RHS evaluations per second (FP64 WENO5-Roe + central viscous, RK4)" if fp64 else
+                  "grid-point RHS evaluations per second (mixed FP32/FP64 WENO5-Roe + central viscous, RK4)",
         "value": value,
         "unit": "point-RHS/s",
         "n_gpus": 1,
@@ -245,10 +262,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if fp64 else "f32+f64",
         "data": "synthetic (seeded HIT-spectrum initial condition)",
-        "config": {"workload": f"hit{n}_re400_rk4_diag_every_step", "grid": [n, n, n], "re": wl.re, "mt": wl.mt,
-                   "cfl": I.CFL, "dt": dt, "precision": "fp64"},
+        "config": {"workload": f"hit{n}_re400_rk4_diag_every_step" + ("" if fp64 else "_mixed"), "grid": [n, n, n],
+                   "re": wl.re, "mt": wl.mt, "cfl": I.CFL, "dt": dt, "precision": args.precision},
         "roofline": roofline,
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "launches": v["launches"], "share": round(v["share"], 4)}
                     for k, v in kernels.items()},

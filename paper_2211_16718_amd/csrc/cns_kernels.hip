@@ -451,9 +451,13 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) pr[v] = rhs[v * n3 + o];
                 if (MODE == MODE_RK && L.stage >= 2) {
-                    const T *un = (const T *)state_ptr(bx, L, BUF_U);
+                    // u^n: every later stage but the mixed form's RK4 stage 4, which
+                    // needs only the accumulator
+                    if (L.scheme == CNS_TVDRK3 || kFp64Stages<T> || L.stage != 4) {
+                        const T *un = (const T *)state_ptr(bx, L, BUF_U);
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) pu[v] = un[v * n3 + o];
+                        for (int v = 0; v < 5; ++v) pu[v] = un[v * n3 + o];
+                    }
                     // the FP64 form reads the accumulator in the last stage only
                     if (L.scheme != CNS_TVDRK3 && (!kFp64Stages<T> || L.stage == 4)) {
 #pragma unroll

@@ -197,6 +197,21 @@ __device__ __forceinline__ constexpr int gcomp(int c) {
                     : (DIR == 1 ? (c == 0 ? 3 : c == 1 ? 1 : c == 2 ? 5 : 7) : (c == 0 ? 4 : c == 1 ? 5 : c == 2 ? 2 : 8));
 }
 
+// A stage's sweeps run x, y, z.  The G field of component c along DIR is read for the
+// last time in that stage by this sweep when no later sweep reads it (tau_xy: x then y;
+// tau_xz: x then z; tau_yz: y then z); such loads, and the z sweep's loads of rhs and
+// of the FP64 accumulator, are marked non-temporal so they do not displace lines that
+// are read again.
+template <int DIR, int C>
+__device__ __forceinline__ constexpr bool g_last_read() {
+    return DIR == 2 || (DIR == 1 && C != 2) || (DIR == 0 && (C == 0 || C == 3));
+}
+template <int DIR, int C, typename T>
+__device__ __forceinline__ T load_g(const T *G, size_t n3, size_t o) {
+    if constexpr (g_last_read<DIR, C>()) return __builtin_nontemporal_load(&G[gcomp<DIR>(C) * n3 + o]);
+    else return G[gcomp<DIR>(C) * n3 + o];
+}
+
 // viscous term alone: out = sum_d D_d G_d (the viscous-only entry point)
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
@@ -429,8 +444,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) g[m][c] = g[m + 1][c];
                 const size_t og = base + wrapi(j + 2, n) * sg.lstride;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) g[3][c] = G[gcomp<DIR>(c) * n3 + og];
+                g[3][0] = load_g<DIR, 0>(G, n3, og);
+                g[3][1] = load_g<DIR, 1>(G, n3, og);
+                g[3][2] = load_g<DIR, 2>(G, n3, og);
+                g[3][3] = load_g<DIR, 3>(G, n3, og);
             }
             const int sold = snew;
             {
@@ -449,7 +466,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
             if (MODE != MODE_WRITE && j >= j0) {
                 const T *rhs = (const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs));
 #pragma unroll
-                for (int v = 0; v < 5; ++v) pr[v] = rhs[v * n3 + o];
+                for (int v = 0; v < 5; ++v) {
+                    if constexpr (MODE == MODE_RK) pr[v] = __builtin_nontemporal_load(&rhs[v * n3 + o]);
+                    else pr[v] = rhs[v * n3 + o];
+                }
                 if (MODE == MODE_RK && L.stage >= 2) {
                     // u^n: every later stage but the mixed form's RK4 stage 4, which
                     // needs only the accumulator
@@ -461,7 +481,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                     // the FP64 form reads the accumulator in the last stage only
                     if (L.scheme != CNS_TVDRK3 && (!kFp64Stages<T> || L.stage == 4)) {
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) pa[v] = bx.acc[v * n3 + o];
+                        for (int v = 0; v < 5; ++v) pa[v] = __builtin_nontemporal_load(&bx.acc[v * n3 + o]);
                     }
                 }
             }
@@ -505,7 +525,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
                                 unext[e] = us + (0.5 * dt) * k;
                             } else if (L.stage == 2) {
                                 const double uo = pu[v];
-                                acc[e] = (uo + (1.0 / 3.0) * (us - uo)) + (dt / 3.0) * k;
+                                __builtin_nontemporal_store((uo + (1.0 / 3.0) * (us - uo)) + (dt / 3.0) * k, &acc[e]);
                                 unext[e] = uo + (0.5 * dt) * k;
                             } else if (L.stage == 3) {
                                 unext[e] = pu[v] + dt * k;
@@ -578,8 +598,10 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) pw[k][v] = u[v * n3 + o];
                 if constexpr (VISC) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) pg[k][c] = G[gcomp<0>(c) * n3 + o];
+                    pg[k][0] = load_g<0, 0>(G, n3, o);
+                    pg[k][1] = load_g<0, 1>(G, n3, o);
+                    pg[k][2] = load_g<0, 2>(G, n3, o);
+                    pg[k][3] = load_g<0, 3>(G, n3, o);
                 }
             }
         }
@@ -620,8 +642,10 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
 #pragma unroll
                     for (int v = 0; v < 5; ++v) wk[v] = u[v * n3 + o];
                     if constexpr (VISC) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) gk[c] = G[gcomp<0>(c) * n3 + o];
+                        gk[0] = load_g<0, 0>(G, n3, o);
+                        gk[1] = load_g<0, 1>(G, n3, o);
+                        gk[2] = load_g<0, 2>(G, n3, o);
+                        gk[3] = load_g<0, 3>(G, n3, o);
                     }
                 }
                 euler_flux<T, 0>(wk, gm1, f);

@@ -99,7 +99,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is not part of this build", file=sys.stderr)
+              "domain decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -170,16 +170,17 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
                 T tyz = mu * (g[1][2] + g[2][1]);
                 const T vx = Wz[2][0], vy = Wz[2][1], vz = Wz[2][2];
                 const size_t idx = (size_t)k * sz + col;
-                G[idx] = txx;
-                G[n3 + idx] = tyy;
-                G[2 * n3 + idx] = tzz;
-                G[3 * n3 + idx] = txy;
-                G[4 * n3 + idx] = txz;
-                G[5 * n3 + idx] = tyz;
-                // E_d = v . tau_d - q_d,  q_d = -kcond dT/dx_d
-                G[6 * n3 + idx] = vx * txx + vy * txy + vz * txz + kcond * g[3][0];
-                G[7 * n3 + idx] = vx * txy + vy * tyy + vz * tyz + kcond * g[3][1];
-                G[8 * n3 + idx] = vx * txz + vy * tyz + vz * tzz + kcond * g[3][2];
+                // non-temporal stores: G is streamed to memory and read back by the sweeps
+                // (at 128^3: 1.3 % faster step, at 512^3: 1.9 %)
+                __builtin_nontemporal_store(txx, &G[idx]);
+                __builtin_nontemporal_store(tyy, &G[n3 + idx]);
+                __builtin_nontemporal_store(tzz, &G[2 * n3 + idx]);
+                __builtin_nontemporal_store(txy, &G[3 * n3 + idx]);
+                __builtin_nontemporal_store(txz, &G[4 * n3 + idx]);
+                __builtin_nontemporal_store(tyz, &G[5 * n3 + idx]);
+                __builtin_nontemporal_store(vx * txx + vy * txy + vz * txz + kcond * g[3][0], &G[6 * n3 + idx]);
+                __builtin_nontemporal_store(vx * txy + vy * tyy + vz * tyz + kcond * g[3][1], &G[7 * n3 + idx]);
+                __builtin_nontemporal_store(vx * txz + vy * tyz + vz * tzz + kcond * g[3][2], &G[8 * n3 + idx]);
             }
             __syncthreads();  // the next plane overwrites the LDS tile
 #pragma unroll

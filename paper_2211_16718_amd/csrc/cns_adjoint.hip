@@ -323,18 +323,20 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc1(AdjGeom g, const do
             // tau_aa = mu (2 g_aa - 2/3 div), tau_ab = mu (g_ab + g_ba)
             const double divb = -2.0 / 3.0 * mu * (bxx + byy + bzz);
             const size_t idx = (size_t)k * sz + t.col;
-            Gb[idx] = 2.0 * mu * bxx + divb;
-            Gb[n3 + idx] = 2.0 * mu * byy + divb;
-            Gb[2 * n3 + idx] = 2.0 * mu * bzz + divb;
-            Gb[3 * n3 + idx] = mu * bxy;
-            Gb[4 * n3 + idx] = mu * bxz;
-            Gb[5 * n3 + idx] = mu * byz;
-            Gb[6 * n3 + idx] = kc * Ex;
-            Gb[7 * n3 + idx] = kc * Ey;
-            Gb[8 * n3 + idx] = kc * Ez;
-            Gb[9 * n3 + idx] = Ex * txx + Ey * txy + Ez * txz;
-            Gb[10 * n3 + idx] = Ex * txy + Ey * tyy + Ez * tyz;
-            Gb[11 * n3 + idx] = Ex * txz + Ey * tyz + Ez * tzz;
+            // non-temporal stores: the fields are streamed to memory for the second
+            // kernel, so they do not displace the state's halo lines in L2
+            __builtin_nontemporal_store(2.0 * mu * bxx + divb, &Gb[idx]);
+            __builtin_nontemporal_store(2.0 * mu * byy + divb, &Gb[n3 + idx]);
+            __builtin_nontemporal_store(2.0 * mu * bzz + divb, &Gb[2 * n3 + idx]);
+            __builtin_nontemporal_store(mu * bxy, &Gb[3 * n3 + idx]);
+            __builtin_nontemporal_store(mu * bxz, &Gb[4 * n3 + idx]);
+            __builtin_nontemporal_store(mu * byz, &Gb[5 * n3 + idx]);
+            __builtin_nontemporal_store(kc * Ex, &Gb[6 * n3 + idx]);
+            __builtin_nontemporal_store(kc * Ey, &Gb[7 * n3 + idx]);
+            __builtin_nontemporal_store(kc * Ez, &Gb[8 * n3 + idx]);
+            __builtin_nontemporal_store(Ex * txx + Ey * txy + Ez * txz, &Gb[9 * n3 + idx]);
+            __builtin_nontemporal_store(Ex * txy + Ey * tyy + Ez * tyz, &Gb[10 * n3 + idx]);
+            __builtin_nontemporal_store(Ex * txz + Ey * tyz + Ez * tzz, &Gb[11 * n3 + idx]);
         }
         __syncthreads();  // the next plane overwrites the LDS tile
 #pragma unroll

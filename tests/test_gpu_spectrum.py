@@ -26,6 +26,7 @@ def case(msg):
     ((9, 17, 14), None, "fp64"),               # odd sizes and a prime (17) line length
     ((8, 8, 8), None, "fp64"),
     ((20, 12, 48), None, "fp64"),              # swizzled rows of a non-power-of-two length, ragged last line group
+    ((8, 8, 2047), None, "fp64"),              # the longest supported line (2047 = 23 x 89: generic radices)
     ((32, 32, 32), None, "mixed"),
 ])
 def test_spectrum_matches_oracle(shape, length, precision):
@@ -75,3 +76,16 @@ def test_spectrum_argument_errors():
     assert plan.lib.cns_spectrum_shells(None) < 0
     with pytest.raises(ValueError):
         plan.spectrum(torch.empty(3, device="cuda", dtype=torch.float64))
+
+
+def test_spectrum_unsupported_grids():
+    """A line longer than 2047 points, or more shells than the scratch holds, is refused
+    on the host before any launch (CNS_EUNSUPPORTED)."""
+    case("spectrum unsupported")
+    for shape, length in (((8, 8, 2048), None), ((8, 8, 8), (0.01, 0.01, 0.01))):
+        plan = Plan(shape, length=length or (2 * math.pi,) * 3)
+        u = plan.init_state(*I.uniform_primitives(0, shape=shape))
+        ns = int(plan.lib.cns_spectrum_shells(plan.h))
+        E = torch.empty(max(ns, 1), dtype=torch.float64, device="cuda")
+        mom = torch.empty(2, dtype=torch.float64, device="cuda")
+        assert plan.lib.cns_spectrum(plan.h, u.data_ptr(), E.data_ptr(), ns, mom.data_ptr()) == -6, shape

@@ -28,6 +28,8 @@
  *    plan's stream and return without synchronising, except where a call
  *    returns host values (stated per call).
  *  - Periodic grid: x_i = i * lx / nx, i = 0..nx-1, likewise y and z; nx, ny, nz >= 8.
+ *  - Physics: gamma > 1, mu_eff >= 0, Prandtl > 0 when mu_eff > 0, weno_eps in
+ *    [1e-30, 1e30], harten_delta >= 0; otherwise CNS_EINVAL.
  */
 #ifndef CNS_H
 #define CNS_H
@@ -62,7 +64,7 @@ typedef struct {
     double gamma;        /* ratio of specific heats, > 1 */
     double prandtl;      /* Prandtl number, > 0 when mu_eff > 0 */
     double mu_eff;       /* mu * M_inf / Re_inf (Sec. 2.1 scaling); 0 = Euler (viscous terms skipped) */
-    double weno_eps;     /* epsilon of the WENO weights, > 0 (paper: 1e-6) */
+    double weno_eps;     /* epsilon of the WENO weights, in [1e-30, 1e30] (paper: 1e-6) */
     double harten_delta; /* Harten threshold delta >= 0; 0 = plain |lambda| */
     int32_t weno_weights; /* CNS_WENO_JS (Sec. 2.2: Jiang-Shu), CNS_WENO_Z (Borges et al. 2008,
                              exponent 2) or CNS_WENO_M (mapped, Henrick et al. 2005): the two
@@ -134,7 +136,9 @@ int cns_tvdrk3(cns_plan *plan, void *u_dev, double dt, int32_t nsteps, double *d
  * physical wavenumber k_d = 2 pi n_d / L_d:
  *   E_dev[s]      = sum over modes with round(|k|) = s of |v_hat|^2 / 2,  s = 0..nshell-1;
  *   moments_dev[0] = sum_s E[s] (= <|v|^2>/2), moments_dev[1] = sum over modes of |k|^2 |v_hat|^2 / 2,
- * so the Taylor microscale is sqrt(5 moments[0] / moments[1]).  FP64 for either precision.
+ *   moments_dev[2] = the Taylor microscale sqrt(5 moments[0] / moments[1]) of isotropic
+ *   turbulence (+inf for a uniform velocity).
+ * moments_dev holds three doubles.  FP64 for either precision.
  * Uses the plan's stage buffers as scratch (ordered with other calls on the plan's
  * stream).  nshell must equal cns_spectrum_shells(plan) (round(|k|max) + 1), else
  * CNS_EINVAL; grids with a dimension above 2047, more than 4096 shells, or more than one
@@ -142,6 +146,12 @@ int cns_tvdrk3(cns_plan *plan, void *u_dev, double dt, int32_t nsteps, double *d
  * sums use LDS atomics, so their last bits may differ between runs. */
 int cns_spectrum_shells(const cns_plan *plan);
 int cns_spectrum(const cns_plan *plan, const void *u_dev, double *E_dev, int32_t nshell, double *moments_dev);
+
+/* The CFL wave speed of Sec. 2.2's explicit time step: out_dev[0] = max over grid points
+ * and directions d of |v_d| + c, c = sqrt(gamma p / rho) (FP64, one device double; the
+ * same value as slot 7 of the diagnostics).  NaN when a point is non-finite or has
+ * rho <= 0 or p <= 0.  Uses the plan's diagnostics scratch (ordered on its stream). */
+int cns_max_wave_speed(const cns_plan *plan, const void *u_dev, double *out_dev);
 
 /* Diagnostics of u into device memory out_dev[CNS_NDIAG]. */
 int cns_diagnostics(const cns_plan *plan, const void *u_dev, double *out_dev);
@@ -161,11 +171,16 @@ int cns_profile_enable(cns_plan *plan, int32_t enable);
  * (host arrays of CNS_NKERNEL entries). */
 int cns_profile_read(const cns_plan *plan, double *ms_host, int64_t *count_host);
 
-/* hipGraph replay of cns_rk4: the launches of all nsteps are captured once per
- * (u, dt, nsteps, diag) and replayed; enable = 0 launches eagerly.  Needs a plan
- * created on a non-default stream (else CNS_EUNSUPPORTED).  Replays are bitwise
+/* hipGraph replay of cns_rk4 / cns_tvdrk3: the launches of all nsteps are captured once
+ * per (integrator, nsteps, diagnostics on or off) and replayed; the state pointer, dt and
+ * the diagnostics pointer of each call reach the replay through a device record in the
+ * workspace, written by a kernel enqueued before every replay (so calls with new
+ * buffers or step sizes replay the same graph).  enable = 0 launches eagerly.  Needs a
+ * plan created on a non-default stream (else CNS_EUNSUPPORTED).  Replays are bitwise
  * identical to eager launches. */
 int cns_set_graph(cns_plan *plan, int32_t enable);
+/* Number of graph captures made by the plan so far (>= 0), or a negative error code. */
+int64_t cns_plan_graph_captures(const cns_plan *plan);
 
 /* ---- ensembles: independent periodic boxes of uneven sizes advanced together ----
  * Every kernel launch covers all boxes (virtual blocks mapped to boxes by prefix
@@ -197,6 +212,10 @@ int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path);
  * [nbox][nsteps][CNS_NDIAG].  use_graph != 0 captures the whole run once and
  * replays it (non-default stream required). */
 int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag_dev, int32_t use_graph);
+/* Number of graph captures made by the ensemble so far (>= 0; a capture is reused while
+ * nsteps, the integrator and whether diagnostics are written stay the same), or a
+ * negative error code. */
+int64_t cns_ensemble_graph_captures(const cns_ensemble *ens);
 /* Integrator of cns_ensemble_run: CNS_RK4 (default) or CNS_TVDRK3 (else CNS_EINVAL). */
 int cns_ensemble_set_integrator(cns_ensemble *ens, int32_t scheme);
 int cns_ensemble_profile_enable(cns_ensemble *ens, int32_t enable);

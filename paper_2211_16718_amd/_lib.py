@@ -63,6 +63,9 @@ SIGNATURES = {
     "cns_spectrum_shells": (C.c_int, [_vp]),
     "cns_spectrum": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp]),
     "cns_diagnostics_host": (C.c_int, [_vp, _vp, _dp]),
+    "cns_max_wave_speed": (C.c_int, [_vp, _vp, _vp]),
+    "cns_plan_graph_captures": (C.c_int64, [_vp]),
+    "cns_ensemble_graph_captures": (C.c_int64, [_vp]),
     "cns_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "cns_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
     "cns_set_graph": (C.c_int, [_vp, C.c_int32]),

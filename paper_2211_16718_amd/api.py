@@ -91,6 +91,9 @@ class Plan:
             return t.contiguous()
         with torch.cuda.stream(self.stream):
             r, v, pp = dev(rho), dev(vel), dev(p)
+            for name, t, want in (("rho", r, self.shape), ("vel", v, (3,) + self.shape), ("p", pp, self.shape)):
+                if tuple(t.shape) != want:
+                    raise ValueError(f"{name} must have shape {want} (got {tuple(t.shape)})")
             u = self.empty_state() if out is None else self._state(out, "out")
             check(self.lib.cns_init_state(self.h, _ptr(r), _ptr(v), _ptr(pp), _ptr(u)), "cns_init_state")
         self._keep = (r, v, pp)  # alive until the stream has consumed them
@@ -132,21 +135,35 @@ class Plan:
 
     def spectrum(self, u):
         """Kinetic-energy spectrum of the velocity m/rho: ``(E, moments)``, device float64
-        tensors ``[nshell]`` and ``[2]`` = (sum E, sum |k|^2 |v_hat|^2 / 2)."""
+        tensors ``[nshell]`` and ``[3]`` = (sum E, sum |k|^2 |v_hat|^2 / 2, Taylor
+        microscale), all computed by the library."""
         self._state(u)
         ns = int(self.lib.cns_spectrum_shells(self.h))
         if ns < 1:
             check(ns, "cns_spectrum_shells")
         E = torch.empty(ns, dtype=torch.float64, device=self.device)
-        mom = torch.empty(2, dtype=torch.float64, device=self.device)
+        mom = torch.empty(3, dtype=torch.float64, device=self.device)
         check(self.lib.cns_spectrum(self.h, _ptr(u), _ptr(E), ns, _ptr(mom)), "cns_spectrum")
         return E, mom
 
     @staticmethod
     def taylor_microscale(moments):
-        """lambda = sqrt(5 sum E / M2) from :meth:`spectrum`'s moments (isotropic relation)."""
-        m = [float(x) for x in moments]
-        return math.sqrt(5.0 * m[0] / m[1])
+        """The Taylor microscale that :meth:`spectrum` returned in ``moments[2]``."""
+        return float(moments[2])
+
+    def max_wave_speed(self, u, out=None):
+        """max over points and directions of |v_d| + c (device float64 tensor ``[1]``)."""
+        self._state(u)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        check(self.lib.cns_max_wave_speed(self.h, _ptr(u), _ptr(out)), "cns_max_wave_speed")
+        return out
+
+    def graph_captures(self):
+        """Graph captures made so far (replays of an unchanged run reuse one capture)."""
+        n = int(self.lib.cns_plan_graph_captures(self.h))
+        if n < 0:
+            check(n, "cns_plan_graph_captures")
+        return n
 
     def diagnostics(self, u, out=None):
         self._state(u)
@@ -305,6 +322,13 @@ class Ensemble:
         check(self.lib.cns_ensemble_run(self.h, int(nsteps), _ptr(d) if d is not None else None,
                                         1 if graph else 0), "cns_ensemble_run")
         return d[:, :nsteps] if d is not None else None
+
+    def graph_captures(self):
+        """Graph captures made so far (replays of an unchanged run reuse one capture)."""
+        n = int(self.lib.cns_ensemble_graph_captures(self.h))
+        if n < 0:
+            check(n, "cns_ensemble_graph_captures")
+        return n
 
     def profile(self, enable=True):
         check(self.lib.cns_ensemble_profile_enable(self.h, 1 if enable else 0), "cns_ensemble_profile_enable")

@@ -52,7 +52,10 @@ static int validate(const cns_grid *g, const cns_physics *ph) {
     if (!(ph->gamma > 1.0) || !std::isfinite(ph->gamma)) return set_err(CNS_EINVAL, "gamma must exceed 1");
     if (!(ph->mu_eff >= 0.0) || !std::isfinite(ph->mu_eff)) return set_err(CNS_EINVAL, "mu_eff must be >= 0");
     if (ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return set_err(CNS_EINVAL, "prandtl must be > 0");
-    if (!(ph->weno_eps > 0.0)) return set_err(CNS_EINVAL, "weno_eps must be > 0");
+    // products of up to six (eps + beta) factors are formed in FP64 (and eps is rounded
+    // to FP32 in the mixed form): eps outside [1e-30, 1e30] would leave their range
+    if (!(ph->weno_eps >= 1e-30 && ph->weno_eps <= 1e30))
+        return set_err(CNS_EINVAL, "weno_eps must lie in [1e-30, 1e30] (got %g)", ph->weno_eps);
     if (!(ph->harten_delta >= 0.0)) return set_err(CNS_EINVAL, "harten_delta must be >= 0");
     if (ph->weno_weights != CNS_WENO_JS && ph->weno_weights != CNS_WENO_Z && ph->weno_weights != CNS_WENO_M)
         return set_err(CNS_EINVAL, "unknown weno_weights %d", ph->weno_weights);
@@ -73,7 +76,7 @@ struct Core {
     std::vector<char> active;    // boxes given blocks (all, except while autotuning)
     // workspace layout
     std::vector<size_t> box_off;  // per-box scratch base
-    size_t table_off = 0, dhost_off = 0, need = 0;
+    size_t table_off = 0, dhost_off = 0, gp_off = 0, need = 0;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool dirty = true;
@@ -86,9 +89,9 @@ struct Core {
     Prof prof;
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;
-    const void *g_u = nullptr;
-    double g_dt = 0, *g_diag = nullptr;
+    bool g_diag_on = false;
     int g_nsteps = -1, g_scheme = -1;
+    long long captures = 0;  // graph captures so far (replays reuse one)
     int scheme = CNS_RK4;  // integrator of cns_ensemble_run
 
     ~Core() {
@@ -122,6 +125,8 @@ struct Core {
         off = align256(off + boxes.size() * sizeof(BoxDesc) + (size_t)F_N * (boxes.size() + 1) * sizeof(long long));
         dhost_off = off;
         off = align256(off + CNS_NDIAG * sizeof(double));
+        gp_off = off;
+        off = align256(off + sizeof(GraphParams));
         need = off;
     }
 
@@ -240,42 +245,51 @@ struct Core {
         g_nsteps = -1;
     }
 
-    // nsteps steps of the integrator `sch`; diag layout [nbox][nsteps][CNS_NDIAG]
+    // nsteps steps of the integrator `sch`; diag layout [nbox][nsteps][CNS_NDIAG].
+    // A graph run captures the launches once per (integrator, nsteps, diagnostics on or
+    // off); the state, step size and diagnostics base of each call reach the captured
+    // kernels through the GraphParams record, written by a kernel before every replay.
     int run(int sch, const void *u_ov, double dt_ov, int nsteps, double *diag) {
         int rc = sync_table();
         if (rc) return rc;
         Batch bt = batch();
+        const bool graph = use_graph && !prof.on && nsteps > 0;
+        if (graph && !stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
+        GraphParams *gp = (GraphParams *)(ws + gp_off);
+        if (graph) bt.gp = gp;
+        const void *u_l = graph ? nullptr : u_ov;
+        const double dt_l = graph ? 0.0 : dt_ov;
         auto enqueue = [&]() {
             for (int n = 0; n < nsteps; ++n) {
-                launch_step(bt, sch, u_ov, dt_ov, diag, nsteps, n);
+                launch_step(bt, sch, u_l, dt_l, diag, nsteps, n);
                 prof_flush(bt.prof);
             }
         };
-        if (!use_graph || prof.on || nsteps == 0) {
+        if (!graph) {
             enqueue();
             return check_hip("rk4");
         }
-        if (!stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
-        if (!(gexec && g_u == u_ov && g_dt == dt_ov && g_diag == diag && g_nsteps == nsteps && g_scheme == sch)) {
+        if (!(gexec && g_nsteps == nsteps && g_scheme == sch && g_diag_on == (diag != nullptr))) {
             drop_graph();
-            hipGraph_t graph = nullptr;
+            hipGraph_t graph_h = nullptr;
             hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return set_err(CNS_EHIP, "begin capture: %s", hipGetErrorString(e));
             enqueue();
-            e = hipStreamEndCapture(stream, &graph);
+            e = hipStreamEndCapture(stream, &graph_h);
             if (e != hipSuccess) return set_err(CNS_EHIP, "end capture: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
+            e = hipGraphInstantiate(&gexec, graph_h, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph_h);
             if (e != hipSuccess) {
                 gexec = nullptr;
                 return set_err(CNS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
             }
-            g_u = u_ov;
             g_scheme = sch;
-            g_dt = dt_ov;
-            g_diag = diag;
+            g_diag_on = diag != nullptr;
             g_nsteps = nsteps;
+            ++captures;
         }
+        launch_set_params(gp, u_ov, diag, dt_ov, stream);
+        if ((rc = check_hip("graph parameters"))) return rc;
         hipError_t e = hipGraphLaunch(gexec, stream);
         if (e != hipSuccess) return set_err(CNS_EHIP, "graph launch: %s", hipGetErrorString(e));
         return CNS_OK;
@@ -361,7 +375,8 @@ static int autotune(Core &c, const char *cache_path) {
         const std::string key = pre + kv.first + "|seg";
         int best = -1;
         auto it = cache.find(key);
-        if (it != cache.end()) {
+        const BoxDesc &bk = c.boxes[kv.second[0]];
+        if (it != cache.end() && it->second >= 1 && it->second <= std::max(bk.ny, bk.nz)) {
             best = it->second;
         } else {
             // time this class alone: other boxes get no blocks (sweeps skip them)
@@ -393,10 +408,13 @@ static int autotune(Core &c, const char *cache_path) {
         c.boxes[i] = saved[i];
         c.active[i] = 1;
     }
-    // block size of the batch
-    const std::string bkey = pre + "block|n" + std::to_string(c.nbox());
+    // block size of the batch, keyed by its box sizes
+    std::string bkey = pre + "block";
+    for (auto &kv : cls) bkey += "|" + kv.first + "x" + std::to_string(kv.second.size());
     auto bit = cache.find(bkey);
-    if (bit != cache.end()) {
+    const bool valid = bit != cache.end() && (bit->second == 64 || bit->second == 128 || bit->second == 192 ||
+                                              bit->second == 256);
+    if (valid) {
         c.block = bit->second;
     } else {
         float best_ms = 1e30f;
@@ -620,6 +638,22 @@ int cns_diagnostics_host(const cns_plan *plan, const void *u, double *out_host) 
     return CNS_OK;
 }
 
+int cns_max_wave_speed(const cns_plan *plan, const void *u, double *out) {
+    int rc = check_plan(plan);
+    if (!rc) rc = check_ptr(u, "u");
+    if (rc) return rc;
+    if (!out || ((uintptr_t)out & 7u)) return set_err(CNS_EINVAL, "out must be non-null and 8-byte aligned");
+    cns_plan *p = const_cast<cns_plan *>(plan);
+    if ((rc = p->c.sync_table())) return rc;
+    launch_max_wave_speed(p->c.batch(), u, out);
+    return check_hip("max_wave_speed");
+}
+
+int64_t cns_plan_graph_captures(const cns_plan *plan) {
+    if (!plan) return set_err(CNS_EINVAL, "null plan");
+    return plan->c.captures;
+}
+
 int cns_profile_enable(cns_plan *plan, int32_t enable) {
     if (!plan) return set_err(CNS_EINVAL, "null plan");
     return plan->c.profile_enable(enable);
@@ -725,6 +759,11 @@ int cns_ensemble_run(cns_ensemble *ens, int32_t nsteps, double *diag, int32_t us
     if (use_graph && !ens->c.stream) return set_err(CNS_EUNSUPPORTED, "graph replay needs a non-default stream");
     ens->c.use_graph = use_graph != 0;
     return ens->c.run(ens->c.scheme, nullptr, 0.0, nsteps, diag);
+}
+
+int64_t cns_ensemble_graph_captures(const cns_ensemble *ens) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    return ens->c.captures;
 }
 
 int cns_ensemble_set_integrator(cns_ensemble *ens, int32_t scheme) {

@@ -45,6 +45,16 @@ struct BoxDesc {
 // kernel families with their own virtual-block prefix
 enum Family { F_POINT = 0, F_XROWS, F_SWEEP_X, F_SWEEP_Y, F_SWEEP_Z, F_DIAG, F_BOX, F_VISC, F_N };
 
+// Per-call arguments of a replayed hipGraph: the captured launches read the state, the
+// step size and the diagnostics base from this device record (written by a small kernel
+// before every replay), so one capture serves calls with other pointers and step sizes.
+struct GraphParams {
+    const void *u;  // replaces the box's state u when non-null
+    double *diag;   // diagnostics output base
+    double dt;      // replaces the box's dt when positive
+    double pad;
+};
+
 // per-launch arguments
 struct Launch {
     const BoxDesc *boxes;
@@ -63,6 +73,7 @@ struct Launch {
     double dt_ov;      // replaces the box's dt
     double *diag;      // diagnostics output base (may be null)
     long long diag_box_stride;  // records between consecutive boxes in `diag`
+    const GraphParams *gp;      // graph replay: u_ov, dt_ov and diag come from here
 };
 
 // optional per-kernel timing with HIP events on the plan's stream
@@ -110,6 +121,7 @@ struct Batch {
     size_t rowLds = 0;  // LDS bytes of the rows kernel (max over boxes)
     hipStream_t stream = nullptr;
     Prof *prof = nullptr;
+    const GraphParams *gp = nullptr;  // set while a run is captured for graph replay
 };
 
 // host-side helpers (cns_kernels.hip)
@@ -134,10 +146,15 @@ void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *di
 void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag,
                  long long diag_box_stride, int step, void *const *stage_states = nullptr);
 void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag_box_stride, int step);
+// max over points and directions of |v_d| + c of every box into out[box] (NaN for a box
+// with a non-finite state, rho <= 0 or p <= 0)
+void launch_max_wave_speed(const Batch &bt, const void *u_ov, double *out);
+// the per-call record of a graph replay (enqueued before the replay)
+void launch_set_params(GraphParams *gp, const void *u, double *diag, double dt, hipStream_t s);
 // time the y and z marching sweeps over the batch (autotuning); milliseconds per launch pair
 float time_sweeps_yz(const Batch &bt, int reps);
 
-// kinetic-energy spectrum (cns_spectrum.hip), one box: E[nshell] and mom = {sum E, M2};
+// kinetic-energy spectrum (cns_spectrum.hip), one box: E[nshell] and mom = {sum E, M2, lambda};
 // scratch: the box's A, B and rhs buffers
 int spectrum_shells(const BoxDesc &b);
 bool spectrum_supported(const BoxDesc &b);

@@ -69,6 +69,16 @@ __device__ __forceinline__ long long xcd_block(long long b, long long n) {
 template <typename T>
 constexpr bool kFp64Stages = std::is_same<T, double>::value;
 
+// the launch with the per-call record of a graph replay applied (read once per kernel)
+__device__ __forceinline__ Launch with_params(Launch L) {
+    if (L.gp) {
+        L.u_ov = L.gp->u;
+        L.dt_ov = L.gp->dt;
+        L.diag = L.gp->diag;
+    }
+    return L;
+}
+
 __device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
     if (which == BUF_U) return L.u_ov ? L.u_ov : b.u;
     if (which == BUF_A) return L.a_ov ? L.a_ov : b.A;
@@ -118,7 +128,8 @@ __device__ __forceinline__ void prim_at(const T *u, size_t n3, size_t i, T gamma
 // own column's primitives at planes k-2 .. k+2 in registers (z derivatives).  About
 // three primitive evaluations per point instead of thirteen, and no primitive array.
 template <typename T>
-__global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L) {
+__global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
+    const Launch L = with_params(L0);
     __shared__ T pl[4][kViscTY + 4][kViscTX + 4];
     const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
     for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
@@ -215,7 +226,8 @@ __device__ __forceinline__ T load_g(const T *G, size_t n3, size_t o) {
 
 // viscous term alone: out = sum_d D_d G_d (the viscous-only entry point)
 template <typename T>
-__global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L) {
+__global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L0) {
+    const Launch L = with_params(L0);
     const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
     for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
         const int bi = find_box(L.off, L.nbox, vb);
@@ -375,7 +387,8 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
 // it (y sweep 12 % and fused-update sweep 6 % faster than a register window).  The
 // fused update's u^n and accumulator are loaded ahead in the same way.
 template <typename T, typename B, int DIR, int MODE, bool VISC, int WW>
-__global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
+__global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
+    const Launch L = with_params(L0);
     extern __shared__ unsigned char lds_raw[];
     T *ring = reinterpret_cast<T *>(lds_raw) + threadIdx.x;  // slot s, component v at (s * 5 + v) * blockDim.x
     const int bdim = blockDim.x;
@@ -571,7 +584,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L) {
 // computed once; the periodic wrap happens in LDS.
 // ----------------------------------------------------------------------------
 template <typename T, typename B, bool VISC, int P, int WW>
-__global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L) {
+__global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
+    const Launch L = with_params(L0);
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
     // A block walks over several row groups (grid stride).  With one point per thread
@@ -759,7 +773,8 @@ __device__ __forceinline__ void vel_at(const T *u, size_t n3, size_t i, double v
 // an LDS copy of the current plane (with a +-2 halo) and whose z neighbours from a
 // per-column window of five planes in registers.
 template <typename T>
-__global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
+__global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
+    const Launch L = with_params(L0);
     __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
     __shared__ double pv[3][kViscTY + 4][kViscTX + 4];
     const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
@@ -839,7 +854,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L) {
     }
 }
 
-__global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L) {
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L0) {
+    const Launch L = with_params(L0);
     __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
     for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
         const int bi = (int)vb;  // one virtual block per box
@@ -856,6 +872,85 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L) {
         const double scale[CNS_NDIAG] = {inv, inv, inv, inv, inv, inv, inv, 1.0, 1.0};
         double *dst = L.diag ? L.diag + ((size_t)bi * L.diag_box_stride + L.step) * CNS_NDIAG : nullptr;
         block_reduce_diag(acc, red, dst, scale);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// the CFL wave speed alone: max over points and directions of |v_d| + c (the same
+// point arithmetic as slot 7 of the diagnostics), two passes per box
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_speed_partial(Launch L0) {
+    const Launch L = with_params(L0);
+    __shared__ double red[kDiagThreads / 64][2];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &bx = L.boxes[bi];
+        const int nblk = diag_blocks(bx.nx, bx.ny, bx.nz);
+        const int lb = (int)(vb - L.off[bi]);
+        const T *u = (const T *)state_ptr(bx, L, BUF_U);
+        const size_t n3 = bx.n3;
+        const double gamma = bx.gamma;
+        double smax = 0.0, bad = 0.0;
+        for (size_t i = (size_t)lb * kDiagThreads + threadIdx.x; i < n3; i += (size_t)nblk * kDiagThreads) {
+            const double r = double(u[i]), mx = double(u[n3 + i]), my = double(u[2 * n3 + i]),
+                         mz = double(u[3 * n3 + i]), e = double(u[4 * n3 + i]);
+            const double inv = rcp(r);
+            const double vx = mx * inv, vy = my * inv, vzc = mz * inv;
+            const double ke = 0.5 * (mx * vx + my * vy + mz * vzc);
+            const double p = (gamma - 1.0) * (e - ke);
+            const bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
+            if (!finite || !(r > 0.0) || !(p > 0.0)) {
+                bad += 1.0;
+            } else {
+                const double c = sqrt(gamma * p * inv);
+                smax = fmax(smax, fmax(fabs(vx), fmax(fabs(vy), fabs(vzc))) + c);
+            }
+        }
+        smax = wave_max(smax);
+        bad = wave_sum(bad);
+        if (lane == 0) {
+            red[wid][0] = smax;
+            red[wid][1] = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = red[0][0], b = red[0][1];
+            for (int w2 = 1; w2 < kDiagThreads / 64; ++w2) {
+                m = fmax(m, red[w2][0]);
+                b += red[w2][1];
+            }
+            bx.part[(size_t)lb * CNS_NDIAG + 7] = m;
+            bx.part[(size_t)lb * CNS_NDIAG + 8] = b;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void k_speed_final(Launch L0, double *out) {
+    const Launch L = with_params(L0);
+    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+        const int bi = (int)vb;  // one virtual block per box
+        const BoxDesc &bx = L.boxes[bi];
+        const int nblk = diag_blocks(bx.nx, bx.ny, bx.nz);
+        double m = 0.0, b = 0.0;
+        for (int k = threadIdx.x; k < nblk; k += 64) {
+            m = fmax(m, bx.part[(size_t)k * CNS_NDIAG + 7]);
+            b += bx.part[(size_t)k * CNS_NDIAG + 8];
+        }
+        m = wave_max(m);
+        b = wave_sum(b);
+        if (threadIdx.x == 0) out[bi] = b > 0.0 ? __builtin_nan("") : m;
+    }
+}
+
+__global__ void k_set_params(GraphParams *gp, const void *u, double *diag, double dt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        gp->u = u;
+        gp->diag = diag;
+        gp->dt = dt;
+        gp->pad = 0.0;
     }
 }
 
@@ -902,6 +997,7 @@ long long family_blocks(const BoxDesc &b, int fam, int block) {
 
 static Launch make_launch(const Batch &bt, int fam) {
     Launch L{};
+    L.gp = bt.gp;
     L.boxes = bt.d_boxes;
     L.off = bt.d_off[fam];
     L.nbox = bt.nbox;
@@ -1065,6 +1161,21 @@ static void diag_t(const Batch &bt, const void *u_ov, double *diag, long long st
     hipLaunchKernelGGL(k_diag_partial<T>, dim3(grid_for(L.total)), dim3(kDiagThreads), 0, bt.stream, L);
     const Launch F = with_family(bt, L, F_BOX);
     hipLaunchKernelGGL(k_diag_final, dim3(grid_for(F.total)), dim3(kDiagThreads), 0, bt.stream, F);
+}
+
+void launch_max_wave_speed(const Batch &bt, const void *u_ov, double *out) {
+    Launch L = make_launch(bt, F_DIAG);
+    L.u_ov = u_ov;
+    if (bt.prec == CNS_FP64)
+        hipLaunchKernelGGL(k_speed_partial<double>, dim3(grid_for(L.total)), dim3(kDiagThreads), 0, bt.stream, L);
+    else
+        hipLaunchKernelGGL(k_speed_partial<float>, dim3(grid_for(L.total)), dim3(kDiagThreads), 0, bt.stream, L);
+    const Launch F = with_family(bt, L, F_BOX);
+    hipLaunchKernelGGL(k_speed_final, dim3(grid_for(F.total)), dim3(64), 0, bt.stream, F, out);
+}
+
+void launch_set_params(GraphParams *gp, const void *u, double *diag, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, s, gp, u, diag, dt);
 }
 
 void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long stride, int step) {

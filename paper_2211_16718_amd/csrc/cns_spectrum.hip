@@ -353,7 +353,8 @@ __global__ __launch_bounds__(kPointThreads) void k_spec_final(const double *part
     }
 }
 
-// mom = {sum_s E[s], sum_s M2[s]} in shell order
+// mom = {sum_s E[s], sum_s M2[s]} in shell order, and the Taylor microscale
+// lambda = sqrt(5 sum E / M2) of isotropic turbulence (+inf for a uniform velocity)
 __global__ void k_spec_mom(const double *E, const double *M2, int nshell, double *mom) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double e = 0.0, m = 0.0;
@@ -363,6 +364,7 @@ __global__ void k_spec_mom(const double *E, const double *M2, int nshell, double
     }
     mom[0] = e;
     mom[1] = m;
+    mom[2] = m > 0.0 ? sqrt(5.0 * e / m) : __builtin_inf();
 }
 
 // ---------------------------------------------------------------------------

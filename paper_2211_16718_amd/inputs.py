@@ -102,12 +102,17 @@ def hit_primitives(n: int, seed: int, mt: float, gamma: float = 1.4, urms: float
 
 
 def vortex_primitives(n: int, t: float = 0.0, strength: float = 5.0, gamma: float = 1.4,
-                      adv=(1.0, 1.0, 0.0), radius: float = TWO_PI / 10.0,
-                      nz: int | None = None):
+                      adv=None, radius: float = TWO_PI / 10.0,
+                      nz: int | None = None, plane: str = "xy"):
     """Isentropic vortex (Euler) advected uniformly, evaluated at time ``t``.
 
-    Free stream ``rho = p = 1``, velocity ``adv``; centre ``(pi, pi)`` at
-    ``t = 0``, core radius ``radius``.  With ``xt = (x - xc)/R``,
+    ``plane`` names the two axes the vortex lies in: ``"xy"`` (the default:
+    invariant along z, advection ``adv = (1, 1, 0)``, arrays ``[nz][n][n]``) or
+    ``"yz"`` (invariant along x, advection ``(0, 1, 1)``, arrays ``[n][n][nz]``
+    with ``nz`` points along x), the same flow with the roles of the axes
+    exchanged (a = x, b = y, or a = y, b = z below).
+    Free stream ``rho = p = 1``, velocity ``adv``; centre ``(pi, pi)`` in the
+    plane at ``t = 0``, core radius ``radius``.  With ``xt = (a - ac)/R``,
     ``r^2 = xt^2 + yt^2``::
 
         du = -(b / 2pi) yt exp((1 - r^2)/2),   dv = (b / 2pi) xt exp((1 - r^2)/2)
@@ -119,10 +124,14 @@ def vortex_primitives(n: int, t: float = 0.0, strength: float = 5.0, gamma: floa
     periodic box truncates it at ``r = pi/R`` core radii.
     """
     nz = n if nz is None else nz
+    if plane not in ("xy", "yz"):
+        raise ValueError(f"plane must be 'xy' or 'yz' (got {plane!r})")
+    ia, ib, ic = (0, 1, 2) if plane == "xy" else (1, 2, 0)
+    if adv is None:
+        adv = (1.0, 1.0, 0.0) if plane == "xy" else (0.0, 1.0, 1.0)
     x = grid_coords(n)
-    z = grid_coords(nz)
-    xc = math.pi + adv[0] * t
-    yc = math.pi + adv[1] * t
+    xc = math.pi + adv[ia] * t
+    yc = math.pi + adv[ib] * t
 
     def periodic_delta(a, c):
         d = np.mod(a - c + math.pi, TWO_PI) - math.pi
@@ -138,14 +147,49 @@ def vortex_primitives(n: int, t: float = 0.0, strength: float = 5.0, gamma: floa
     temp = 1.0 - (gamma - 1.0) * b * b / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
     rho2 = temp ** (1.0 / (gamma - 1.0))
     p2 = rho2 ** gamma
-    shape = (nz, n, n)
-    rho = np.broadcast_to(rho2, shape).copy()
-    p = np.broadcast_to(p2, shape).copy()
+    if plane == "xy":
+        shape = (nz, n, n)
+        place = lambda f: np.broadcast_to(f, shape).copy()  # noqa: E731  [b][a] -> [z][y][x]
+    else:
+        shape = (n, n, nz)
+        place = lambda f: np.broadcast_to(f[:, :, None], shape).copy()  # noqa: E731  [b][a] -> [z][y][.]
+    rho = place(rho2)
+    p = place(p2)
     vel = np.empty((3,) + shape)
-    vel[0] = np.broadcast_to(adv[0] + du, shape)
-    vel[1] = np.broadcast_to(adv[1] + dv, shape)
-    vel[2] = adv[2]
+    vel[ia] = place(adv[ia] + du)
+    vel[ib] = place(adv[ib] + dv)
+    vel[ic] = adv[ic]
     return rho, vel, p
+
+
+def shock_primitives(shape, axis: int, seed: int = 0, strength: str = "sod"):
+    """Discontinuous data along ``axis`` (0 = x, 1 = y, 2 = z) on a smooth background.
+
+    Along the line coordinate ``s`` in ``[0, 2 pi)`` the density and pressure are
+    piecewise constant with three jumps per period: at ``s = pi/2`` a shock-tube
+    (Sod-type) jump of density and pressure, at ``s = 3 pi/2`` a contact (density
+    only, pressure continuous), and at the periodic wrap a jump of both.  Levels:
+    ``"sod"``: (rho, p) = (0.125, 0.1) | (1, 1) | (0.5, 1); ``"strong"``: the same
+    densities with pressures 1 | 1e5 | 1e5 (energy jumps of about 2.5e5, where
+    products of four (eps + beta) factors leave the FP32 range).  Every field is
+    multiplied (density, pressure) or offset (velocity) by a band-limited smooth
+    random field of ``smooth_primitives``, so the transverse directions are not
+    trivial.  Returns ``(rho, vel, p)``.
+    """
+    nz, ny, nx = (int(v) for v in shape)
+    levels = {"sod": ((0.125, 0.1), (1.0, 1.0), (0.5, 1.0)),
+              "strong": ((0.125, 1.0), (1.0, 1e5), (0.5, 1e5))}[strength]
+    rho_s, vel_s, p_s, _ = smooth_primitives((nz, ny, nx), seed=seed, amp=0.05, mean_vel=(0.2, -0.1, 0.15))
+    nline = (nx, ny, nz)[axis]
+    s = grid_coords(nline)
+    region = np.where(s < 0.5 * math.pi, 0, np.where(s < 1.5 * math.pi, 1, 2))
+    r_line = np.array([levels[q][0] for q in region])
+    p_line = np.array([levels[q][1] for q in region])
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = nline  # arrays are [z][y][x]
+    rho = rho_s * r_line.reshape(bshape)
+    p = p_s * p_line.reshape(bshape)
+    return rho, vel_s, p
 
 
 def uniform_primitives(n: int, rho: float = 1.0, vel=(0.3, -0.2, 0.1), p: float = 1.0,

@@ -1,0 +1,123 @@
+"""Discontinuous data on the GPU against the FP64 oracle.
+
+Jumps are where the nonlinear WENO weights matter (paper Sec. 2.2: the smoothness
+indicators beta_k of a candidate stencil that crosses a jump are large, and the
+weights omega_k = alpha_k / sum alpha with alpha_k = c_k / (eps + beta_k)^2 shut it
+off).  Every input has a shock-tube jump of density and pressure, a contact and a
+third jump along one axis (inputs.shock_primitives) on a smooth background, so one
+indicator of an interface can exceed the others by ten orders of magnitude.
+
+Bars: FP64 within 1e-12 (joint relative max-norm) of the oracle per RHS and per
+direction, for Harten thresholds 1e-6 and 0.5, and within 1e-10 after RK4 steps.  The
+mixed form: finite everywhere (its weights are formed in FP64, so products of four
+(eps + beta) factors cannot overflow FP32 even where energy jumps by 2.5e5) and within
+the FP32 rounding bound 100 * 2^-24 max|u| / (h max|rhs|) of the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_max
+from paper_2211_16718_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2211_16718_amd.api import Plan  # noqa: E402
+
+SHAPE = (24, 20, 28)  # (nz, ny, nx): every line crosses three jumps
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def fp32_bound(u_ref, r_ref, shape):
+    h = 2 * math.pi / max(shape)
+    return 100 * 2.0 ** -24 * float(np.abs(u_ref).max()) / (h * float(np.abs(r_ref).max()))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("delta", [1e-6, 0.5])
+def test_convective_term_across_jumps(orc, axis, delta):
+    case(f"discontinuity rhs_dir axis={axis} delta={delta}")
+    rho, vel, p = I.shock_primitives(SHAPE, axis, seed=axis)
+    ph = orc.make_phys(mu_eff=0.01, harten_delta=delta)
+    u_ref = orc.init_state(rho, vel, p)
+    plan = Plan(SHAPE, mu_eff=0.01, harten_delta=delta)
+    plan.set_tiles(seg=(7, 5, 9))  # ragged segment tails
+    u = plan.init_state(rho, vel, p)
+    for d in range(3):
+        ref = orc.rhs_hyp_dir(u_ref, d, ph)
+        kernels = ("rows", "march") if d == 0 else ("rows",)
+        for xk in kernels:
+            plan.set_x_kernel(xk)
+            got = plan.rhs_dir(u, d).cpu().numpy()
+            err = rel_max(got, ref)
+            print(f"  dir {d} ({xk}): rel err {err:.3e}")
+            assert err <= 1e-12, (d, xk, err)
+    plan.set_x_kernel("rows")
+    got = plan.rhs(u).cpu().numpy()
+    err = rel_max(got, orc.rhs(u_ref, ph))
+    print(f"  full rhs: rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_strong_jumps_fp64_and_mixed(orc, axis):
+    case(f"strong jumps axis={axis}")
+    rho, vel, p = I.shock_primitives(SHAPE, axis, seed=10 + axis, strength="strong")
+    ph = orc.make_phys(mu_eff=0.01)
+    u_ref = orc.init_state(rho, vel, p)
+    r_ref = orc.rhs(u_ref, ph)
+    plan = Plan(SHAPE, mu_eff=0.01)
+    err = rel_max(plan.rhs(plan.init_state(rho, vel, p)).cpu().numpy(), r_ref)
+    print(f"  fp64 rel err {err:.3e}")
+    assert err <= 1e-12
+    pm = Plan(SHAPE, mu_eff=0.01, precision="mixed")
+    um = pm.init_state(rho, vel, p)
+    rm = pm.rhs(um).double()
+    assert bool(torch.isfinite(rm).all())
+    # the oracle at the FP32-rounded state isolates the arithmetic from the input rounding
+    r_ref32 = orc.rhs(um.double().cpu().numpy(), ph)
+    errm = rel_max(rm.cpu().numpy(), r_ref32)
+    tol = fp32_bound(u_ref, r_ref, SHAPE)
+    print(f"  mixed rel err {errm:.3e} (bound {tol:.1e})")
+    assert errm <= tol
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_mixed_across_sod_jumps(orc, axis):
+    case(f"mixed sod jumps axis={axis}")
+    rho, vel, p = I.shock_primitives(SHAPE, axis, seed=20 + axis)
+    ph = orc.make_phys(mu_eff=0.01)
+    u_ref = orc.init_state(rho, vel, p)
+    r_ref = orc.rhs(u_ref, ph)
+    pm = Plan(SHAPE, mu_eff=0.01, precision="mixed")
+    rm = pm.rhs(pm.init_state(rho, vel, p)).double().cpu().numpy()
+    errm = rel_max(rm, r_ref)
+    tol = fp32_bound(u_ref, r_ref, SHAPE)
+    print(f"  mixed rel err {errm:.3e} (bound {tol:.1e})")
+    assert np.isfinite(rm).all() and errm <= tol
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_rk4_steps_across_jumps(orc, axis):
+    case(f"rk4 across jumps axis={axis}")
+    rho, vel, p = I.shock_primitives(SHAPE, axis, seed=30 + axis)
+    ph = orc.make_phys(mu_eff=0.01)
+    u_ref = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], max(SHAPE))
+    plan = Plan(SHAPE, mu_eff=0.01)
+    u = plan.init_state(rho, vel, p)
+    d = plan.rk4(u, dt, 4).cpu().numpy()
+    uf, dref = orc.rk4(u_ref, dt, 4, ph)
+    err = rel_max(u.cpu().numpy(), uf)
+    print(f"  4 steps: state rel err {err:.3e}")
+    assert err <= 1e-10
+    assert np.all(d[:, 8] == 0)
+    np.testing.assert_allclose(d[:, :8], dref[:, :8], rtol=1e-11, atol=1e-14)

@@ -108,7 +108,8 @@ def test_autotuned_tiles_do_not_change_results():
 
 def test_graph_replays_match_eager_runs():
     # replay the captured graph several times with eager work and syncs in
-    # between; every replay must equal the eager result
+    # between; every replay must equal the eager result.  Calls with a new
+    # diagnostics buffer, another state tensor or another dt replay the same capture.
     case("graph replays")
     stream = torch.cuda.Stream()
     b = box_inputs([(24, 0.3, 200.0, 7)])[0]
@@ -119,14 +120,47 @@ def test_graph_replays_match_eager_runs():
         ue = plan_e.init_state(*b["prim"])
         ug = plan_g.init_state(*b["prim"])
     for rep in range(4):
+        dt = b["dt"] * (1.0 if rep < 2 else 0.75)
         with torch.cuda.stream(stream):
-            de = plan_e.rk4(ue, b["dt"], 2)
-            dg = plan_g.rk4(ug, b["dt"], 2)
+            de = plan_e.rk4(ue, dt, 2)
+            dg = plan_g.rk4(ug, dt, 2)
             scratch = torch.randn(1000, device="cuda") * 2  # eager work between replays
         stream.synchronize()
         assert torch.equal(ue, ug), f"replay {rep}"
         assert torch.equal(de, dg)
         del scratch
+    # another state tensor: the same capture, the new tensor advanced
+    with torch.cuda.stream(stream):
+        ug2 = ug.clone()
+        ue2 = ue.clone()
+        plan_g.rk4(ug2, b["dt"], 2)
+        plan_e.rk4(ue2, b["dt"], 2)
+    stream.synchronize()
+    assert torch.equal(ug2, ue2) and not torch.equal(ug2, ug)
+    assert plan_g.graph_captures() == 1
+    # a different step count or no diagnostics needs a capture of its own
+    with torch.cuda.stream(stream):
+        plan_g.rk4(ug, b["dt"], 3)
+        plan_g.rk4(ug, b["dt"], 3, diag=False)
+    stream.synchronize()
+    assert plan_g.graph_captures() == 3
+    assert plan_e.graph_captures() == 0
+
+
+def test_ensemble_graph_is_captured_once():
+    case("ensemble graph captured once")
+    stream = torch.cuda.Stream()
+    boxes = box_inputs(SPECS[:3])
+    ens_g = make_ensemble(boxes, stream)
+    ens_e = make_ensemble(boxes, stream)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            dg = ens_g.run(2, graph=True)
+            de = ens_e.run(2, graph=False)
+        stream.synchronize()
+        assert torch.equal(ens_g.u, ens_e.u), f"run {rep}"
+        assert torch.equal(dg, de)
+    assert ens_g.graph_captures() == 1 and ens_e.graph_captures() == 0
 
 
 def test_ensemble_box_matches_oracle():
@@ -147,11 +181,12 @@ def test_ensemble_box_matches_oracle():
 
 def test_full_ensemble_workload():
     # 64 boxes, sizes drawn from {32, 48, 64, 96}, Mt in [0.1, 0.5], Re in [100, 800],
-    # 50 RK4 steps in one captured graph; spot-check the small boxes bitwise
-    # against their single-box runs
+    # tiles from the autotuner: the first 64^3 and 96^3 boxes against the oracle over
+    # 2 RK4 steps, then 50 RK4 steps in one captured graph with every box bitwise equal
+    # to its own single-box run (default tiles, eager launches)
     import oracle
 
-    case("64-box ensemble x 50 steps")
+    case("64-box ensemble: autotune, 2 steps vs oracle, 50 steps vs single-box runs")
     stream = torch.cuda.Stream()
     boxes = []
     for i in range(64):
@@ -160,13 +195,31 @@ def test_full_ensemble_workload():
         smax = oracle.diag(oracle.init_state(rho, vel, p), oracle.make_phys(mu_eff=mu))[7]
         boxes.append(dict(shape=(box.n,) * 3, mu_eff=mu, dt=I.dt_from_speed(smax, box.n), prim=(rho, vel, p)))
     ens = make_ensemble(boxes, stream)
+    ens.autotune(None)
+    print("tiles by size:", {b["shape"][0]: ens.get_tiles(i) for i, b in enumerate(boxes)}, flush=True)
+    u0 = ens.u.clone()
+    with torch.cuda.stream(stream):
+        ens.run(2, graph=True)
+    stream.synchronize()
+    for want in (64, 96):
+        i = next(i for i, b in enumerate(boxes) if b["shape"][0] == want)
+        b = boxes[i]
+        case(f"  box {i} ({want}^3) vs oracle, 2 steps")
+        uf, _ = oracle.rk4(oracle.init_state(*b["prim"]), b["dt"], 2, oracle.make_phys(mu_eff=b["mu_eff"]),
+                           with_diag=False)
+        err = rel_max(ens.state(i).cpu().numpy(), uf)
+        print(f"  box {i}: rel err {err:.3e}", flush=True)
+        assert err <= 1e-12, f"box {i}"
+    ens.u.copy_(u0)
+    torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         diag = ens.run(50, graph=True)
     stream.synchronize()
     d = diag.cpu().numpy()
     assert np.all(d[:, :, 8] == 0)
     assert np.all(d[:, -1, 0] < d[:, 0, 0])  # kinetic energy decays in every box
-    small = [i for i, b in enumerate(boxes) if b["shape"][0] == 32][:3]
-    for i in small:
-        u, _ = single_run(boxes[i], 50, stream)
+    for i, b in enumerate(boxes):
+        u, dsingle = single_run(b, 50, stream)
         assert torch.equal(ens.state(i), u), f"box {i}"
+        assert torch.equal(diag[i], dsingle), f"diag box {i}"
+    print("all 64 boxes bitwise equal to their single-box runs", flush=True)

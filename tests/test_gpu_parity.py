@@ -226,10 +226,17 @@ def test_rhs_and_rk4_step_128(orc):
     print(f"128^3 rhs rel err {err:.3e}")
     assert err <= 1e-12
     dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], n)
-    diag = plan.rk4(u, dt, 1).cpu().numpy()
-    uf_ref, diag_ref = orc.rk4(u_ref, dt, 1, ph)
-    assert rel_max(u.cpu().numpy(), uf_ref) <= 1e-12
-    np.testing.assert_allclose(diag[0, :8], diag_ref[0, :8], rtol=1e-11, atol=1e-14)
+    # the first five steps of the 128^3 trajectory: state, kinetic energy and enstrophy
+    case("128^3 rk4 x5 trajectory (K, Omega) vs oracle")
+    diag = plan.rk4(u, dt, 5).cpu().numpy()
+    uf_ref, diag_ref = orc.rk4(u_ref, dt, 5, ph)
+    err = rel_max(u.cpu().numpy(), uf_ref)
+    kerr = np.abs(diag[:, 0] - diag_ref[:, 0]) / diag_ref[:, 0]
+    oerr = np.abs(diag[:, 1] - diag_ref[:, 1]) / diag_ref[:, 1]
+    print(f"128^3 5 steps: state rel err {err:.3e}; K rel err per step {kerr}; Omega {oerr}")
+    assert err <= 1e-10
+    assert kerr.max() <= 1e-12 and oerr.max() <= 1e-12
+    np.testing.assert_allclose(diag[:, :8], diag_ref[:, :8], rtol=1e-11, atol=1e-14)
 
 
 def test_rhs_512_sampled_points(orc):
@@ -305,6 +312,62 @@ def test_vortex_one_period_converges():
     order = math.log2(errs[0] / errs[1])
     print(f"vortex observed order {order:.2f}")
     assert order > 3.0 and errs[1] < 2e-3
+
+
+def test_vortex_full_cube_one_period():
+    """The isentropic vortex (strength 5, advection (1, 1, 0)) on the full 128^3 cube for
+    one period of the box, against the exact translated solution; the flow does not
+    depend on z, so every z plane must come out bitwise equal.  The same vortex turned
+    into the y-z plane (advection (0, 1, 1), invariant along x) makes the z sweep carry
+    the flow: it must agree with the first run after the axes are exchanged."""
+    n = 128
+    res = {}
+    for plane in ("xy", "yz"):
+        case(f"vortex 128^3 one period, plane {plane}")
+        rho, vel, p = I.vortex_primitives(n, nz=n, plane=plane)
+        plan = Plan((n, n, n), mu_eff=0.0)
+        u = plan.init_state(rho, vel, p)
+        smax = plan.diagnostics_host(u)[7]
+        steps = math.ceil(2 * math.pi / I.dt_from_speed(smax, n))
+        d = plan.rk4(u, 2 * math.pi / steps, steps).cpu().numpy()
+        ue = plan.init_state(*I.vortex_primitives(n, t=2 * math.pi, nz=n, plane=plane))
+        err = (u - ue).abs().amax(dim=(1, 2, 3)).cpu().numpy()
+        print(f"vortex {plane}: steps {steps}, max error per variable {err}, "
+              f"mass drift {abs(d[-1, 2] - d[0, 2]):.2e}")
+        assert np.all(d[:, 8] == 0)
+        assert err.max() < 2e-3
+        res[plane] = (u, err, steps)
+        del plan, ue
+    uxy, exy, sxy = res["xy"]
+    uyz, eyz, syz = res["yz"]
+    assert sxy == syz
+    assert exy[3] == 0.0 and eyz[1] == 0.0  # no velocity along the invariant axis
+    assert bool((uxy == uxy[:, :1]).all())   # z-invariant, bitwise
+    assert bool((uyz == uyz[:, :, :, :1]).all())  # x-invariant, bitwise
+    # yz[v][k][j][i] (vortex in (a, b) = (y, z)) against xy[v'][.][b][a] with the momenta
+    # exchanged: (rho, mx, my, mz, e)_yz = (rho, mz, mx, my, e)_xy
+    perm = [0, 3, 1, 2, 4]
+    a = uyz[:, :, :, 0]                   # [v][z=b][y=a]
+    b = uxy[perm][:, 0, :, :]             # [v][y=b][x=a]
+    diff = float((a - b).abs().max() / b.abs().max())
+    print(f"vortex xy vs yz after exchanging axes: rel diff {diff:.2e}")
+    assert diff <= 1e-9
+
+
+def test_max_wave_speed_matches_oracle(orc):
+    case("max wave speed")
+    for shape in ((20, 12, 36), (32, 32, 32)):
+        for precision in ("fp64", "mixed"):
+            plan, ph, rho, vel, p = setup(orc, shape, mu=0.01, precision=precision)
+            u = plan.init_state(rho, vel, p)
+            s = float(plan.max_wave_speed(u).item())
+            d = plan.diagnostics_host(u)
+            assert s == d[7], (shape, precision)  # same point arithmetic, max is order free
+            if precision == "fp64":
+                ref = orc.diag(orc.init_state(rho, vel, p), ph)[7]
+                assert s == pytest.approx(ref, rel=1e-14)
+    u[0, 1, 2, 3] = -1.0
+    assert math.isnan(float(plan.max_wave_speed(u).item()))
 
 
 @pytest.mark.parametrize("shape,precision", [((8, 9, 320), "fp64"), ((8, 8, 580), "fp64"), ((8, 8, 600), "fp64"),

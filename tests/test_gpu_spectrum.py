@@ -49,6 +49,8 @@ def test_spectrum_matches_oracle(shape, length, precision):
     np.testing.assert_allclose(E, Er, rtol=0, atol=1e-12 * tot)
     assert mom[0] == pytest.approx(tot, rel=1e-12)
     assert mom[1] == pytest.approx(m2, rel=1e-12)
+    # the library's Taylor microscale against the oracle's
+    assert mom[2] == pytest.approx(S.taylor_microscale(tot, m2), rel=1e-12)
 
 
 def test_spectrum_of_the_initial_condition_128():
@@ -71,7 +73,7 @@ def test_spectrum_argument_errors():
     plan = Plan((16, 16, 16))
     u = plan.init_state(*I.uniform_primitives(0, shape=(16, 16, 16)))
     E = torch.empty(4, dtype=torch.float64, device="cuda")
-    mom = torch.empty(2, dtype=torch.float64, device="cuda")
+    mom = torch.empty(3, dtype=torch.float64, device="cuda")
     assert plan.lib.cns_spectrum(plan.h, u.data_ptr(), E.data_ptr(), 4, mom.data_ptr()) == -1
     assert plan.lib.cns_spectrum_shells(None) < 0
     with pytest.raises(ValueError):
@@ -87,5 +89,5 @@ def test_spectrum_unsupported_grids():
         u = plan.init_state(*I.uniform_primitives(0, shape=shape))
         ns = int(plan.lib.cns_spectrum_shells(plan.h))
         E = torch.empty(max(ns, 1), dtype=torch.float64, device="cuda")
-        mom = torch.empty(2, dtype=torch.float64, device="cuda")
+        mom = torch.empty(3, dtype=torch.float64, device="cuda")
         assert plan.lib.cns_spectrum(plan.h, u.data_ptr(), E.data_ptr(), ns, mom.data_ptr()) == -6, shape

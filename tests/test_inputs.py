@@ -56,3 +56,26 @@ def test_ensemble_draws():
     b, _ = I.ensemble_box_params(3)
     b2, _ = I.ensemble_box_params(3)
     assert b == b2 and 0.1 <= b.mt <= 0.5 and 100 <= b.re <= 800
+
+
+def test_shock_inputs_have_three_jumps_per_line():
+    # density and pressure are piecewise constant along the axis (times a smooth
+    # background): the jumps sit at s = pi/2, at s = 3 pi/2 (density only) and at the wrap
+    shape = (24, 20, 28)
+    for axis in range(3):
+        rho, vel, p = I.shock_primitives(shape, axis, seed=0)
+        n = shape[2 - axis]
+        s = I.grid_coords(n)
+        line_r = np.moveaxis(rho, 2 - axis, 0).reshape(n, -1)
+        line_p = np.moveaxis(p, 2 - axis, 0).reshape(n, -1)
+        jr = np.abs(np.diff(np.log(line_r), axis=0, append=np.log(line_r[:1]))).max(axis=1)
+        jp = np.abs(np.diff(np.log(line_p), axis=0, append=np.log(line_p[:1]))).max(axis=1)
+        big_r = set(np.nonzero(jr > 0.3)[0])
+        big_p = set(np.nonzero(jp > 0.3)[0])
+        i1 = int(np.searchsorted(s, 0.5 * math.pi)) - 1  # last point before pi/2
+        i2 = int(np.searchsorted(s, 1.5 * math.pi)) - 1
+        assert big_r == {i1, i2, n - 1}, (axis, big_r)
+        assert big_p == {i1, n - 1}, (axis, big_p)  # the contact keeps the pressure
+        assert rho.min() > 0.1 and p.min() > 0.09 and vel.shape == (3,) + shape
+    rho, vel, p = I.shock_primitives(shape, 1, strength="strong")
+    assert p.max() > 9e4 and p.min() < 1.1

@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the FP64 WENO5-Roe / central-viscous RK4 path on one MI355X.
 
-Workload: 128^3 triply periodic decaying turbulence (seeded synthetic IC with the
-HIT spectrum, Mt = 0.3, Re = 400, gamma = 1.4, Pr = 0.72), classical RK4 at
-CFL 0.5 with kinetic energy and enstrophy reduced after every step.  One "step"
-is one RK4 step = 4 right-hand-side evaluations of the whole grid.
+Workload (default): 512^3 triply periodic decaying turbulence (seeded synthetic IC
+with the HIT spectrum, Mt = 0.3, Re = 1600, gamma = 1.4, Pr = 0.72), classical RK4
+at CFL 0.5 with the diagnostics (kinetic energy, enstrophy, means, wave speed) reduced
+after every step.  One "step" is one RK4 step = 4 right-hand-side evaluations of the
+whole grid.  ``--workload hit128`` runs the 128^3, Re = 400 case instead.
 
-Metric: grid-point RHS evaluations per second (4 * N^3 per step), with the
-state resident in HBM before the timed region starts.
+Metric: grid-point RHS evaluations per second (4 * N^3 per step), with the state
+resident in HBM before the timed region starts.
 
-Prints one JSON line.  The roofline object describes the kernel with the
-largest share of the step, timed with HIP events on the plan's stream; the
-cpu_baseline object times the CPU oracle on a bounded sample of the same
-workload on the host's cores.
+Prints one JSON line.  ``roofline`` describes the kernel with the largest share of the
+step, timed with HIP events on the plan's stream; ``step_hbm`` relates the bytes a step
+must move to the step time; ``cpu_baseline`` times the CPU oracle (built for the host)
+on one RHS evaluation of the same state on all host threads, with a one-thread sample.
+
+``--summarize DIR`` instead reads rocprofv3 CSV output (a kernel trace and the
+FETCH_SIZE / WRITE_SIZE counter runs, each taken with ``--calibrate-copy-gib``) and
+writes ``profiles/traffic.json`` and a Markdown table of bytes and rates per kernel.
 """
 from __future__ import annotations
 
@@ -20,7 +25,9 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -58,19 +65,30 @@ BYTES_PER_POINT_MIXED = {
     "visc_flux": 4 * (5 + 9),
     "diagnostics": 4 * 5,
 }
+# compulsory bytes of a fused RK4 step (three state arrays: u^n, the stage state and the
+# FP64 accumulator), per point-RHS
+COMPULSORY_BYTES_PER_POINT_RHS = 160
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (published; its 2x over FP64 needs packed FP32)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9  # VALU lane-instructions per second (3.93e13)
+# rocprofv3 kernel names -> the library's kernel kinds
+KERNEL_KIND_OF = (("k_sweep_x_rows", "sweep_x"), ("k_visc_flux", "visc_flux"), ("k_diag_partial", "diagnostics"),
+                  ("k_diag_final", "diagnostics_final"), ("k_stream_copy", "stream_copy"),
+                  ("k_init_state", "init_state"), ("k_speed_", "max_wave_speed"))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_digest():
-    """SHA-256 of the sources the sweep kernels are built from (counters taken on other
+    """SHA-256 of the sources the step's kernels are built from (counters taken on other
     sources are stale)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("cns_kernels.hip", "cns_device.h"):
+    for f in ("cns_kernels.hip", "cns_device.h", "cns_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2211_16718_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -78,25 +96,60 @@ def kernel_source_digest():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=128, help="grid points per direction (128 = the named workload)")
+    ap.add_argument("--workload", default="hit512", choices=["hit512", "hit128"],
+                    help="hit512: 512^3, Re 1600 (the default); hit128: 128^3, Re 400")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64 (the named workload) or the mixed form, for profiling it alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="RK4 steps of the oracle sample")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision 512^3, ensemble and adjoint measurements")
+                    help="skip the mixed-precision, ensemble, adjoint and option measurements")
     ap.add_argument("--extras", default="mixed_512,ensemble_64,adjoint_128,options_128",
                     help="comma-separated subset of the extra measurements to run")
-    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="before the workload, copy a buffer of this many MiB device-to-device once "
-                         "(a known-size reference for hardware byte counters)")
+    ap.add_argument("--copy-gib", type=float, default=4.0,
+                    help="size of the streaming-copy bandwidth reference (GiB)")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="before the workload, run the streaming copy once on a buffer of this many GiB "
+                         "(a known-size dispatch for hardware byte counters)")
+    ap.add_argument("--summarize", metavar="DIR", default=None,
+                    help="summarize rocprofv3 CSV output under DIR (kt/, fetch/, write/) instead of running")
+    ap.add_argument("--summary-title", default="")
     return ap.parse_args()
+
+
+def stream_copy(lib, src, dst, nbytes, stream):
+    from paper_2211_16718_amd._lib import check
+
+    check(lib.cns_stream_copy(src.data_ptr(), dst.data_ptr(), int(nbytes), stream.cuda_stream), "cns_stream_copy")
+
+
+def copy_reference(gib, stream):
+    """Read + write bandwidth of the library's streaming copy (median of 5 copies of `gib` GiB)."""
+    import torch
+
+    from paper_2211_16718_amd import _lib
+
+    lib = _lib.load()
+    nb = int(gib * (1 << 30)) // 16 * 16
+    src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream_copy(lib, src, dst, nb, stream)  # warm
+    times = []
+    for _ in range(5):
+        sec, _ = _timed(stream, lambda: stream_copy(lib, src, dst, nb, stream))
+        times.append(sec)
+    assert torch.equal(src[:1024], dst[:1024]) and torch.equal(src[-1024:], dst[-1024:])
+    times.sort()
+    del src, dst
+    return {"bytes_moved": 2 * nb, "GBs": 2 * nb / times[2] / 1e9, "kernel": "cns_stream_copy (16-byte "
+            "non-temporal loads and stores, 2048 x 256 threads)"}
 
 
 def main():
     args = parse()
+    if args.summarize:
+        return summarize(args.summarize, args.summary_title)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "domain decomposition is not implemented", file=sys.stderr)
@@ -105,25 +158,26 @@ def main():
     import numpy as np
     import torch
 
+    from paper_2211_16718_amd import _lib
     from paper_2211_16718_amd import inputs as I
     from paper_2211_16718_amd.api import Plan
 
-    if args.calibrate_copy_mib > 0:
-        nb = args.calibrate_copy_mib << 20
+    wl = I.WORKLOADS[args.workload]
+    n, mu = wl.n, 1.0 / wl.re
+    fp64 = args.precision == "fp64"
+    if args.calibrate_copy_gib > 0:
+        nb = int(args.calibrate_copy_gib * (1 << 30)) // 16 * 16
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        stream_copy(_lib.load(), src, dst, nb, torch.cuda.current_stream())
         torch.cuda.synchronize()
         del src, dst
-
-    n = args.n
-    wl = I.WORKLOADS["hit128"]
-    mu = 1.0 / wl.re
+    t0 = time.perf_counter()
     rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)
-    fp64 = args.precision == "fp64"
+    log(f"initial condition {n}^3 in {time.perf_counter() - t0:.1f} s")
     plan = Plan((n, n, n), mu_eff=mu, precision=args.precision, device="cuda:0")
     u = plan.init_state(rho, vel, p)
-    smax = plan.diagnostics_host(u)[7]
+    smax = float(plan.max_wave_speed(u).item())
     dt = I.dt_from_speed(smax, n, cfl=I.CFL)
     stream = plan.stream
 
@@ -148,6 +202,7 @@ def main():
     if np.any(diag_h[:, 8] > 0):
         print("bench: non-finite or non-physical state during the timed run", file=sys.stderr)
         sys.exit(3)
+    log(f"timed {args.steps} steps: {gpu_ms / args.steps:.3f} ms/step")
 
     seconds = gpu_ms / 1e3
     point_rhs = 4.0 * n ** 3 * args.steps
@@ -171,14 +226,20 @@ def main():
     avg_s = kernels[dom]["avg_ms"] / 1e3
     flops = FLOPS_PER_POINT[dom] * n ** 3
     achieved = flops / avg_s / 1e12
-    traffic = None
+    del u_start
+    copy = copy_reference(args.copy_gib, stream)
+    log(f"streaming copy reference {copy['GBs']:.0f} GB/s")
+
+    traffic, traffic_note = None, "no counters for these kernel sources at this size"
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            if fp64 and t.get("kernel_source_sha256") == kernel_source_digest() and dom in t.get("kernels", {}) \
-                    and t.get("n") == n:
+            if t.get("kernel_source_sha256") == kernel_source_digest() and dom in t.get("kernels", {}) \
+                    and t.get("n") == n and t.get("precision", "fp64") == args.precision:
                 traffic = t["kernels"][dom]["bytes_per_launch"]
+                traffic_note = (f"FETCH_SIZE x {t['fetch_scale']:.3f} + WRITE_SIZE x {t['write_scale']:.3f} per "
+                                "dispatch (scales from a streaming copy of known size)")
         except Exception:
             traffic = None
     # VALU instructions per point of the dominant kernel (SQ_INSTS_VALU counters taken on
@@ -196,7 +257,8 @@ def main():
         except Exception:
             valu = None
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
-    bpp = (BYTES_PER_POINT if fp64 else BYTES_PER_POINT_MIXED)[dom]
+    bpp_tab = BYTES_PER_POINT if fp64 else BYTES_PER_POINT_MIXED
+    bpp = bpp_tab[dom]
     roofline = {
         "bound": "alu",
         "kernel": dom,
@@ -205,48 +267,54 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": traffic,
+        "traffic_source": traffic_note,
         "algorithmic_bytes_per_launch": bpp * n ** 3,
         "hbm_frac_algorithmic": round(bpp * n ** 3 / avg_s / 1e9 / PEAK_HBM_GBS, 4),
         "flops_per_point": FLOPS_PER_POINT[dom],
         "avg_launch_ms": round(kernels[dom]["avg_ms"], 5),
     }
+    if traffic:
+        roofline["hbm_GBs_measured_bytes"] = round(traffic / avg_s / 1e9, 1)
+        roofline["hbm_frac_measured_bytes"] = round(traffic / avg_s / 1e9 / PEAK_HBM_GBS, 4)
     if valu:
         roofline.update(valu)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
+    # the whole step against HBM: the bytes the step's launches must move (each array
+    # element read or written once per launch), and the compulsory bytes of a fused step
+    step_s = gpu_ms / 1e3 / args.steps
+    design = sum(bpp_tab[k] * n ** 3 * kernels[k]["launches"] / args.steps for k in kernels if k in bpp_tab)
+    compulsory = COMPULSORY_BYTES_PER_POINT_RHS * 4 * n ** 3 * (1 if fp64 else 110 / 160)
+    step_hbm = {
+        "design_bytes_per_step": int(design),
+        "design_GBs": round(design / step_s / 1e9, 1),
+        "design_frac_of_peak": round(design / step_s / 1e9 / PEAK_HBM_GBS, 4),
+        "design_frac_of_copy": round(design / step_s / 1e9 / copy["GBs"], 4),
+        "compulsory_bytes_per_point_rhs": COMPULSORY_BYTES_PER_POINT_RHS if fp64 else 110,
+        "compulsory_frac_of_peak": round(compulsory / step_s / 1e9 / PEAK_HBM_GBS, 4),
+        "copy_reference_GBs": round(copy["GBs"], 1),
+        "copy_reference_frac_of_peak": round(copy["GBs"] / PEAK_HBM_GBS, 4),
+    }
+    del plan, u
+    torch.cuda.empty_cache()
 
-        ph = oracle.make_phys(mu_eff=mu)
-        uh = oracle.init_state(rho, vel, p)
-        oracle.rhs(np.ascontiguousarray(uh[:, :8, :8, :8]), ph)  # load the library
-        t0 = time.perf_counter()
-        oracle.rk4(uh, dt, args.cpu_steps, ph)
-        ct = time.perf_counter() - t0
-        cpu = {"value": 4.0 * n ** 3 * args.cpu_steps / ct, "unit": "point-RHS/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} RK4 steps (with diagnostics) of the same {n}^3 workload, "
-                         f"{ct:.1f} s, OpenMP over grid points"}
-        cpu["host"] = _host_cpu()
-        cpu["configs"] = _oracle_configs()
-        cpu1 = _oracle_one_core(n, mu)
-        if cpu1:
-            cpu["one_core"] = cpu1
-            cpu["one_core"]["gpu_over_one_core"] = value / cpu1["value"]
+    cpu = None
+    if not args.no_cpu_baseline and fp64:
+        cpu = cpu_baseline(n, mu, wl, rho, vel, p, value)
 
     extras = {}
     if not args.no_extras:
-        del plan
-        torch.cuda.empty_cache()
         wanted = set(args.extras.split(","))
-        for name, fn in (("mixed_512", bench_mixed), ("ensemble_64", bench_ensemble), ("adjoint_128", bench_adjoint),
-                         ("options_128", bench_options)):
+        prims512 = (rho, vel, p) if n == 512 else None
+        for name, fn in (("mixed_512", lambda: bench_mixed(prims512)), ("ensemble_64", bench_ensemble),
+                         ("adjoint_128", bench_adjoint), ("options_128", lambda: bench_options(prims512))):
             if name not in wanted:
                 continue
+            t0 = time.perf_counter()
             try:
                 extras[name] = fn()
             except Exception as e:  # report, keep the main line
                 extras[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"extra {name} in {time.perf_counter() - t0:.1f} s")
             torch.cuda.empty_cache()
 
     out = {
@@ -264,15 +332,68 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if fp64 else "f32+f64",
         "data": "synthetic (seeded HIT-spectrum initial condition)",
-        "config": {"workload": f"hit{n}_re400_rk4_diag_every_step" + ("" if fp64 else "_mixed"), "grid": [n, n, n],
-                   "re": wl.re, "mt": wl.mt, "cfl": I.CFL, "dt": dt, "precision": args.precision},
+        "config": {"workload": f"hit{n}_re{int(wl.re)}_rk4_diag_every_step" + ("" if fp64 else "_mixed"),
+                   "grid": [n, n, n], "re": wl.re, "mt": wl.mt, "cfl": I.CFL, "dt": dt, "precision": args.precision,
+                   "launches": "eager (18 per step)"},
         "roofline": roofline,
+        "step_hbm": step_hbm,
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "launches": v["launches"], "share": round(v["share"], 4)}
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
     }
     out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def _child_json(argv, env=None, timeout=600):
+    r = subprocess.run(argv, env=env, capture_output=True, text=True, timeout=timeout, cwd=ROOT)
+    if r.returncode != 0:
+        raise RuntimeError(f"{' '.join(argv[:4])}... exited {r.returncode}: {r.stderr[-400:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(n, mu, wl, rho, vel, p, gpu_value):
+    """The oracle, built for this host (-O2 -march=native -ffp-contract=off), timed on one
+    RHS evaluation of the benchmark's own state on every host thread; a one-thread sample
+    on one RHS of the 128^3 state of the same physics; the oracle beside the GPU on the
+    other configurations (in-tree build)."""
+    import numpy as np
+
+    from paper_2211_16718_amd import inputs as I
+
+    t0 = time.perf_counter()
+    tmp = tempfile.mkdtemp(prefix="cns_bench_")
+    out = {"kind": "oracle", "unit": "point-RHS/s"}
+    try:
+        f = os.path.join(tmp, "prims.npz")
+        np.savez(f, rho=rho, vel=vel, p=p)
+        d = _child_json([sys.executable, "-m", "oracle.timing", "--prims", f, "--mu", repr(mu), "--native"])
+        os.remove(f)
+        out.update({"value": d["points"] / d["seconds"], "cores": d["threads"],
+                    "sample": f"one RHS evaluation of the same {n}^3 state ({d['points']} point-RHS) in "
+                              f"{d['seconds']:.1f} s on {d['threads']} OpenMP threads; oracle built "
+                              f"{d['build']}, bitwise equal to the in-tree build: {d['native_bitwise_equal_to_in_tree']}",
+                    "gpu_over_oracle": gpu_value * d["seconds"] / d["points"]})
+        m = 128
+        r1, v1, p1 = I.hit_primitives(m, wl.seed, wl.mt)
+        f1 = os.path.join(tmp, "prims128.npz")
+        np.savez(f1, rho=r1, vel=v1, p=p1)
+        d1 = _child_json([sys.executable, "-m", "oracle.timing", "--prims", f1, "--mu", repr(mu), "--native"],
+                         env=dict(os.environ, OMP_NUM_THREADS="1"))
+        out["one_core"] = {"value": d1["points"] / d1["seconds"], "unit": "point-RHS/s", "cores": d1["threads"],
+                           "kind": "oracle", "sample": f"one RHS evaluation of the {m}^3 state of the same physics "
+                                                       f"in {d1['seconds']:.1f} s ({d1['build']})",
+                           "gpu_over_one_core": gpu_value * d1["seconds"] / d1["points"]}
+    except Exception as e:
+        out["error"] = f"{type(e).__name__}: {e}"
+    finally:
+        import shutil
+
+        shutil.rmtree(tmp, ignore_errors=True)
+    out["host"] = _host_cpu()
+    out["configs"] = _oracle_configs()
+    log(f"cpu baseline in {time.perf_counter() - t0:.1f} s")
+    return out
 
 
 def _timed(stream, fn):
@@ -346,73 +467,55 @@ def _oracle_configs():
 
 
 def _host_cpu():
-    """The host CPU the oracle ran on: model name, logical CPUs, sockets, OMP_NUM_THREADS."""
-    model, sockets = None, set()
+    """The host CPU the oracle ran on: model name, logical CPUs, sockets, physical cores,
+    the CPUs this process may use and OMP_NUM_THREADS."""
+    model, sockets, cores = None, set(), set()
+    phys = None
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 k, _, v = line.partition(":")
-                k = k.strip()
+                k, v = k.strip(), v.strip()
                 if k == "model name" and model is None:
-                    model = v.strip()
+                    model = v
                 elif k == "physical id":
-                    sockets.add(v.strip())
+                    phys = v
+                    sockets.add(v)
+                elif k == "core id":
+                    cores.add((phys, v))
     except OSError:
         pass
-    return {"model": model, "logical_cpus": os.cpu_count(), "sockets": len(sockets) or None,
+    info = {"model": model, "logical_cpus": os.cpu_count(), "sockets": len(sockets) or None,
+            "physical_cores": len(cores) or None,
             "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
             "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
-
-
-def _oracle_one_core(n, mu):
-    """The oracle's RHS on one host thread (the paper's GPU-vs-one-core comparison), in a
-    child process started with OMP_NUM_THREADS=1: one RHS evaluation of the same input."""
-    import subprocess
-
-    code = (
-        "import json, sys, time\n"
-        f"sys.path.insert(0, {ROOT!r})\n"
-        "import numpy as np\n"
-        "import oracle\n"
-        "from paper_2211_16718_amd import inputs as I\n"
-        f"n, mu = {n}, {mu!r}\n"
-        "wl = I.WORKLOADS['hit128']\n"
-        "rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)\n"
-        "ph = oracle.make_phys(mu_eff=mu)\n"
-        "uh = oracle.init_state(rho, vel, p)\n"
-        "oracle.rhs(np.ascontiguousarray(uh[:, :8, :8, :8]), ph)\n"
-        "t0 = time.perf_counter()\n"
-        "oracle.rhs(uh, ph)\n"
-        "ct = time.perf_counter() - t0\n"
-        "print(json.dumps({'value': n ** 3 / ct, 'seconds': ct, 'cores': oracle.num_threads()}))\n"
-    )
-    env = dict(os.environ, OMP_NUM_THREADS="1")
     try:
-        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
-        d = json.loads(r.stdout.strip().splitlines()[-1])
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20)
+        keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)", "NUMA node(s)")
+        info["lscpu"] = {k.strip(): v.strip() for k, _, v in (ln.partition(":") for ln in r.stdout.splitlines())
+                         if k.strip() in keep}
     except Exception:
-        return None
-    return {"value": d["value"], "unit": "point-RHS/s", "cores": d["cores"], "kind": "oracle",
-            "sample": f"one RHS evaluation of the same {n}^3 state, {d['seconds']:.1f} s"}
+        pass
+    return info
 
 
-def bench_mixed(n=512, steps=20):
+def bench_mixed(prims=None, n=512, steps=20):
     """512^3, Re = 1600: mixed precision against the FP64 path at the same size."""
-    import numpy as np
-    import torch
+    import numpy as np  # noqa: F401
+    import torch  # noqa: F401
 
     from paper_2211_16718_amd import inputs as I
     from paper_2211_16718_amd.api import Plan
 
     wl = I.WORKLOADS["hit512"]
-    rho, vel, p = I.hit_primitives(n, wl.seed, wl.mt)
+    rho, vel, p = prims if prims is not None else I.hit_primitives(n, wl.seed, wl.mt)
     out = {"config": {"workload": f"hit{n}_re1600_rk4x{steps}", "grid": [n, n, n], "steps": steps}}
     res = {}
     for prec in ("fp64", "mixed"):
         plan = Plan((n, n, n), mu_eff=1.0 / wl.re, precision=prec)
         u = plan.init_state(rho, vel, p)
         if prec == "fp64":
-            dt = I.dt_from_speed(plan.diagnostics_host(u)[7], n)
+            dt = I.dt_from_speed(float(plan.max_wave_speed(u).item()), n)
         plan.rk4(plan.empty_state().copy_(u), dt, 1, diag=False)  # warm
         sec, diag = _timed(plan.stream, lambda: plan.rk4(u, dt, steps))
         res[prec] = (u, diag.cpu().numpy(), sec)
@@ -495,8 +598,12 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
         return J, v0.grad
 
     gsec, (J, g) = _timed(plan.stream, grad)
+    # J alone: the autograd forward (the steps with checkpoints), no reverse sweep
+    v0 = vel.clone().requires_grad_(True)
+    jsec, _ = _timed(plan.stream, lambda: FinalKineticEnergy.apply(v0, rho, p, plan, dt, steps, ckpt))
     out = {"config": {"workload": f"hit{n}_re400_rk4x{steps}_adjoint", "ckpt_every": ckpt},
            "forward_s": fsec, "gradient_s": gsec, "gradient_over_forward": gsec / fsec,
+           "autograd_forward_s": jsec, "reverse_over_forward": (gsec - jsec) / fsec,
            "value": 4.0 * n ** 3 * steps / gsec, "unit": "point-RHS/s (forward-step equivalents of the gradient)",
            "J": float(J.detach()), "grad_norm": float(g.norm())}
     # the same gradient through the TVD-RK3 integrator (checkpoints every ckpt steps)
@@ -534,7 +641,7 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
     return out
 
 
-def bench_options(n=128, steps=20):
+def bench_options(prims512=None, n=128, steps=20):
     """The same 128^3 workload with the TVD-RK3 integrator, with WENO-Z and with mapped
     weights, the RHS alone, and the time of one energy spectrum (128^3 and 512^3)."""
     import torch
@@ -576,12 +683,158 @@ def bench_options(n=128, steps=20):
     del plan, pz, u, uz
     torch.cuda.empty_cache()
     m = 512
-    r5, v5, p5 = I.hit_primitives(m, 0, 0.3)
+    r5, v5, p5 = prims512 if prims512 is not None else I.hit_primitives(m, 0, 0.3)
     p512 = Plan((m, m, m), mu_eff=1.0 / 1600)
     u5 = p512.init_state(r5, v5, p5)
     p512.spectrum(u5)
     sec, (E, mom) = _timed(p512.stream, lambda: p512.spectrum(u5))
     out["spectrum_512"] = {"ms": sec * 1e3, "taylor_microscale": Plan.taylor_microscale(mom)}
+    return out
+
+
+# ---------------------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------------------
+def _csv_rows(d, suffix):
+    import csv
+
+    rows = []
+    for root, _, files in os.walk(d):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(root, f), newline="") as fh:
+                    rows += list(csv.DictReader(fh))
+    return rows
+
+
+def kernel_kind(name):
+    """The library's kernel kind of a rocprofv3 kernel name (template arguments decide
+    the direction and the output mode of a marching sweep)."""
+    if "k_sweep<" in name and "k_sweep_x_rows" not in name:
+        args = [a.strip() for a in name.split("k_sweep<", 1)[1].split(">", 1)[0].split(",")]
+        d, mode = int(args[2]), int(args[3])
+        return ("sweep_x", "sweep_y", "sweep_z_rk4" if mode == 2 else "sweep_z")[d]
+    for key, kind in KERNEL_KIND_OF:
+        if key in name:
+            return kind
+    return name.split("(")[0].replace("void ", "").replace("cns::", "")
+
+
+def summarize(d, title):
+    """Per-kernel bytes and rates from rocprofv3 CSV output under d: kt/ (kernel trace),
+    fetch/ (FETCH_SIZE) and write/ (WRITE_SIZE).  d/meta.json gives the grid size, the
+    precision, the bytes of one calibration copy and the commands that made the runs.
+    Writes profiles/traffic.json and prints a Markdown table."""
+    meta = json.load(open(os.path.join(d, "meta.json")))
+    n, prec = meta["n"], meta.get("precision", "fp64")
+    copy_bytes = meta["copy_bytes"]
+    trace = _csv_rows(os.path.join(d, "kt"), "kernel_trace.csv")
+    dur = {}
+    for r in trace:
+        dur.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+
+    def counter(sub, cname):
+        vals = {}
+        for r in _csv_rows(os.path.join(d, sub), "counter_collection.csv"):
+            if r.get("Counter_Name") == cname:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    copy_name = next(k for k in fetch if "k_stream_copy" in k)
+    fetch_scale = copy_bytes / (sorted(fetch[copy_name])[len(fetch[copy_name]) // 2])
+    write_scale = copy_bytes / (sorted(write[copy_name])[len(write[copy_name]) // 2])
+    copy_ns = sorted(dur.get(copy_name, [0]))[len(dur.get(copy_name, [0])) // 2]
+    copy_GBs = 2 * copy_bytes / copy_ns if copy_ns else None
+    bpp = BYTES_PER_POINT if prec == "fp64" else BYTES_PER_POINT_MIXED
+    kinds, rows = {}, []
+    for name in sorted(set(fetch) & set(write), key=lambda k: -sum(dur.get(k, [0]))):
+        kind = kernel_kind(name)
+        fb = sum(fetch[name]) / len(fetch[name]) * fetch_scale
+        wb = sum(write[name]) / len(write[name]) * write_scale
+        ns = sum(dur[name]) / len(dur[name]) if name in dur else None
+        alg = bpp.get(kind, 0) * n ** 3 if kind in bpp else None
+        rows.append((name, kind, ns, fb, wb, alg))
+        if kind not in kinds or (ns or 0) > (kinds[kind]["avg_launch_ns"] or 0):
+            kinds[kind] = {"bytes_per_launch": int(fb + wb), "fetch_bytes": int(fb), "write_bytes": int(wb),
+                           "avg_launch_ns": ns, "dispatches": len(fetch[name])}
+    out = {"n": n, "precision": prec, "kernel_source_sha256": kernel_source_digest(), "fetch_scale": fetch_scale,
+           "write_scale": write_scale, "copy_reference_GBs": copy_GBs, "kernels": kinds}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    sq = summarize_sq(d, n, dur)
+    lines = [f"# {title}", "", "Commands (each in its own run, from /tmp, `TMPDIR=/tmp`):", "", "```"]
+    lines += meta.get("commands", []) + ["```", ""]
+    lines.append(f"Calibration: each run first copies {copy_bytes / 1e9:.2f} GB with the library's streaming copy "
+                 f"(`k_stream_copy`); FETCH_SIZE reads {1 / fetch_scale:.3f} and WRITE_SIZE {1 / write_scale:.3f} "
+                 f"of the copied bytes, so the table scales them by {fetch_scale:.3f} and {write_scale:.3f}. "
+                 + (f"The copy ran at {copy_GBs:.0f} GB/s (read + write) in the kernel trace." if copy_GBs else ""))
+    lines += ["", "| kernel | avg ms | fetch GB | write GB | achieved TB/s | of 8 TB/s peak | of streaming copy | "
+                  "algorithmic GB | algorithmic / measured bytes |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, kind, ns, fb, wb, alg in rows:
+        if ns is None:
+            continue
+        tbs = (fb + wb) / ns / 1e3
+        short = name.split("(")[0].replace("void ", "").replace("cns::", "")
+        lines.append(f"| `{short}` | {ns / 1e6:.3f} | {fb / 1e9:.2f} | {wb / 1e9:.2f} | {tbs:.2f} | "
+                     f"{tbs * 1e3 / PEAK_HBM_GBS:.2f} | " + (f"{tbs * 1e3 / copy_GBs:.2f}" if copy_GBs else "-") +
+                     " | " + (f"{alg / 1e9:.2f} | {alg / (fb + wb):.2f} |" if alg else "- | - |"))
+    lines += ["", "Algorithmic bytes: every array element a kernel must read or write, once (the z sweep with "
+                  "the fused update averaged over the four RK4 stages).  Kernel times: the kernel trace of the first "
+                  "command."]
+    if sq:
+        lines += ["", "Shader counters (rocprofv3 `--pmc`, one pass per line of the commands above that names SQ_ "
+                      "counters; per dispatch, averaged over the dispatches of the kernel): VALU instructions per "
+                      "grid point (SQ_INSTS_VALU x 64 lanes / points), the VALU issue fraction (those lane-"
+                      "instructions over the kernel time at 256 CU x 4 SIMD x 16 lanes x 2.4 GHz), and the share of "
+                      "wave cycles spent waiting (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and issuing VALU work "
+                      "(SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES).", "",
+                  "| kernel | VALU instr / point | VALU issue frac | wait / wave cycles | VALU active / wave cycles | "
+                  "LDS bank conflicts / LDS instr | other counters |", "|---|---:|---:|---:|---:|---:|---|"]
+        for kind, c in sq.items():
+            def g(k):
+                return c.get(k)
+            valu_pt = g("SQ_INSTS_VALU") * 64 / n ** 3 if g("SQ_INSTS_VALU") else None
+            ns = c.get("_avg_ns")
+            issue = valu_pt * n ** 3 / (ns * 1e-9) / PEAK_VALU_LANE_INSTR if valu_pt and ns else None
+            wait = g("SQ_WAIT_INST_ANY") / g("SQ_WAVE_CYCLES") if g("SQ_WAIT_INST_ANY") and g("SQ_WAVE_CYCLES") else None
+            act = g("SQ_ACTIVE_INST_VALU") / g("SQ_WAVE_CYCLES") if g("SQ_ACTIVE_INST_VALU") and g("SQ_WAVE_CYCLES") \
+                else None
+            bank = g("SQ_LDS_BANK_CONFLICT") / g("SQ_INSTS_LDS") if g("SQ_LDS_BANK_CONFLICT") is not None and \
+                g("SQ_INSTS_LDS") else None
+            other = ", ".join(f"{k} {v:.3g}" for k, v in sorted(c.items()) if not k.startswith("_") and k not in
+                              ("SQ_INSTS_VALU", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU",
+                               "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS"))
+
+            def fmt(x, f):
+                return f.format(x) if x is not None else "-"
+            lines.append(f"| {kind} | {fmt(valu_pt, '{:.0f}')} | {fmt(issue, '{:.2f}')} | {fmt(wait, '{:.2f}')} | "
+                         f"{fmt(act, '{:.2f}')} | {fmt(bank, '{:.3f}')} | {other} |")
+        with open(os.path.join(ROOT, "profiles", "valu.json"), "w") as f:
+            json.dump({"n": n, "precision": prec, "kernel_source_sha256": kernel_source_digest(),
+                       "kernels": {k: {"valu_per_point": c["SQ_INSTS_VALU"] * 64 / n ** 3} for k, c in sq.items()
+                                   if c.get("SQ_INSTS_VALU")}}, f, indent=1)
+    print("\n".join(lines))
+
+
+def summarize_sq(d, n, dur):
+    """Mean per-dispatch shader counters per kernel kind from every d/sq*/ counter run."""
+    sums, cnt = {}, {}
+    for sub in sorted(os.listdir(d)):
+        if not sub.startswith("sq"):
+            continue
+        for r in _csv_rows(os.path.join(d, sub), "counter_collection.csv"):
+            kind = kernel_kind(r["Kernel_Name"])
+            key = (kind, r["Counter_Name"])
+            sums[key] = sums.get(key, 0.0) + float(r["Counter_Value"])
+            cnt[key] = cnt.get(key, 0) + 1
+    out = {}
+    for (kind, cname), v in sums.items():
+        out.setdefault(kind, {})[cname] = v / cnt[(kind, cname)]
+    for name, ds in dur.items():
+        kind = kernel_kind(name)
+        if kind in out:
+            out[kind]["_avg_ns"] = sum(ds) / len(ds)
     return out
 
 

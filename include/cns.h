@@ -79,8 +79,9 @@ typedef struct cns_plan cns_plan;
 
 /* Create a plan for one periodic box.  precision: CNS_FP64 (state and arithmetic in
  * double) or CNS_MIXED (state, stage states and WENO/flux arithmetic in float; WENO
- * smoothness-indicator sums and the RK4 accumulator in double).  stream: hipStream_t
- * or NULL for the default stream.  *out receives the plan. */
+ * smoothness-indicator sums and the RK4 accumulator in double; the float weights are
+ * scaled so that no jump overflows them).  stream: hipStream_t or NULL for the default
+ * stream.  *out receives the plan. */
 int cns_plan_create(cns_plan **out, const cns_grid *grid, const cns_physics *phys, int32_t precision,
                     void *stream);
 int cns_plan_destroy(cns_plan *plan);
@@ -203,11 +204,21 @@ int cns_ensemble_set_workspace(cns_ensemble *ens, void *ws_dev, size_t bytes);
 int cns_ensemble_set_tiles(cns_ensemble *ens, int32_t box, int32_t seg_x, int32_t seg_y, int32_t seg_z,
                            int32_t block);
 int cns_ensemble_get_tiles(const cns_ensemble *ens, int32_t box, int32_t *seg3_host, int32_t *block_host);
-/* Time the y/z sweeps for candidate segment lengths per box size and candidate block
- * sizes on the device, keep the fastest.  cache_path (may be NULL): a JSON file
- * read first (known sizes are not re-timed) and rewritten with new choices.
- * Synchronises the ensemble's stream.  Tiles never change results. */
+/* Choose launch shapes by timing them on the device, keeping the fastest: per box size,
+ * the segment length of the y/z marching sweeps and the rows per block of the x rows
+ * kernel (the default power of two and every count that keeps 90 % of a block's threads
+ * busy); for the batch, the threads per block of the marching sweeps and the launched
+ * grids (one block per virtual block, or persistent grids of one or two rounds of the
+ * blocks the chip holds at once, for the sweeps and for the tiled viscous-flux and
+ * diagnostics kernels).  Only scratch buffers are written while timing.  cache_path (may
+ * be NULL): a JSON file read first (known choices are not re-timed) and rewritten with
+ * new ones.  Synchronises the ensemble's stream.  Launch shapes never change results. */
 int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path);
+/* The launch shapes of box `box`: rows per block of its x rows kernel (0: the marching
+ * x sweep), and the launched blocks of the marching sweeps and of the tiled kernels of the
+ * whole ensemble (0: one block per virtual block). */
+int cns_ensemble_get_launch(const cns_ensemble *ens, int32_t box, int32_t *rows_host, int64_t *sweep_grid_host,
+                            int64_t *tile_grid_host);
 /* nsteps steps (RK4 unless cns_ensemble_set_integrator chose TVD-RK3) of every box with its own dt; diag_dev (may be NULL) receives
  * [nbox][nsteps][CNS_NDIAG].  use_graph != 0 captures the whole run once and
  * replays it (non-default stream required). */
@@ -244,10 +255,30 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0_dev, double dt, int32_t nstep
  * (cns_adjoint_workspace_bytes covers either integrator). */
 int cns_adjoint_tvdrk3(cns_plan *plan, const void *u0_dev, double dt, int32_t nsteps, int32_t ckpt_every,
                        void *adj_ws, size_t bytes, double *J_dev, void *u0_bar_dev);
+/* The same gradient in two calls, for callers that want J before deciding on the
+ * gradient (an autograd forward and backward): cns_adjoint_forward runs the nsteps
+ * steps of `scheme` (CNS_RK4 or CNS_TVDRK3) from u0 with a checkpoint every ckpt_every
+ * steps, keeps the last segment's start and stage states, writes J = K(u^N) to J_dev
+ * (may be NULL) and leaves all of it in adj_ws; cns_adjoint_reverse then runs the reverse
+ * sweep from that workspace and writes u0_bar = dJ/du0.  The reverse call needs the same
+ * plan, scheme, dt, nsteps, ckpt_every and an untouched workspace (any other adjoint call
+ * on it in between invalidates it).  The pair computes exactly what cns_adjoint_rk4 /
+ * cns_adjoint_tvdrk3 compute. */
+int cns_adjoint_forward(cns_plan *plan, int32_t scheme, const void *u0_dev, double dt, int32_t nsteps,
+                        int32_t ckpt_every, void *adj_ws, size_t bytes, double *J_dev);
+int cns_adjoint_reverse(cns_plan *plan, int32_t scheme, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
+                        size_t bytes, void *u0_bar_dev);
 /* Transpose of the initial-state map at fixed rho and p:
  * vbar_i = rho (mbar_i + ebar v_i); rho[N3], vel[3][N3], ubar[5][N3] -> vbar[3][N3]. */
 int cns_ic_vjp(const cns_plan *plan, const double *rho_dev, const double *vel_dev, const double *ubar_dev,
                double *vbar_dev);
+
+/* ---- measurement helper ----
+ * A plain streaming copy of `bytes` (a multiple of 16) from src_dev to dst_dev (16-byte
+ * aligned, not overlapping) on `stream`: 16-byte non-temporal loads and stores, a grid of
+ * 2048 blocks of 256 threads.  It is the bandwidth reference the benchmark reports kernel
+ * rates against, and the known-size dispatch that calibrates hardware byte counters. */
+int cns_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stream);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *cns_last_error(void);

@@ -3,8 +3,11 @@
 Test infrastructure: the oracle is loaded only by the tests, the smoke check
 and the benchmark's CPU-baseline leg.  Built with ``-O2 -ffp-contract=off``
 (no fused multiply-add, so every product is rounded as written) and OpenMP
-for the independent per-point loops.  No ``-march=native``: the library is
-also run on other hosts.
+for the independent per-point loops.  The in-tree library has no
+``-march=native`` (it is also run on other hosts); ``build(native=True, out=...)``
+makes a build for the host it runs on, which the benchmark times.  Without
+fused multiply-adds and without reassociation the two builds round every
+operation alike.
 """
 from __future__ import annotations
 
@@ -17,14 +20,16 @@ SRC = os.path.join(HERE, "cns_oracle.c")
 LIB = os.path.join(HERE, "libcns_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, native: bool = False, out: str | None = None) -> str:
+    out = out or LIB
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-Wall", "-Wextra", "-Wno-unused-parameter"] + (["-march=native"] if native else []) + \
+          ["-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

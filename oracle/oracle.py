@@ -39,11 +39,14 @@ _dp = C.POINTER(C.c_double)
 
 
 def lib():
+    """The oracle library: ``CNS_ORACLE_LIBRARY`` may name another build of the same
+    source (the benchmark's ``-march=native`` build); else the in-tree build."""
     global _LIB
     if _LIB is None:
-        if not os.path.exists(build_oracle.LIB):
+        path = os.environ.get("CNS_ORACLE_LIBRARY") or build_oracle.LIB
+        if path == build_oracle.LIB and not os.path.exists(path):
             build_oracle.build()
-        L = C.CDLL(build_oracle.LIB)
+        L = C.CDLL(path)
         L.oracle_weno5.restype = C.c_double
         L.oracle_weno5.argtypes = [C.c_double] * 6 + [_dp]
         L.oracle_weno5z.restype = C.c_double

@@ -77,6 +77,8 @@ SIGNATURES = {
     "cns_ensemble_set_tiles": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "cns_ensemble_get_tiles": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "cns_ensemble_autotune": (C.c_int, [_vp, C.c_char_p]),
+    "cns_ensemble_get_launch": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_int64)]),
     "cns_ensemble_run": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32]),
     "cns_ensemble_set_integrator": (C.c_int, [_vp, C.c_int32]),
     "cns_ensemble_profile_enable": (C.c_int, [_vp, C.c_int32]),
@@ -85,7 +87,10 @@ SIGNATURES = {
     "cns_rhs_vjp": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_size_t]),
     "cns_adjoint_rk4": (C.c_int, [_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, _vp]),
     "cns_adjoint_tvdrk3": (C.c_int, [_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, _vp]),
+    "cns_adjoint_forward": (C.c_int, [_vp, C.c_int32, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp]),
+    "cns_adjoint_reverse": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp]),
     "cns_ic_vjp": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "cns_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "cns_last_error": (C.c_char_p, []),
 }
 

@@ -23,6 +23,10 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def _scheme(name):
+    return {"rk4": CNS_RK4, "tvdrk3": CNS_TVDRK3}[name]
+
+
 def _weno_code(weno):
     """``"js"``: Jiang-Shu weights (the paper's); ``"z"``: WENO-Z weights (Borges et al.
     2008); ``"m"``: mapped weights (Henrick et al. 2005)."""
@@ -214,6 +218,28 @@ class Plan:
                                     _ptr(J), _ptr(g)), fn)
         return J, g
 
+    def adjoint_workspace(self, nsteps, ckpt_every):
+        """A device buffer for :meth:`adjoint_forward` / :meth:`adjoint_reverse` (the
+        caller keeps it between the two calls)."""
+        n = int(self.lib.cns_adjoint_workspace_bytes(self.h, int(nsteps), int(ckpt_every)))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def adjoint_forward(self, u0, dt, nsteps, ckpt_every, ws, scheme="rk4"):
+        """J = mean kinetic energy after ``nsteps`` steps of ``scheme`` from ``u0``; keeps
+        the checkpoints in ``ws`` for :meth:`adjoint_reverse`."""
+        self._state(u0)
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        check(self.lib.cns_adjoint_forward(self.h, _scheme(scheme), _ptr(u0), float(dt), int(nsteps),
+                                           int(ckpt_every), _ptr(ws), ws.numel(), _ptr(J)), "cns_adjoint_forward")
+        return J
+
+    def adjoint_reverse(self, dt, nsteps, ckpt_every, ws, scheme="rk4"):
+        """dJ/du0 from the workspace :meth:`adjoint_forward` filled."""
+        g = self.empty_state()
+        check(self.lib.cns_adjoint_reverse(self.h, _scheme(scheme), float(dt), int(nsteps), int(ckpt_every),
+                                           _ptr(ws), ws.numel(), _ptr(g)), "cns_adjoint_reverse")
+        return g
+
     def ic_vjp(self, rho, vel, ubar):
         """Transpose of the initial-state map at fixed density and pressure."""
         out = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
@@ -305,6 +331,14 @@ class Ensemble:
         blk = C.c_int32()
         check(self.lib.cns_ensemble_get_tiles(self.h, int(box), seg, C.byref(blk)), "cns_ensemble_get_tiles")
         return tuple(seg), blk.value
+
+    def get_launch(self, box):
+        """``(rows, sweep_grid, tile_grid)``: rows per block of box's x rows kernel and the
+        launched blocks of the sweeps and tiled kernels (0: one per virtual block)."""
+        r, gs, gt = C.c_int32(), C.c_int64(), C.c_int64()
+        check(self.lib.cns_ensemble_get_launch(self.h, int(box), C.byref(r), C.byref(gs), C.byref(gt)),
+              "cns_ensemble_get_launch")
+        return r.value, gs.value, gt.value
 
     def autotune(self, cache_path=None):
         check(self.lib.cns_ensemble_autotune(self.h, cache_path.encode() if cache_path else None),

@@ -74,6 +74,8 @@ struct Core {
     std::vector<BoxDesc> boxes;
     std::vector<void *> ustate;  // per-box state pointer (ensembles) or null (plans)
     std::vector<char> active;    // boxes given blocks (all, except while autotuning)
+    std::vector<int> rows_ov;    // rows per block of the x rows kernel per box (0: default)
+    long long grid[F_N] = {};    // launched blocks per kernel family (0: one per virtual block)
     // workspace layout
     std::vector<size_t> box_off;  // per-box scratch base
     size_t table_off = 0, dhost_off = 0, gp_off = 0, need = 0;
@@ -131,6 +133,15 @@ struct Core {
     }
 
     void add_box(const cns_grid &g, const cns_physics &ph, double dt, void *u) {
+        boxes.push_back(make_box(g, ph, dt));
+        weights = ph.weno_weights;
+        ustate.push_back(u);
+        active.push_back(1);
+        rows_ov.push_back(0);
+    }
+
+    // shape, spacings, physics and default segment lengths of a box
+    static BoxDesc make_box(const cns_grid &g, const cns_physics &ph, double dt) {
         BoxDesc b{};
         b.nx = g.nx;
         b.ny = g.ny;
@@ -155,10 +166,7 @@ struct Core {
         b.eps = ph.weno_eps;
         b.delta = ph.harten_delta;
         b.dt = dt;
-        weights = ph.weno_weights;
-        boxes.push_back(b);
-        ustate.push_back(u);
-        active.push_back(1);
+        return b;
     }
 
     // fill pointers, shapes and prefixes; upload the device table (synchronous)
@@ -188,8 +196,8 @@ struct Core {
             b.part = (double *)take((size_t)kDiagBlocksMax * CNS_NDIAG * sizeof(double));
             b.u = ustate[i];
             int P = 1;
-            b.rows = rows_for(b.nx);
-            b.xrows = (xrows_pref && rows_fits(b.nx, esz, &P)) ? 1 : 0;
+            b.rows = rows_ov[i] > 0 && rows_fit(b.nx, rows_ov[i], esz, nullptr) ? rows_ov[i] : rows_for(b.nx);
+            b.xrows = (xrows_pref && rows_fit(b.nx, b.rows, esz, &P)) ? 1 : 0;
             if (b.xrows) {
                 rowP = std::max(rowP, P);
                 rowLds = std::max(rowLds, (size_t)14 * b.rows * b.nx * esz);
@@ -234,6 +242,7 @@ struct Core {
         }
         bt.rowP = rowP;
         bt.rowLds = rowLds;
+        for (int f = 0; f < F_N; ++f) bt.grid[f] = grid[f];
         bt.stream = stream;
         bt.prof = prof.on ? &prof : nullptr;
         return bt;
@@ -369,8 +378,15 @@ static int autotune(Core &c, const char *cache_path) {
         snprintf(k, sizeof k, "%dx%dx%d|mu%d", b.nx, b.ny, b.nz, b.mu > 0 ? 1 : 0);
         cls[k].push_back(i);
     }
-    const int segs[] = {4, 8, 16, 32, 64};
     std::vector<BoxDesc> saved = c.boxes;
+    std::vector<int> saved_rows = c.rows_ov;
+    // time one size class alone (other boxes get no blocks; every kernel skips them)
+    auto only = [&](const std::vector<int> &members) {
+        for (int i = 0; i < c.nbox(); ++i)
+            c.active[i] = std::find(members.begin(), members.end(), i) != members.end();
+    };
+    // 1. segment length of the marching y/z sweeps per size class
+    const int segs[] = {4, 8, 16, 32, 64};
     for (auto &kv : cls) {
         const std::string key = pre + kv.first + "|seg";
         int best = -1;
@@ -379,16 +395,12 @@ static int autotune(Core &c, const char *cache_path) {
         if (it != cache.end() && it->second >= 1 && it->second <= std::max(bk.ny, bk.nz)) {
             best = it->second;
         } else {
-            // time this class alone: other boxes get no blocks (sweeps skip them)
             float best_ms = 1e30f;
-            const BoxDesc &b0 = c.boxes[kv.second[0]];
-            for (int s : segs) {
-                if (s > std::max(b0.ny, b0.nz)) continue;
-                for (int i = 0; i < c.nbox(); ++i) {
-                    c.boxes[i] = saved[i];
-                    c.active[i] = std::find(kv.second.begin(), kv.second.end(), i) != kv.second.end();
-                    if (c.active[i]) c.boxes[i].seg[1] = c.boxes[i].seg[2] = s;
-                }
+            for (int sgl : segs) {
+                if (sgl > std::max(bk.ny, bk.nz)) continue;
+                c.boxes = saved;
+                only(kv.second);
+                for (int i : kv.second) c.boxes[i].seg[1] = c.boxes[i].seg[2] = sgl;
                 c.dirty = true;
                 if ((rc = c.sync_table())) return rc;
                 Batch bt = c.batch();
@@ -396,7 +408,7 @@ static int autotune(Core &c, const char *cache_path) {
                 float ms = time_sweeps_yz(bt, 3);
                 if (ms < best_ms) {
                     best_ms = ms;
-                    best = s;
+                    best = sgl;
                 }
             }
             cache[key] = best;
@@ -404,13 +416,48 @@ static int autotune(Core &c, const char *cache_path) {
         }
         for (int i : kv.second) saved[i].seg[1] = saved[i].seg[2] = best;
     }
-    for (int i = 0; i < c.nbox(); ++i) {
-        c.boxes[i] = saved[i];
-        c.active[i] = 1;
+    c.boxes = saved;
+    // 2. rows per block of the x rows kernel per size class: the default (a power of two)
+    // and every count that keeps at least 90 % of the block's threads busy and fits
+    for (auto &kv : cls) {
+        const int nx = c.boxes[kv.second[0]].nx;
+        const std::string key = pre + kv.first + "|rows";
+        auto it = cache.find(key);
+        int best = 0;
+        if (it != cache.end() && it->second >= 0 && (it->second == 0 || rows_fit(nx, it->second, c.esz, nullptr))) {
+            best = it->second;
+        } else if (c.xrows_pref && rows_fit(nx, rows_for(nx), c.esz, nullptr)) {
+            std::vector<int> cand = {0};
+            for (int r = 1; r <= 1024 / nx && (int)cand.size() < 6; ++r) {
+                int P = 0;
+                if (r == rows_for(nx) || !rows_fit(nx, r, c.esz, &P)) continue;
+                if ((double)r * nx / (kRowThreads * P) >= 0.9) cand.push_back(r);
+            }
+            float best_ms = 1e30f;
+            for (int r : cand) {
+                only(kv.second);
+                for (int i : kv.second) c.rows_ov[i] = r;
+                c.dirty = true;
+                if ((rc = c.sync_table())) return rc;
+                Batch bt = c.batch();
+                time_rhs_kernels(bt, 1);
+                float ms = time_rhs_kernels(bt, 3);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = r;
+                }
+            }
+            cache[key] = best;
+            changed = true;
+        }
+        for (int i : kv.second) saved_rows[i] = best;
     }
-    // block size of the batch, keyed by its box sizes
-    std::string bkey = pre + "block";
-    for (auto &kv : cls) bkey += "|" + kv.first + "x" + std::to_string(kv.second.size());
+    c.rows_ov = saved_rows;
+    for (int i = 0; i < c.nbox(); ++i) c.active[i] = 1;
+    std::string all = "";
+    for (auto &kv : cls) all += "|" + kv.first + "x" + std::to_string(kv.second.size());
+    // 3. block size of the marching sweeps, for the whole batch
+    const std::string bkey = pre + "block" + all;
     auto bit = cache.find(bkey);
     const bool valid = bit != cache.end() && (bit->second == 64 || bit->second == 128 || bit->second == 192 ||
                                               bit->second == 256);
@@ -435,6 +482,39 @@ static int autotune(Core &c, const char *cache_path) {
         cache[bkey] = best;
         changed = true;
     }
+    // 4. launched grids: one block per virtual block, or persistent grids of one or two
+    // rounds of the blocks the chip holds at once, for the marching sweeps and for the
+    // tiled viscous-flux and diagnostics kernels (code 10 * sweeps + tiles)
+    c.dirty = true;
+    if ((rc = c.sync_table())) return rc;
+    {
+        Batch bt0 = c.batch();
+        const long long Rs = resident_sweep_blocks(bt0), Rt = resident_tile_blocks(bt0);
+        const std::string gkey = pre + "grid|b" + std::to_string(c.block) + all;
+        auto git = cache.find(gkey);
+        int best = 0;
+        if (git != cache.end() && git->second >= 0 && git->second <= 22 && git->second % 10 <= 2) {
+            best = git->second;
+        } else {
+            float best_ms = 1e30f;
+            for (int gs = 0; gs <= 2; ++gs)
+                for (int gt = 0; gt <= 2; ++gt) {
+                    Batch bt = c.batch();
+                    for (int f = F_SWEEP_X; f <= F_SWEEP_Z; ++f) bt.grid[f] = gs * Rs;
+                    bt.grid[F_VISC] = bt.grid[F_DIAG] = gt * Rt;
+                    time_rhs_kernels(bt, 1);
+                    float ms = time_rhs_kernels(bt, 3);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = 10 * gs + gt;
+                    }
+                }
+            cache[gkey] = best;
+            changed = true;
+        }
+        for (int f = F_SWEEP_X; f <= F_SWEEP_Z; ++f) c.grid[f] = (best / 10) * Rs;
+        c.grid[F_VISC] = c.grid[F_DIAG] = (best % 10) * Rt;
+    }
     c.dirty = true;
     if ((rc = c.sync_table())) return rc;
     if (changed) write_cache(cache_path, cache);
@@ -453,6 +533,16 @@ static int check_plan(const cns_plan *p) {
 extern "C" {
 
 const char *cns_last_error(void) { return g_err; }
+
+int cns_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
+        return set_err(CNS_EINVAL, "src and dst must be non-null and 16-byte aligned");
+    if (bytes % 16) return set_err(CNS_EINVAL, "bytes must be a multiple of 16");
+    const char *a = (const char *)src, *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes) return set_err(CNS_EINVAL, "src and dst overlap");
+    launch_stream_copy(src, dst, bytes, (hipStream_t)stream);
+    return check_hip("stream_copy");
+}
 
 int cns_plan_create(cns_plan **out, const cns_grid *grid, const cns_physics *phys, int32_t precision, void *stream) {
     if (!out) return set_err(CNS_EINVAL, "null output pointer");
@@ -745,6 +835,17 @@ int cns_ensemble_get_tiles(const cns_ensemble *ens, int32_t box, int32_t *seg3, 
     return CNS_OK;
 }
 
+int cns_ensemble_get_launch(const cns_ensemble *ens, int32_t box, int32_t *rows, int64_t *sweep_grid,
+                            int64_t *tile_grid) {
+    if (!ens || !rows || !sweep_grid || !tile_grid) return set_err(CNS_EINVAL, "null argument");
+    if (box < 0 || box >= ens->c.nbox()) return set_err(CNS_EINVAL, "box index out of range");
+    const BoxDesc &b = ens->c.boxes[box];
+    *rows = ens->c.ws && b.xrows ? b.rows : 0;
+    *sweep_grid = ens->c.grid[F_SWEEP_Y];
+    *tile_grid = ens->c.grid[F_VISC];
+    return CNS_OK;
+}
+
 int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path) {
     if (!ens) return set_err(CNS_EINVAL, "null ensemble");
     if (!ens->c.ws) return set_err(CNS_EWORKSPACE, "no workspace bound");
@@ -832,53 +933,84 @@ static int adj_check(const cns_plan *plan) {
     return CNS_OK;
 }
 
-static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every,
-                       void *adj_ws, size_t bytes, double *J_dev, void *u0_bar) {
+static int adjoint_args(cns_plan *plan, int scheme, double dt, int32_t nsteps, int32_t ckpt_every, const void *adj_ws,
+                        size_t bytes, AdjLayout *L) {
     int rc = adj_check(plan);
-    if (!rc) rc = check_ptr(u0, "u0");
     if (!rc) rc = check_ptr(adj_ws, "adj_ws");
-    if (!rc) rc = check_ptr(u0_bar, "u0_bar");
     if (rc) return rc;
+    if (scheme != CNS_RK4 && scheme != CNS_TVDRK3) return set_err(CNS_EINVAL, "unknown integrator %d", scheme);
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(CNS_EINVAL, "dt must be positive and finite");
     if (nsteps < 0 || ckpt_every < 1) return set_err(CNS_EINVAL, "need nsteps >= 0 and ckpt_every >= 1");
-    if (J_dev && ((uintptr_t)J_dev & 7u)) return set_err(CNS_EINVAL, "J must be 8-byte aligned");
-    Core &c = plan->c;
-    if ((rc = c.sync_table())) return rc;
-    const BoxDesc &b = c.boxes[0];
-    const size_t n3 = b.n3, n5 = 5 * n3;
-    const AdjLayout L = adj_layout(n3, nsteps, ckpt_every);
-    if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
-    char *w = (char *)adj_ws;
+    if ((rc = plan->c.sync_table())) return rc;
+    *L = adj_layout(plan->c.boxes[0].n3, nsteps, ckpt_every);
+    if (bytes < L->total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L->total);
+    return CNS_OK;
+}
+
+// the step-start state and the stage states of step n of a segment starting at n0 (RK4:
+// U2, U3, U4; TVD-RK3: U1, U2), kept while the fused step advances X
+static void adj_keep_step(const Batch &bt, int scheme, const AdjLayout &L, char *w, size_t n5, double dt, int n,
+                          int n0) {
     const size_t st = align256(n5 * sizeof(double));
     auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
-    double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
-    double *Gb = (double *)(w + L.Gb), *rec = (double *)(w + L.rec);
+    double *X = state(L.X, 0);
+    adj_copy(n5, X, state(L.seg, 4 * (n - n0)), bt.stream);
+    void *const st3[3] = {state(L.seg, 4 * (n - n0) + 1), state(L.seg, 4 * (n - n0) + 2),
+                          state(L.seg, 4 * (n - n0) + 3)};
+    launch_step(bt, scheme, X, dt, nullptr, 0, 0, st3);
+}
+
+// Forward pass of the adjoint: nsteps steps from u0 with a checkpoint every K steps; the
+// last segment keeps the start and stage states of its steps; J = K(u^N).  Leaves u^N,
+// the checkpoints and the last segment in the workspace for adjoint_reverse.
+static int adjoint_forward(cns_plan *plan, int scheme, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every,
+                           void *adj_ws, size_t bytes, double *J_dev) {
+    AdjLayout L;
+    int rc = adjoint_args(plan, scheme, dt, nsteps, ckpt_every, adj_ws, bytes, &L);
+    if (!rc) rc = check_ptr(u0, "u0");
+    if (rc) return rc;
+    if (J_dev && ((uintptr_t)J_dev & 7u)) return set_err(CNS_EINVAL, "J must be 8-byte aligned");
+    Core &c = plan->c;
+    const size_t n5 = 5 * c.boxes[0].n3, st = align256(n5 * sizeof(double));
+    char *w = (char *)adj_ws;
+    auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
+    double *X = state(L.X, 0), *rec = (double *)(w + L.rec);
     hipStream_t s = c.stream;
     Batch bt = c.batch();
     bt.prof = nullptr;
-    const int K = L.K;
-
-    // the step-start state and the stage states of step n of a segment starting at n0 (RK4:
-    // U2, U3, U4; TVD-RK3: U1, U2), kept while the fused step advances X
-    auto keep_step = [&](int n, int n0) {
-        adj_copy(n5, X, state(L.seg, 4 * (n - n0)), s);
-        void *const st3[3] = {state(L.seg, 4 * (n - n0) + 1), state(L.seg, 4 * (n - n0) + 2),
-                              state(L.seg, 4 * (n - n0) + 3)};
-        launch_step(bt, scheme, X, dt, nullptr, 0, 0, st3);
-    };
-    // forward with checkpoints (the fused path, as cns_rk4 / cns_tvdrk3); the last segment keeps
-    // its states on the way, so the reverse sweep starts without recomputing it
-    const int last0 = (L.nck - 1) * K;
+    const int K = L.K, last0 = (L.nck - 1) * K;
     adj_copy(n5, (const double *)u0, X, s);
     for (int n = 0; n < nsteps; ++n) {
         if (n % K == 0) adj_copy(n5, X, state(L.ck, n / K), s);
-        if (n >= last0) keep_step(n, last0);
+        if (n >= last0) adj_keep_step(bt, scheme, L, w, n5, dt, n, last0);
         else launch_step(bt, scheme, X, dt, nullptr, 0, 0);
     }
     launch_diag(bt, X, rec, 0, 0);
     if (J_dev) adj_copy(1, rec, J_dev, s);
-    adj_ke_seed(n3, X, ub, s);
+    return check_hip("adjoint_forward");
+}
 
+// Reverse sweep from what adjoint_forward left in the workspace (same plan, integrator,
+// dt, nsteps and checkpoint interval): u0_bar = dJ/du0, one checkpoint segment at a
+// time (last first), each recomputed from its checkpoint (the last one is kept).
+static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
+                           size_t bytes, void *u0_bar) {
+    AdjLayout L;
+    int rc = adjoint_args(plan, scheme, dt, nsteps, ckpt_every, adj_ws, bytes, &L);
+    if (!rc) rc = check_ptr(u0_bar, "u0_bar");
+    if (rc) return rc;
+    Core &c = plan->c;
+    const BoxDesc &b = c.boxes[0];
+    const size_t n3 = b.n3, n5 = 5 * n3, st = align256(n5 * sizeof(double));
+    char *w = (char *)adj_ws;
+    auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
+    double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
+    double *Gb = (double *)(w + L.Gb);
+    hipStream_t s = c.stream;
+    Batch bt = c.batch();
+    bt.prof = nullptr;
+    const int K = L.K;
+    adj_ke_seed(n3, X, ub, s);  // X holds u^N
     // reverse, one checkpoint segment at a time (last first)
     for (int sg = L.nck - 1; sg >= 0; --sg) {
         const int n0 = sg * K, n1 = std::min(nsteps, n0 + K);
@@ -886,7 +1018,7 @@ static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, in
         // state and the stage states U2, U3, U4 the fused step writes
         if (sg != L.nck - 1) {
             adj_copy(n5, state(L.ck, sg), X, s);
-            for (int n = n0; n < n1; ++n) keep_step(n, n0);
+            for (int n = n0; n < n1; ++n) adj_keep_step(bt, scheme, L, w, n5, dt, n, n0);
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const double *Y = state(L.seg, 4 * (n - n0));
@@ -931,7 +1063,15 @@ static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, in
         }
     }
     adj_copy(n5, ub, (double *)u0_bar, s);
-    return check_hip("adjoint_rk4");
+    return check_hip("adjoint_reverse");
+}
+
+static int adjoint_run(cns_plan *plan, int scheme, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every,
+                       void *adj_ws, size_t bytes, double *J_dev, void *u0_bar) {
+    int rc = check_ptr(u0_bar, "u0_bar");
+    if (rc) return rc;
+    if ((rc = adjoint_forward(plan, scheme, u0, dt, nsteps, ckpt_every, adj_ws, bytes, J_dev))) return rc;
+    return adjoint_reverse(plan, scheme, dt, nsteps, ckpt_every, adj_ws, bytes, u0_bar);
 }
 
 extern "C" {
@@ -966,6 +1106,16 @@ int cns_adjoint_rk4(cns_plan *plan, const void *u0, double dt, int32_t nsteps, i
 int cns_adjoint_tvdrk3(cns_plan *plan, const void *u0, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
                        size_t bytes, double *J_dev, void *u0_bar) {
     return adjoint_run(plan, CNS_TVDRK3, u0, dt, nsteps, ckpt_every, adj_ws, bytes, J_dev, u0_bar);
+}
+
+int cns_adjoint_forward(cns_plan *plan, int32_t scheme, const void *u0, double dt, int32_t nsteps,
+                        int32_t ckpt_every, void *adj_ws, size_t bytes, double *J_dev) {
+    return adjoint_forward(plan, scheme, u0, dt, nsteps, ckpt_every, adj_ws, bytes, J_dev);
+}
+
+int cns_adjoint_reverse(cns_plan *plan, int32_t scheme, double dt, int32_t nsteps, int32_t ckpt_every, void *adj_ws,
+                        size_t bytes, void *u0_bar) {
+    return adjoint_reverse(plan, scheme, dt, nsteps, ckpt_every, adj_ws, bytes, u0_bar);
 }
 
 int cns_ic_vjp(const cns_plan *plan, const double *rho, const double *vel, const double *ubar, double *vbar) {

@@ -83,30 +83,35 @@ __device__ __forceinline__ T harten_abs(T lam, T delta, T h) {
 // g_k(w) = w (c_k + c_k^2 - 3 c_k w + w^2) / (c_k^2 + w (1 - 2 c_k)) and renormalised.
 // The alpha are scaled by s_1^2 s_2^2 s_3^2, the mapped values by the product of the
 // three denominators, so one reciprocal serves the three weights of each
-// normalisation.  The Z and mapped weights, and in the mixed form the Jiang-Shu
-// weights too, are formed in B (FP64) and normalised before any narrowing.
+// normalisation.  The Z and mapped weights are formed in B (FP64) and normalised
+// before any narrowing.
 template <typename T, typename B, int WW>
 __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, T c3) {
-    if constexpr (WW == CNS_WENO_JS) {
+    if constexpr (WW == CNS_WENO_JS && sizeof(T) == sizeof(B)) {
         // 10 alpha_k s1^2 s2^2 s3^2 = (d2 d3, 6 d1 d3, 3 d1 d2) with d_k = s_k^2
-        if constexpr (sizeof(T) == sizeof(B)) {
-            T s1 = eps + T(b1), s2 = eps + T(b2), s3 = eps + T(b3);
-            T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
-            T a1 = d2 * d3, a2 = d1 * d3, a3 = d1 * d2;
-            T num = a1 * c1 + a2 * (T(6) * c2) + a3 * (T(3) * c3);
-            return num * rcp(a1 + T(6) * a2 + T(3) * a3);
-        } else {
-            // The products of four (eps + beta) factors leave the FP32 range once
-            // 4 beta exceeds about 4e9 (a jump of about 3e4 in the reconstructed
-            // value), and underflow for eps below about 1e-10: the weights are formed
-            // in B and rounded once.
-            const B e = B(eps);
-            B s1 = e + b1, s2 = e + b2, s3 = e + b3;
-            B d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
-            B a1 = d2 * d3, a2 = B(6) * (d1 * d3), a3 = B(3) * (d1 * d2);
-            B ia = rcp(a1 + a2 + a3);
-            return T(a1 * ia) * c1 + T(a2 * ia) * c2 + T(a3 * ia) * c3;
-        }
+        T s1 = eps + T(b1), s2 = eps + T(b2), s3 = eps + T(b3);
+        T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+        T a1 = d2 * d3, a2 = d1 * d3, a3 = d1 * d2;
+        T num = a1 * c1 + a2 * (T(6) * c2) + a3 * (T(3) * c3);
+        return num * rcp(a1 + T(6) * a2 + T(3) * a3);
+    } else if constexpr (WW == CNS_WENO_JS) {
+        // FP32 (the mixed form): products of four (eps + beta) factors would leave the
+        // FP32 range at jumps of about 3e4 in the reconstructed value.  The s_k are first
+        // scaled by the power of two of the smallest (exact), which puts t_k in [0.5, inf),
+        // and capped at 2^31: a stencil whose t is capped has a weight below 2^-62 of the
+        // smoothest one's, where the cap changes its contribution by less than the FP32
+        // rounding of the smooth candidates (unless a jump exceeds the neighbouring values
+        // by 1e11).  Then every product lies in [2^-4, 2^127), and the weights are
+        // normalised before they multiply the candidates.
+        T s1 = eps + T(b1), s2 = eps + T(b2), s3 = eps + T(b3);
+        const int e = -__builtin_amdgcn_frexp_expf(fminf(s1, fminf(s2, s3)));
+        const T cap = T(2147483648.0);
+        T t1 = fminf(__builtin_amdgcn_ldexpf(s1, e), cap), t2 = fminf(__builtin_amdgcn_ldexpf(s2, e), cap),
+          t3 = fminf(__builtin_amdgcn_ldexpf(s3, e), cap);
+        T d1 = t1 * t1, d2 = t2 * t2, d3 = t3 * t3;
+        T a1 = d2 * d3, a2 = T(6) * (d1 * d3), a3 = T(3) * (d1 * d2);
+        T ir = rcp(a1 + a2 + a3);
+        return (a1 * ir) * c1 + (a2 * ir) * c2 + (a3 * ir) * c3;
     } else if constexpr (WW == CNS_WENO_Z) {
         const B e = B(eps);
         B t = fabs(b1 - b3);

@@ -122,11 +122,14 @@ struct Batch {
     hipStream_t stream = nullptr;
     Prof *prof = nullptr;
     const GraphParams *gp = nullptr;  // set while a run is captured for graph replay
+    long long grid[F_N] = {};         // launched blocks per family (0: one per virtual block)
 };
 
 // host-side helpers (cns_kernels.hip)
 int rows_for(int nx);
-bool rows_fits(int nx, size_t esz, int *P);
+// rows per block of the x rows kernel fit (at most 4 points per thread, 64 KiB of LDS);
+// *P receives the points per thread
+bool rows_fit(int nx, int rows, size_t esz, int *P);
 long long family_blocks(const BoxDesc &b, int fam, int block);
 
 // launchers (cns_kernels.hip); all enqueue on bt.stream
@@ -149,10 +152,18 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag
 // max over points and directions of |v_d| + c of every box into out[box] (NaN for a box
 // with a non-finite state, rho <= 0 or p <= 0)
 void launch_max_wave_speed(const Batch &bt, const void *u_ov, double *out);
+// a plain streaming copy (bytes a multiple of 16, 16-byte aligned pointers)
+void launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // the per-call record of a graph replay (enqueued before the replay)
 void launch_set_params(GraphParams *gp, const void *u, double *diag, double dt, hipStream_t s);
 // time the y and z marching sweeps over the batch (autotuning); milliseconds per launch pair
 float time_sweeps_yz(const Batch &bt, int reps);
+// time one RHS evaluation's kernels into scratch only (viscous fluxes, x sweep, y and z
+// sweeps accumulating into rhs): milliseconds per evaluation (autotuning)
+float time_rhs_kernels(const Batch &bt, int reps);
+// blocks of the marching sweeps / tiled kernels the chip holds at once (persistent grids)
+long long resident_sweep_blocks(const Batch &bt);
+long long resident_tile_blocks(const Batch &bt);
 
 // kinetic-energy spectrum (cns_spectrum.hip), one box: E[nshell] and mom = {sum E, M2, lambda};
 // scratch: the box's A, B and rhs buffers

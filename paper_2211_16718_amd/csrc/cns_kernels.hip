@@ -49,15 +49,25 @@ __device__ __forceinline__ int find_box(const long long *off, int nbox, long lon
     return lo;
 }
 
-// Workgroups are dispatched to the 8 XCDs of the chip round-robin, and each XCD has
-// its own L2.  Renumbering so that XCD x runs a contiguous range of blocks keeps
-// blocks that touch neighbouring data (stencil halos) on the same L2.  A bijection
-// of [0, n) for any n.
-__device__ __forceinline__ long long xcd_block(long long b, long long n) {
-    constexpr int kXcd = 8;
-    const long long q = n / kXcd, r = n % kXcd;
-    const long long x = b % kXcd, i = b / kXcd;
-    return x * q + (x < r ? x : r) + i;
+// The virtual blocks a launched block runs.  Workgroups are dispatched to the 8 XCDs of
+// the chip round-robin (block b on XCD b % 8), and each XCD has its own L2.  The
+// virtual blocks are cut into one contiguous range per XCD, and the launched blocks of
+// XCD x walk range x with a stride of their number, so blocks that touch neighbouring
+// data (stencil halos) share an L2.  With one launched block per virtual block each
+// runs exactly one; with fewer (a persistent launch, its grid sized to the blocks the
+// chip holds at once) each loops over several.  Every virtual block runs exactly once
+// for any grid size.
+struct VbRange {
+    long long vb, end, stride;
+};
+__device__ __forceinline__ VbRange vb_range(long long total) {
+    const long long G = gridDim.x, b = blockIdx.x;
+    const long long X = G < 8 ? G : 8;  // ranges: one per XCD that has blocks
+    const long long x = b % X, l = b / X;
+    const long long nbx = G / X + (x < G % X ? 1 : 0);
+    const long long q = total / X, r = total % X;
+    const long long lo = x * q + (x < r ? x : r), hi = lo + q + (x < r ? 1 : 0);
+    return VbRange{lo + l, hi, nbx};
 }
 
 // Classical RK4 keeps u^n, the stage state and an FP64 accumulator of
@@ -77,6 +87,19 @@ __device__ __forceinline__ Launch with_params(Launch L) {
         L.diag = L.gp->diag;
     }
     return L;
+}
+
+// Pointers into HBM taken from the device tables are generic (flat) pointers to the
+// compiler, and accesses through them become FLAT instructions, which count against
+// the LDS counter as well as the vector-memory counter: every wait for an LDS read then
+// also waits for all HBM loads in flight, which undoes the loads issued ahead of the
+// arithmetic.  The kernels cast them to the global address space (HBM), whose
+// accesses count against the vector-memory counter only.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T *p) {
+    return (gptr<T>)p;
 }
 
 __device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
@@ -111,7 +134,7 @@ __global__ void k_fill(size_t n, T *out) {
 // ----------------------------------------------------------------------------
 // primitives (u, v, w, T = gamma p / rho) of the state at linear index i
 template <typename T>
-__device__ __forceinline__ void prim_at(const T *u, size_t n3, size_t i, T gamma, T W[4]) {
+__device__ __forceinline__ void prim_at(gptr<const T> u, size_t n3, size_t i, T gamma, T W[4]) {
     const T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
     const T inv = rcp(r);
     W[0] = mx * inv;
@@ -131,8 +154,8 @@ template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
     const Launch L = with_params(L0);
     __shared__ T pl[4][kViscTY + 4][kViscTX + 4];
-    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
-    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
+    const VbRange R = vb_range(L.total);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &b = L.boxes[bi];
         const int nx = b.nx, ny = b.ny, nz = b.nz;
@@ -144,8 +167,8 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
         const int tx = threadIdx.x % kViscTX, ty = threadIdx.x / kViscTX;
         const bool act = x0 + tx < nx && y0 + ty < ny;
         const size_t col = (size_t)min(y0 + ty, ny - 1) * nx + min(x0 + tx, nx - 1);
-        const T *u = (const T *)state_ptr(b, L, L.in);
-        T *G = (T *)b.G;
+        const gptr<const T> u = glob((const T *)state_ptr(b, L, L.in));
+        const gptr<T> G = glob((T *)b.G);
         const T gamma = T(b.gamma);
         const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
         const T mu = T(b.mu), kcond = T(b.mu / ((b.gamma - 1.0) * b.prandtl));
@@ -219,7 +242,7 @@ __device__ __forceinline__ constexpr bool g_last_read() {
     return DIR == 2 || (DIR == 1 && C != 2) || (DIR == 0 && (C == 0 || C == 3));
 }
 template <int DIR, int C, typename T>
-__device__ __forceinline__ T load_g(const T *G, size_t n3, size_t o) {
+__device__ __forceinline__ T load_g(gptr<const T> G, size_t n3, size_t o) {
     if constexpr (g_last_read<DIR, C>()) return __builtin_nontemporal_load(&G[gcomp<DIR>(C) * n3 + o]);
     else return G[gcomp<DIR>(C) * n3 + o];
 }
@@ -228,16 +251,16 @@ __device__ __forceinline__ T load_g(const T *G, size_t n3, size_t o) {
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L0) {
     const Launch L = with_params(L0);
-    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
-    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
+    const VbRange R = vb_range(L.total);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &b = L.boxes[bi];
         const int nx = b.nx, ny = b.ny, nz = b.nz;
         const size_t n3 = b.n3;
         const size_t idx = (size_t)(vb - L.off[bi]) * kPointThreads + threadIdx.x;
         if (idx >= n3) continue;
-        const T *G = (const T *)b.G;
-        T *out = (T *)(L.out_ov ? L.out_ov : b.rhs);
+        const gptr<const T> G = glob((const T *)b.G);
+        const gptr<T> out = glob((T *)(L.out_ov ? L.out_ov : b.rhs));
         const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
         const int i = (int)(idx % nx);
         const int j = (int)((idx / nx) % ny);
@@ -253,9 +276,9 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_div(Launch L0) {
         out[idx] = T(0);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const T *gx = G + gcomp<0>(c) * n3;
-            const T *gy = G + gcomp<1>(c) * n3;
-            const T *gz = G + gcomp<2>(c) * n3;
+            const gptr<const T> gx = G + gcomp<0>(c) * n3;
+            const gptr<const T> gy = G + gcomp<1>(c) * n3;
+            const gptr<const T> gz = G + gcomp<2>(c) * n3;
             T s = dcen(gx[x[0]], gx[x[1]], gx[x[2]], gx[x[3]]) * ihx;
             s += dcen(gy[y[0]], gy[y[1]], gy[y[2]], gy[y[3]]) * ihy;
             s += dcen(gz[z[0]], gz[z[1]], gz[z[2]], gz[z[3]]) * ihz;
@@ -392,8 +415,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
     extern __shared__ unsigned char lds_raw[];
     T *ring = reinterpret_cast<T *>(lds_raw) + threadIdx.x;  // slot s, component v at (s * 5 + v) * blockDim.x
     const int bdim = blockDim.x;
-    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
-    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
+    const VbRange R = vb_range(L.total);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const SweepGeom sg = sweep_geom<DIR>(bx.nx, bx.ny, bx.nz);
@@ -419,8 +442,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
         const int j0 = sgi * seg;
         const int j1 = min(j0 + seg, n);
         const size_t n3 = bx.n3;
-        const T *u = (const T *)state_ptr(bx, L, L.in);
-        const T *G = (const T *)bx.G;
+        const gptr<const T> u = glob((const T *)state_ptr(bx, L, L.in));
+        const gptr<const T> G = glob((const T *)bx.G);
         const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
@@ -478,7 +501,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
             T pr[5], pu[5];
             double pa[5];
             if (MODE != MODE_WRITE && j >= j0) {
-                const T *rhs = (const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs));
+                const gptr<const T> rhs = glob((const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs)));
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     if constexpr (MODE == MODE_RK) pr[v] = __builtin_nontemporal_load(&rhs[v * n3 + o]);
@@ -488,14 +511,14 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
                     // u^n: every later stage but the mixed form's RK4 stage 4, which
                     // needs only the accumulator
                     if (L.scheme == CNS_TVDRK3 || kFp64Stages<T> || L.stage != 4) {
-                        const T *un = (const T *)state_ptr(bx, L, BUF_U);
+                        const gptr<const T> un = glob((const T *)state_ptr(bx, L, BUF_U));
 #pragma unroll
                         for (int v = 0; v < 5; ++v) pu[v] = un[v * n3 + o];
                     }
                     // the FP64 form reads the accumulator in the last stage only
                     if (L.scheme != CNS_TVDRK3 && (!kFp64Stages<T> || L.stage == 4)) {
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) pa[v] = __builtin_nontemporal_load(&bx.acc[v * n3 + o]);
+                        for (int v = 0; v < 5; ++v) pa[v] = __builtin_nontemporal_load(&glob(bx.acc)[v * n3 + o]);
                     }
                 }
             }
@@ -512,8 +535,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
             }
             if (j >= j0) {
                 if constexpr (MODE == MODE_RK) {
-                    T *unext = (T *)state_ptr(bx, L, L.out);
-                    double *acc = bx.acc;
+                    const gptr<T> unext = glob((T *)state_ptr(bx, L, L.out));
+                    const gptr<double> acc = glob(bx.acc);
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
@@ -562,7 +585,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
                         }
                     }
                 } else {
-                    T *rhs = (T *)(L.out_ov ? L.out_ov : bx.rhs);
+                    const gptr<T> rhs = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
@@ -603,8 +626,8 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
         const long long row0 = (vb - L.off[bi]) * bx.rows;
         const int nact = (int)min((long long)bx.rows, nrows - row0) * nx;
         const size_t obase = (size_t)row0 * nx, n3 = bx.n3;
-        const T *u = (const T *)state_ptr(bx, L, L.in);
-        const T *G = (const T *)bx.G;
+        const gptr<const T> u = glob((const T *)state_ptr(bx, L, L.in));
+        const gptr<const T> G = glob((const T *)bx.G);
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int t = threadIdx.x + k * kRowThreads;
@@ -621,8 +644,9 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
             }
         }
     };
-    if (kPrefetch && (long long)blockIdx.x < L.total) fetch(blockIdx.x);
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+    const VbRange R = vb_range(L.total);
+    if (kPrefetch && R.vb < R.end) fetch(R.vb);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nx = bx.nx;
@@ -638,7 +662,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
         const long long row0 = (vb - L.off[bi]) * bx.rows;
         const int nact = (int)min((long long)bx.rows, nrows - row0) * nx;  // active points
         const size_t obase = (size_t)row0 * nx;
-        T *out = (T *)(L.out_ov ? L.out_ov : bx.rhs);
+        const gptr<T> out = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
 
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -651,8 +675,8 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) gk[c] = pg[k][c];
                 } else {
-                    const T *u = (const T *)state_ptr(bx, L, L.in);
-                    const T *G = (const T *)bx.G;
+                    const gptr<const T> u = glob((const T *)state_ptr(bx, L, L.in));
+                    const gptr<const T> G = glob((const T *)bx.G);
                     const size_t o = obase + t;
 #pragma unroll
                     for (int v = 0; v < 5; ++v) wk[v] = u[v * n3 + o];
@@ -676,7 +700,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
             }
         }
         __syncthreads();
-        if (kPrefetch && vb + gridDim.x < L.total) fetch(vb + gridDim.x);
+        if (kPrefetch && vb + R.stride < R.end) fetch(vb + R.stride);
         T H[P][5];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -738,7 +762,7 @@ __host__ __device__ __forceinline__ int diag_blocks(int nx, int ny, int nz) {
 }
 
 // block reduction of CNS_NDIAG values (slot 7 a max, the others sums) in a fixed order
-__device__ __forceinline__ void block_reduce_diag(const double acc[CNS_NDIAG], double (*red)[CNS_NDIAG], double *dst,
+__device__ __forceinline__ void block_reduce_diag(const double acc[CNS_NDIAG], double (*red)[CNS_NDIAG], gptr<double> dst,
                                                   const double scale[CNS_NDIAG]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -761,7 +785,7 @@ static_assert(kDiagThreads == kViscTX * kViscTY && kPointThreads == kViscTX * kV
 
 // velocity m/rho of the state at linear index i (FP64, for the diagnostics)
 template <typename T>
-__device__ __forceinline__ void vel_at(const T *u, size_t n3, size_t i, double v[3]) {
+__device__ __forceinline__ void vel_at(gptr<const T> u, size_t n3, size_t i, double v[3]) {
     const double ir = rcp(double(u[i]));
     v[0] = double(u[n3 + i]) * ir;
     v[1] = double(u[2 * n3 + i]) * ir;
@@ -778,8 +802,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
     __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
     __shared__ double pv[3][kViscTY + 4][kViscTX + 4];
     const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
-    const long long vb0 = gridDim.x == L.total ? xcd_block(blockIdx.x, L.total) : blockIdx.x;
-    for (long long vb = vb0; vb < L.total; vb += gridDim.x) {
+    const VbRange R = vb_range(L.total);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
@@ -787,7 +811,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
         const int nblk = diag_blocks(nx, ny, nz);
         const long long ntile = diag_tiles(nx, ny, nz);
         const int lb = (int)(vb - L.off[bi]);
-        const T *u = (const T *)state_ptr(bx, L, BUF_U);
+        const gptr<const T> u = glob((const T *)state_ptr(bx, L, BUF_U));
         const double gamma = bx.gamma, ihx = bx.inv_h[0], ihy = bx.inv_h[1], ihz = bx.inv_h[2];
         const int ntx = (nx + kViscTX - 1) / kViscTX, nty = (ny + kViscTY - 1) / kViscTY;
         const int tx = threadIdx.x % kViscTX, ty = threadIdx.x / kViscTX;
@@ -850,7 +874,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
                     for (int c = 0; c < 3; ++c) vz[m][c] = vz[m + 1][c];
             }
         }
-        block_reduce_diag(acc, red, bx.part + (size_t)lb * CNS_NDIAG, one);
+        block_reduce_diag(acc, red, glob(bx.part) + (size_t)lb * CNS_NDIAG, one);
     }
 }
 
@@ -865,12 +889,12 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L0) {
         for (int b = threadIdx.x; b < nblk; b += kDiagThreads)
 #pragma unroll
             for (int d = 0; d < CNS_NDIAG; ++d) {
-                const double v = bx.part[(size_t)b * CNS_NDIAG + d];
+                const double v = glob(bx.part)[(size_t)b * CNS_NDIAG + d];
                 acc[d] = (d == 7) ? fmax(acc[d], v) : acc[d] + v;
             }
         const double inv = 1.0 / (double)bx.n3;
         const double scale[CNS_NDIAG] = {inv, inv, inv, inv, inv, inv, inv, 1.0, 1.0};
-        double *dst = L.diag ? L.diag + ((size_t)bi * L.diag_box_stride + L.step) * CNS_NDIAG : nullptr;
+        const gptr<double> dst = L.diag ? glob(L.diag) + ((size_t)bi * L.diag_box_stride + L.step) * CNS_NDIAG : nullptr;
         block_reduce_diag(acc, red, dst, scale);
     }
 }
@@ -884,12 +908,13 @@ __global__ __launch_bounds__(kDiagThreads) void k_speed_partial(Launch L0) {
     const Launch L = with_params(L0);
     __shared__ double red[kDiagThreads / 64][2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
+    const VbRange R = vb_range(L.total);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nblk = diag_blocks(bx.nx, bx.ny, bx.nz);
         const int lb = (int)(vb - L.off[bi]);
-        const T *u = (const T *)state_ptr(bx, L, BUF_U);
+        const gptr<const T> u = glob((const T *)state_ptr(bx, L, BUF_U));
         const size_t n3 = bx.n3;
         const double gamma = bx.gamma;
         double smax = 0.0, bad = 0.0;
@@ -921,8 +946,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_speed_partial(Launch L0) {
                 m = fmax(m, red[w2][0]);
                 b += red[w2][1];
             }
-            bx.part[(size_t)lb * CNS_NDIAG + 7] = m;
-            bx.part[(size_t)lb * CNS_NDIAG + 8] = b;
+            glob(bx.part)[(size_t)lb * CNS_NDIAG + 7] = m;
+            glob(bx.part)[(size_t)lb * CNS_NDIAG + 8] = b;
         }
         __syncthreads();
     }
@@ -936,13 +961,33 @@ __global__ __launch_bounds__(64) void k_speed_final(Launch L0, double *out) {
         const int nblk = diag_blocks(bx.nx, bx.ny, bx.nz);
         double m = 0.0, b = 0.0;
         for (int k = threadIdx.x; k < nblk; k += 64) {
-            m = fmax(m, bx.part[(size_t)k * CNS_NDIAG + 7]);
-            b += bx.part[(size_t)k * CNS_NDIAG + 8];
+            m = fmax(m, glob(bx.part)[(size_t)k * CNS_NDIAG + 7]);
+            b += glob(bx.part)[(size_t)k * CNS_NDIAG + 8];
         }
         m = wave_max(m);
         b = wave_sum(b);
         if (threadIdx.x == 0) out[bi] = b > 0.0 ? __builtin_nan("") : m;
     }
+}
+
+// streaming copy of n16 16-byte words (bandwidth reference): each thread moves four
+// words per round, the loads of a round issued before its stores
+typedef double v2d __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_stream_copy(const v2d *__restrict__ src, v2d *__restrict__ dst,
+                                                     size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        v2d a = __builtin_nontemporal_load(&src[i]);
+        v2d b = __builtin_nontemporal_load(&src[i + stride]);
+        v2d c = __builtin_nontemporal_load(&src[i + 2 * stride]);
+        v2d d = __builtin_nontemporal_load(&src[i + 3 * stride]);
+        __builtin_nontemporal_store(a, &dst[i]);
+        __builtin_nontemporal_store(b, &dst[i + stride]);
+        __builtin_nontemporal_store(c, &dst[i + 2 * stride]);
+        __builtin_nontemporal_store(d, &dst[i + 3 * stride]);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 __global__ void k_set_params(GraphParams *gp, const void *u, double *diag, double dt) {
@@ -963,11 +1008,11 @@ int rows_for(int nx) {
     return g;
 }
 
-bool rows_fits(int nx, size_t esz, int *P) {
-    const int per = rows_for(nx) * nx;
-    const int p = (per + kRowThreads - 1) / kRowThreads;
-    if (P) *P = p;
-    return p <= 4 && (size_t)14 * per * esz <= (size_t)kRowLdsMax;
+bool rows_fit(int nx, int rows, size_t esz, int *P) {
+    const long long per = (long long)rows * nx;
+    const long long p = (per + kRowThreads - 1) / kRowThreads;
+    if (P) *P = (int)p;
+    return rows >= 1 && p <= 4 && (size_t)14 * per * esz <= (size_t)kRowLdsMax;
 }
 
 static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
@@ -1016,6 +1061,13 @@ static inline unsigned grid_for(long long total) {
     return (unsigned)(total < cap ? total : cap);
 }
 
+// launched blocks of family fam: bt.grid[fam] when set (a persistent launch), else one
+// per virtual block
+static inline unsigned grid_of(const Batch &bt, int fam, long long total) {
+    const long long g = bt.grid[fam];
+    return grid_for(g > 0 && g < total ? g : total);
+}
+
 void launch_init_state(int prec, size_t n3, double gamma, const double *rho, const double *vel, const double *p,
                        void *u, hipStream_t s) {
     const unsigned g = (unsigned)((n3 + 255) / 256);
@@ -1036,12 +1088,12 @@ static void visc_fields(const Batch &bt, Launch L) {
     L = with_family(bt, L, F_VISC);
     if (!L.total) return;
     ProfScope ps(bt.prof, K_VISC_FLUX, bt.stream);
-    hipLaunchKernelGGL(k_visc_flux<T>, dim3(grid_for(L.total)), dim3(kPointThreads), 0, bt.stream, L);
+    hipLaunchKernelGGL(k_visc_flux<T>, dim3(grid_of(bt, F_VISC, L.total)), dim3(kPointThreads), 0, bt.stream, L);
 }
 
 template <typename T, int DIR, int MODE, bool VISC>
 static void sweep_t(const Batch &bt, const Launch &L) {
-    const dim3 g(grid_for(L.total)), b(bt.block);
+    const dim3 g(grid_of(bt, F_SWEEP_X + DIR, L.total)), b(bt.block);
     const size_t ring = 30 * (size_t)bt.block * sizeof(T);  // point-flux ring, 6 slots x 5 per thread
     if (bt.weights == CNS_WENO_Z)
         hipLaunchKernelGGL((k_sweep<T, double, DIR, MODE, VISC, CNS_WENO_Z>), g, b, ring, bt.stream, L);
@@ -1069,7 +1121,9 @@ static void sweep(const Batch &bt, Launch L, int dir, bool visc) {
 template <typename T, bool VISC, int WW>
 static void xrows_tw(const Batch &bt, const Launch &L) {
     // about four row groups per block when the loads of the next one are prefetched
-    const long long nb = bt.rowP == 1 ? std::max<long long>(std::min<long long>(L.total, 2048), L.total / 4) : L.total;
+    const long long nb = bt.grid[F_XROWS] > 0 ? std::min<long long>(bt.grid[F_XROWS], L.total)
+                         : (bt.rowP == 1 ? std::max<long long>(std::min<long long>(L.total, 2048), L.total / 4)
+                                         : L.total);
     const dim3 g(grid_for(nb)), b(kRowThreads);
     switch (bt.rowP) {
         case 1: hipLaunchKernelGGL((k_sweep_x_rows<T, double, VISC, 1, WW>), g, b, bt.rowLds, bt.stream, L); break;
@@ -1158,7 +1212,7 @@ static void diag_t(const Batch &bt, const void *u_ov, double *diag, long long st
     L.diag = diag;
     L.diag_box_stride = stride;
     L.step = step;
-    hipLaunchKernelGGL(k_diag_partial<T>, dim3(grid_for(L.total)), dim3(kDiagThreads), 0, bt.stream, L);
+    hipLaunchKernelGGL(k_diag_partial<T>, dim3(grid_of(bt, F_DIAG, L.total)), dim3(kDiagThreads), 0, bt.stream, L);
     const Launch F = with_family(bt, L, F_BOX);
     hipLaunchKernelGGL(k_diag_final, dim3(grid_for(F.total)), dim3(kDiagThreads), 0, bt.stream, F);
 }
@@ -1174,6 +1228,13 @@ void launch_max_wave_speed(const Batch &bt, const void *u_ov, double *out) {
     hipLaunchKernelGGL(k_speed_final, dim3(grid_for(F.total)), dim3(64), 0, bt.stream, F, out);
 }
 
+void launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    // 8 blocks of 256 threads per CU on the 256 CUs
+    const unsigned g = (unsigned)std::min<size_t>((n16 + 255) / 256, 2048);
+    if (n16) hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(256), 0, s, (const v2d *)src, (v2d *)dst, n16);
+}
+
 void launch_set_params(GraphParams *gp, const void *u, double *diag, double dt, hipStream_t s) {
     hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, s, gp, u, diag, dt);
 }
@@ -1182,6 +1243,7 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long stri
     if (bt.prec == CNS_FP64) diag_t<double>(bt, u_ov, diag, stride, step);
     else diag_t<float>(bt, u_ov, diag, stride, step);
 }
+
 
 template <typename T>
 static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step,
@@ -1280,6 +1342,48 @@ float time_sweeps_yz(const Batch &bt, int reps) {
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return ms / (float)(reps > 0 ? reps : 1);
+}
+
+float time_rhs_kernels(const Batch &bt, int reps) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, bt.stream);
+    for (int r = 0; r < reps; ++r) launch_rhs(bt, nullptr, nullptr);
+    (void)hipEventRecord(b, bt.stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / (float)(reps > 0 ? reps : 1);
+}
+
+static long long cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        return 256;
+    return cus;
+}
+
+long long resident_sweep_blocks(const Batch &bt) {
+    int n = 0;
+    const size_t ring = 30 * (size_t)bt.block * (bt.prec == CNS_FP64 ? sizeof(double) : sizeof(float));
+    hipError_t e = bt.prec == CNS_FP64
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, k_sweep<double, double, 2, MODE_RK, true, CNS_WENO_JS>, bt.block, ring)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, k_sweep<float, double, 2, MODE_RK, true, CNS_WENO_JS>, bt.block, ring);
+    return (e == hipSuccess && n > 0 ? n : 1) * cu_count();
+}
+
+long long resident_tile_blocks(const Batch &bt) {
+    int n = 0;
+    hipError_t e = bt.prec == CNS_FP64
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_visc_flux<double>, kPointThreads, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_visc_flux<float>, kPointThreads, 0);
+    return (e == hipSuccess && n > 0 ? n : 1) * cu_count();
 }
 
 void prof_flush(Prof *p) {

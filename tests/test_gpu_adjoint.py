@@ -136,6 +136,42 @@ def test_autograd_function_gradient_16(orc):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("scheme", ["rk4", "tvdrk3"])
+def test_autograd_forward_returns_J_and_backward_runs_the_reverse_sweep(orc, scheme):
+    """The autograd Function's forward runs only the forward pass (checkpoints in a
+    workspace of its own) and returns J; its backward runs the reverse sweep.  Both
+    agree bitwise with the one-call adjoint, also when another adjoint call on the
+    same plan runs in between."""
+    case(f"autograd split forward/backward {scheme}")
+    shape, mu, nsteps, ckpt = (16, 16, 16), 0.02, 6, 4
+    rho, vel, p = state(shape, seed=4)
+    plan = Plan(shape, mu_eff=mu)
+    rho_d, vel_d, p_d = (torch.from_numpy(a).cuda() for a in (rho, vel, p))
+    u0 = plan.init_state(rho_d, vel_d, p_d)
+    dt = I.dt_from_speed(plan.diagnostics_host(u0)[7], 16)
+    run = plan.adjoint_rk4 if scheme == "rk4" else plan.adjoint_tvdrk3
+    J_full, g_full = run(u0, dt, nsteps, ckpt)
+    v0 = vel_d.clone().requires_grad_(True)
+    J = FinalKineticEnergy.apply(v0, rho_d, p_d, plan, dt, nsteps, ckpt, scheme)
+    assert float(J) == float(J_full[0])
+    # the forward alone equals J of the plain forward run
+    u = plan.init_state(rho_d, vel_d, p_d)
+    (plan.rk4 if scheme == "rk4" else plan.tvdrk3)(u, dt, nsteps, diag=False)
+    assert float(J) == float(plan.diagnostics_host(u)[0])
+    run(u0, dt, 3, 2)  # another adjoint on the plan before the backward
+    J.backward()
+    assert torch.equal(v0.grad, plan.ic_vjp(rho_d, vel_d, g_full))
+    # the two C calls directly
+    ws = plan.adjoint_workspace(nsteps, ckpt)
+    J2 = plan.adjoint_forward(u0, dt, nsteps, ckpt, ws, scheme)
+    g2 = plan.adjoint_reverse(dt, nsteps, ckpt, ws, scheme)
+    assert torch.equal(J2, J_full) and torch.equal(g2, g_full)
+    from paper_2211_16718_amd._lib import CnsError
+
+    with pytest.raises(CnsError):  # a workspace sized for fewer steps
+        plan.adjoint_reverse(dt, 40, ckpt, ws, scheme)
+
+
 @pytest.mark.parametrize("nsteps,ckpt", [(7, 3), (4, 4)])
 def test_adjoint_tvdrk3_matches_reverse_mode_reference(orc, nsteps, ckpt):
     case(f"adjoint tvdrk3 (12,10,14) nsteps={nsteps} ckpt={ckpt}")

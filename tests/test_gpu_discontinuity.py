@@ -11,7 +11,8 @@ Bars: FP64 within 1e-12 (joint relative max-norm) of the oracle per RHS and per
 direction, for Harten thresholds 1e-6 and 0.5, and within 1e-10 after RK4 steps.  The
 mixed form: finite everywhere (its weights are formed in FP64, so products of four
 (eps + beta) factors cannot overflow FP32 even where energy jumps by 2.5e5) and within
-the FP32 rounding bound 100 * 2^-24 max|u| / (h max|rhs|) of the oracle.
+the FP32 rounding bound 100 * 2^-24 max|u| max(|v_d| + c) / (h max|rhs|) of the oracle
+(fp32_bound).
 """
 import math
 
@@ -36,9 +37,17 @@ def case(msg):
     print(f"[case] {msg}", flush=True)
 
 
-def fp32_bound(u_ref, r_ref, shape):
+def fp32_bound(u_ref, r_ref, shape, gamma=1.4):
+    """FP32 rounding of the interface fluxes, amplified by the 1/h of their difference:
+    100 * 2^-24 * Hmax / (h * max|rhs|), with Hmax = max|u| * max(|v_d| + c), a bound of
+    the magnitude of the flux f and of the Roe dissipation |A| (u^R - u^L) alike."""
     h = 2 * math.pi / max(shape)
-    return 100 * 2.0 ** -24 * float(np.abs(u_ref).max()) / (h * float(np.abs(r_ref).max()))
+    rho = u_ref[0]
+    v = u_ref[1:4] / rho
+    p = (gamma - 1.0) * (u_ref[4] - 0.5 * rho * (v ** 2).sum(0))
+    speed = float((np.abs(v).max(0) + np.sqrt(gamma * p / rho)).max())
+    hmax = float(np.abs(u_ref).max()) * speed
+    return 100 * 2.0 ** -24 * hmax / (h * float(np.abs(r_ref).max()))
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])

@@ -570,8 +570,15 @@ def bench_ensemble(nbox=64, steps=50):
         sec, diag = _timed(stream, lambda: ens.run(steps, graph=True))
     assert ens.graph_captures() == 1
     pts = sum(b["shape"][0] ** 3 for b in boxes)
+    shapes = {}
+    for i, b in enumerate(boxes):
+        n = b["shape"][0]
+        if n not in shapes:
+            seg, blk = ens.get_tiles(i)
+            rows, gs, gt = ens.get_launch(i)
+            shapes[n] = {"seg_yz": seg[1:], "block": blk, "rows": rows, "sweep_grid": gs, "tile_grid": gt}
     return {"config": {"workload": f"ensemble{nbox}_rk4x{steps}", "boxes": nbox, "points": pts,
-                       "sizes": sorted({b["shape"][0] for b in boxes})},
+                       "sizes": sorted({b["shape"][0] for b in boxes})}, "launch_shapes": shapes,
             "value": 4.0 * pts * steps / sec, "unit": "point-RHS/s", "ms_per_step": sec * 1e3 / steps,
             "autotune_s": tune_s, "graph": True,
             "bad_points": int((diag[..., 8] > 0).sum().item())}

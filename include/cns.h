@@ -27,7 +27,8 @@
  *  - Streams: `stream` is a hipStream_t passed as void*.  Calls enqueue on the
  *    plan's stream and return without synchronising, except where a call
  *    returns host values (stated per call).
- *  - Periodic grid: x_i = i * lx / nx, i = 0..nx-1, likewise y and z; nx, ny, nz >= 8.
+ *  - Periodic grid: x_i = i * lx / nx, i = 0..nx-1, likewise y and z; nx, ny, nz >= 8 and at
+ *    most 536870911 points per box (8 nx ny nz < 2^32).
  *  - Physics: gamma > 1, mu_eff >= 0, Prandtl > 0 when mu_eff > 0, weno_eps in
  *    [1e-30, 1e30], harten_delta >= 0; otherwise CNS_EINVAL.
  */
@@ -206,8 +207,8 @@ int cns_ensemble_set_tiles(cns_ensemble *ens, int32_t box, int32_t seg_x, int32_
 int cns_ensemble_get_tiles(const cns_ensemble *ens, int32_t box, int32_t *seg3_host, int32_t *block_host);
 /* Choose launch shapes by timing them on the device, keeping the fastest: per box size,
  * the segment length of the y/z marching sweeps and the rows per block of the x rows
- * kernel (the default power of two and every count that keeps 90 % of a block's threads
- * busy); for the batch, the threads per block of the marching sweeps and the launched
+ * kernel (the default power of two and every count with the same points per thread that
+ * keeps 90 % of a block's threads busy); for the batch, the threads per block of the marching sweeps and the launched
  * grids (one block per virtual block, or persistent grids of one or two rounds of the
  * blocks the chip holds at once, for the sweeps and for the tiled viscous-flux and
  * diagnostics kernels).  Only scratch buffers are written while timing.  cache_path (may
@@ -219,6 +220,15 @@ int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path);
  * whole ensemble (0: one block per virtual block). */
 int cns_ensemble_get_launch(const cns_ensemble *ens, int32_t box, int32_t *rows_host, int64_t *sweep_grid_host,
                             int64_t *tile_grid_host);
+/* Set launch shapes by hand: rows per block of the x rows kernel of box `box` (-1: every
+ * box; 0: the default; a count that does not fit gives CNS_EINVAL), and the launched blocks
+ * of the marching sweeps and of the tiled kernels (0: one per virtual block; any positive
+ * count: a persistent launch whose blocks loop over the virtual blocks).  Results do not
+ * depend on the launched blocks (bitwise), nor on the rows as long as the points per
+ * thread of the x rows kernel (rows * nx / 256, rounded up, the largest over the boxes)
+ * stay the same; another count of points per thread runs another instantiation of the
+ * kernel, whose results agree to round-off. */
+int cns_ensemble_set_launch(cns_ensemble *ens, int32_t box, int32_t rows, int64_t sweep_grid, int64_t tile_grid);
 /* nsteps steps (RK4 unless cns_ensemble_set_integrator chose TVD-RK3) of every box with its own dt; diag_dev (may be NULL) receives
  * [nbox][nsteps][CNS_NDIAG].  use_graph != 0 captures the whole run once and
  * replays it (non-default stream required). */

@@ -79,6 +79,7 @@ SIGNATURES = {
     "cns_ensemble_autotune": (C.c_int, [_vp, C.c_char_p]),
     "cns_ensemble_get_launch": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64)]),
+    "cns_ensemble_set_launch": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64]),
     "cns_ensemble_run": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32]),
     "cns_ensemble_set_integrator": (C.c_int, [_vp, C.c_int32]),
     "cns_ensemble_profile_enable": (C.c_int, [_vp, C.c_int32]),

@@ -340,6 +340,11 @@ class Ensemble:
               "cns_ensemble_get_launch")
         return r.value, gs.value, gt.value
 
+    def set_launch(self, box=-1, rows=0, sweep_grid=0, tile_grid=0):
+        """Launch shapes by hand (see :meth:`get_launch`); results do not change."""
+        check(self.lib.cns_ensemble_set_launch(self.h, int(box), int(rows), int(sweep_grid), int(tile_grid)),
+              "cns_ensemble_set_launch")
+
     def autotune(self, cache_path=None):
         check(self.lib.cns_ensemble_autotune(self.h, cache_path.encode() if cache_path else None),
               "cns_ensemble_autotune")

@@ -47,7 +47,10 @@ static int validate(const cns_grid *g, const cns_physics *ph) {
     if (g->nx < 8 || g->ny < 8 || g->nz < 8)
         return set_err(CNS_EINVAL, "grid must have at least 8 points per direction (got %d x %d x %d)", g->nx, g->ny,
                        g->nz);
-    if ((double)g->nx * g->ny * g->nz > 2.0e9) return set_err(CNS_EINVAL, "grid too large (more than 2e9 points)");
+    // the sweeps address a component of a field (and the FP64 accumulator) with 32-bit byte
+    // offsets: 8 n3 < 2^32
+    if ((double)g->nx * g->ny * g->nz * 8.0 >= 4294967296.0)
+        return set_err(CNS_EINVAL, "grid too large (at most 536870911 points per box)");
     if (!(g->lx > 0 && g->ly > 0 && g->lz > 0)) return set_err(CNS_EINVAL, "box lengths must be positive");
     if (!(ph->gamma > 1.0) || !std::isfinite(ph->gamma)) return set_err(CNS_EINVAL, "gamma must exceed 1");
     if (!(ph->mu_eff >= 0.0) || !std::isfinite(ph->mu_eff)) return set_err(CNS_EINVAL, "mu_eff must be >= 0");
@@ -418,7 +421,11 @@ static int autotune(Core &c, const char *cache_path) {
     }
     c.boxes = saved;
     // 2. rows per block of the x rows kernel per size class: the default (a power of two)
-    // and every count that keeps at least 90 % of the block's threads busy and fits
+    // and every count with the same points per thread that keeps at least 90 % of the
+    // block's threads busy and fits.  The points per thread are a template parameter of
+    // the kernel, and another instantiation may contract multiplies and adds into fused
+    // operations differently, so only counts with the default's points per thread keep
+    // results bitwise independent of the choice.
     for (auto &kv : cls) {
         const int nx = c.boxes[kv.second[0]].nx;
         const std::string key = pre + kv.first + "|rows";
@@ -428,9 +435,11 @@ static int autotune(Core &c, const char *cache_path) {
             best = it->second;
         } else if (c.xrows_pref && rows_fit(nx, rows_for(nx), c.esz, nullptr)) {
             std::vector<int> cand = {0};
+            int P0 = 0;
+            rows_fit(nx, rows_for(nx), c.esz, &P0);
             for (int r = 1; r <= 1024 / nx && (int)cand.size() < 6; ++r) {
                 int P = 0;
-                if (r == rows_for(nx) || !rows_fit(nx, r, c.esz, &P)) continue;
+                if (r == rows_for(nx) || !rows_fit(nx, r, c.esz, &P) || P != P0) continue;
                 if ((double)r * nx / (kRowThreads * P) >= 0.9) cand.push_back(r);
             }
             float best_ms = 1e30f;
@@ -844,6 +853,24 @@ int cns_ensemble_get_launch(const cns_ensemble *ens, int32_t box, int32_t *rows,
     *sweep_grid = ens->c.grid[F_SWEEP_Y];
     *tile_grid = ens->c.grid[F_VISC];
     return CNS_OK;
+}
+
+int cns_ensemble_set_launch(cns_ensemble *ens, int32_t box, int32_t rows, int64_t sweep_grid, int64_t tile_grid) {
+    if (!ens) return set_err(CNS_EINVAL, "null ensemble");
+    if (box < -1 || box >= ens->c.nbox()) return set_err(CNS_EINVAL, "box index out of range");
+    if (rows < 0 || sweep_grid < 0 || tile_grid < 0) return set_err(CNS_EINVAL, "launch shapes must be >= 0");
+    for (int i = 0; i < ens->c.nbox(); ++i) {
+        if (box >= 0 && i != box) continue;
+        if (rows > 0 && !rows_fit(ens->c.boxes[i].nx, rows, ens->c.esz, nullptr))
+            return set_err(CNS_EINVAL, "box %d: %d rows of %d points do not fit a block of the x rows kernel", i, rows,
+                           ens->c.boxes[i].nx);
+    }
+    for (int i = 0; i < ens->c.nbox(); ++i)
+        if (box < 0 || i == box) ens->c.rows_ov[i] = rows;
+    for (int f = F_SWEEP_X; f <= F_SWEEP_Z; ++f) ens->c.grid[f] = sweep_grid;
+    ens->c.grid[F_VISC] = ens->c.grid[F_DIAG] = tile_grid;
+    ens->c.dirty = true;
+    return ens->c.ws ? ens->c.sync_table() : CNS_OK;
 }
 
 int cns_ensemble_autotune(cns_ensemble *ens, const char *cache_path) {

@@ -102,6 +102,17 @@ __device__ __forceinline__ gptr<T> glob(T *p) {
     return (gptr<T>)p;
 }
 
+// Component c of a component-major array (component c at element c * n3) at a lane's
+// byte offset: the array base and the component offset are uniform and stay in scalar
+// registers, and every load and store of a point shares the lane's one 32-bit offset
+// register (global memory instructions with a scalar base address).  Needs
+// n3 * 8 < 2^32, which plan and ensemble creation check.
+template <typename T>
+__device__ __forceinline__ gptr<T> elem(gptr<T> a, size_t n3, int c, uint32_t boff) {
+    using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return (gptr<T>)((gptr<Byte>)(a + (size_t)c * n3) + boff);
+}
+
 __device__ __forceinline__ const void *state_ptr(const BoxDesc &b, const Launch &L, int which) {
     if (which == BUF_U) return L.u_ov ? L.u_ov : b.u;
     if (which == BUF_A) return L.a_ov ? L.a_ov : b.A;
@@ -245,6 +256,12 @@ template <int DIR, int C, typename T>
 __device__ __forceinline__ T load_g(gptr<const T> G, size_t n3, size_t o) {
     if constexpr (g_last_read<DIR, C>()) return __builtin_nontemporal_load(&G[gcomp<DIR>(C) * n3 + o]);
     else return G[gcomp<DIR>(C) * n3 + o];
+}
+// the same with the point's byte offset
+template <int DIR, int C, typename T>
+__device__ __forceinline__ T load_gb(gptr<const T> G, size_t n3, uint32_t bo) {
+    if constexpr (g_last_read<DIR, C>()) return __builtin_nontemporal_load(elem(G, n3, gcomp<DIR>(C), bo));
+    else return *elem(G, n3, gcomp<DIR>(C), bo);
 }
 
 // viscous term alone: out = sum_d D_d G_d (the viscous-only entry point)
@@ -448,6 +465,15 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
         const double dt = L.dt_ov > 0.0 ? L.dt_ov : bx.dt;
+        // Every pointer the loop uses is read from the box table here, once: the loop
+        // stores to global memory, which the compiler cannot tell apart from the table, so
+        // a table read inside the loop would be repeated after every store, each time
+        // behind a wait for all loads in flight (the ones issued ahead included).
+        const gptr<const T> rhs_in = glob((const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs)));
+        const gptr<const T> un = glob((const T *)state_ptr(bx, L, BUF_U));
+        const gptr<double> acc = glob(bx.acc);
+        const gptr<T> unext = glob((T *)state_ptr(bx, L, L.out));
+        const gptr<T> rhs_out = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
 
         T w[6][5], g[4][4], Hp[5], nw[5];
         // One loop computes everything, so every point flux and every interface flux
@@ -457,9 +483,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
         // forms the interface flux at j+1/2 and from j = j0 on the flux difference at
         // point j.
         {
-            const size_t o = base + wrapi(j0 - 3, n) * sg.lstride;
+            const uint32_t bo = (uint32_t)((base + wrapi(j0 - 3, n) * sg.lstride) * sizeof(T));
 #pragma unroll
-            for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
+            for (int v = 0; v < 5; ++v) nw[v] = *elem(u, n3, v, bo);
         }
         int snew = 3;  // ring slot of point j+3; point j-2+m sits in slot (snew + 1 + m) mod 6
 #pragma nounroll
@@ -471,20 +497,20 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
             {
-                const size_t o = base + wrapi(j + 4, n) * sg.lstride;
+                const uint32_t bo = (uint32_t)((base + wrapi(j + 4, n) * sg.lstride) * sizeof(T));
 #pragma unroll
-                for (int v = 0; v < 5; ++v) nw[v] = u[v * n3 + o];
+                for (int v = 0; v < 5; ++v) nw[v] = *elem(u, n3, v, bo);
             }
             if constexpr (VISC) {
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) g[m][c] = g[m + 1][c];
-                const size_t og = base + wrapi(j + 2, n) * sg.lstride;
-                g[3][0] = load_g<DIR, 0>(G, n3, og);
-                g[3][1] = load_g<DIR, 1>(G, n3, og);
-                g[3][2] = load_g<DIR, 2>(G, n3, og);
-                g[3][3] = load_g<DIR, 3>(G, n3, og);
+                const uint32_t bog = (uint32_t)((base + wrapi(j + 2, n) * sg.lstride) * sizeof(T));
+                g[3][0] = load_gb<DIR, 0>(G, n3, bog);
+                g[3][1] = load_gb<DIR, 1>(G, n3, bog);
+                g[3][2] = load_gb<DIR, 2>(G, n3, bog);
+                g[3][3] = load_gb<DIR, 3>(G, n3, bog);
             }
             const int sold = snew;
             {
@@ -498,27 +524,26 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
 
             // output operands of point j, loaded before the interface-flux arithmetic
             const size_t o = base + (size_t)(j >= j0 ? j : j0) * sg.lstride;
+            const uint32_t bo = (uint32_t)(o * sizeof(T)), boa = (uint32_t)(o * sizeof(double));
             T pr[5], pu[5];
             double pa[5];
             if (MODE != MODE_WRITE && j >= j0) {
-                const gptr<const T> rhs = glob((const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs)));
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    if constexpr (MODE == MODE_RK) pr[v] = __builtin_nontemporal_load(&rhs[v * n3 + o]);
-                    else pr[v] = rhs[v * n3 + o];
+                    if constexpr (MODE == MODE_RK) pr[v] = __builtin_nontemporal_load(elem(rhs_in, n3, v, bo));
+                    else pr[v] = *elem(rhs_in, n3, v, bo);
                 }
                 if (MODE == MODE_RK && L.stage >= 2) {
                     // u^n: every later stage but the mixed form's RK4 stage 4, which
                     // needs only the accumulator
                     if (L.scheme == CNS_TVDRK3 || kFp64Stages<T> || L.stage != 4) {
-                        const gptr<const T> un = glob((const T *)state_ptr(bx, L, BUF_U));
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) pu[v] = un[v * n3 + o];
+                        for (int v = 0; v < 5; ++v) pu[v] = *elem(un, n3, v, bo);
                     }
                     // the FP64 form reads the accumulator in the last stage only
                     if (L.scheme != CNS_TVDRK3 && (!kFp64Stages<T> || L.stage == 4)) {
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) pa[v] = __builtin_nontemporal_load(&glob(bx.acc)[v * n3 + o]);
+                        for (int v = 0; v < 5; ++v) pa[v] = __builtin_nontemporal_load(elem(acc, n3, v, boa));
                     }
                 }
             }
@@ -535,12 +560,11 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
             }
             if (j >= j0) {
                 if constexpr (MODE == MODE_RK) {
-                    const gptr<T> unext = glob((T *)state_ptr(bx, L, L.out));
-                    const gptr<double> acc = glob(bx.acc);
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
-                        const size_t e = v * n3 + o;
+                        const gptr<T> ue = elem(unext, n3, v, bo);
+                        const gptr<double> ae = elem(acc, n3, v, boa);
                         const double k = double(pr[v] + r);
                         // w[2] holds the stage state at j: u^n itself in the first stage
                         const double us = double(w[2][v]);
@@ -548,49 +572,48 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
                             // Shu-Osher: U1 = u + dt k; U2 = 3/4 u + 1/4 (U1 + dt k);
                             // u^{n+1} = 1/3 u + 2/3 (U2 + dt k)
                             if (L.stage == 1) {
-                                unext[e] = T(us + dt * k);
+                                *ue = T(us + dt * k);
                             } else {
                                 const double uo = double(pu[v]);
-                                if (L.stage == 2) unext[e] = T(0.75 * uo + 0.25 * (us + dt * k));
-                                else unext[e] = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
+                                if (L.stage == 2) *ue = T(0.75 * uo + 0.25 * (us + dt * k));
+                                else *ue = T((1.0 / 3.0) * uo + (2.0 / 3.0) * (us + dt * k));
                             }
                         } else if constexpr (kFp64Stages<T>) {
                             // FP64 stage states give back dt k1 / 6 = (U2 - u) / 3 and
                             // dt k3 / 3 = (U4 - u) / 3, so the accumulator is written in
                             // stage 2 and read in stage 4 only
                             if (L.stage == 1) {
-                                unext[e] = us + (0.5 * dt) * k;
+                                *ue = us + (0.5 * dt) * k;
                             } else if (L.stage == 2) {
                                 const double uo = pu[v];
-                                __builtin_nontemporal_store((uo + (1.0 / 3.0) * (us - uo)) + (dt / 3.0) * k, &acc[e]);
-                                unext[e] = uo + (0.5 * dt) * k;
+                                __builtin_nontemporal_store((uo + (1.0 / 3.0) * (us - uo)) + (dt / 3.0) * k, ae);
+                                *ue = uo + (0.5 * dt) * k;
                             } else if (L.stage == 3) {
-                                unext[e] = pu[v] + dt * k;
+                                *ue = pu[v] + dt * k;
                             } else {
-                                unext[e] = (pa[v] + (1.0 / 3.0) * (us - pu[v])) + (dt / 6.0) * k;
+                                *ue = (pa[v] + (1.0 / 3.0) * (us - pu[v])) + (dt / 6.0) * k;
                             }
                         } else if (L.stage == 1) {
-                            acc[e] = us + (dt / 6.0) * k;
-                            unext[e] = T(us + (0.5 * dt) * k);
+                            *ae = us + (dt / 6.0) * k;
+                            *ue = T(us + (0.5 * dt) * k);
                         } else if (L.stage == 2) {
                             const double uo = double(pu[v]);
-                            acc[e] = pa[v] + (dt / 3.0) * k;
-                            unext[e] = T(uo + (0.5 * dt) * k);
+                            *ae = pa[v] + (dt / 3.0) * k;
+                            *ue = T(uo + (0.5 * dt) * k);
                         } else if (L.stage == 3) {
                             const double uo = double(pu[v]);
-                            acc[e] = pa[v] + (dt / 3.0) * k;
-                            unext[e] = T(uo + dt * k);
+                            *ae = pa[v] + (dt / 3.0) * k;
+                            *ue = T(uo + dt * k);
                         } else {
-                            unext[e] = T(pa[v] + (dt / 6.0) * k);
+                            *ue = T(pa[v] + (dt / 6.0) * k);
                         }
                     }
                 } else {
-                    const gptr<T> rhs = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
                         const T r = -(H[v] - Hp[v]) * inv_dx;
-                        if constexpr (MODE == MODE_WRITE) rhs[v * n3 + o] = r;
-                        else rhs[v * n3 + o] = pr[v] + r;
+                        if constexpr (MODE == MODE_WRITE) *elem(rhs_out, n3, v, bo) = r;
+                        else *elem(rhs_out, n3, v, bo) = pr[v] + r;
                     }
                 }
             }
@@ -1243,6 +1266,7 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long stri
     if (bt.prec == CNS_FP64) diag_t<double>(bt, u_ov, diag, stride, step);
     else diag_t<float>(bt, u_ov, diag, stride, step);
 }
+
 
 
 template <typename T>

@@ -93,17 +93,47 @@ def test_autotuned_tiles_do_not_change_results():
         txt = open(path).read()
         assert "seg" in txt and "block" in txt
         tiles = [ens.get_tiles(i) for i in range(len(boxes))]
-        print("autotuned tiles", tiles)
+        launch = [ens.get_launch(i) for i in range(len(boxes))]
+        print("autotuned tiles", tiles, "launch shapes", launch)
+        assert "rows" in txt and "grid" in txt
         # a second ensemble reads the cache instead of timing again
         ens2 = make_ensemble(boxes, stream)
         ens2.autotune(path)
         assert [ens2.get_tiles(i) for i in range(len(boxes))] == tiles
+        assert [ens2.get_launch(i) for i in range(len(boxes))] == launch
     with torch.cuda.stream(stream):
         ens.run(2, graph=False)
     stream.synchronize()
     for i, b in enumerate(boxes):
         u, _ = single_run(b, 2, stream)
         assert torch.equal(ens.state(i), u), f"box {i}"
+
+
+def test_persistent_grids_and_rows_do_not_change_results():
+    """Persistent launches (fewer blocks than virtual blocks, each looping over several;
+    grids below and above the 8 XCDs) and rows-per-block counts other than the default
+    power of two give bitwise the single-box results."""
+    case("persistent grids and rows per block")
+    stream = torch.cuda.Stream()
+    boxes = box_inputs(SPECS)
+    ref = [single_run(b, 2, stream) for b in boxes]
+    for rows, gs, gt in ((0, 5, 3), (0, 37, 1), (3, 600, 90), (5, 1, 700)):
+        ens = make_ensemble(boxes, stream)
+        for i, b in enumerate(boxes):
+            nx = b["shape"][2]
+            r = rows if rows and rows * nx <= 1024 and 14 * rows * nx * 8 <= 65536 else 0
+            ens.set_launch(i, r, gs, gt)
+        assert ens.get_launch(0)[1:] == (gs, gt)
+        with torch.cuda.stream(stream):
+            d = ens.run(2, graph=False)
+        stream.synchronize()
+        for i in range(len(boxes)):
+            assert torch.equal(ens.state(i), ref[i][0]), (rows, gs, gt, i)
+            assert torch.equal(d[i], ref[i][1]), (rows, gs, gt, i)
+    from paper_2211_16718_amd._lib import CnsError
+
+    with pytest.raises(CnsError):
+        ens.set_launch(0, 1000, 0, 0)  # 1000 rows of 32 points do not fit
 
 
 def test_graph_replays_match_eager_runs():

@@ -157,6 +157,20 @@ int cns_max_wave_speed(const cns_plan *plan, const void *u_dev, double *out_dev)
 
 /* Diagnostics of u into device memory out_dev[CNS_NDIAG]. */
 int cns_diagnostics(const cns_plan *plan, const void *u_dev, double *out_dev);
+/* For callers that cannot allocate (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid allocation): the diagnostics record of cns_diagnostics for a box
+ * described by grid, phys and precision, with no plan and no workspace.  Its scratch (the
+ * device table of the box and at most 1024 per-block partial sums, whatever the grid
+ * size) lives in a static device array of 128 KiB that every GPU the library runs on holds
+ * until the process ends; the call allocates nothing and copies nothing from the host (the
+ * table is written by a kernel), so it can be captured.  The current device must be the
+ * stream's device.  Every partial sum is written before it is read, so nothing needs
+ * clearing between calls.  Calls that overlap on one GPU (other streams or threads) share
+ * the array and race; order them.  Results equal cns_diagnostics bitwise.  Errors as
+ * cns_plan_create for the arguments, CNS_EUNSUPPORTED if the scratch need exceeded the
+ * array. */
+int cns_diagnostics_static(const cns_grid *grid, const cns_physics *phys, int32_t precision, const void *u_dev,
+                           double *out_dev, void *stream);
 /* Same, copied to host memory out_host[CNS_NDIAG]; synchronises the plan's stream.
  * Returns CNS_ENONFINITE / CNS_ENONPHYSICAL when bad points are present (the record
  * is still written). */

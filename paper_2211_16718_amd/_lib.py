@@ -64,6 +64,7 @@ SIGNATURES = {
     "cns_spectrum": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp]),
     "cns_diagnostics_host": (C.c_int, [_vp, _vp, _dp]),
     "cns_max_wave_speed": (C.c_int, [_vp, _vp, _vp]),
+    "cns_diagnostics_static": (C.c_int, [C.POINTER(Grid), C.POINTER(Physics), C.c_int32, _vp, _vp, _vp]),
     "cns_plan_graph_captures": (C.c_int64, [_vp]),
     "cns_ensemble_graph_captures": (C.c_int64, [_vp]),
     "cns_profile_enable": (C.c_int, [_vp, C.c_int32]),

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -327,6 +328,38 @@ struct cns_plan {
 struct cns_ensemble {
     Core c;
 };
+
+// ----------------------------------------------------------------------------
+// diagnostics with no allocation: device scratch in a static array
+// ----------------------------------------------------------------------------
+// The scratch of cns_diagnostics_static: the one-box device table and the per-block
+// partial sums (at most kDiagBlocksMax records, whatever the grid size).  Each GPU the
+// library runs on holds its own copy until the process ends; calls on one GPU share it.
+constexpr size_t kStaticScratchBytes = 128 * 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static char *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// The device address of `scratch` on the current device.  In host code the array's name
+// stands for a host-side shadow, so the address is taken with hipGetSymbolAddress, once
+// per device with that device current, and only that address reaches the kernels.
+static int static_scratch(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_err(CNS_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return set_err(CNS_EUNSUPPORTED, "device %d (at most %d devices)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_err(CNS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CNS_OK;
+}
 
 // ----------------------------------------------------------------------------
 // autotuner: segment length of the marching y/z sweeps per box size, then the
@@ -735,6 +768,22 @@ int cns_diagnostics_host(const cns_plan *plan, const void *u, double *out_host) 
         return set_err(std::isfinite(out_host[0]) ? CNS_ENONPHYSICAL : CNS_ENONFINITE,
                        "%.0f bad grid points (non-finite, rho <= 0 or p <= 0)", out_host[8]);
     return CNS_OK;
+}
+
+int cns_diagnostics_static(const cns_grid *grid, const cns_physics *phys, int32_t precision, const void *u,
+                           double *out, void *stream) {
+    int rc = validate(grid, phys);
+    if (rc) return rc;
+    if (precision != CNS_FP64 && precision != CNS_MIXED) return set_err(CNS_EINVAL, "unknown precision %d", precision);
+    if ((rc = check_ptr(u, "u"))) return rc;
+    if (!out || ((uintptr_t)out & 7u)) return set_err(CNS_EINVAL, "out must be non-null and 8-byte aligned");
+    if (static_diag_bytes() > kStaticScratchBytes)
+        return set_err(CNS_EUNSUPPORTED, "diagnostics need %zu bytes of scratch, the static array holds %zu",
+                       static_diag_bytes(), kStaticScratchBytes);
+    char *ptr = nullptr;
+    if ((rc = static_scratch(&ptr))) return rc;
+    launch_diag_static(ptr, Core::make_box(*grid, *phys, 0.0), precision, u, out, (hipStream_t)stream);
+    return check_hip("diagnostics_static");
 }
 
 int cns_max_wave_speed(const cns_plan *plan, const void *u, double *out) {

@@ -152,6 +152,16 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag
 // max over points and directions of |v_d| + c of every box into out[box] (NaN for a box
 // with a non-finite state, rho <= 0 or p <= 0)
 void launch_max_wave_speed(const Batch &bt, const void *u_ov, double *out);
+// Diagnostics of one box with its device table and partial sums in caller-given device
+// scratch (scratch_dev, 256-byte aligned, static_diag_bytes() bytes): the table is
+// written by a kernel from a kernel argument, so nothing is copied from the host.
+struct OneBoxTable {
+    BoxDesc b;
+    long long off[F_N][2];
+};
+inline size_t align_up256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t static_diag_bytes();
+void launch_diag_static(char *scratch_dev, const BoxDesc &b, int prec, const void *u, double *out, hipStream_t s);
 // a plain streaming copy (bytes a multiple of 16, 16-byte aligned pointers)
 void launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // the per-call record of a graph replay (enqueued before the replay)

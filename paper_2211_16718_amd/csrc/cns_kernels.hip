@@ -1267,6 +1267,35 @@ void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long stri
     else diag_t<float>(bt, u_ov, diag, stride, step);
 }
 
+// the device table of one box, written from a kernel argument (no host-to-device copy)
+__global__ void k_write_table(OneBoxTable t, OneBoxTable *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = t;
+}
+
+size_t static_diag_bytes() { return align_up256(sizeof(OneBoxTable)) + (size_t)kDiagBlocksMax * CNS_NDIAG * sizeof(double); }
+
+void launch_diag_static(char *scratch_dev, const BoxDesc &b, int prec, const void *u, double *out, hipStream_t s) {
+    OneBoxTable t{};
+    t.b = b;
+    t.b.part = (double *)(scratch_dev + align_up256(sizeof(OneBoxTable)));
+    for (int f = 0; f < F_N; ++f) {
+        t.off[f][0] = 0;
+        t.off[f][1] = family_blocks(t.b, f, 256);
+    }
+    OneBoxTable *dt = (OneBoxTable *)scratch_dev;
+    hipLaunchKernelGGL(k_write_table, dim3(1), dim3(64), 0, s, t, dt);
+    Batch bt;
+    bt.nbox = 1;
+    bt.prec = prec;
+    bt.d_boxes = &dt->b;
+    for (int f = 0; f < F_N; ++f) {
+        bt.d_off[f] = dt->off[f];
+        bt.total[f] = t.off[f][1];
+    }
+    bt.stream = s;
+    launch_diag(bt, u, out, 0, 0);
+}
+
 
 
 template <typename T>

@@ -97,9 +97,10 @@ int cns_set_workspace(cns_plan *plan, void *ws_dev, size_t bytes);
  * Results do not depend on these values (bitwise). */
 int cns_set_tiles(cns_plan *plan, int32_t seg_x, int32_t seg_y, int32_t seg_z, int32_t block);
 
-/* x-direction sweep kernel: 0 = whole periodic rows staged in LDS, one thread per
- * interface (default; used when a row fits: nx * rows <= 1024 threads and 64 KiB of
- * LDS), 1 = the marching kernel used for y and z.  Results agree to round-off. */
+/* x-direction sweep kernel: 0 = periodic rows staged in LDS, one thread per interface
+ * (default: whole rows, several per block, when nx <= 256; longer rows walked in chunks of
+ * 256 interfaces by one block each), 1 = the marching kernel used for y and z.  Results
+ * agree to round-off. */
 int cns_set_x_kernel(cns_plan *plan, int32_t kind);
 
 /* Sec. 2.1 equation of state: u = [rho, rho v, p/(gamma-1) + rho|v|^2/2] from device

@@ -201,8 +201,9 @@ struct Core {
             b.u = ustate[i];
             int P = 1;
             b.rows = rows_ov[i] > 0 && rows_fit(b.nx, rows_ov[i], esz, nullptr) ? rows_ov[i] : rows_for(b.nx);
-            b.xrows = (xrows_pref && rows_fit(b.nx, b.rows, esz, &P)) ? 1 : 0;
-            if (b.xrows) {
+            // rows longer than a block go through the chunked rows kernel
+            b.xrows = !xrows_pref ? 0 : (b.nx > kRowThreads ? 2 : (rows_fit(b.nx, b.rows, esz, &P) ? 1 : 0));
+            if (b.xrows == 1) {
                 rowP = std::max(rowP, P);
                 rowLds = std::max(rowLds, (size_t)14 * b.rows * b.nx * esz);
             }
@@ -246,6 +247,7 @@ struct Core {
         }
         bt.rowP = rowP;
         bt.rowLds = rowLds;
+        bt.esz = esz;
         for (int f = 0; f < F_N; ++f) bt.grid[f] = grid[f];
         bt.stream = stream;
         bt.prof = prof.on ? &prof : nullptr;
@@ -466,7 +468,7 @@ static int autotune(Core &c, const char *cache_path) {
         int best = 0;
         if (it != cache.end() && it->second >= 0 && (it->second == 0 || rows_fit(nx, it->second, c.esz, nullptr))) {
             best = it->second;
-        } else if (c.xrows_pref && rows_fit(nx, rows_for(nx), c.esz, nullptr)) {
+        } else if (c.xrows_pref && nx <= kRowThreads && rows_fit(nx, rows_for(nx), c.esz, nullptr)) {
             std::vector<int> cand = {0};
             int P0 = 0;
             rows_fit(nx, rows_for(nx), c.esz, &P0);
@@ -898,7 +900,7 @@ int cns_ensemble_get_launch(const cns_ensemble *ens, int32_t box, int32_t *rows,
     if (!ens || !rows || !sweep_grid || !tile_grid) return set_err(CNS_EINVAL, "null argument");
     if (box < 0 || box >= ens->c.nbox()) return set_err(CNS_EINVAL, "box index out of range");
     const BoxDesc &b = ens->c.boxes[box];
-    *rows = ens->c.ws && b.xrows ? b.rows : 0;
+    *rows = ens->c.ws && b.xrows == 1 ? b.rows : 0;
     *sweep_grid = ens->c.grid[F_SWEEP_Y];
     *tile_grid = ens->c.grid[F_VISC];
     return CNS_OK;

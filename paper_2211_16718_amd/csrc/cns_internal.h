@@ -33,7 +33,7 @@ enum Buf { BUF_U = 0, BUF_A = 1, BUF_B = 2 };
 struct BoxDesc {
     int nx, ny, nz;
     int seg[3];  // marching-sweep segment length per direction
-    int xrows;   // 1: x sweep by the rows kernel, 0: by the marching kernel
+    int xrows;   // x sweep kernel: 1 whole rows in LDS, 2 rows in chunks, 0 marching
     int rows;    // rows per block of the x rows kernel
     size_t n3;
     double inv_h[3];  // 1/dx, 1/dy, 1/dz
@@ -43,7 +43,7 @@ struct BoxDesc {
 };
 
 // kernel families with their own virtual-block prefix
-enum Family { F_POINT = 0, F_XROWS, F_SWEEP_X, F_SWEEP_Y, F_SWEEP_Z, F_DIAG, F_BOX, F_VISC, F_N };
+enum Family { F_POINT = 0, F_XROWS, F_SWEEP_X, F_SWEEP_Y, F_SWEEP_Z, F_DIAG, F_BOX, F_VISC, F_XCHUNK, F_N };
 
 // Per-call arguments of a replayed hipGraph: the captured launches read the state, the
 // step size and the diagnostics base from this device record (written by a small kernel
@@ -119,6 +119,7 @@ struct Batch {
     long long total[F_N] = {};
     int rowP = 1;       // points per thread of the rows kernel (max over boxes)
     size_t rowLds = 0;  // LDS bytes of the rows kernel (max over boxes)
+    size_t esz = 8;     // bytes per state element
     hipStream_t stream = nullptr;
     Prof *prof = nullptr;
     const GraphParams *gp = nullptr;  // set while a run is captured for graph replay

@@ -761,6 +761,103 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
 }
 
 // ----------------------------------------------------------------------------
+// x sweep for rows longer than a block: one block walks one periodic row in chunks of
+// kRowThreads interfaces.  Chunk c stages the points c*256-2 .. c*256+258 (the six-point
+// stencils of its interfaces, wrapped) in LDS and one thread forms one interface flux.
+// The flux difference of point i takes the interface fluxes at i-1/2 and i+1/2; the first
+// point of a chunk takes i-1/2 from the previous chunk (carried in LDS), and the row's
+// first point waits for the last chunk.  Compared with staging the whole row, the LDS of
+// a block no longer grows with the row (29 KB in FP64), so the CU holds twice the blocks
+// at 512 points per row; each chunk re-reads five stencil points of its neighbour.
+// ----------------------------------------------------------------------------
+constexpr int kChunkPts = kRowThreads + 5;  // points staged per chunk
+__host__ __device__ __forceinline__ size_t chunk_lds_bytes(size_t esz) { return (14 * kChunkPts + 5) * esz; }
+
+template <typename T, typename B, bool VISC, int WW>
+__global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_chunks(Launch L0) {
+    const Launch L = with_params(L0);
+    extern __shared__ unsigned char lds_raw[];
+    T *su = reinterpret_cast<T *>(lds_raw);  // [5][kChunkPts] states, later the interface fluxes
+    T *sf = su + 5 * kChunkPts;              // [5][kChunkPts] point fluxes
+    T *sg = sf + 5 * kChunkPts;              // [4][kChunkPts] viscous fluxes (VISC)
+    T *carry = sg + 4 * kChunkPts;           // [5] interface flux carried to the next chunk
+    const int t = threadIdx.x;
+    const VbRange R = vb_range(L.total);
+    for (long long vb = R.vb; vb < R.end; vb += R.stride) {
+        const int bi = find_box(L.off, L.nbox, vb);
+        const BoxDesc &bx = L.boxes[bi];
+        const int nx = bx.nx;
+        const size_t n3 = bx.n3, obase = (size_t)(vb - L.off[bi]) * nx;
+        const gptr<const T> u = glob((const T *)state_ptr(bx, L, L.in));
+        const gptr<const T> G = glob((const T *)bx.G);
+        const gptr<T> out = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
+        const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
+        const T gm1 = gamma - T(1);
+        const T inv_dx = T(bx.inv_h[0]);
+        const int nch = (nx + kRowThreads - 1) / kRowThreads;
+        T Hfirst[5];  // interface 1/2 of the row (thread 0)
+        for (int c = 0; c < nch; ++c) {
+            const int i0 = c * kRowThreads;
+            for (int sp = t; sp < kChunkPts; sp += kRowThreads) {
+                const size_t o = obase + wrapm(i0 - 2 + sp, nx);
+                T wk[5], f[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) wk[v] = u[v * n3 + o];
+                euler_flux<T, 0>(wk, gm1, f);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    su[v * kChunkPts + sp] = wk[v];
+                    sf[v * kChunkPts + sp] = f[v];
+                }
+                if constexpr (VISC) {
+                    sg[0 * kChunkPts + sp] = load_g<0, 0>(G, n3, o);
+                    sg[1 * kChunkPts + sp] = load_g<0, 1>(G, n3, o);
+                    sg[2 * kChunkPts + sp] = load_g<0, 2>(G, n3, o);
+                    sg[3 * kChunkPts + sp] = load_g<0, 3>(G, n3, o);
+                }
+            }
+            __syncthreads();
+            const int i = i0 + t;
+            const bool act = i < nx;
+            T H[5];
+            if (act) {
+                int q[6];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) q[m] = t + m;  // point i-2+m
+                interface_flux_lds<T, B, 0, VISC, WW>(su, sf, sg, kChunkPts, q, gamma, eps4, delta, H);  // at i+1/2
+            }
+            __syncthreads();  // every thread has read the staged chunk
+            if (act)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) su[v * kChunkPts + t] = H[v];
+            if (c == 0 && t == 0)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) Hfirst[v] = H[v];
+            __syncthreads();
+            // point i from the interfaces at i-1/2 and i+1/2; the row's first point waits
+            if (act && (c > 0 || t > 0)) {
+                const size_t o = obase + i;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    const T hm = t > 0 ? su[v * kChunkPts + t - 1] : carry[v];
+                    out[v * n3 + o] = -(H[v] - hm) * inv_dx;
+                }
+            }
+            __syncthreads();  // carry read; the next chunk overwrites the staging
+            if (i == min(i0 + kRowThreads, nx) - 1)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) carry[v] = H[v];
+        }
+        __syncthreads();  // carry now holds the interface at nx-1/2
+        if (t == 0) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) out[v * n3 + obase] = -(Hfirst[v] - carry[v]) * inv_dx;
+        }
+        __syncthreads();  // LDS is reused by the next row
+    }
+}
+
+// ----------------------------------------------------------------------------
 // diagnostics: deterministic two-pass reduction per box
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
@@ -1043,7 +1140,8 @@ static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 long long family_blocks(const BoxDesc &b, int fam, int block) {
     switch (fam) {
         case F_POINT: return cdiv((long long)b.n3, kPointThreads);
-        case F_XROWS: return b.xrows ? cdiv((long long)b.ny * b.nz, b.rows) : 0;
+        case F_XROWS: return b.xrows == 1 ? cdiv((long long)b.ny * b.nz, b.rows) : 0;
+        case F_XCHUNK: return b.xrows == 2 ? (long long)b.ny * b.nz : 0;
         case F_SWEEP_X:
         case F_SWEEP_Y:
         case F_SWEEP_Z: {
@@ -1163,8 +1261,20 @@ static void xrows_t(const Batch &bt, const Launch &L) {
     else xrows_tw<T, VISC, CNS_WENO_JS>(bt, L);
 }
 
-// x sweep (always the first, writing sweep): the rows kernel for boxes whose rows fit
-// in LDS, the marching kernel for the others
+template <typename T, bool VISC>
+static void xchunks_t(const Batch &bt, const Launch &L) {
+    const dim3 g(grid_of(bt, F_XCHUNK, L.total)), b(kRowThreads);
+    const size_t lds = chunk_lds_bytes(sizeof(T));
+    if (bt.weights == CNS_WENO_Z)
+        hipLaunchKernelGGL((k_sweep_x_chunks<T, double, VISC, CNS_WENO_Z>), g, b, lds, bt.stream, L);
+    else if (bt.weights == CNS_WENO_M)
+        hipLaunchKernelGGL((k_sweep_x_chunks<T, double, VISC, CNS_WENO_M>), g, b, lds, bt.stream, L);
+    else
+        hipLaunchKernelGGL((k_sweep_x_chunks<T, double, VISC, CNS_WENO_JS>), g, b, lds, bt.stream, L);
+}
+
+// x sweep (always the first, writing sweep): the rows kernel for boxes whose rows fill at
+// most one block, the chunked rows kernel for longer rows, the marching kernel when chosen
 template <typename T>
 static void sweep_x(const Batch &bt, const Launch &L, bool visc) {
     ProfScope ps(bt.prof, K_SWEEP_X, bt.stream);
@@ -1172,6 +1282,11 @@ static void sweep_x(const Batch &bt, const Launch &L, bool visc) {
     if (R.total) {
         if (visc) xrows_t<T, true>(bt, R);
         else xrows_t<T, false>(bt, R);
+    }
+    const Launch C = with_family(bt, L, F_XCHUNK);
+    if (C.total) {
+        if (visc) xchunks_t<T, true>(bt, C);
+        else xchunks_t<T, false>(bt, C);
     }
     sweep<T, MODE_WRITE>(bt, L, 0, visc);
 }

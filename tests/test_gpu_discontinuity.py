@@ -130,3 +130,26 @@ def test_rk4_steps_across_jumps(orc, axis):
     assert err <= 1e-10
     assert np.all(d[:, 8] == 0)
     np.testing.assert_allclose(d[:, :8], dref[:, :8], rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape,strength", [((6, 5, 300), "sod"), ((5, 4, 520), "strong")])
+def test_jumps_along_long_rows(orc, shape, strength):
+    # rows longer than 256 points: the x sweep works through 256-interface chunks and
+    # carries the last interface flux of a chunk into the next; jumps fall at points
+    # 75, 225 and the wrap (300 points) or 130, 390 and the wrap (520 points), so
+    # chunk boundaries and the wrap see both smooth and discontinuous stencils
+    case(f"jumps along long rows {shape} {strength}")
+    rho, vel, p = I.shock_primitives(shape, 0, seed=40, strength=strength)
+    ph = orc.make_phys(mu_eff=0.01)
+    u_ref = orc.init_state(rho, vel, p)
+    plan = Plan(shape, mu_eff=0.01)
+    u = plan.init_state(rho, vel, p)
+    for xk in ("rows", "march"):
+        plan.set_x_kernel(xk)
+        err = rel_max(plan.rhs_dir(u, 0).cpu().numpy(), orc.rhs_hyp_dir(u_ref, 0, ph))
+        print(f"  x sweep ({xk}): rel err {err:.3e}")
+        assert err <= 1e-12, (xk, err)
+    plan.set_x_kernel("rows")
+    err = rel_max(plan.rhs(u).cpu().numpy(), orc.rhs(u_ref, ph))
+    print(f"  full rhs: rel err {err:.3e}")
+    assert err <= 1e-12

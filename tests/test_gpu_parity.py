@@ -371,11 +371,12 @@ def test_max_wave_speed_matches_oracle(orc):
 
 
 @pytest.mark.parametrize("shape,precision", [((8, 9, 320), "fp64"), ((8, 8, 580), "fp64"), ((8, 8, 600), "fp64"),
-                                             ((8, 9, 600), "mixed")])
+                                             ((8, 9, 600), "mixed"), ((8, 8, 257), "fp64"), ((9, 8, 512), "fp64"),
+                                             ((8, 8, 1100), "fp64"), ((8, 9, 513), "mixed")])
 def test_long_rows(orc, shape, precision):
-    # 320- and 580-point FP64 rows: two and three points per thread in the rows kernel;
-    # 600-point FP64 rows do not fit in LDS, so the x sweep marches; 600-point FP32
-    # rows: three points per thread
+    # rows longer than 256 points go through the chunked rows kernel (256 interfaces per
+    # chunk): a last chunk of one interface (257), full chunks (512), five chunks (1100),
+    # ragged last chunks (320, 580, 600, 513), FP64 and FP32
     case(f"long rows {shape} {precision}")
     plan, ph, rho, vel, p = setup(orc, shape, mu=0.02, kind="smooth", precision=precision)
     u_ref = orc.init_state(rho, vel, p)
@@ -383,7 +384,11 @@ def test_long_rows(orc, shape, precision):
     r_ref = orc.rhs(u_ref, ph)
     err = rel_max(plan.rhs(u).double().cpu().numpy(), r_ref)
     if precision == "fp64":
-        tol, tol_rk = 1e-12, 1e-11
+        # on this smooth field the rounding noise of the x differences grows as nx^2: the
+        # oracle built with and without fused multiply-adds differs by 8e-19 nx^2 (9.7e-13
+        # at 1100 points, 3.3e-12 at 2048); three times that, and never below 1e-12
+        tol = max(1e-12, 2.4e-18 * shape[2] ** 2)
+        tol_rk = 10 * tol
     else:
         # FP32 rounding of the point values, amplified by the 1/h of the differences:
         # about 2^-24 max|u| / (h_min max|rhs|), with a factor 100 for the stencil weights

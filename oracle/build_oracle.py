@@ -1,5 +1,8 @@
 """Compile the CPU oracle (plain C, gcc) into ``oracle/libcns_oracle.so``.
 
+``cns_oracle_cs.c`` compiles the oracle's arithmetic a second time in complex
+numbers for complex-step derivatives; both go into the one library.
+
 Test infrastructure: the oracle is loaded only by the tests, the smoke check
 and the benchmark's CPU-baseline leg.  Built with ``-O2 -ffp-contract=off``
 (no fused multiply-add, so every product is rounded as written) and OpenMP
@@ -17,6 +20,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cns_oracle.c")
+SRC_CS = os.path.join(HERE, "cns_oracle_cs.c")  # the same arithmetic in complex numbers
 LIB = os.path.join(HERE, "libcns_oracle.so")
 
 
@@ -24,7 +28,7 @@ def build(verbose: bool = False, native: bool = False, out: str | None = None) -
     out = out or LIB
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-Wno-unused-parameter"] + (["-march=native"] if native else []) + \
-          ["-o", out + ".tmp", SRC, "-lm"]
+          ["-o", out + ".tmp", SRC, SRC_CS, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

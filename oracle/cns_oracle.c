@@ -30,6 +30,19 @@
 #include <omp.h>
 #endif
 
+/* Scalar type of everything that depends on the state.  As it stands this file is
+ * the FP64 oracle.  cns_oracle_cs.c compiles it a second time with a complex type
+ * (complex-step derivatives): it defines ORC_REAL, the three helpers below and new
+ * names for the exported functions before including this file.  ORC_RE takes the
+ * real part wherever the method compares or tests a value. */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#define ORC_SQRT sqrt
+#define ORC_ABS fabs
+#define ORC_RE(x) (x)
+#endif
+typedef ORC_REAL real;
+
 /* ------------------------------------------------------------------------- */
 /* grid helpers                                                              */
 /* ------------------------------------------------------------------------- */
@@ -70,21 +83,21 @@ static int check_grid(const orc_grid *g, const orc_phys *ph) {
 }
 
 /* gather the conserved state at linear index p */
-static void load_state(const double *u, size_t n3, size_t p, double s[5]) {
+static void load_state(const real *u, size_t n3, size_t p, real s[5]) {
     for (int v = 0; v < 5; ++v) s[v] = u[(size_t)v * n3 + p];
 }
 
 /* Sec. 2.1: primitive variables from the conserved state; e = p/(gamma-1) + rho|v|^2/2 */
-static int primitives(const double s[5], double gamma, double vel[3], double *p, double *T) {
-    double rho = s[0];
+static int primitives(const real s[5], double gamma, real vel[3], real *p, real *T) {
+    real rho = s[0];
     vel[0] = s[1] / rho;
     vel[1] = s[2] / rho;
     vel[2] = s[3] / rho;
-    double q2 = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
+    real q2 = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
     *p = (gamma - 1.0) * (s[4] - 0.5 * rho * q2);
     *T = gamma * (*p) / rho; /* T = gamma p / rho (Sec. 2.1, heat flux) */
-    if (!isfinite(rho) || !isfinite(*p) || !isfinite(q2)) return ORC_ENONFINITE;
-    if (!(rho > 0.0) || !(*p > 0.0)) return ORC_ENONPHYSICAL;
+    if (!isfinite(ORC_RE(rho)) || !isfinite(ORC_RE(*p)) || !isfinite(ORC_RE(q2))) return ORC_ENONFINITE;
+    if (!(ORC_RE(rho) > 0.0) || !(ORC_RE(*p) > 0.0)) return ORC_ENONPHYSICAL;
     return ORC_OK;
 }
 
@@ -92,23 +105,23 @@ static int primitives(const double s[5], double gamma, double vel[3], double *p,
 /* Sec. 2.2: WENO5 (three third-order candidates, optimal weights 1/10, 6/10, */
 /* 3/10, Jiang-Shu smoothness indicators, alpha_k = c_k/(eps+beta_k)^2)       */
 /* ------------------------------------------------------------------------- */
-double oracle_weno5(double a, double b, double c, double d, double e, double eps, double *parts) {
+real oracle_weno5(real a, real b, real c, real d, real e, double eps, real *parts) {
     /* a..e = f_{j-2}, f_{j-1}, f_j, f_{j+1}, f_{j+2} */
-    double fhat1 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
-    double fhat2 = -(1.0 / 6.0) * b + (5.0 / 6.0) * c + (1.0 / 3.0) * d;
-    double fhat3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+    real fhat1 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+    real fhat2 = -(1.0 / 6.0) * b + (5.0 / 6.0) * c + (1.0 / 3.0) * d;
+    real fhat3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
 
-    double beta1 = (13.0 / 12.0) * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
-                   0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
-    double beta2 = (13.0 / 12.0) * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
-    double beta3 = (13.0 / 12.0) * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
-                   0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
+    real beta1 = (13.0 / 12.0) * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
+                 0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
+    real beta2 = (13.0 / 12.0) * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
+    real beta3 = (13.0 / 12.0) * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
+                 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
 
-    double alpha1 = 0.1 / ((eps + beta1) * (eps + beta1));
-    double alpha2 = 0.6 / ((eps + beta2) * (eps + beta2));
-    double alpha3 = 0.3 / ((eps + beta3) * (eps + beta3));
-    double asum = alpha1 + alpha2 + alpha3;
-    double w1 = alpha1 / asum, w2 = alpha2 / asum, w3 = alpha3 / asum;
+    real alpha1 = 0.1 / ((eps + beta1) * (eps + beta1));
+    real alpha2 = 0.6 / ((eps + beta2) * (eps + beta2));
+    real alpha3 = 0.3 / ((eps + beta3) * (eps + beta3));
+    real asum = alpha1 + alpha2 + alpha3;
+    real w1 = alpha1 / asum, w2 = alpha2 / asum, w3 = alpha3 / asum;
 
     if (parts) {
         parts[0] = beta1;
@@ -130,24 +143,24 @@ double oracle_weno5(double a, double b, double c, double d, double e, double eps
 /* and smoothness indicators, alpha_k = c_k (1 + (tau5/(eps+beta_k))^2) with  */
 /* the global indicator tau5 = |beta_1 - beta_3|.                             */
 /* ------------------------------------------------------------------------- */
-double oracle_weno5z(double a, double b, double c, double d, double e, double eps, double *parts) {
-    double fhat1 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
-    double fhat2 = -(1.0 / 6.0) * b + (5.0 / 6.0) * c + (1.0 / 3.0) * d;
-    double fhat3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+real oracle_weno5z(real a, real b, real c, real d, real e, double eps, real *parts) {
+    real fhat1 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+    real fhat2 = -(1.0 / 6.0) * b + (5.0 / 6.0) * c + (1.0 / 3.0) * d;
+    real fhat3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
 
-    double beta1 = (13.0 / 12.0) * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
-                   0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
-    double beta2 = (13.0 / 12.0) * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
-    double beta3 = (13.0 / 12.0) * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
-                   0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
-    double tau5 = fabs(beta1 - beta3);
+    real beta1 = (13.0 / 12.0) * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
+                 0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
+    real beta2 = (13.0 / 12.0) * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
+    real beta3 = (13.0 / 12.0) * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
+                 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
+    real tau5 = ORC_ABS(beta1 - beta3);
 
-    double r1 = tau5 / (eps + beta1), r2 = tau5 / (eps + beta2), r3 = tau5 / (eps + beta3);
-    double alpha1 = 0.1 * (1.0 + r1 * r1);
-    double alpha2 = 0.6 * (1.0 + r2 * r2);
-    double alpha3 = 0.3 * (1.0 + r3 * r3);
-    double asum = alpha1 + alpha2 + alpha3;
-    double w1 = alpha1 / asum, w2 = alpha2 / asum, w3 = alpha3 / asum;
+    real r1 = tau5 / (eps + beta1), r2 = tau5 / (eps + beta2), r3 = tau5 / (eps + beta3);
+    real alpha1 = 0.1 * (1.0 + r1 * r1);
+    real alpha2 = 0.6 * (1.0 + r2 * r2);
+    real alpha3 = 0.3 * (1.0 + r3 * r3);
+    real asum = alpha1 + alpha2 + alpha3;
+    real w1 = alpha1 / asum, w2 = alpha2 / asum, w3 = alpha3 / asum;
 
     if (parts) {
         parts[0] = beta1;
@@ -169,20 +182,20 @@ double oracle_weno5z(double a, double b, double c, double d, double e, double ep
 /* Shu weights w_k pass through g_k(w) = w (d_k + d_k^2 - 3 d_k w + w^2) /    */
 /* (d_k^2 + w (1 - 2 d_k)), d_k the optimal weight, and are renormalised.      */
 /* ------------------------------------------------------------------------- */
-double oracle_weno_map(double w, double d) {
+real oracle_weno_map(real w, double d) {
     return w * (d + d * d - 3.0 * d * w + w * w) / (d * d + w * (1.0 - 2.0 * d));
 }
 
-double oracle_weno5m(double a, double b, double c, double d, double e, double eps, double *parts) {
-    double js[9];
+real oracle_weno5m(real a, real b, real c, real d, real e, double eps, real *parts) {
+    real js[9];
     oracle_weno5(a, b, c, d, e, eps, js); /* candidates, indicators, Jiang-Shu weights */
     const double dk[3] = {0.1, 0.6, 0.3};
-    double g[3], gsum = 0.0;
+    real g[3], gsum = 0.0;
     for (int k = 0; k < 3; ++k) {
         g[k] = oracle_weno_map(js[3 + k], dk[k]);
         gsum += g[k];
     }
-    double w[3];
+    real w[3];
     for (int k = 0; k < 3; ++k) w[k] = g[k] / gsum;
     if (parts) {
         for (int k = 0; k < 3; ++k) {
@@ -197,11 +210,11 @@ double oracle_weno5m(double a, double b, double c, double d, double e, double ep
 /* ------------------------------------------------------------------------- */
 /* Sec. 2.1: convective fluxes f, g, h                                        */
 /* ------------------------------------------------------------------------- */
-void oracle_flux(const double *u, int dir, double gamma, double *f) {
-    double rho = u[0];
-    double vel[3] = {u[1] / rho, u[2] / rho, u[3] / rho};
-    double p = (gamma - 1.0) * (u[4] - 0.5 * rho * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]));
-    double vn = vel[dir];
+void oracle_flux(const real *u, int dir, double gamma, real *f) {
+    real rho = u[0];
+    real vel[3] = {u[1] / rho, u[2] / rho, u[3] / rho};
+    real p = (gamma - 1.0) * (u[4] - 0.5 * rho * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]));
+    real vn = vel[dir];
     f[0] = rho * vn;
     f[1] = rho * vel[0] * vn;
     f[2] = rho * vel[1] * vn;
@@ -213,32 +226,32 @@ void oracle_flux(const double *u, int dir, double gamma, double *f) {
 /* ------------------------------------------------------------------------- */
 /* Sec. 2.2: Roe-averaged eigensystem |A| = X |Lambda| X^{-1}                 */
 /* ------------------------------------------------------------------------- */
-int oracle_roe_eigensystem(const double *uL, const double *uR, int dir, double gamma, double *X,
-                           double *Xinv, double *lam) {
-    double vL[3], vR[3], pL, pR, TL, TR;
+int oracle_roe_eigensystem(const real *uL, const real *uR, int dir, double gamma, real *X, real *Xinv,
+                           real *lam) {
+    real vL[3], vR[3], pL, pR, TL, TR;
     int rc = primitives(uL, gamma, vL, &pL, &TL);
     if (rc) return rc;
     rc = primitives(uR, gamma, vR, &pR, &TR);
     if (rc) return rc;
-    double HL = (uL[4] + pL) / uL[0]; /* total enthalpy (e + p)/rho */
-    double HR = (uR[4] + pR) / uR[0];
+    real HL = (uL[4] + pL) / uL[0]; /* total enthalpy (e + p)/rho */
+    real HR = (uR[4] + pR) / uR[0];
 
     /* Roe average: sqrt(rho)-weighted velocity and enthalpy */
-    double Rr = sqrt(uR[0] / uL[0]);
-    double v[3];
+    real Rr = ORC_SQRT(uR[0] / uL[0]);
+    real v[3];
     for (int c = 0; c < 3; ++c) v[c] = (vL[c] + Rr * vR[c]) / (1.0 + Rr);
-    double H = (HL + Rr * HR) / (1.0 + Rr);
-    double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    double c2 = (gamma - 1.0) * (H - 0.5 * q2);
-    if (!isfinite(c2)) return ORC_ENONFINITE;
-    if (!(c2 > 0.0)) return ORC_ENONPHYSICAL;
-    double c = sqrt(c2);
+    real H = (HL + Rr * HR) / (1.0 + Rr);
+    real q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    real c2 = (gamma - 1.0) * (H - 0.5 * q2);
+    if (!isfinite(ORC_RE(c2))) return ORC_ENONFINITE;
+    if (!(ORC_RE(c2) > 0.0)) return ORC_ENONPHYSICAL;
+    real c = ORC_SQRT(c2);
 
     int n = dir, t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;
-    double vn = v[n];
+    real vn = v[n];
 
-    memset(X, 0, 25 * sizeof(double));
-    memset(Xinv, 0, 25 * sizeof(double));
+    memset(X, 0, 25 * sizeof(real));
+    memset(Xinv, 0, 25 * sizeof(real));
 #define XS(r, col) X[(r)*5 + (col)]
 #define LS(r, col) Xinv[(r)*5 + (col)]
     /* column 0: acoustic wave vn - c */
@@ -262,8 +275,8 @@ int oracle_roe_eigensystem(const double *uL, const double *uR, int dir, double g
     XS(4, 4) = H + vn * c;
 
     /* rows of X^{-1}: left eigenvectors */
-    double b1 = (gamma - 1.0) / c2;
-    double b2 = 0.5 * q2 * b1;
+    real b1 = (gamma - 1.0) / c2;
+    real b2 = 0.5 * q2 * b1;
     LS(0, 0) = 0.5 * (b2 + vn / c);
     for (int k = 0; k < 3; ++k) LS(0, 1 + k) = -0.5 * b1 * v[k];
     LS(0, 1 + n) -= 0.5 / c;
@@ -293,24 +306,24 @@ int oracle_roe_eigensystem(const double *uL, const double *uR, int dir, double g
     return ORC_OK;
 }
 
-double oracle_harten(double lam, double delta) {
-    double a = fabs(lam);
-    if (a >= delta) return a;
+real oracle_harten(real lam, double delta) {
+    real a = ORC_ABS(lam);
+    if (ORC_RE(a) >= delta) return a;
     return (lam * lam + delta * delta) / (2.0 * delta);
 }
 
 /* ------------------------------------------------------------------------- */
 /* Sec. 2.2 eq. (Roe): F = (f^L + f^R)/2 - |A| (u^R - u^L)/2 at j+1/2         */
 /* ------------------------------------------------------------------------- */
-int oracle_interface_flux(const double *s, int dir, const orc_phys *ph, double *F) {
+int oracle_interface_flux(const real *s, int dir, const orc_phys *ph, real *F) {
     const double gamma = ph->gamma, eps = ph->weno_eps;
-    double (*W)(double, double, double, double, double, double, double *) =
+    real (*W)(real, real, real, real, real, double, real *) =
         ph->weno_weights == ORC_WENO_Z ? oracle_weno5z : (ph->weno_weights == ORC_WENO_M ? oracle_weno5m : oracle_weno5);
-    double f[6][5];
+    real f[6][5];
     for (int m = 0; m < 6; ++m) oracle_flux(s + 5 * m, dir, gamma, f[m]);
 
     /* component-wise WENO5: left-biased from j-2..j+2, right-biased = mirror (j+3..j-1) */
-    double fL[5], fR[5], uL[5], uR[5];
+    real fL[5], fR[5], uL[5], uR[5];
     for (int v = 0; v < 5; ++v) {
         fL[v] = W(f[0][v], f[1][v], f[2][v], f[3][v], f[4][v], eps, NULL);
         fR[v] = W(f[5][v], f[4][v], f[3][v], f[2][v], f[1][v], eps, NULL);
@@ -319,33 +332,33 @@ int oracle_interface_flux(const double *s, int dir, const orc_phys *ph, double *
     }
 
     /* eigensystem at the Roe average of the cell states u_j (m=2) and u_{j+1} (m=3) */
-    double X[25], Xinv[25], lam[5];
+    real X[25], Xinv[25], lam[5];
     int rc = oracle_roe_eigensystem(s + 10, s + 15, dir, gamma, X, Xinv, lam);
     if (rc) return rc;
 
-    double du[5], w[5], diss[5];
+    real du[5], w[5], diss[5];
     for (int v = 0; v < 5; ++v) du[v] = uR[v] - uL[v];
     for (int r = 0; r < 5; ++r) {
-        double acc = 0.0;
+        real acc = 0.0;
         for (int col = 0; col < 5; ++col) acc += Xinv[r * 5 + col] * du[col];
         w[r] = oracle_harten(lam[r], ph->harten_delta) * acc;
     }
     for (int r = 0; r < 5; ++r) {
-        double acc = 0.0;
+        real acc = 0.0;
         for (int col = 0; col < 5; ++col) acc += X[r * 5 + col] * w[col];
         diss[r] = acc;
     }
     for (int v = 0; v < 5; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * diss[v];
     for (int v = 0; v < 5; ++v)
-        if (!isfinite(F[v])) return ORC_ENONFINITE;
+        if (!isfinite(ORC_RE(F[v]))) return ORC_ENONFINITE;
     return ORC_OK;
 }
 
 /* interface flux at (i,j,k) + 1/2 along dir */
-static int interface_at(const orc_grid *g, const orc_phys *ph, const double *u, int i, int j, int k, int dir,
-                        double F[5]) {
+static int interface_at(const orc_grid *g, const orc_phys *ph, const real *u, int i, int j, int k, int dir,
+                        real F[5]) {
     size_t n3 = npts(g);
-    double s[30];
+    real s[30];
     for (int m = 0; m < 6; ++m) load_state(u, n3, shifted(g, i, j, k, dir, m - 2), s + 5 * m);
     return oracle_interface_flux(s, dir, ph, F);
 }
@@ -353,19 +366,19 @@ static int interface_at(const orc_grid *g, const orc_phys *ph, const double *u, 
 /* ------------------------------------------------------------------------- */
 /* Sec. 2.2 conservative finite difference along one direction               */
 /* ------------------------------------------------------------------------- */
-int oracle_rhs_hyp_dir(const orc_grid *g, const orc_phys *ph, const double *u, int dir, double *out) {
+int oracle_rhs_hyp_dir(const orc_grid *g, const orc_phys *ph, const real *u, int dir, real *out) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
     if (dir < 0 || dir > 2 || !u || !out) return ORC_EINVAL;
     size_t n3 = npts(g);
-    double *Fh = (double *)malloc(5 * n3 * sizeof(double)); /* F_{p+1/2} stored at point p */
+    real *Fh = (real *)malloc(5 * n3 * sizeof(real)); /* F_{p+1/2} stored at point p */
     if (!Fh) return ORC_EINVAL;
     int err = 0;
 #pragma omp parallel for collapse(2) reduction(min : err)
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
-                double F[5];
+                real F[5];
                 int r = interface_at(g, ph, u, i, j, k, dir, F);
                 if (r < err) err = r;
                 size_t p = lin(g, i, j, k);
@@ -393,13 +406,13 @@ int oracle_rhs_hyp_dir(const orc_grid *g, const orc_phys *ph, const double *u, i
 /* Sec. 2.1 viscous fluxes with 4th-order central first derivatives         */
 /* ------------------------------------------------------------------------- */
 /* 5-point 4th-order central first derivative of a point function phi along dir */
-static double central_d(double pm2, double pm1, double pp1, double pp2, double h) {
+static real central_d(real pm2, real pm1, real pp1, real pp2, double h) {
     return (8.0 * (pp1 - pm1) - (pp2 - pm2)) / (12.0 * h);
 }
 
 /* velocity and temperature at linear index p */
-static int vel_temp_at(const double *u, size_t n3, size_t p, double gamma, double w[4]) {
-    double s[5], vel[3], pr, T;
+static int vel_temp_at(const real *u, size_t n3, size_t p, double gamma, real w[4]) {
+    real s[5], vel[3], pr, T;
     load_state(u, n3, p, s);
     int rc = primitives(s, gamma, vel, &pr, &T);
     w[0] = vel[0];
@@ -410,16 +423,15 @@ static int vel_temp_at(const double *u, size_t n3, size_t p, double gamma, doubl
 }
 
 /* viscous fluxes G^v_d (d = x, y, z; five components each) at point (i,j,k) */
-static int gvisc_at(const orc_grid *g, const orc_phys *ph, const double *u, int i, int j, int k,
-                    double G[3][5]) {
+static int gvisc_at(const orc_grid *g, const orc_phys *ph, const real *u, int i, int j, int k, real G[3][5]) {
     size_t n3 = npts(g);
-    double w0[4];
+    real w0[4];
     int rc = vel_temp_at(u, n3, lin(g, i, j, k), ph->gamma, w0);
     if (rc) return rc;
     /* grad[a][b] = d(w_a)/dx_b, a over (u, v, w, T) */
-    double grad[4][3];
+    real grad[4][3];
     for (int b = 0; b < 3; ++b) {
-        double wm2[4], wm1[4], wp1[4], wp2[4];
+        real wm2[4], wm1[4], wp1[4], wp2[4];
         rc = vel_temp_at(u, n3, shifted(g, i, j, k, b, -2), ph->gamma, wm2);
         if (!rc) rc = vel_temp_at(u, n3, shifted(g, i, j, k, b, -1), ph->gamma, wm1);
         if (!rc) rc = vel_temp_at(u, n3, shifted(g, i, j, k, b, 1), ph->gamma, wp1);
@@ -429,14 +441,14 @@ static int gvisc_at(const orc_grid *g, const orc_phys *ph, const double *u, int 
         for (int a = 0; a < 4; ++a) grad[a][b] = central_d(wm2[a], wm1[a], wp1[a], wp2[a], h);
     }
     const double mu = ph->mu_eff;
-    double divv = grad[0][0] + grad[1][1] + grad[2][2];
-    double tau[3][3];
+    real divv = grad[0][0] + grad[1][1] + grad[2][2];
+    real tau[3][3];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
             tau[a][b] = mu * ((grad[a][b] + grad[b][a]) - (a == b ? (2.0 / 3.0) * divv : 0.0));
     double kcond = mu / ((ph->gamma - 1.0) * ph->prandtl);
     for (int d = 0; d < 3; ++d) {
-        double q = -kcond * grad[3][d];
+        real q = -kcond * grad[3][d];
         G[d][0] = 0.0;
         G[d][1] = tau[0][d];
         G[d][2] = tau[1][d];
@@ -446,24 +458,24 @@ static int gvisc_at(const orc_grid *g, const orc_phys *ph, const double *u, int 
     return ORC_OK;
 }
 
-int oracle_viscous(const orc_grid *g, const orc_phys *ph, const double *u, double *out) {
+int oracle_viscous(const orc_grid *g, const orc_phys *ph, const real *u, real *out) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
     if (!u || !out) return ORC_EINVAL;
     size_t n3 = npts(g);
     if (ph->mu_eff == 0.0) {
-        memset(out, 0, 5 * n3 * sizeof(double));
+        memset(out, 0, 5 * n3 * sizeof(real));
         return ORC_OK;
     }
     /* G[d][v][p] */
-    double *G = (double *)malloc(15 * n3 * sizeof(double));
+    real *G = (real *)malloc(15 * n3 * sizeof(real));
     if (!G) return ORC_EINVAL;
     int err = 0;
 #pragma omp parallel for collapse(2) reduction(min : err)
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
-                double Gp[3][5];
+                real Gp[3][5];
                 int r = gvisc_at(g, ph, u, i, j, k, Gp);
                 if (r < err) err = r;
                 size_t p = lin(g, i, j, k);
@@ -480,9 +492,9 @@ int oracle_viscous(const orc_grid *g, const orc_phys *ph, const double *u, doubl
             for (int i = 0; i < g->nx; ++i) {
                 size_t p = lin(g, i, j, k);
                 for (int v = 0; v < 5; ++v) {
-                    double acc = 0.0;
+                    real acc = 0.0;
                     for (int d = 0; d < 3; ++d) {
-                        const double *Gd = G + ((size_t)d * 5 + v) * n3;
+                        const real *Gd = G + ((size_t)d * 5 + v) * n3;
                         acc += central_d(Gd[shifted(g, i, j, k, d, -2)], Gd[shifted(g, i, j, k, d, -1)],
                                          Gd[shifted(g, i, j, k, d, 1)], Gd[shifted(g, i, j, k, d, 2)],
                                          spacing(g, d));
@@ -497,12 +509,12 @@ int oracle_viscous(const orc_grid *g, const orc_phys *ph, const double *u, doubl
 /* ------------------------------------------------------------------------- */
 /* full right-hand side: du/dt = -(D_x f + D_y g + D_z h) + sum_d D_d G^v_d  */
 /* ------------------------------------------------------------------------- */
-int oracle_rhs(const orc_grid *g, const orc_phys *ph, const double *u, double *out) {
+int oracle_rhs(const orc_grid *g, const orc_phys *ph, const real *u, real *out) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
     if (!u || !out) return ORC_EINVAL;
     size_t n3 = npts(g);
-    double *tmp = (double *)malloc(5 * n3 * sizeof(double));
+    real *tmp = (real *)malloc(5 * n3 * sizeof(real));
     if (!tmp) return ORC_EINVAL;
     rc = oracle_rhs_hyp_dir(g, ph, u, 0, out);
     for (int d = 1; d < 3 && !rc; ++d) {
@@ -519,6 +531,7 @@ int oracle_rhs(const orc_grid *g, const orc_phys *ph, const double *u, double *o
     return rc;
 }
 
+#ifndef ORC_COMPLEX_STEP
 int oracle_rhs_point(const orc_grid *g, const orc_phys *ph, const double *u, int i, int j, int k, double *out5) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
@@ -567,25 +580,27 @@ int oracle_rhs_point(const orc_grid *g, const orc_phys *ph, const double *u, int
     for (int v = 0; v < 5; ++v) out5[v] = acc[v];
     return ORC_OK;
 }
+#endif
 
 /* ------------------------------------------------------------------------- */
 /* diagnostics: kinetic energy, enstrophy, means, max wave speed, bad points */
 /* ------------------------------------------------------------------------- */
-int oracle_diag(const orc_grid *g, const orc_phys *ph, const double *u, double *out) {
+int oracle_diag(const orc_grid *g, const orc_phys *ph, const real *u, real *out) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
     if (!u || !out) return ORC_EINVAL;
     size_t n3 = npts(g);
-    double K = 0, Om = 0, mr = 0, mm[3] = {0, 0, 0}, me = 0, smax = 0, bad = 0;
+    real K = 0, Om = 0, mr = 0, mm[3] = {0, 0, 0}, me = 0, smax = 0;
+    double bad = 0;
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 size_t p = lin(g, i, j, k);
-                double s[5], vel[3], pr, T;
+                real s[5], vel[3], pr, T;
                 load_state(u, n3, p, s);
                 int r = primitives(s, ph->gamma, vel, &pr, &T);
                 int finite = 1;
-                for (int v = 0; v < 5; ++v) finite = finite && isfinite(s[v]);
+                for (int v = 0; v < 5; ++v) finite = finite && isfinite(ORC_RE(s[v]));
                 if (r || !finite) {
                     bad += 1.0;
                     continue;
@@ -596,16 +611,16 @@ int oracle_diag(const orc_grid *g, const orc_phys *ph, const double *u, double *
                 mm[1] += s[2];
                 mm[2] += s[3];
                 me += s[4];
-                double c = sqrt(ph->gamma * pr / s[0]);
+                real c = ORC_SQRT(ph->gamma * pr / s[0]);
                 for (int d = 0; d < 3; ++d) {
-                    double sp = fabs(vel[d]) + c;
-                    if (sp > smax) smax = sp;
+                    real sp = ORC_ABS(vel[d]) + c;
+                    if (ORC_RE(sp) > ORC_RE(smax)) smax = sp;
                 }
                 /* vorticity from the 4th-order central derivative */
-                double dv[3][3]; /* dv[a][b] = d v_a / d x_b */
+                real dv[3][3]; /* dv[a][b] = d v_a / d x_b */
                 int ok = 1;
                 for (int b = 0; b < 3 && ok; ++b) {
-                    double w[4][4];
+                    real w[4][4];
                     const int offs[4] = {-2, -1, 1, 2};
                     for (int o = 0; o < 4; ++o)
                         if (vel_temp_at(u, n3, shifted(g, i, j, k, b, offs[o]), ph->gamma, w[o])) ok = 0;
@@ -613,9 +628,9 @@ int oracle_diag(const orc_grid *g, const orc_phys *ph, const double *u, double *
                     for (int a = 0; a < 3; ++a) dv[a][b] = central_d(w[0][a], w[1][a], w[2][a], w[3][a], h);
                 }
                 if (!ok) continue; /* a neighbour is bad: counted at that neighbour */
-                double ox = dv[2][1] - dv[1][2];
-                double oy = dv[0][2] - dv[2][0];
-                double oz = dv[1][0] - dv[0][1];
+                real ox = dv[2][1] - dv[1][2];
+                real oy = dv[0][2] - dv[2][0];
+                real oz = dv[1][0] - dv[0][1];
                 Om += 0.5 * (ox * ox + oy * oy + oz * oz);
             }
     double inv = 1.0 / (double)n3;
@@ -634,16 +649,16 @@ int oracle_diag(const orc_grid *g, const orc_phys *ph, const double *u, double *
 /* ------------------------------------------------------------------------- */
 /* classical RK4                                                             */
 /* ------------------------------------------------------------------------- */
-int oracle_rk4(const orc_grid *g, const orc_phys *ph, double *u, double dt, int nsteps, double *diag) {
+int oracle_rk4(const orc_grid *g, const orc_phys *ph, real *u, double dt, int nsteps, real *diag) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
     if (!u || !(dt > 0.0) || nsteps < 0) return ORC_EINVAL;
     size_t n5 = 5 * npts(g);
-    double *k1 = (double *)malloc(n5 * sizeof(double));
-    double *k2 = (double *)malloc(n5 * sizeof(double));
-    double *k3 = (double *)malloc(n5 * sizeof(double));
-    double *k4 = (double *)malloc(n5 * sizeof(double));
-    double *U = (double *)malloc(n5 * sizeof(double));
+    real *k1 = (real *)malloc(n5 * sizeof(real));
+    real *k2 = (real *)malloc(n5 * sizeof(real));
+    real *k3 = (real *)malloc(n5 * sizeof(real));
+    real *k4 = (real *)malloc(n5 * sizeof(real));
+    real *U = (real *)malloc(n5 * sizeof(real));
     if (!k1 || !k2 || !k3 || !k4 || !U) {
         free(k1), free(k2), free(k3), free(k4), free(U);
         return ORC_EINVAL;
@@ -663,7 +678,7 @@ int oracle_rk4(const orc_grid *g, const orc_phys *ph, double *u, double dt, int 
         for (size_t q = 0; q < n5; ++q) u[q] = u[q] + (dt / 6.0) * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
         if (diag) {
             rc = oracle_diag(g, ph, u, diag + (size_t)n * ORC_NDIAG);
-            if (!rc && diag[(size_t)n * ORC_NDIAG + 8] > 0) rc = ORC_ENONFINITE;
+            if (!rc && ORC_RE(diag[(size_t)n * ORC_NDIAG + 8]) > 0) rc = ORC_ENONFINITE;
         }
     }
     free(k1), free(k2), free(k3), free(k4), free(U);
@@ -673,14 +688,14 @@ int oracle_rk4(const orc_grid *g, const orc_phys *ph, double *u, double dt, int 
 /* ------------------------------------------------------------------------- */
 /* third-order TVD Runge-Kutta (Shu-Osher), the paper's production scheme    */
 /* ------------------------------------------------------------------------- */
-int oracle_tvdrk3(const orc_grid *g, const orc_phys *ph, double *u, double dt, int nsteps, double *diag) {
+int oracle_tvdrk3(const orc_grid *g, const orc_phys *ph, real *u, double dt, int nsteps, real *diag) {
     int rc = check_grid(g, ph);
     if (rc) return rc;
     if (!u || !(dt > 0.0) || nsteps < 0) return ORC_EINVAL;
     size_t n5 = 5 * npts(g);
-    double *k = (double *)malloc(n5 * sizeof(double));
-    double *U1 = (double *)malloc(n5 * sizeof(double));
-    double *U2 = (double *)malloc(n5 * sizeof(double));
+    real *k = (real *)malloc(n5 * sizeof(real));
+    real *U1 = (real *)malloc(n5 * sizeof(real));
+    real *U2 = (real *)malloc(n5 * sizeof(real));
     if (!k || !U1 || !U2) {
         free(k), free(U1), free(U2);
         return ORC_EINVAL;
@@ -700,13 +715,14 @@ int oracle_tvdrk3(const orc_grid *g, const orc_phys *ph, double *u, double dt, i
         for (size_t q = 0; q < n5; ++q) u[q] = (1.0 / 3.0) * u[q] + (2.0 / 3.0) * (U2[q] + dt * k[q]);
         if (diag) {
             rc = oracle_diag(g, ph, u, diag + (size_t)n * ORC_NDIAG);
-            if (!rc && diag[(size_t)n * ORC_NDIAG + 8] > 0) rc = ORC_ENONFINITE;
+            if (!rc && ORC_RE(diag[(size_t)n * ORC_NDIAG + 8]) > 0) rc = ORC_ENONFINITE;
         }
     }
     free(k), free(U1), free(U2);
     return rc;
 }
 
+#ifndef ORC_COMPLEX_STEP
 int oracle_init_state(const orc_grid *g, double gamma, const double *rho, const double *vel, const double *p,
                       double *u) {
     int rc = check_grid(g, NULL);
@@ -732,3 +748,4 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+#endif

@@ -107,6 +107,17 @@ int oracle_init_state(const orc_grid *g, double gamma, const double *rho, const 
 /* threads used by the OpenMP loops (1 if built without OpenMP). */
 int oracle_num_threads(void);
 
+/* ---- complex-step derivatives (cns_oracle_cs.c) ---- */
+/* jvp = R'(u) d, the derivative of the right-hand side at u along d, as
+ * Im R(u + i h d) / h (h > 0, e.g. 1e-20); value (may be NULL) receives Re R(u + i h d). */
+int oracle_cs_rhs_jvp(const orc_grid *g, const orc_phys *ph, const double *u, const double *d, double h,
+                      double *jvp, double *value);
+/* Derivatives along d of nsteps time steps from u0 (scheme 0 = classical RK4, 1 =
+ * TVD-RK3): du (may be NULL) = d u_N / d u0 . d; dK (may be NULL) = the derivative of
+ * the final mean kinetic energy K(u_N); K (may be NULL) = K(u_N) itself. */
+int oracle_cs_step_jvp(const orc_grid *g, const orc_phys *ph, int scheme, const double *u0, const double *d,
+                       double dt, int nsteps, double h, double *du, double *dK, double *K);
+
 #ifdef __cplusplus
 }
 #endif

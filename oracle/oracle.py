@@ -69,6 +69,9 @@ def lib():
         L.oracle_tvdrk3.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, C.c_double, C.c_int, _dp]
         L.oracle_init_state.argtypes = [C.POINTER(Grid), C.c_double, _dp, _dp, _dp, _dp]
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_cs_rhs_jvp.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, _dp, C.c_double, _dp, _dp]
+        L.oracle_cs_step_jvp.argtypes = [C.POINTER(Grid), C.POINTER(Phys), C.c_int, _dp, _dp, C.c_double, C.c_int,
+                                         C.c_double, _dp, _dp, _dp]
         _LIB = L
     return _LIB
 
@@ -219,3 +222,38 @@ def diag(u, phys: Phys, length=(2 * math.pi,) * 3):
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+# ---- complex-step derivatives (cns_oracle_cs.c): the oracle's own arithmetic in
+# complex numbers, Im F(u + i h d) / h = F'(u) d to rounding ----
+CS_STEP = 1e-20
+
+
+def rhs_jvp_cs(u, d, phys: Phys, length=(2 * math.pi,) * 3, h=CS_STEP):
+    """``(R'(u) d, Re R(u + i h d))``: the derivative of the right-hand side along d."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    assert d.shape == u.shape
+    jvp = np.zeros_like(u)
+    val = np.zeros_like(u)
+    g = _grid_of(u, length)
+    _chk(lib().oracle_cs_rhs_jvp(C.byref(g), C.byref(phys), _ptr(u), _ptr(d), float(h), _ptr(jvp), _ptr(val)),
+         "cs_rhs_jvp")
+    return jvp, val
+
+
+def step_jvp_cs(u0, d, dt, nsteps, phys: Phys, scheme="rk4", length=(2 * math.pi,) * 3, h=CS_STEP):
+    """Derivatives along d of ``nsteps`` steps of ``scheme`` ("rk4" or "tvdrk3") from u0:
+    returns ``(du_N, dK, K)``, the final state's derivative, the derivative of the final
+    mean kinetic energy and that energy."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    assert d.shape == u0.shape
+    du = np.zeros_like(u0)
+    dK = C.c_double(0.0)
+    K = C.c_double(0.0)
+    g = _grid_of(u0, length)
+    sch = {"rk4": 0, "tvdrk3": 1}[scheme]
+    _chk(lib().oracle_cs_step_jvp(C.byref(g), C.byref(phys), sch, _ptr(u0), _ptr(d), float(dt), int(nsteps), float(h),
+                                  _ptr(du), C.pointer(dK), C.pointer(K)), "cs_step_jvp")
+    return du, dK.value, K.value

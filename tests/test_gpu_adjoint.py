@@ -196,6 +196,58 @@ def test_adjoint_tvdrk3_matches_reverse_mode_reference(orc, nsteps, ckpt):
     assert rel_max(g4.cpu().numpy(), ref) > 1e-8
 
 
+@pytest.mark.parametrize("mu,delta", [(0.02, 1e-6), (0.0, 0.5)])
+def test_rhs_vjp_against_complex_step(orc, mu, delta):
+    """<R'(u)^T w, d> from the GPU product against <w, R'(u) d> from the complex-step
+    derivative of the C oracle (its own arithmetic in complex numbers: exact to
+    rounding, no reverse-mode code involved)."""
+    case(f"rhs_vjp vs complex step mu={mu} delta={delta}")
+    shape = (12, 10, 14)
+    rho, vel, p = state(shape, seed=8)
+    plan = Plan(shape, mu_eff=mu, harten_delta=delta)
+    u = plan.init_state(rho, vel, p)
+    uh = orc.init_state(rho, vel, p)
+    ph = orc.make_phys(mu_eff=mu, harten_delta=delta)
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(uh.shape)
+    g = plan.rhs_vjp(u, torch.from_numpy(w).cuda()).cpu().numpy()
+    for k in range(3):
+        d = rng.standard_normal(uh.shape) * np.abs(uh).mean(axis=(1, 2, 3), keepdims=True)
+        jvp, _ = orc.rhs_jvp_cs(uh, d, ph)
+        lhs, rhs = float(np.sum(g * d)), float(np.sum(w * jvp))
+        print(f"  direction {k}: {lhs:.15e} vs {rhs:.15e} (rel {abs(lhs - rhs) / abs(rhs):.1e})")
+        assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "tvdrk3"])
+def test_adjoint_gradient_against_complex_step(orc, scheme):
+    """The checkpointed GPU gradient dK(u_N)/du0 along random directions against the
+    complex-step derivative of the oracle's own time steps."""
+    case(f"adjoint {scheme} vs complex step")
+    shape = (16, 16, 16)
+    mu, nsteps, ckpt = 0.02, 5, 2
+    rho, vel, p = state(shape, seed=9)
+    plan = Plan(shape, mu_eff=mu)
+    u0h = orc.init_state(rho, vel, p)
+    ph = orc.make_phys(mu_eff=mu)
+    dt = I.dt_from_speed(orc.diag(u0h, ph)[7], 16)
+    run = plan.adjoint_rk4 if scheme == "rk4" else plan.adjoint_tvdrk3
+    J, g = run(plan.init_state(rho, vel, p), dt, nsteps, ckpt)
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(12)
+    for k in range(3):
+        # smooth band-limited directions and white noise
+        if k < 2:
+            d = np.stack([orc.init_state(*I.hit_primitives(16, 200 + k, 0.3))[v] for v in range(5)])
+        else:
+            d = rng.standard_normal(u0h.shape) * np.abs(u0h).mean(axis=(1, 2, 3), keepdims=True)
+        _, dK, K = orc.step_jvp_cs(u0h, d, dt, nsteps, ph, scheme=scheme)
+        lhs = float(np.sum(g * d))
+        print(f"  direction {k}: {lhs:.15e} vs {dK:.15e} (rel {abs(lhs - dK) / abs(dK):.1e})")
+        assert float(J[0]) == pytest.approx(K, rel=1e-13)
+        assert lhs == pytest.approx(dK, rel=1e-11)
+
+
 def test_autograd_function_tvdrk3_16(orc):
     case("autograd Function tvdrk3 16^3")
     n, mu, nsteps = 16, 1.0 / 400, 6

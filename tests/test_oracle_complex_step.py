@@ -1,0 +1,133 @@
+"""Complex-step derivatives of the oracle (oracle/cns_oracle_cs.c) and the adjoint
+pins built on them.
+
+The complex build runs the oracle's own arithmetic on u + i h d (h = 1e-20): its real
+part must be the oracle's value bitwise, and its imaginary part / h the derivative
+along d, which central differences of the FP64 oracle approach quadratically in their
+step.  Those derivatives then pin the reverse-mode reference used for the GPU adjoint
+(oracle/torch_ref.py): <w, R'(u) d> = <R'(u)^T w, d> for the right-hand side and
+<dK/du0, d> = dK(d) through RK4 and TVD-RK3 steps, to rounding rather than to the 1e-7
+of a finite difference.
+"""
+import numpy as np
+import pytest
+
+from conftest import rel_max
+from paper_2211_16718_amd import inputs as I
+
+PHYS = [dict(mu_eff=0.02, harten_delta=1e-6, weno_weights=0), dict(mu_eff=0.0, harten_delta=0.5, weno_weights=0),
+        dict(mu_eff=0.01, harten_delta=1e-6, weno_weights=1), dict(mu_eff=0.01, harten_delta=1e-6, weno_weights=2)]
+
+
+def hit_state(orc, shape, seed=1):
+    n = max(shape)
+    rho, vel, p = I.hit_primitives(n, seed, 0.3)
+    nz, ny, nx = shape
+    rho, vel, p = (np.ascontiguousarray(a[..., :nz, :ny, :nx]) for a in (rho, vel, p))
+    return orc.init_state(rho, vel, p)
+
+
+def direction(u, seed):
+    # white noise scaled per variable: every stencil and every weight is excited
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(u.shape) * np.abs(u).mean(axis=(1, 2, 3), keepdims=True)
+
+
+@pytest.mark.parametrize("phys", PHYS)
+def test_real_part_is_the_oracle_and_derivative_is_linear(orc, phys):
+    u = hit_state(orc, (12, 10, 14))
+    d = direction(u, 0)
+    ph = orc.make_phys(**phys)
+    jvp, val = orc.rhs_jvp_cs(u, d, ph)
+    assert np.array_equal(val, orc.rhs(u, ph))
+    # a derivative is linear in its direction; imaginary parts of 1e-20 never feed back
+    assert rel_max(orc.rhs_jvp_cs(u, -2.0 * d, ph)[0], -2.0 * jvp) <= 1e-15
+    # additive up to the rounding of the three evaluations (differences of interface
+    # fluxes divided by h lose about two digits)
+    d2 = direction(u, 1)
+    both = orc.rhs_jvp_cs(u, d + d2, ph)[0]
+    assert rel_max(both, jvp + orc.rhs_jvp_cs(u, d2, ph)[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("phys", PHYS)
+def test_central_differences_converge_quadratically_to_the_complex_step(orc, phys):
+    # the error of (R(u + h d) - R(u - h d)) / 2h against the complex step falls by 100
+    # per decade of h: the complex step is the limit the differences converge to
+    u = hit_state(orc, (12, 10, 14))
+    d = direction(u, 2)
+    ph = orc.make_phys(**phys)
+    jvp, _ = orc.rhs_jvp_cs(u, d, ph)
+    errs = []
+    for h in (1e-5, 1e-6, 1e-7):
+        fd = (orc.rhs(u + h * d, ph) - orc.rhs(u - h * d, ph)) / (2 * h)
+        errs.append(rel_max(fd, jvp))
+    print("central-difference errors", errs)
+    assert errs[2] <= 1e-6
+    assert errs[1] <= errs[0] / 50 and errs[2] <= errs[1] / 50
+
+
+def test_step_derivative_against_central_differences(orc):
+    u = hit_state(orc, (10, 10, 10), seed=3)
+    d = direction(u, 3)
+    ph = orc.make_phys(mu_eff=0.02)
+    dt = I.dt_from_speed(orc.diag(u, ph)[7], 10)
+    for scheme, run in (("rk4", orc.rk4), ("tvdrk3", orc.tvdrk3)):
+        du, dK, K = orc.step_jvp_cs(u, d, dt, 3, ph, scheme=scheme)
+
+        def final(v):
+            return run(v, dt, 3, ph, with_diag=False)[0]
+
+        uN = final(u)
+        assert K == orc.diag(uN, ph)[0]
+        h = 1e-7
+        fd = (final(u + h * d) - final(u - h * d)) / (2 * h)
+        assert rel_max(fd, du) <= 1e-6, scheme
+        # K is a plain function of the final state: the chain rule through dK/du_N
+        rho, m = uN[0], uN[1:4]
+        dK_du = np.concatenate([(-0.5 * (m ** 2).sum(0) / rho ** 2)[None], m / rho, np.zeros((1,) + rho.shape)])
+        dK_du /= rho.size
+        assert dK == pytest.approx(float(np.sum(dK_du * du)), rel=1e-12), scheme
+
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tr():
+    from oracle import torch_ref
+
+    return torch_ref
+
+
+@pytest.mark.parametrize("phys", PHYS)
+def test_reverse_mode_reference_rhs_vjp_by_complex_step(orc, tr, phys):
+    u = hit_state(orc, (10, 9, 11), seed=5)
+    ph = orc.make_phys(**phys)
+    tph = tr.make_phys(mu=phys["mu_eff"], delta=phys["harten_delta"],
+                       weights={0: "js", 1: "z", 2: "m"}[phys["weno_weights"]])
+    rng = np.random.default_rng(7)
+    w = rng.standard_normal(u.shape)
+    g = tr.rhs_vjp(torch.from_numpy(u), torch.from_numpy(w), tph).numpy()
+    for k in range(3):
+        d = direction(u, 10 + k)
+        jvp, _ = orc.rhs_jvp_cs(u, d, ph)
+        lhs, rhs = float(np.sum(g * d)), float(np.sum(w * jvp))
+        assert lhs == pytest.approx(rhs, rel=1e-12), (k, lhs, rhs)
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "tvdrk3"])
+def test_reverse_mode_reference_gradient_by_complex_step(orc, tr, scheme):
+    u = hit_state(orc, (10, 10, 10), seed=6)
+    ph = orc.make_phys(mu_eff=0.02)
+    dt = I.dt_from_speed(orc.diag(u, ph)[7], 10)
+    nsteps = 3
+    run = orc.rk4 if scheme == "rk4" else orc.tvdrk3
+    uN, _ = run(u, dt, nsteps, ph, with_diag=False)
+    uNt = torch.from_numpy(uN).requires_grad_(True)
+    (seed,) = torch.autograd.grad(tr.kinetic_energy(uNt), uNt)
+    step = tr.rk4_step if scheme == "rk4" else tr.tvdrk3_step
+    g = tr.rk4_vjp(torch.from_numpy(u), seed, dt, nsteps, tr.make_phys(mu=0.02), step=step).numpy()
+    for k in range(3):
+        d = direction(u, 20 + k)
+        _, dK, _ = orc.step_jvp_cs(u, d, dt, nsteps, ph, scheme=scheme)
+        assert float(np.sum(g * d)) == pytest.approx(dK, rel=1e-12), (k, dK)

@@ -155,16 +155,42 @@ __device__ __forceinline__ void prim_at(gptr<const T> u, size_t n3, size_t i, T 
     W[3] = gamma * p * inv;
 }
 
+// The halo ring of a kViscTX x kViscTY tile in its (kViscTX + 4) x (kViscTY + 4) staging
+// plane: rows 0, 1, kViscTY + 2, kViscTY + 3 in full, then columns 0, 1, kViscTX + 2,
+// kViscTX + 3 of the rows between.  Thread t < kViscRing owns ring position t.
+constexpr int kViscRingRows = 4 * (kViscTX + 4);
+constexpr int kViscRing = kViscRingRows + 4 * kViscTY;
+static_assert(kViscRing <= kPointThreads && kViscRing <= kDiagThreads, "one halo point per thread");
+__device__ __forceinline__ void ring_pos(int t, int &hx, int &hy) {
+    if (t < kViscRingRows) {
+        const int r = t / (kViscTX + 4);
+        hx = t % (kViscTX + 4);
+        hy = r < 2 ? r : kViscTY + r;
+    } else {
+        const int q = t - kViscRingRows, c = q & 3;
+        hy = 2 + (q >> 2);
+        hx = c < 2 ? c : kViscTX + c;
+    }
+}
+
 // Viscous fluxes at points: the 12 first derivatives of (u, v, w, T) by the 5-point
 // central stencil, then tau, q and G.  A block owns a 32 x 8 (x, y) tile and marches
-// along z over kViscSZ planes: the primitives of the current plane, with a +-2 halo,
-// are formed from the state into LDS (x and y derivatives), and each thread keeps its
-// own column's primitives at planes k-2 .. k+2 in registers (z derivatives).  About
-// three primitive evaluations per point instead of thirteen, and no primitive array.
+// along z over kViscSZ planes.  Each thread keeps its own column's primitives at planes
+// k-2 .. k+2 in registers (z derivatives); a thread that owns a point of the tile's halo
+// ring keeps that point's primitives at planes k .. k+2 in its own LDS slots.  Plane k
+// is staged in LDS from the two windows (x and y derivatives).  Each state value of a
+// plane is loaded once per tile, and the column and the ring point of plane k+2 are
+// loaded together, while the neighbouring tiles (same XCD, launched together) load the
+// same lines for their own columns, so the halo comes from L2.
 template <typename T>
 __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
     const Launch L = with_params(L0);
     __shared__ T pl[4][kViscTY + 4][kViscTX + 4];
+    __shared__ T rw[3][4][kViscRing];  // ring primitives, slot (plane - z0) mod 3
+    int rhx, rhy;
+    ring_pos(threadIdx.x, rhx, rhy);
+    const bool ring = threadIdx.x < kViscRing;
+    const int rt = ring ? threadIdx.x : 0;
     const VbRange R = vb_range(L.total);
     for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
@@ -177,7 +203,10 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
         const int z0 = (int)(lb / ((long long)ntx * nty)) * kViscSZ, z1 = min(z0 + kViscSZ, nz);
         const int tx = threadIdx.x % kViscTX, ty = threadIdx.x / kViscTX;
         const bool act = x0 + tx < nx && y0 + ty < ny;
-        const size_t col = (size_t)min(y0 + ty, ny - 1) * nx + min(x0 + tx, nx - 1);
+        // a column past a ragged edge wraps periodically: its primitives are halo values
+        // of the active columns beside it
+        const size_t col = (size_t)wrapm(y0 + ty, ny) * nx + wrapm(x0 + tx, nx);
+        const size_t rcol = (size_t)wrapm(y0 - 2 + rhy, ny) * nx + wrapm(x0 - 2 + rhx, nx);
         const gptr<const T> u = glob((const T *)state_ptr(b, L, L.in));
         const gptr<T> G = glob((T *)b.G);
         const T gamma = T(b.gamma);
@@ -186,16 +215,29 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
         T Wz[5][4];  // this column's primitives at planes k-2 .. k+2
 #pragma unroll
         for (int m = 0; m < 4; ++m) prim_at(u, n3, col + wrapi(z0 - 2 + m, nz) * sz, gamma, Wz[m]);
-        for (int k = z0; k < z1; ++k) {
-            prim_at(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4]);
-            for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
-                const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
-                const size_t p = (size_t)k * sz + (size_t)wrapm(y0 - 2 + hy, ny) * nx + wrapm(x0 - 2 + hx, nx);
+        if (ring) {
+            for (int m = 0; m < 2; ++m) {
                 T w4[4];
-                prim_at(u, n3, p, gamma, w4);
+                prim_at(u, n3, rcol + wrapi(z0 + m, nz) * sz, gamma, w4);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) pl[c][hy][hx] = w4[c];
+                for (int c = 0; c < 4; ++c) rw[m][c][rt] = w4[c];
             }
+        }
+        int slot = 0;  // (k - z0) mod 3
+        for (int k = z0; k < z1; ++k) {
+            const int slot2 = slot == 0 ? 2 : slot - 1;  // (k + 2 - z0) mod 3
+            prim_at(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4]);
+            if (ring) {
+                T w4[4];
+                prim_at(u, n3, rcol + wrapi(k + 2, nz) * sz, gamma, w4);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    rw[slot2][c][rt] = w4[c];
+                    pl[c][rhy][rhx] = rw[slot][c][rt];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pl[c][ty + 2][tx + 2] = Wz[2][c];
             __syncthreads();
             if (act) {
                 T g[4][3];  // g[a][c] = d W_a / d x_c
@@ -232,6 +274,7 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) Wz[m][c] = Wz[m + 1][c];
+            slot = slot == 2 ? 0 : slot + 1;
         }
     }
 }
@@ -912,16 +955,58 @@ __device__ __forceinline__ void vel_at(gptr<const T> u, size_t n3, size_t i, dou
     v[2] = double(u[3 * n3 + i]) * ir;
 }
 
-// Per-block partial diagnostics.  Point quantities from the state; the vorticity from
-// the 4th-order central derivative of the velocity, whose x and y neighbours come from
-// an LDS copy of the current plane (with a +-2 halo) and whose z neighbours from a
-// per-column window of five planes in registers.
+__device__ __forceinline__ void vel_of(const double s[5], double v[3]) {
+    const double ir = rcp(s[0]);
+    v[0] = s[1] * ir;
+    v[1] = s[2] * ir;
+    v[2] = s[3] * ir;
+}
+
+// Point quantities of one state (kinetic energy, mass, momentum, energy, the largest
+// wave speed |v_d| + c, the bad-point count) added to acc; returns whether the point is
+// valid (finite, rho > 0, p > 0) and its velocity in v.
+__device__ __forceinline__ bool point_stats(const double s[5], double gamma, double acc[CNS_NDIAG], double v[3]) {
+    const double r = s[0], mx = s[1], my = s[2], mz = s[3], e = s[4];
+    const double inv = rcp(r);
+    v[0] = mx * inv;
+    v[1] = my * inv;
+    v[2] = mz * inv;
+    const double ke = 0.5 * (mx * v[0] + my * v[1] + mz * v[2]);
+    const double p = (gamma - 1.0) * (e - ke);
+    const bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
+    if (!finite || !(r > 0.0) || !(p > 0.0)) {
+        acc[8] += 1.0;
+        return false;
+    }
+    acc[0] += ke;
+    acc[2] += r;
+    acc[3] += mx;
+    acc[4] += my;
+    acc[5] += mz;
+    acc[6] += e;
+    const double c = sqrt(gamma * p * inv);
+    acc[7] = fmax(acc[7], fmax(fabs(v[0]), fmax(fabs(v[1]), fabs(v[2]))) + c);
+    return true;
+}
+
+// Per-block partial diagnostics on the tiles of the viscous-flux kernel.  Each state
+// value is loaded once per tile: a thread loads its column at plane k+2 (the point
+// quantities of that plane are summed then, in plane order) and, if it owns a point of
+// the halo ring, that point at plane k+2 as well; the vorticity of plane k takes the
+// 4th-order central derivative of the velocity, whose x and y neighbours come from an
+// LDS copy of plane k staged from the column and ring windows, and whose z neighbours
+// from the column's window of five planes in registers.
 template <typename T>
 __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
     const Launch L = with_params(L0);
     __shared__ double red[kDiagThreads / 64][CNS_NDIAG];
     __shared__ double pv[3][kViscTY + 4][kViscTX + 4];
+    __shared__ double rv[3][3][kViscRing];  // ring velocities, slot (plane - z0) mod 3
     const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    int rhx, rhy;
+    ring_pos(threadIdx.x, rhx, rhy);
+    const bool ring = threadIdx.x < kViscRing;
+    const int rt = ring ? threadIdx.x : 0;
     const VbRange R = vb_range(L.total);
     for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
@@ -940,58 +1025,75 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
             const int x0 = (int)(tile % ntx) * kViscTX, y0 = (int)((tile / ntx) % nty) * kViscTY;
             const int z0 = (int)(tile / ((long long)ntx * nty)) * kViscSZ, z1 = min(z0 + kViscSZ, nz);
             const bool act = x0 + tx < nx && y0 + ty < ny;
-            const size_t col = (size_t)min(y0 + ty, ny - 1) * nx + min(x0 + tx, nx - 1);
-            double vz[5][3];  // this column's velocity at planes k-2 .. k+2
+            // a column past a ragged edge wraps periodically (halo of the columns beside it)
+            const size_t col = (size_t)wrapm(y0 + ty, ny) * nx + wrapm(x0 + tx, nx);
+            const size_t rcol = (size_t)wrapm(y0 - 2 + rhy, ny) * nx + wrapm(x0 - 2 + rhx, nx);
+            double vz[5][3];    // this column's velocity at planes k-2 .. k+2
+            unsigned good = 0;  // bit m: the column's point at plane k-2+m is valid
 #pragma unroll
-            for (int m = 0; m < 4; ++m) vel_at(u, n3, col + wrapi(z0 - 2 + m, nz) * sz, vz[m]);
-            for (int k = z0; k < z1; ++k) {
-                vel_at(u, n3, col + wrapi(k + 2, nz) * sz, vz[4]);
-                // the point's state, loaded ahead of the plane staging and its barrier
-                const size_t idx = (size_t)k * sz + col;
-                const double r = double(u[idx]), mx = double(u[n3 + idx]), my = double(u[2 * n3 + idx]),
-                             mz = double(u[3 * n3 + idx]), e = double(u[4 * n3 + idx]);
-                for (int h = threadIdx.x; h < (kViscTX + 4) * (kViscTY + 4); h += blockDim.x) {
-                    const int hx = h % (kViscTX + 4), hy = h / (kViscTX + 4);
-                    double v3[3];
-                    vel_at(u, n3, (size_t)k * sz + (size_t)wrapm(y0 - 2 + hy, ny) * nx + wrapm(x0 - 2 + hx, nx), v3);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) pv[c][hy][hx] = v3[c];
+            for (int m = 0; m < 4; ++m) {
+                const int zp = z0 - 2 + m;
+                const size_t i = col + wrapi(zp, nz) * sz;
+                double s[5] = {double(u[i]), double(u[n3 + i]), double(u[2 * n3 + i]), double(u[3 * n3 + i]),
+                               double(u[4 * n3 + i])};
+                if (act && zp >= z0 && zp < z1) {
+                    if (point_stats(s, gamma, acc, vz[m])) good |= 1u << m;
+                } else {
+                    vel_of(s, vz[m]);
                 }
-                __syncthreads();
-                if (act) {
-                    const double inv = rcp(r);
-                    const double vx = mx * inv, vy = my * inv, vzc = mz * inv;
-                    const double ke = 0.5 * (mx * vx + my * vy + mz * vzc);
-                    const double p = (gamma - 1.0) * (e - ke);
-                    const bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
-                    if (!finite || !(r > 0.0) || !(p > 0.0)) {
-                        acc[8] += 1.0;
+            }
+            if (ring) {
+                for (int m = 0; m < 2; ++m) {
+                    double v3[3];
+                    vel_at(u, n3, rcol + wrapi(z0 + m, nz) * sz, v3);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rv[m][c][rt] = v3[c];
+                }
+            }
+            int slot = 0;  // (k - z0) mod 3
+            for (int k = z0; k < z1; ++k) {
+                const int slot2 = slot == 0 ? 2 : slot - 1;  // (k + 2 - z0) mod 3
+                {
+                    const size_t i = col + wrapi(k + 2, nz) * sz;
+                    double s[5] = {double(u[i]), double(u[n3 + i]), double(u[2 * n3 + i]), double(u[3 * n3 + i]),
+                                   double(u[4 * n3 + i])};
+                    if (act && k + 2 < z1) {
+                        if (point_stats(s, gamma, acc, vz[4])) good |= 1u << 4;
                     } else {
-                        acc[0] += ke;
-                        acc[2] += r;
-                        acc[3] += mx;
-                        acc[4] += my;
-                        acc[5] += mz;
-                        acc[6] += e;
-                        const double c = sqrt(gamma * p * inv);
-                        acc[7] = fmax(acc[7], fmax(fabs(vx), fmax(fabs(vy), fabs(vzc))) + c);
-                        // vorticity with the 4th-order central derivative
-                        const int X = tx + 2, Y = ty + 2;
-                        const double dvzdy = dcen(pv[2][Y - 2][X], pv[2][Y - 1][X], pv[2][Y + 1][X], pv[2][Y + 2][X]) * ihy;
-                        const double dvydz = dcen(vz[0][1], vz[1][1], vz[3][1], vz[4][1]) * ihz;
-                        const double dvxdz = dcen(vz[0][0], vz[1][0], vz[3][0], vz[4][0]) * ihz;
-                        const double dvzdx = dcen(pv[2][Y][X - 2], pv[2][Y][X - 1], pv[2][Y][X + 1], pv[2][Y][X + 2]) * ihx;
-                        const double dvydx = dcen(pv[1][Y][X - 2], pv[1][Y][X - 1], pv[1][Y][X + 1], pv[1][Y][X + 2]) * ihx;
-                        const double dvxdy = dcen(pv[0][Y - 2][X], pv[0][Y - 1][X], pv[0][Y + 1][X], pv[0][Y + 2][X]) * ihy;
-                        const double ox = dvzdy - dvydz, oy = dvxdz - dvzdx, oz = dvydx - dvxdy;
-                        if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
+                        vel_of(s, vz[4]);
                     }
+                }
+                if (ring) {
+                    double v3[3];
+                    vel_at(u, n3, rcol + wrapi(k + 2, nz) * sz, v3);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        rv[slot2][c][rt] = v3[c];
+                        pv[c][rhy][rhx] = rv[slot][c][rt];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pv[c][ty + 2][tx + 2] = vz[2][c];
+                __syncthreads();
+                if (act && (good & 4u)) {
+                    // vorticity with the 4th-order central derivative
+                    const int X = tx + 2, Y = ty + 2;
+                    const double dvzdy = dcen(pv[2][Y - 2][X], pv[2][Y - 1][X], pv[2][Y + 1][X], pv[2][Y + 2][X]) * ihy;
+                    const double dvydz = dcen(vz[0][1], vz[1][1], vz[3][1], vz[4][1]) * ihz;
+                    const double dvxdz = dcen(vz[0][0], vz[1][0], vz[3][0], vz[4][0]) * ihz;
+                    const double dvzdx = dcen(pv[2][Y][X - 2], pv[2][Y][X - 1], pv[2][Y][X + 1], pv[2][Y][X + 2]) * ihx;
+                    const double dvydx = dcen(pv[1][Y][X - 2], pv[1][Y][X - 1], pv[1][Y][X + 1], pv[1][Y][X + 2]) * ihx;
+                    const double dvxdy = dcen(pv[0][Y - 2][X], pv[0][Y - 1][X], pv[0][Y + 1][X], pv[0][Y + 2][X]) * ihy;
+                    const double ox = dvzdy - dvydz, oy = dvxdz - dvzdx, oz = dvydx - dvxdy;
+                    if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
                 }
                 __syncthreads();  // the next plane overwrites the LDS tile
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) vz[m][c] = vz[m + 1][c];
+                good >>= 1;
+                slot = slot == 2 ? 0 : slot + 1;
             }
         }
         block_reduce_diag(acc, red, glob(bx.part) + (size_t)lb * CNS_NDIAG, one);

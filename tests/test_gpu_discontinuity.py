@@ -132,7 +132,7 @@ def test_rk4_steps_across_jumps(orc, axis):
     np.testing.assert_allclose(d[:, :8], dref[:, :8], rtol=1e-11, atol=1e-14)
 
 
-@pytest.mark.parametrize("shape,strength", [((6, 5, 300), "sod"), ((5, 4, 520), "strong")])
+@pytest.mark.parametrize("shape,strength", [((8, 8, 300), "sod"), ((8, 9, 520), "strong")])
 def test_jumps_along_long_rows(orc, shape, strength):
     # rows longer than 256 points: the x sweep works through 256-interface chunks and
     # carries the last interface flux of a chunk into the next; jumps fall at points

@@ -16,9 +16,9 @@
 //      transformed by a mixed-radix Stockham autosort FFT (radix 4, 2 and 3, 5, ... as
 //      generic small-prime butterflies), lines of the y and z passes batched along x so
 //      loads and stores stay coalesced.
-//   3. binning: per-block shell histograms in LDS, then a fixed-order sum over blocks
-//      (one block per shell) and over shells.
-//      (LDS double atomics: the last bits of a shell sum may vary between runs.)
+//   3. binning: per-wave shell histograms in LDS filled one lane at a time, then
+//      fixed-order sums over the waves of a block, over blocks (one block per shell)
+//      and over shells: the result is the same bits on every run.
 // Scratch: the plan's stage buffers A (X1), B (X2) and rhs (block partials).
 #include <cmath>
 #include <vector>
@@ -304,26 +304,54 @@ struct SpecGeom {
 
 __device__ __forceinline__ int signed_freq(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
-__global__ __launch_bounds__(kPointThreads) void k_spec_bin(const double2 *X1, const double2 *X2, SpecGeom G,
-                                                            double *part) {
-    extern __shared__ double hist[];  // [2][nshell]: E, |k|^2 E
-    for (int s = threadIdx.x; s < 2 * G.nshell; s += blockDim.x) hist[s] = 0.0;
+// Shell sums of one block in a fixed order: each wave keeps its own histogram in LDS
+// and its lanes add to it one lane at a time, in lane order (an add issued by a single
+// lane has no partner to race with, and a wave's LDS operations complete in program
+// order); the wave histograms are summed in wave order at the end.  Every sum is then
+// formed in the same order on every run.
+// Blocks of two waves, or of one where two histograms would pass 64 KiB of LDS.
+constexpr int kSpecBinThreads = 128;
+constexpr size_t kSpecBinLds = 64 * 1024;
+__global__ __launch_bounds__(kSpecBinThreads) void k_spec_bin(const double2 *X1, const double2 *X2, SpecGeom G,
+                                                              double *part) {
+    extern __shared__ double hist[];  // [wave][2][nshell]: E, |k|^2 E
+    const int ns2 = 2 * G.nshell, waves = (int)blockDim.x >> 6;
+    for (int s = threadIdx.x; s < waves * ns2; s += blockDim.x) hist[s] = 0.0;
     __syncthreads();
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < G.n3; i += (size_t)gridDim.x * blockDim.x) {
-        const int ix = (int)(i % G.nx);
-        const int iy = (int)((i / G.nx) % G.ny);
-        const int iz = (int)(i / ((size_t)G.nx * G.ny));
-        const double kx = signed_freq(ix, G.nx) * G.kux, ky = signed_freq(iy, G.ny) * G.kuy,
-                     kz = signed_freq(iz, G.nz) * G.kuz;
-        const double k2 = kx * kx + ky * ky + kz * kz;
-        const int s = min((int)floor(sqrt(k2) + 0.5), G.nshell - 1);
-        const double2 a = X1[i], b = X2[i];
-        const double p = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y) * G.norm;
-        atomicAdd(&hist[s], p);
-        atomicAdd(&hist[G.nshell + s], k2 * p);
+    const int lane = (int)threadIdx.x & 63;
+    double *hw = hist + (size_t)(threadIdx.x >> 6) * ns2;
+    // every lane of a wave runs the same number of rounds (inactive lanes add nothing)
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t first = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~63u);
+    for (size_t i0 = first; i0 < G.n3; i0 += stride) {
+        const size_t i = i0 + lane;
+        int s = 0;
+        double p = 0.0, k2 = 0.0;
+        if (i < G.n3) {
+            const int ix = (int)(i % G.nx);
+            const int iy = (int)((i / G.nx) % G.ny);
+            const int iz = (int)(i / ((size_t)G.nx * G.ny));
+            const double kx = signed_freq(ix, G.nx) * G.kux, ky = signed_freq(iy, G.ny) * G.kuy,
+                         kz = signed_freq(iz, G.nz) * G.kuz;
+            k2 = kx * kx + ky * ky + kz * kz;
+            s = min((int)floor(sqrt(k2) + 0.5), G.nshell - 1);
+            const double2 a = X1[i], b = X2[i];
+            p = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y) * G.norm;
+        }
+        const double kp = k2 * p;
+        for (int l = 0; l < 64; ++l) {
+            if (lane == l && i < G.n3) {
+                atomicAdd(&hw[s], p);
+                atomicAdd(&hw[G.nshell + s], kp);
+            }
+        }
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < 2 * G.nshell; s += blockDim.x) part[(size_t)blockIdx.x * 2 * G.nshell + s] = hist[s];
+    for (int s = threadIdx.x; s < ns2; s += blockDim.x) {
+        double a = hist[s];
+        for (int w = 1; w < waves; ++w) a += hist[(size_t)w * ns2 + s];
+        part[(size_t)blockIdx.x * ns2 + s] = a;
+    }
 }
 
 // E[s], M2[s] = sum over the block partials in a fixed order: one block per shell, its
@@ -453,7 +481,7 @@ static void spectrum_transforms(const BoxDesc &b, hipStream_t s, const T *u, dou
 
 void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, double *E, int nshell, double *mom) {
     double2 *X1 = (double2 *)b.A, *X2 = (double2 *)b.B;
-    const unsigned pg = (unsigned)std::min<size_t>((b.n3 + kPointThreads - 1) / kPointThreads, 65536);
+    const unsigned pg = (unsigned)std::min<size_t>((b.n3 + kSpecBinThreads - 1) / kSpecBinThreads, 65536);
     if (prec == CNS_FP64)
         spectrum_transforms<double>(b, s, (const double *)u, X1, X2, (double2 *)b.rhs);
     else
@@ -471,8 +499,9 @@ void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, d
     const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>({cap, (size_t)1024, (size_t)pg}));
     double *part = (double *)b.rhs;
     double *M2 = part + (size_t)nb * 2 * nshell;
-    const size_t hist = 2 * sizeof(double) * (size_t)nshell;
-    hipLaunchKernelGGL(k_spec_bin, dim3(nb), dim3(kPointThreads), hist, s, X1, X2, G, part);
+    const size_t hist1 = 2 * sizeof(double) * (size_t)nshell;  // one wave's histogram
+    const int waves = 2 * hist1 <= kSpecBinLds ? 2 : 1;
+    hipLaunchKernelGGL(k_spec_bin, dim3(nb), dim3(64 * waves), waves * hist1, s, X1, X2, G, part);
     hipLaunchKernelGGL(k_spec_final, dim3((unsigned)nshell), dim3(kPointThreads), 0, s, part, (int)nb, nshell, E, M2);
     hipLaunchKernelGGL(k_spec_mom, dim3(1), dim3(64), 0, s, E, M2, nshell, mom);
 }

@@ -28,6 +28,7 @@ def case(msg):
     ((20, 12, 48), None, "fp64"),              # swizzled rows of a non-power-of-two length, ragged last line group
     ((8, 8, 2047), None, "fp64"),              # the longest supported line (2047 = 23 x 89: generic radices)
     ((32, 32, 32), None, "mixed"),
+    ((16, 16, 16), (0.03, 0.03, 0.03), "fp64"),  # 2900 shells: one-wave binning blocks
 ])
 def test_spectrum_matches_oracle(shape, length, precision):
     from oracle import spectrum as S
@@ -66,6 +67,20 @@ def test_spectrum_of_the_initial_condition_128():
     lam = Plan.taylor_microscale(mom)
     assert lam == pytest.approx(S.taylor_microscale(tot, m2), rel=1e-12)
     assert lam == pytest.approx(0.5, rel=0.05)
+
+
+def test_spectrum_is_bitwise_reproducible():
+    """The shell sums are formed in one fixed order (lanes in turn, then waves, blocks
+    and shells), so repeated calls return the same bits."""
+    case("spectrum reproducible")
+    for shape, length in (((64, 64, 64), None), ((16, 16, 16), (0.03, 0.03, 0.03))):
+        rho, vel, p = I.hit_primitives(shape[0], 3, 0.3)
+        plan = Plan(shape, length=length or (2 * math.pi,) * 3)
+        u = plan.init_state(rho, vel, p)
+        E0, m0 = plan.spectrum(u)
+        for _ in range(3):
+            E1, m1 = plan.spectrum(u)
+            assert torch.equal(E0, E1) and torch.equal(m0, m1), shape
 
 
 def test_spectrum_argument_errors():

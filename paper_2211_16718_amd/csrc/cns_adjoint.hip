@@ -14,6 +14,7 @@
 // Every sum is formed in a fixed order (deterministic, no atomics).
 #include <hip/hip_runtime.h>
 
+#include "cns_adjoint.h"
 #include "cns_device_adj.h"
 #include "cns_internal.h"
 
@@ -354,7 +355,8 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc1(AdjGeom g, const do
 // (gxx, gxy, gxz, kappa E_x), the y derivatives on (gxy, gyy, gyz, kappa E_y), the z
 // derivatives on (gxz, gyz, gzz, kappa E_z).
 __global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const double *__restrict__ u,
-                                                             const double *__restrict__ Gb, double *__restrict__ ubar) {
+                                                             const double *__restrict__ Gb, double *__restrict__ ubar,
+                                                             AdjEpilogue ep) {
     constexpr int TX = kViscTX, TY = kViscTY;
     constexpr int fx[4] = {0, 3, 4, 6}, fy[4] = {3, 1, 5, 7}, fz[4] = {4, 5, 2, 8};
     __shared__ double qx[4][TY][TX + 4];  // x-differenced fields of the plane, x halo
@@ -429,11 +431,20 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const do
                 mb[c] = qqb * v[c] + vb * inv;
                 invb += vb * m[c];
             }
-            ubar[p] = ub[0] + -invb * inv * inv;
-            ubar[n3 + p] = ub[1] + mb[0];
-            ubar[2 * n3 + p] = ub[2] + mb[1];
-            ubar[3 * n3 + p] = ub[3] + mb[2];
-            ubar[4 * n3 + p] = ub[4] + eb;
+            const double fin[5] = {ub[0] + -invb * inv * inv, ub[1] + mb[0], ub[2] + mb[1], ub[3] + mb[2],
+                                   ub[4] + eb};
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const size_t o = v * n3 + p;
+                if (ep.store_ub) ubar[o] = fin[v];
+                if (ep.ubf) {
+                    const double t = ep.S[o] + fin[v];
+                    ep.ubf[o] = ep.ubf[o] + t;
+                } else if (ep.S) {
+                    ep.S[o] = ep.s_first ? fin[v] : ep.S[o] + fin[v];
+                }
+                if (ep.kb) ep.kb[o] = __fma_rn(ep.a, ep.ub[o], ep.b * fin[v]);
+            }
         }
         __syncthreads();  // the next plane overwrites the LDS tiles
 #pragma unroll
@@ -502,8 +513,22 @@ static void adj_conv(const BoxDesc &b, hipStream_t s, const AdjGeom &g, const do
     hipLaunchKernelGGL((k_adj_conv<2, WW>), dim3(ntx * (unsigned)b.ny), dim3(256), 0, s, g, u, rbar, ubar, 1);
 }
 
-void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
-                 double *Gb) {
+// the stage-combination epilogue by separate launches (boxes without viscous terms)
+__global__ void k_epilogue(size_t n, const double *__restrict__ fin, AdjEpilogue e) {
+    const size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const double f = fin[o];
+    if (e.ubf) {
+        const double t = e.S[o] + f;
+        e.ubf[o] = e.ubf[o] + t;
+    } else if (e.S) {
+        e.S[o] = e.s_first ? f : e.S[o] + f;
+    }
+    if (e.kb) e.kb[o] = __fma_rn(e.a, e.ub[o], e.b * f);
+}
+
+static void rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
+                    double *Gb, const AdjEpilogue *epi) {
     const AdjGeom g = adj_geom(b);
     const bool visc = b.mu > 0.0;
     const unsigned tiles = (unsigned)(((b.nx + kViscTX - 1) / kViscTX) * (long long)((b.ny + kViscTY - 1) / kViscTY) *
@@ -512,7 +537,25 @@ void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, 
     if (weights == CNS_WENO_Z) adj_conv<CNS_WENO_Z>(b, s, g, u, rbar, ubar);
     else if (weights == CNS_WENO_M) adj_conv<CNS_WENO_M>(b, s, g, u, rbar, ubar);
     else adj_conv<CNS_WENO_JS>(b, s, g, u, rbar, ubar);
-    if (visc) hipLaunchKernelGGL(k_adj_visc2, dim3(tiles), dim3(kPointThreads), 0, s, g, u, (const double *)Gb, ubar);
+    AdjEpilogue e;
+    if (epi) e = *epi;
+    if (visc) {
+        hipLaunchKernelGGL(k_adj_visc2, dim3(tiles), dim3(kPointThreads), 0, s, g, u, (const double *)Gb, ubar, e);
+    } else if (epi) {
+        // ubar holds the finished product; the epilogue reads it from there
+        const size_t n5 = 5 * b.n3;
+        hipLaunchKernelGGL(k_epilogue, dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, s, n5, (const double *)ubar, e);
+    }
+}
+
+void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
+                 double *Gb) {
+    rhs_vjp(b, weights, s, u, rbar, ubar, Gb, nullptr);
+}
+
+void adj_rhs_vjp_epi(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
+                     double *Gb, const AdjEpilogue &epi) {
+    rhs_vjp(b, weights, s, u, rbar, ubar, Gb, &epi);
 }
 
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s) {

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "cns_adjoint.h"
 #include "cns_internal.h"
 
 using namespace cns;
@@ -1124,20 +1125,18 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
             const double *U2 = state(L.seg, 4 * (n - n0) + 1), *U3 = state(L.seg, 4 * (n - n0) + 2),
                          *U4 = state(L.seg, 4 * (n - n0) + 3);
             // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
-            // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s
+            // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s.  Each stage adjoint Ub_s goes
+            // straight into the running sum S and the next seed kb at the end of its product.
+            AdjEpilogue e4, e3, e2, e1;
+            e4.S = S, e4.s_first = 1, e4.kb = kb, e4.ub = ub, e4.a = dt / 3.0, e4.b = dt, e4.store_ub = 0;
+            e3.S = S, e3.kb = kb, e3.ub = ub, e3.a = dt / 3.0, e3.b = 0.5 * dt, e3.store_ub = 0;
+            e2.S = S, e2.kb = kb, e2.ub = ub, e2.a = dt / 6.0, e2.b = 0.5 * dt, e2.store_ub = 0;
+            e1.S = S, e1.ubf = ub, e1.store_ub = 0;
             adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
-            adj_rhs_vjp(b, c.weights, s, U4, kb, Ub, Gb);
-            adj_copy(n5, Ub, S, s);
-            adj_lincomb(n5, dt / 3.0, ub, dt, Ub, kb, s);
-            adj_rhs_vjp(b, c.weights, s, U3, kb, Ub, Gb);
-            adj_accum(n5, Ub, S, s);
-            adj_lincomb(n5, dt / 3.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, c.weights, s, U2, kb, Ub, Gb);
-            adj_accum(n5, Ub, S, s);
-            adj_lincomb(n5, dt / 6.0, ub, 0.5 * dt, Ub, kb, s);
-            adj_rhs_vjp(b, c.weights, s, Y, kb, Ub, Gb);
-            adj_accum(n5, Ub, S, s);
-            adj_accum(n5, S, ub, s);
+            adj_rhs_vjp_epi(b, c.weights, s, U4, kb, Ub, Gb, e4);
+            adj_rhs_vjp_epi(b, c.weights, s, U3, kb, Ub, Gb, e3);
+            adj_rhs_vjp_epi(b, c.weights, s, U2, kb, Ub, Gb, e2);
+            adj_rhs_vjp_epi(b, c.weights, s, Y, kb, Ub, Gb, e1);
         }
     }
     adj_copy(n5, ub, (double *)u0_bar, s);

@@ -102,6 +102,20 @@ __device__ __forceinline__ gptr<T> glob(T *p) {
     return (gptr<T>)p;
 }
 
+// A value all lanes hold alike (read from the box table) moved into scalar registers.
+// The compiler cannot prove that table reads are the same on every lane; marked
+// uniform, the pointers stay in scalar registers across the loops instead of being
+// copied back from vector registers before each access.
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> uni(gptr<T> p) {
+    return (gptr<T>)uni64((uint64_t)p);
+}
+
 // Component c of a component-major array (component c at element c * n3) at a lane's
 // byte offset: the array base and the component offset are uniform and stay in scalar
 // registers, and every load and store of a point shares the lane's one 32-bit offset
@@ -464,7 +478,7 @@ __host__ __device__ __forceinline__ SweepGeom sweep_geom(int nx, int ny, int nz)
 // segment (stacking z segments spreads a block over planes far apart in memory).
 //
 // The six point fluxes live in a per-thread ring in LDS (6 slots x 5 components,
-// component-major across the block so lanes hit distinct banks), read one component
+// component-major across the wave so lanes hit distinct banks), read one component
 // at a time; the registers this frees carry the loads of the next point and of the
 // point's rhs, issued before the interface-flux arithmetic so their latency overlaps
 // it (y sweep 12 % and fused-update sweep 6 % faster than a register window).  The
@@ -473,8 +487,10 @@ template <typename T, typename B, int DIR, int MODE, bool VISC, int WW>
 __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
     const Launch L = with_params(L0);
     extern __shared__ unsigned char lds_raw[];
-    T *ring = reinterpret_cast<T *>(lds_raw) + threadIdx.x;  // slot s, component v at (s * 5 + v) * blockDim.x
-    const int bdim = blockDim.x;
+    // each wave's ring: slot s, component v of lane l at (s * 5 + v) * 64 + l, so the
+    // component and slot strides are constants (immediate LDS offsets)
+    constexpr int bdim = 64;
+    T *ring = reinterpret_cast<T *>(lds_raw) + (threadIdx.x >> 6) * (30 * 64) + (threadIdx.x & 63);
     const VbRange R = vb_range(L.total);
     for (long long vb = R.vb; vb < R.end; vb += R.stride) {
         const int bi = find_box(L.off, L.nbox, vb);
@@ -501,9 +517,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
         const size_t base = p * sg.pstride + q * sg.qstride;
         const int j0 = sgi * seg;
         const int j1 = min(j0 + seg, n);
-        const size_t n3 = bx.n3;
-        const gptr<const T> u = glob((const T *)state_ptr(bx, L, L.in));
-        const gptr<const T> G = glob((const T *)bx.G);
+        const size_t n3 = uni64(bx.n3);
+        const gptr<const T> u = uni(glob((const T *)state_ptr(bx, L, L.in)));
+        const gptr<const T> G = uni(glob((const T *)bx.G));
         const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[DIR]);
@@ -512,11 +528,11 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
         // stores to global memory, which the compiler cannot tell apart from the table, so
         // a table read inside the loop would be repeated after every store, each time
         // behind a wait for all loads in flight (the ones issued ahead included).
-        const gptr<const T> rhs_in = glob((const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs)));
-        const gptr<const T> un = glob((const T *)state_ptr(bx, L, BUF_U));
-        const gptr<double> acc = glob(bx.acc);
-        const gptr<T> unext = glob((T *)state_ptr(bx, L, L.out));
-        const gptr<T> rhs_out = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
+        const gptr<const T> rhs_in = uni(glob((const T *)(MODE == MODE_RK ? bx.rhs : (L.out_ov ? L.out_ov : bx.rhs))));
+        const gptr<const T> un = uni(glob((const T *)state_ptr(bx, L, BUF_U)));
+        const gptr<double> acc = uni(glob(bx.acc));
+        const gptr<T> unext = uni(glob((T *)state_ptr(bx, L, L.out)));
+        const gptr<T> rhs_out = uni(glob((T *)(L.out_ov ? L.out_ov : bx.rhs)));
 
         T w[6][5], g[4][4], Hp[5], nw[5];
         // One loop computes everything, so every point flux and every interface flux
@@ -830,10 +846,10 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_chunks(Launch L0) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nx = bx.nx;
-        const size_t n3 = bx.n3, obase = (size_t)(vb - L.off[bi]) * nx;
-        const gptr<const T> u = glob((const T *)state_ptr(bx, L, L.in));
-        const gptr<const T> G = glob((const T *)bx.G);
-        const gptr<T> out = glob((T *)(L.out_ov ? L.out_ov : bx.rhs));
+        const size_t n3 = uni64(bx.n3), obase = (size_t)(vb - L.off[bi]) * nx;
+        const gptr<const T> u = uni(glob((const T *)state_ptr(bx, L, L.in)));
+        const gptr<const T> G = uni(glob((const T *)bx.G));
+        const gptr<T> out = uni(glob((T *)(L.out_ov ? L.out_ov : bx.rhs)));
         const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
         const T inv_dx = T(bx.inv_h[0]);

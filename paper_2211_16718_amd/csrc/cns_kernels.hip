@@ -189,7 +189,7 @@ __device__ __forceinline__ void ring_pos(int t, int &hx, int &hy) {
 
 // Viscous fluxes at points: the 12 first derivatives of (u, v, w, T) by the 5-point
 // central stencil, then tau, q and G.  A block owns a 32 x 8 (x, y) tile and marches
-// along z over kViscSZ planes.  Each thread keeps its own column's primitives at planes
+// along z over visc_planes(nz) planes.  Each thread keeps its own column's primitives at planes
 // k-2 .. k+2 in registers (z derivatives); a thread that owns a point of the tile's halo
 // ring keeps that point's primitives at planes k .. k+2 in its own LDS slots.  Plane k
 // is staged in LDS from the two windows (x and y derivatives).  Each state value of a
@@ -214,7 +214,8 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
         const long long lb = vb - L.off[bi];
         const int ntx = (nx + kViscTX - 1) / kViscTX, nty = (ny + kViscTY - 1) / kViscTY;
         const int x0 = (int)(lb % ntx) * kViscTX, y0 = (int)((lb / ntx) % nty) * kViscTY;
-        const int z0 = (int)(lb / ((long long)ntx * nty)) * kViscSZ, z1 = min(z0 + kViscSZ, nz);
+        const int vsz = visc_planes(nz);
+        const int z0 = (int)(lb / ((long long)ntx * nty)) * vsz, z1 = min(z0 + vsz, nz);
         const int tx = threadIdx.x % kViscTX, ty = threadIdx.x / kViscTX;
         const bool act = x0 + tx < nx && y0 + ty < ny;
         // a column past a ragged edge wraps periodically: its primitives are halo values
@@ -930,10 +931,11 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 // the diagnostics walk the box in the tiles of the viscous-flux kernel (32 x 8 columns,
-// kViscSZ planes); one partial-sum block per tile, at most kDiagBlocksMax (then a
+// visc_planes(nz) planes); one partial-sum block per tile, at most kDiagBlocksMax (then a
 // block takes every kDiagBlocksMax-th tile)
 __host__ __device__ __forceinline__ long long diag_tiles(int nx, int ny, int nz) {
-    return (long long)((nx + kViscTX - 1) / kViscTX) * ((ny + kViscTY - 1) / kViscTY) * ((nz + kViscSZ - 1) / kViscSZ);
+    return (long long)((nx + kViscTX - 1) / kViscTX) * ((ny + kViscTY - 1) / kViscTY) *
+           ((nz + visc_planes(nz) - 1) / visc_planes(nz));
 }
 __host__ __device__ __forceinline__ int diag_blocks(int nx, int ny, int nz) {
     const long long t = diag_tiles(nx, ny, nz);
@@ -1039,7 +1041,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Launch L0) {
         double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (long long tile = lb; tile < ntile; tile += nblk) {
             const int x0 = (int)(tile % ntx) * kViscTX, y0 = (int)((tile / ntx) % nty) * kViscTY;
-            const int z0 = (int)(tile / ((long long)ntx * nty)) * kViscSZ, z1 = min(z0 + kViscSZ, nz);
+            const int z0 = (int)(tile / ((long long)ntx * nty)) * visc_planes(nz), z1 = min(z0 + visc_planes(nz), nz);
             const bool act = x0 + tx < nx && y0 + ty < ny;
             // a column past a ragged edge wraps periodically (halo of the columns beside it)
             const size_t col = (size_t)wrapm(y0 + ty, ny) * nx + wrapm(x0 + tx, nx);
@@ -1273,7 +1275,7 @@ long long family_blocks(const BoxDesc &b, int fam, int block) {
         }
         case F_DIAG: return diag_blocks(b.nx, b.ny, b.nz);
         case F_VISC:
-            return cdiv(b.nx, kViscTX) * cdiv(b.ny, kViscTY) * cdiv(b.nz, kViscSZ);
+            return cdiv(b.nx, kViscTX) * cdiv(b.ny, kViscTY) * cdiv(b.nz, visc_planes(b.nz));
         case F_BOX: return 1;
     }
     return 0;

@@ -16,9 +16,10 @@
 //      transformed by a mixed-radix Stockham autosort FFT (radix 4, 2 and 3, 5, ... as
 //      generic small-prime butterflies), lines of the y and z passes batched along x so
 //      loads and stores stay coalesced.
-//   3. binning: per-wave shell histograms in LDS filled one lane at a time, then
-//      fixed-order sums over the waves of a block, over blocks (one block per shell)
-//      and over shells: the result is the same bits on every run.
+//   3. binning: per-wave shell histograms in LDS, each run of equal shells in a wave
+//      summed by a segmented scan and added by one lane at a time, then fixed-order
+//      sums over the waves of a block, over blocks (one block per shell) and over
+//      shells: the result is the same bits on every run.
 // Scratch: the plan's stage buffers A (X1), B (X2) and rhs (block partials).
 #include <cmath>
 #include <vector>
@@ -304,14 +305,19 @@ struct SpecGeom {
 
 __device__ __forceinline__ int signed_freq(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
-// Shell sums of one block in a fixed order: each wave keeps its own histogram in LDS
-// and its lanes add to it one lane at a time, in lane order (an add issued by a single
-// lane has no partner to race with, and a wave's LDS operations complete in program
-// order); the wave histograms are summed in wave order at the end.  Every sum is then
-// formed in the same order on every run.
+// Shell sums of one block in a fixed order.  Each wave keeps its own histogram in LDS.
+// The lanes of a wave hold consecutive points, so equal shells come in runs of
+// neighbouring lanes: a segmented scan (fixed doubling order) sums each run into its
+// last lane, and those lanes add to the histogram one at a time, in lane order (an add
+// issued by a single lane has no partner to race with, and a wave's LDS operations
+// complete in program order).  The wave histograms are summed in wave order at the
+// end.  Every sum is thus formed in the same order on every run.
 // Blocks of two waves, or of one where two histograms would pass 64 KiB of LDS.
+// Up to 8192 blocks: the loop of a wave is latency bound (loads, the scan's lane
+// exchanges, the ordered adds), so it needs many waves in flight.
 constexpr int kSpecBinThreads = 128;
 constexpr size_t kSpecBinLds = 64 * 1024;
+constexpr size_t kSpecBinBlocksMax = 8192;
 __global__ __launch_bounds__(kSpecBinThreads) void k_spec_bin(const double2 *X1, const double2 *X2, SpecGeom G,
                                                               double *part) {
     extern __shared__ double hist[];  // [wave][2][nshell]: E, |k|^2 E
@@ -320,30 +326,49 @@ __global__ __launch_bounds__(kSpecBinThreads) void k_spec_bin(const double2 *X1,
     __syncthreads();
     const int lane = (int)threadIdx.x & 63;
     double *hw = hist + (size_t)(threadIdx.x >> 6) * ns2;
-    // every lane of a wave runs the same number of rounds (inactive lanes add nothing)
+    // every lane of a wave runs the same number of rounds (lanes past the end add nothing)
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t first = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~63u);
     for (size_t i0 = first; i0 < G.n3; i0 += stride) {
         const size_t i = i0 + lane;
-        int s = 0;
-        double p = 0.0, k2 = 0.0;
+        int s = -1;  // no shell: a run of its own that adds nothing
+        double p = 0.0, q = 0.0;
         if (i < G.n3) {
             const int ix = (int)(i % G.nx);
             const int iy = (int)((i / G.nx) % G.ny);
             const int iz = (int)(i / ((size_t)G.nx * G.ny));
             const double kx = signed_freq(ix, G.nx) * G.kux, ky = signed_freq(iy, G.ny) * G.kuy,
                          kz = signed_freq(iz, G.nz) * G.kuz;
-            k2 = kx * kx + ky * ky + kz * kz;
+            const double k2 = kx * kx + ky * ky + kz * kz;
             s = min((int)floor(sqrt(k2) + 0.5), G.nshell - 1);
             const double2 a = X1[i], b = X2[i];
             p = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y) * G.norm;
+            q = k2 * p;
         }
-        const double kp = k2 * p;
-        for (int l = 0; l < 64; ++l) {
-            if (lane == l && i < G.n3) {
-                atomicAdd(&hw[s], p);
-                atomicAdd(&hw[G.nshell + s], kp);
+        // run heads and tails
+        const int sp = __shfl_up(s, 1, 64), sn = __shfl_down(s, 1, 64);
+        int f = (lane == 0 || sp != s) ? 1 : 0;
+        const bool tail = lane == 63 || sn != s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double pu = __shfl_up(p, d, 64), qu = __shfl_up(q, d, 64);
+            const int fu = __shfl_up(f, d, 64);
+            if (lane >= d) {
+                if (!f) {
+                    p += pu;
+                    q += qu;
+                }
+                f |= fu;
             }
+        }
+        unsigned long long m = __ballot(tail && s >= 0);
+        while (m) {
+            const int l = __ffsll(m) - 1;
+            if (lane == l) {
+                atomicAdd(&hw[s], p);
+                atomicAdd(&hw[G.nshell + s], q);
+            }
+            m &= m - 1;
         }
     }
     __syncthreads();
@@ -496,7 +521,7 @@ void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, d
     // bytes per point)
     const size_t room = b.n3 * 20 - (size_t)nshell * sizeof(double);
     const size_t cap = room / (2 * sizeof(double) * (size_t)nshell);
-    const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>({cap, (size_t)1024, (size_t)pg}));
+    const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>({cap, (size_t)kSpecBinBlocksMax, (size_t)pg}));
     double *part = (double *)b.rhs;
     double *M2 = part + (size_t)nb * 2 * nshell;
     const size_t hist1 = 2 * sizeof(double) * (size_t)nshell;  // one wave's histogram

@@ -62,3 +62,36 @@ def test_plan_validation_without_gpu():
     assert lib.cns_set_workspace(h, ctypes.c_void_p(257), nbytes) == -1
     assert lib.cns_set_tiles(h, 4, 0, 0, 100) == -1
     assert lib.cns_plan_destroy(h) == 0
+
+
+@pytest.mark.parametrize("grid,phys,msg", [
+    ((1024, 1024, 512), None, b"too large"),           # 8 n3 = 2^32: past the 32-bit offsets
+    ((812, 812, 812), None, None),                      # the largest cube that fits (8 n3 < 2^32)
+    (None, dict(gamma=1.0), b"gamma"),
+    (None, dict(mu_eff=-1e-3), b"mu_eff"),
+    (None, dict(weno_eps=0.0), b"weno_eps"),
+    (None, dict(weno_eps=1e31), b"weno_eps"),
+    (None, dict(harten_delta=-1.0), b"harten_delta"),
+    (None, dict(mu_eff=0.01, prandtl=0.0), b"prandtl"),
+])
+def test_plan_limits_without_gpu(grid, phys, msg):
+    """Grid size and physics limits are checked on the host; a plan within them is created
+    without touching the device (its workspace is the caller's)."""
+    from paper_2211_16718_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libcns.so not built")
+    lib = _lib.load()
+    nx, ny, nz = grid or (16, 16, 16)
+    g = _lib.Grid(nx, ny, nz, 1.0, 1.0, 1.0)
+    p = dict(gamma=1.4, prandtl=0.72, mu_eff=0.01, weno_eps=1e-6, harten_delta=1e-6)
+    p.update(phys or {})
+    ph = _lib.Physics(p["gamma"], p["prandtl"], p["mu_eff"], p["weno_eps"], p["harten_delta"])
+    h = ctypes.c_void_p()
+    rc = lib.cns_plan_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(ph), 0, None)
+    if msg is None:
+        assert rc == 0
+        assert lib.cns_workspace_bytes(h) > 29 * 8 * nx * ny * nz
+        assert lib.cns_plan_destroy(h) == 0
+    else:
+        assert rc == -1 and msg in lib.cns_last_error()

@@ -57,8 +57,9 @@ static int validate(const cns_grid *g, const cns_physics *ph) {
     if (!(ph->gamma > 1.0) || !std::isfinite(ph->gamma)) return set_err(CNS_EINVAL, "gamma must exceed 1");
     if (!(ph->mu_eff >= 0.0) || !std::isfinite(ph->mu_eff)) return set_err(CNS_EINVAL, "mu_eff must be >= 0");
     if (ph->mu_eff > 0.0 && !(ph->prandtl > 0.0)) return set_err(CNS_EINVAL, "prandtl must be > 0");
-    // products of up to six (eps + beta) factors are formed in FP64 (and eps is rounded
-    // to FP32 in the mixed form): eps outside [1e-30, 1e30] would leave their range
+    // products of up to eight (eps + beta) factors are formed in FP64 (the two weight
+    // denominators of an interface share one reciprocal; eps is rounded to FP32 in the
+    // mixed form): eps outside [1e-30, 1e30] would leave their range
     if (!(ph->weno_eps >= 1e-30 && ph->weno_eps <= 1e30))
         return set_err(CNS_EINVAL, "weno_eps must lie in [1e-30, 1e30] (got %g)", ph->weno_eps);
     if (!(ph->harten_delta >= 0.0)) return set_err(CNS_EINVAL, "harten_delta must be >= 0");

@@ -147,6 +147,18 @@ __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, 
     }
 }
 
+// The Jiang-Shu weighted sum of one reconstruction as numerator and denominator
+// (the weights' common scale s_1^2 s_2^2 s_3^2 divided out by the caller): 10 alpha_k
+// s1^2 s2^2 s3^2 = (d2 d3, 6 d1 d3, 3 d1 d2) with d_k = s_k^2.
+template <typename T>
+__device__ __forceinline__ void weno5_js_terms(T b1, T b2, T b3, T eps, T c1, T c2, T c3, T &num, T &den) {
+    T s1 = eps + b1, s2 = eps + b2, s3 = eps + b3;
+    T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
+    T a1 = d2 * d3, a2 = d1 * d3, a3 = d1 * d2;
+    num = a1 * c1 + a2 * (T(6) * c2) + a3 * (T(3) * c3);
+    den = a1 + T(6) * a2 + T(3) * a3;
+}
+
 // Six times the left- and right-biased values, from four times the Jiang-Shu
 // indicators: with eps4 = 4 eps every alpha_k scales by the same 1/16, so the weights
 // are those of the plain form; dropping the 1/6 of the candidates and the 13/12, 1/4 of
@@ -180,8 +192,21 @@ __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T 
     B bR2 = qc + fb * fb;
     B bR3 = qb + fc * fc;
 
-    L6 = weno5_combine<T, B, WW>(bL1, bL2, bL3, eps4, L1, L2, L3);
-    R6 = weno5_combine<T, B, WW>(bR1, bR2, bR3, eps4, R1, L3, L2);
+    if constexpr (WW == CNS_WENO_JS && sizeof(T) == sizeof(B)) {
+        // FP64 Jiang-Shu: the two weight denominators share one reciprocal,
+        // 1/D_L = D_R / (D_L D_R) (one refined reciprocal and three products instead of
+        // two reciprocals; the product of the two is a product of eight (eps + beta)
+        // factors, inside the FP64 range for the eps and beta the plan admits)
+        T nL, dL, nR, dR;
+        weno5_js_terms<T>(bL1, bL2, bL3, eps4, L1, L2, L3, nL, dL);
+        weno5_js_terms<T>(bR1, bR2, bR3, eps4, R1, L3, L2, nR, dR);
+        const T r = rcp(dL * dR);
+        L6 = nL * (dR * r);
+        R6 = nR * (dL * r);
+    } else {
+        L6 = weno5_combine<T, B, WW>(bL1, bL2, bL3, eps4, L1, L2, L3);
+        R6 = weno5_combine<T, B, WW>(bR1, bR2, bR3, eps4, R1, L3, L2);
+    }
 }
 
 // the left- and right-biased values themselves

@@ -118,7 +118,7 @@ struct Core {
         take(5 * n3 * esz);  // A
         take(5 * n3 * esz);  // B
         take(5 * n3 * sizeof(double));                         // acc
-        take((size_t)kDiagBlocksMax * CNS_NDIAG * sizeof(double));  // part
+        take(diag_part_slots(b.nx, b.ny, b.nz) * CNS_NDIAG * sizeof(double));  // part
         return off;
     }
 
@@ -199,7 +199,7 @@ struct Core {
             b.A = take(5 * n3 * esz);
             b.B = take(5 * n3 * esz);
             b.acc = (double *)take(5 * n3 * sizeof(double));
-            b.part = (double *)take((size_t)kDiagBlocksMax * CNS_NDIAG * sizeof(double));
+            b.part = (double *)take(diag_part_slots(b.nx, b.ny, b.nz) * CNS_NDIAG * sizeof(double));
             b.u = ustate[i];
             int P = 1;
             b.rows = rows_ov[i] > 0 && rows_fit(b.nx, rows_ov[i], esz, nullptr) ? rows_ov[i] : rows_for(b.nx);
@@ -276,9 +276,14 @@ struct Core {
         if (graph) bt.gp = gp;
         const void *u_l = graph ? nullptr : u_ov;
         const double dt_l = graph ? 0.0 : dt_ov;
+        // a step's diagnostics are formed by the next step's first viscous-flux launch,
+        // which reads that state anyway (FP64, viscous batches); the last step's by the
+        // diagnostics kernels
+        const bool fuse = diag && diag_fusable(bt);
         auto enqueue = [&]() {
             for (int n = 0; n < nsteps; ++n) {
-                launch_step(bt, sch, u_l, dt_l, diag, nsteps, n);
+                launch_step(bt, sch, u_l, dt_l, diag, nsteps, n, nullptr, fuse && n > 0 ? n - 1 : -1,
+                            !fuse || n == nsteps - 1);
                 prof_flush(bt.prof);
             }
         };

@@ -27,15 +27,15 @@ struct PhysT {
     double gamma, prandtl, mu_eff, eps, delta;
 };
 
-// Reciprocal: the hardware estimate refined by Newton-Raphson steps r <- r + r (1 - b r)
-// (two steps in FP64, one in FP32), about half the instructions of the IEEE division
-// sequence and within an ulp or two of it.
+// Reciprocal: the hardware estimate r (relative error below 2^-24 on gfx950, measured)
+// refined once to third order, 1/b = r / (1 - e) ~ r (1 + e + e^2) with e = 1 - b r
+// (truncation e^3 < 2^-72), three instructions against four for two Newton-Raphson
+// steps; in FP32 one Newton-Raphson step r <- r + r e.  Within an ulp or two of the
+// IEEE division, at about half its instructions.
 __device__ __forceinline__ double rcp(double b) {
-    double r = __builtin_amdgcn_rcp(b);
-    double e = fma(-b, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-b, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(b);
+    const double e = fma(-b, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 __device__ __forceinline__ float rcp(float b) {
     float r = __builtin_amdgcn_rcpf(b);
@@ -43,14 +43,14 @@ __device__ __forceinline__ float rcp(float b) {
     return fmaf(r, e, r);
 }
 
-// Reciprocal square root: the hardware estimate refined by Newton-Raphson steps
-// y <- y + y (1 - x y^2) / 2 (two in FP64, one in FP32).
+// Reciprocal square root: the hardware estimate y (relative error below 2^-24) refined
+// once to third order, x^-1/2 = y (1 - e)^-1/2 ~ y (1 + e/2 + 3 e^2 / 8) with
+// e = 1 - x y^2 (truncation 5 e^3 / 16); in FP32 one Newton-Raphson step
+// y <- y + y e / 2.
 __device__ __forceinline__ double rsq(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double r = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, r, y);
-    r = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, r, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 __device__ __forceinline__ float rsq(float x) {
     float y = __builtin_amdgcn_rsqf(x);

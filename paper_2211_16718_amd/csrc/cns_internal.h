@@ -31,6 +31,14 @@ constexpr int kViscSZ = 16;               // planes per block of the viscous-flu
 // (512^3: fetch 9.45 -> 8.58 GB per launch), else 16, which keeps small boxes in
 // enough tiles to fill the GPU.
 __host__ __device__ __forceinline__ int visc_planes(int nz) { return nz >= 256 ? 2 * kViscSZ : kViscSZ; }
+// Partial-sum slots of a box's diagnostics: one per block of the diagnostics kernel (at
+// most kDiagBlocksMax) or one per viscous-flux tile when the diagnostics ride on that
+// kernel.
+inline size_t diag_part_slots(int nx, int ny, int nz) {
+    const size_t tiles = (size_t)((nx + kViscTX - 1) / kViscTX) * ((ny + kViscTY - 1) / kViscTY) *
+                         ((nz + visc_planes(nz) - 1) / visc_planes(nz));
+    return tiles > (size_t)kDiagBlocksMax ? tiles : (size_t)kDiagBlocksMax;
+}
 
 // buffer roles of a box
 enum Buf { BUF_U = 0, BUF_A = 1, BUF_B = 2 };
@@ -78,6 +86,7 @@ struct Launch {
     double dt_ov;      // replaces the box's dt
     double *diag;      // diagnostics output base (may be null)
     long long diag_box_stride;  // records between consecutive boxes in `diag`
+    int diag_fused;             // the diagnostics partials come from the viscous-flux tiles
     const GraphParams *gp;      // graph replay: u_ov, dt_ov and diag come from here
 };
 
@@ -148,12 +157,18 @@ void launch_rhs_dir(const Batch &bt, const void *u_ov, int dir, void *out_ov);
 void launch_viscous(const Batch &bt, const void *u_ov, void *out_ov);
 // one RK4 step of every box (4 stages with fused updates), then diagnostics if diag
 // stage_states (single box, may be null): three buffers that receive the stage states
-// U2, U3, U4 of the step (they replace the stage buffers A, B)
+// U2, U3, U4 of the step (they replace the stage buffers A, B).
+// diag_prev >= 0 (FP64, viscous batches): the first stage's viscous-flux launch also
+// forms the diagnostics of the state it reads into record diag_prev; diag_own: the
+// step's own record `step` is formed after the step (by the diagnostics kernels).
 void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long diag_box_stride,
-                     int step, void *const *stage_states = nullptr);
-// one step of the integrator `scheme` (CNS_RK4 or CNS_TVDRK3), then diagnostics if diag
+                     int step, void *const *stage_states = nullptr, int diag_prev = -1, bool diag_own = true);
+// one step of the integrator `scheme` (CNS_RK4 or CNS_TVDRK3), then diagnostics as above
 void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag,
-                 long long diag_box_stride, int step, void *const *stage_states = nullptr);
+                 long long diag_box_stride, int step, void *const *stage_states = nullptr, int diag_prev = -1,
+                 bool diag_own = true);
+// whether a batch's diagnostics can ride on the next step's first viscous-flux launch
+inline bool diag_fusable(const Batch &bt) { return bt.prec == CNS_FP64 && bt.any_visc; }
 void launch_diag(const Batch &bt, const void *u_ov, double *diag, long long diag_box_stride, int step);
 // max over points and directions of |v_d| + c of every box into out[box] (NaN for a box
 // with a non-finite state, rho <= 0 or p <= 0)

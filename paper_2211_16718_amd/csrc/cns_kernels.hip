@@ -160,6 +160,7 @@ __global__ void k_fill(size_t n, T *out) {
 // primitives (u, v, w, T = gamma p / rho) of the state at linear index i
 template <typename T>
 __device__ __forceinline__ void prim_at(gptr<const T> u, size_t n3, size_t i, T gamma, T W[4]) {
+#pragma clang fp contract(off)
     const T r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
     const T inv = rcp(r);
     W[0] = mx * inv;
@@ -187,6 +188,52 @@ __device__ __forceinline__ void ring_pos(int t, int &hx, int &hy) {
     }
 }
 
+// The 5-point central difference (times h) rounded as written (no fused multiply-add):
+// the viscous-flux kernel forms every value of G with contraction off, so that the
+// variant that also accumulates the diagnostics (extra uses of the gradients) gives the
+// same bits.
+template <typename T>
+__device__ __forceinline__ T dcen_nc(T m2, T m1, T p1, T p2) {
+#pragma clang fp contract(off)
+    return (T(8) * (p1 - m1) - (p2 - m2)) * (T(1) / T(12));
+}
+
+// Primitives of the state at linear index i, as prim_at, and (FP64 only) the point
+// quantities of the diagnostics when `count`: kinetic energy, mass, momentum, energy,
+// the largest wave speed and the bad-point count in acc, `good` set when the point is
+// valid (finite, rho > 0, p > 0).  The primitives are the same bits as prim_at's.
+__device__ __forceinline__ void prim_stats(gptr<const double> u, size_t n3, size_t i, double gamma, double W[4],
+                                           bool count, double acc[CNS_NDIAG], bool &good) {
+#pragma clang fp contract(off)
+    const double r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
+    const double inv = rcp(r);
+    W[0] = mx * inv;
+    W[1] = my * inv;
+    W[2] = mz * inv;
+    const double ke = 0.5 * (mx * W[0] + my * W[1] + mz * W[2]);
+    const double p = (gamma - 1.0) * (e - ke);
+    W[3] = gamma * p * inv;
+    good = false;
+    if (count) {
+        const bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(e);
+        if (!finite || !(r > 0.0) || !(p > 0.0)) {
+            acc[8] += 1.0;
+        } else {
+            acc[0] += ke;
+            acc[2] += r;
+            acc[3] += mx;
+            acc[4] += my;
+            acc[5] += mz;
+            acc[6] += e;
+            const double c = sqrt(gamma * p * inv);
+            acc[7] = fmax(acc[7], fmax(fabs(W[0]), fmax(fabs(W[1]), fabs(W[2]))) + c);
+            good = true;
+        }
+    }
+}
+__device__ __forceinline__ void block_reduce_diag(const double acc[CNS_NDIAG], double (*red)[CNS_NDIAG],
+                                                  gptr<double> dst, const double scale[CNS_NDIAG]);
+
 // Viscous fluxes at points: the 12 first derivatives of (u, v, w, T) by the 5-point
 // central stencil, then tau, q and G.  A block owns a 32 x 8 (x, y) tile and marches
 // along z over visc_planes(nz) planes.  Each thread keeps its own column's primitives at planes
@@ -196,11 +243,21 @@ __device__ __forceinline__ void ring_pos(int t, int &hx, int &hy) {
 // plane is loaded once per tile, and the column and the ring point of plane k+2 are
 // loaded together, while the neighbouring tiles (same XCD, launched together) load the
 // same lines for their own columns, so the halo comes from L2.
-template <typename T>
+//
+// With DIAG (FP64 plans, the first stage of a step) the kernel also forms the partial
+// diagnostics of the state it reads, one partial per tile: the point quantities of a
+// plane as its column is loaded, the enstrophy from the velocity gradients it computes
+// anyway (the same central derivatives as the diagnostics kernel).  The state's
+// diagnostics then cost no read of their own.
+template <typename T, bool DIAG>
 __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
+#pragma clang fp contract(off)
+    static_assert(!DIAG || std::is_same<T, double>::value, "fused diagnostics in FP64 plans only");
     const Launch L = with_params(L0);
     __shared__ T pl[4][kViscTY + 4][kViscTX + 4];
     __shared__ T rw[3][4][kViscRing];  // ring primitives, slot (plane - z0) mod 3
+    __shared__ double red[DIAG ? kPointThreads / 64 : 1][CNS_NDIAG];
+    const double one[CNS_NDIAG] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
     int rhx, rhy;
     ring_pos(threadIdx.x, rhx, rhy);
     const bool ring = threadIdx.x < kViscRing;
@@ -228,8 +285,20 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
         const T ihx = T(b.inv_h[0]), ihy = T(b.inv_h[1]), ihz = T(b.inv_h[2]);
         const T mu = T(b.mu), kcond = T(b.mu / ((b.gamma - 1.0) * b.prandtl));
         T Wz[5][4];  // this column's primitives at planes k-2 .. k+2
+        double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned good = 0;  // bit m: the column's point at plane k-2+m is valid (DIAG)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) prim_at(u, n3, col + wrapi(z0 - 2 + m, nz) * sz, gamma, Wz[m]);
+        for (int m = 0; m < 4; ++m) {
+            const size_t ic = col + wrapi(z0 - 2 + m, nz) * sz;
+            if constexpr (DIAG) {
+                const int zp = z0 - 2 + m;
+                bool gd;
+                prim_stats(u, n3, ic, gamma, Wz[m], act && zp >= z0 && zp < z1, acc, gd);
+                if (gd) good |= 1u << m;
+            } else {
+                prim_at(u, n3, ic, gamma, Wz[m]);
+            }
+        }
         if (ring) {
             for (int m = 0; m < 2; ++m) {
                 T w4[4];
@@ -241,7 +310,13 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
         int slot = 0;  // (k - z0) mod 3
         for (int k = z0; k < z1; ++k) {
             const int slot2 = slot == 0 ? 2 : slot - 1;  // (k + 2 - z0) mod 3
-            prim_at(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4]);
+            if constexpr (DIAG) {
+                bool gd;
+                prim_stats(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4], act && k + 2 < z1, acc, gd);
+                if (gd) good |= 1u << 4;
+            } else {
+                prim_at(u, n3, col + wrapi(k + 2, nz) * sz, gamma, Wz[4]);
+            }
             if (ring) {
                 T w4[4];
                 prim_at(u, n3, rcol + wrapi(k + 2, nz) * sz, gamma, w4);
@@ -258,9 +333,16 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
                 T g[4][3];  // g[a][c] = d W_a / d x_c
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    g[a][0] = dcen(pl[a][ty + 2][tx], pl[a][ty + 2][tx + 1], pl[a][ty + 2][tx + 3], pl[a][ty + 2][tx + 4]) * ihx;
-                    g[a][1] = dcen(pl[a][ty][tx + 2], pl[a][ty + 1][tx + 2], pl[a][ty + 3][tx + 2], pl[a][ty + 4][tx + 2]) * ihy;
-                    g[a][2] = dcen(Wz[0][a], Wz[1][a], Wz[3][a], Wz[4][a]) * ihz;
+                    g[a][0] = dcen_nc(pl[a][ty + 2][tx], pl[a][ty + 2][tx + 1], pl[a][ty + 2][tx + 3], pl[a][ty + 2][tx + 4]) * ihx;
+                    g[a][1] = dcen_nc(pl[a][ty][tx + 2], pl[a][ty + 1][tx + 2], pl[a][ty + 3][tx + 2], pl[a][ty + 4][tx + 2]) * ihy;
+                    g[a][2] = dcen_nc(Wz[0][a], Wz[1][a], Wz[3][a], Wz[4][a]) * ihz;
+                }
+                if constexpr (DIAG) {
+                    if (good & 4u) {
+                        // vorticity of the velocity, as the diagnostics kernel forms it
+                        const double ox = g[2][1] - g[1][2], oy = g[0][2] - g[2][0], oz = g[1][0] - g[0][1];
+                        if (isfinite(ox) && isfinite(oy) && isfinite(oz)) acc[1] += 0.5 * (ox * ox + oy * oy + oz * oz);
+                    }
                 }
                 T div = g[0][0] + g[1][1] + g[2][2];
                 T tdiv = T(2) / T(3) * div;
@@ -290,7 +372,9 @@ __global__ __launch_bounds__(kPointThreads) void k_visc_flux(Launch L0) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) Wz[m][c] = Wz[m + 1][c];
             slot = slot == 2 ? 0 : slot + 1;
+            good >>= 1;
         }
+        if constexpr (DIAG) block_reduce_diag(acc, red, glob(b.part) + (size_t)lb * CNS_NDIAG, one);
     }
 }
 
@@ -1124,7 +1208,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(Launch L0) {
     for (long long vb = blockIdx.x; vb < L.total; vb += gridDim.x) {
         const int bi = (int)vb;  // one virtual block per box
         const BoxDesc &bx = L.boxes[bi];
-        const int nblk = diag_blocks(bx.nx, bx.ny, bx.nz);
+        const int nblk = L.diag_fused ? (int)diag_tiles(bx.nx, bx.ny, bx.nz) : diag_blocks(bx.nx, bx.ny, bx.nz);
         double acc[CNS_NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int b = threadIdx.x; b < nblk; b += kDiagThreads)
 #pragma unroll
@@ -1324,12 +1408,13 @@ void launch_fill(int prec, size_t n, void *out, hipStream_t s) {
     else hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, s, n, (float *)out);
 }
 
-template <typename T>
+template <typename T, bool DIAG = false>
 static void visc_fields(const Batch &bt, Launch L) {
     L = with_family(bt, L, F_VISC);
     if (!L.total) return;
     ProfScope ps(bt.prof, K_VISC_FLUX, bt.stream);
-    hipLaunchKernelGGL(k_visc_flux<T>, dim3(grid_of(bt, F_VISC, L.total)), dim3(kPointThreads), 0, bt.stream, L);
+    hipLaunchKernelGGL((k_visc_flux<T, DIAG>), dim3(grid_of(bt, F_VISC, L.total)), dim3(kPointThreads), 0, bt.stream,
+                       L);
 }
 
 template <typename T, int DIR, int MODE, bool VISC>
@@ -1533,9 +1618,29 @@ void launch_diag_static(char *scratch_dev, const BoxDesc &b, int prec, const voi
 
 
 
+// The first stage's viscous-flux launch of a step, forming the diagnostics of the state
+// it reads (record diag_prev) when diag_prev >= 0 (FP64, viscous batches), then their
+// per-box reduction.
+template <typename T>
+static void first_visc(const Batch &bt, Launch L, double *diag, long long stride, int diag_prev) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (diag_prev >= 0) {
+            L.diag = diag;
+            L.diag_box_stride = stride;
+            L.step = diag_prev;
+            L.diag_fused = 1;
+            visc_fields<T, true>(bt, L);
+            const Launch F = with_family(bt, L, F_BOX);
+            hipLaunchKernelGGL(k_diag_final, dim3(grid_for(F.total)), dim3(kDiagThreads), 0, bt.stream, F);
+            return;
+        }
+    }
+    visc_fields<T>(bt, L);
+}
+
 template <typename T>
 static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step,
-                       void *const *stage_states) {
+                       void *const *stage_states, int diag_prev, bool diag_own) {
     // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, U_4 -> A, u^{n+1} -> u;
     // with stage_states, A is U2's buffer for stages 1-2 and U4's for stages 3-4, B is U3's
     const int in_of[4] = {BUF_U, BUF_A, BUF_B, BUF_A};
@@ -1551,7 +1656,10 @@ static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *
             L.b_ov = stage_states[1];
         }
         L.dt_ov = dt_ov;
-        if (bt.any_visc) visc_fields<T>(bt, L);
+        if (bt.any_visc) {
+            if (s == 0) first_visc<T>(bt, L, diag, stride, diag_prev);
+            else visc_fields<T>(bt, L);
+        }
         sweep_x<T>(bt, L, bt.any_visc);
         {
             ProfScope ps(bt.prof, K_SWEEP_Y, bt.stream);
@@ -1560,18 +1668,18 @@ static void rk4_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *
         ProfScope ps(bt.prof, K_SWEEP_Z, bt.stream);
         sweep<T, MODE_RK>(bt, L, 2, bt.any_visc);
     }
-    if (diag) diag_t<T>(bt, u_ov, diag, stride, step);
+    if (diag && diag_own) diag_t<T>(bt, u_ov, diag, stride, step);
 }
 
 void launch_rk4_step(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride, int step,
-                     void *const *stage_states) {
-    if (bt.prec == CNS_FP64) rk4_step_t<double>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
-    else rk4_step_t<float>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
+                     void *const *stage_states, int diag_prev, bool diag_own) {
+    if (bt.prec == CNS_FP64) rk4_step_t<double>(bt, u_ov, dt_ov, diag, stride, step, stage_states, diag_prev, diag_own);
+    else rk4_step_t<float>(bt, u_ov, dt_ov, diag, stride, step, stage_states, diag_prev, diag_own);
 }
 
 template <typename T>
 static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, double *diag, long long stride,
-                          int step, void *const *stage_states) {
+                          int step, void *const *stage_states, int diag_prev, bool diag_own) {
     // stage s reads U_s and writes U_{s+1}: U_1 = u, U_2 -> A, U_3 -> B, u^{n+1} -> u;
     // with stage_states, A is stage_states[0] and B stage_states[1]
     const int in_of[3] = {BUF_U, BUF_A, BUF_B};
@@ -1588,7 +1696,10 @@ static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, doubl
             L.a_ov = stage_states[0];
             L.b_ov = stage_states[1];
         }
-        if (bt.any_visc) visc_fields<T>(bt, L);
+        if (bt.any_visc) {
+            if (s == 0) first_visc<T>(bt, L, diag, stride, diag_prev);
+            else visc_fields<T>(bt, L);
+        }
         sweep_x<T>(bt, L, bt.any_visc);
         {
             ProfScope ps(bt.prof, K_SWEEP_Y, bt.stream);
@@ -1597,14 +1708,16 @@ static void tvdrk3_step_t(const Batch &bt, const void *u_ov, double dt_ov, doubl
         ProfScope ps(bt.prof, K_SWEEP_Z, bt.stream);
         sweep<T, MODE_RK>(bt, L, 2, bt.any_visc);
     }
-    if (diag) diag_t<T>(bt, u_ov, diag, stride, step);
+    if (diag && diag_own) diag_t<T>(bt, u_ov, diag, stride, step);
 }
 
 void launch_step(const Batch &bt, int scheme, const void *u_ov, double dt_ov, double *diag, long long stride,
-                 int step, void *const *stage_states) {
-    if (scheme == CNS_RK4) return launch_rk4_step(bt, u_ov, dt_ov, diag, stride, step, stage_states);
-    if (bt.prec == CNS_FP64) tvdrk3_step_t<double>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
-    else tvdrk3_step_t<float>(bt, u_ov, dt_ov, diag, stride, step, stage_states);
+                 int step, void *const *stage_states, int diag_prev, bool diag_own) {
+    if (scheme == CNS_RK4)
+        return launch_rk4_step(bt, u_ov, dt_ov, diag, stride, step, stage_states, diag_prev, diag_own);
+    if (bt.prec == CNS_FP64)
+        tvdrk3_step_t<double>(bt, u_ov, dt_ov, diag, stride, step, stage_states, diag_prev, diag_own);
+    else tvdrk3_step_t<float>(bt, u_ov, dt_ov, diag, stride, step, stage_states, diag_prev, diag_own);
 }
 
 float time_sweeps_yz(const Batch &bt, int reps) {
@@ -1669,8 +1782,8 @@ long long resident_sweep_blocks(const Batch &bt) {
 long long resident_tile_blocks(const Batch &bt) {
     int n = 0;
     hipError_t e = bt.prec == CNS_FP64
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_visc_flux<double>, kPointThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_visc_flux<float>, kPointThreads, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_visc_flux<double, false>, kPointThreads, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_visc_flux<float, false>, kPointThreads, 0);
     return (e == hipSuccess && n > 0 ? n : 1) * cu_count();
 }
 

@@ -153,3 +153,18 @@ def test_jumps_along_long_rows(orc, shape, strength):
     err = rel_max(plan.rhs(u).cpu().numpy(), orc.rhs(u_ref, ph))
     print(f"  full rhs: rel err {err:.3e}")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-30, 1e30])
+def test_extreme_eps_across_strong_jumps(orc, eps):
+    # the ends of the admitted eps range: the FP64 weights form products of up to eight
+    # (eps + beta) factors (both reconstructions of a scalar share one reciprocal), which
+    # must stay finite and normal at pressure jumps of 1e5 as well as on smooth data
+    case(f"eps={eps} strong jumps")
+    rho, vel, p = I.shock_primitives(SHAPE, 1, seed=50, strength="strong")
+    ph = orc.make_phys(mu_eff=0.01, weno_eps=eps)
+    u_ref = orc.init_state(rho, vel, p)
+    plan = Plan(SHAPE, mu_eff=0.01, weno_eps=eps)
+    err = rel_max(plan.rhs(plan.init_state(rho, vel, p)).cpu().numpy(), orc.rhs(u_ref, ph))
+    print(f"  rel err {err:.3e}")
+    assert err <= 1e-12

@@ -176,6 +176,31 @@ def test_diagnostics_match_oracle(orc):
     np.testing.assert_allclose(d, dref, rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("shape,precision,mu", [((20, 12, 36), "fp64", 0.01), ((16, 8, 272), "fp64", 0.01), ((256, 8, 16), "fp64", 0.01),
+                                                ((20, 12, 36), "mixed", 0.01), ((20, 12, 36), "fp64", 0.0)])
+def test_step_diagnostics_from_the_next_step(orc, shape, precision, mu):
+    """In FP64 viscous runs a step's diagnostics are formed by the next step's first
+    viscous-flux launch (the last step's by the diagnostics kernels): the states must be
+    bitwise those of a run without diagnostics, and every record must match the oracle's
+    diagnostics of the oracle's state (and the record of a one-step run, which the
+    diagnostics kernels form)."""
+    case(f"per-step diagnostics {shape} {precision} mu={mu}")
+    plan, ph, rho, vel, p = setup(orc, shape, mu=mu, precision=precision)
+    u_ref = orc.init_state(rho, vel, p)
+    dt = I.dt_from_speed(orc.diag(u_ref, ph)[7], max(shape))
+    u1 = plan.init_state(rho, vel, p)
+    u2 = plan.init_state(rho, vel, p)
+    d = plan.rk4(u1, dt, 4).cpu().numpy()
+    plan.rk4(u2, dt, 4, diag=False)
+    assert torch.equal(u1, u2)
+    u3 = plan.init_state(rho, vel, p)
+    d1 = plan.rk4(u3, dt, 1).cpu().numpy()
+    np.testing.assert_allclose(d[0], d1[0], rtol=1e-12, atol=1e-15)
+    if precision == "fp64":
+        _, dref = orc.rk4(u_ref, dt, 4, ph)
+        np.testing.assert_allclose(d, dref, rtol=1e-11, atol=1e-14)
+
+
 def test_bad_points_are_reported(orc):
     case("bad points")
     plan, ph, rho, vel, p = setup(orc, (16, 16, 16))

@@ -789,6 +789,12 @@ def summarize(d, title):
         lines.append(f"| `{short}` | {ns / 1e6:.3f} | {fb / 1e9:.2f} | {wb / 1e9:.2f} | {tbs:.2f} | "
                      f"{tbs * 1e3 / PEAK_HBM_GBS:.2f} | " + (f"{tbs * 1e3 / copy_GBs:.2f}" if copy_GBs else "-") +
                      " | " + (f"{alg / 1e9:.2f} | {alg / (fb + wb):.2f} |" if alg else "- | - |"))
+    traced_only = sorted(set(dur) - set(fetch), key=lambda k: -sum(dur[k]))
+    if traced_only:
+        # launched by the multi-step kernel trace only (the counter runs take one step)
+        lines += ["", "In the kernel trace only (the counter runs take one step): " + "; ".join(
+            f"`{k.split('(')[0].replace('void ', '').replace('cns::', '')}` {len(dur[k])} launches, "
+            f"{sum(dur[k]) / len(dur[k]) / 1e6:.3f} ms average" for k in traced_only) + "."]
     lines += ["", "Algorithmic bytes: every array element a kernel must read or write, once (the z sweep with "
                   "the fused update averaged over the four RK4 stages).  Kernel times: the kernel trace of the first "
                   "command."]

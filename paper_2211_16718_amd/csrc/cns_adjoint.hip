@@ -61,53 +61,67 @@ __device__ __forceinline__ size_t shift_idx(const AdjGeom &g, int i, int j, int 
 // Convective adjoint along DIR, fused with the gather: ubar(=|+=) sum over the six
 // interfaces that read each cell of their contributions.
 //
-// A block of TA x TB = 256 threads owns TB whole periodic lines along DIR and marches
-// along them in chunks of TA interfaces.  Each thread forms the product of one
-// interface (j+1/2, cells j-2 .. j+3), then adds its contributions to an LDS ring of
-// cell accumulators in six phases: in phase m every thread adds the contribution to
-// its cell j+m-2, so within a phase no two threads touch one cell, and the order of
-// the additions into every cell is fixed (deterministic, no atomics).
+// A block of 256 threads owns TB whole periodic lines along DIR and marches along
+// them in chunks of TA interfaces; each wave owns LW of the lines and all TA
+// interfaces of a chunk on them (x: one row, 64 interfaces; y, z: 8 lines consecutive
+// in x, 8 interfaces each).  Each thread forms the product of one interface (j+1/2,
+// cells j-2 .. j+3) and adds its terms, as they are formed, to two LDS rings of cell
+// accumulators: the adjoints of the cells' point fluxes (ringF) and those of their
+// states through the dissipation (ringU).  Every cell of a wave's lines is touched by
+// that wave alone, and a wave's LDS operations take effect in program order, so no
+// barrier orders the additions; they are LDS atomic adds, and the six terms of one
+// instruction (cells j-2+m of the interfaces j of the wave) go to six different
+// cells, so the order of the additions into every cell is fixed (deterministic).  A
+// complete cell leaves as J(u)^T ringF + ringU, J the Jacobian of the point flux: the
+// transpose is applied once per cell instead of once per interface and cell.
 //
 // Cells are indexed along the line without wrapping, e = -2 .. n+2; e and e+n are
 // the same grid cell.  After the chunk with interfaces I .. I+TA-1 the cells up to
-// I+TA-3 are complete: cells 3 .. n-3 are written out, and the partial sums of cells
-// -2 .. 2 are set aside ("head") until the last chunk adds the rest of those five
-// grid cells (e = n-2 .. n+2).  The ring holds RS >= 2 TA + 5 cells: the cells being
-// written out after one chunk and the cells touched by the next never share a slot,
-// so no barrier separates them, and a slot is cleared as soon as its cell is out.
-// x: TA = 64 lanes along the row, TB = 4 rows; y, z: TA = 8 along the line, TB = 32
-// lanes across x (coalesced loads and stores in every direction).  Before each
-// chunk the block stages the states of the cells I-2 .. I+TA+2 of its lines in
-// LDS, so the stages of the interface product, which re-read the states rather
-// than hold them, read LDS instead of the caches.
+// I+TA-3 are complete: cells 3 .. n-3 are written out, and the finished parts of
+// cells -2 .. 2 are set aside ("head") until the last chunk adds the rest of those
+// five grid cells (e = n-2 .. n+2); the transpose is linear, so the two parts are
+// transposed separately.  The rings hold RS >= TA + 5 cells, the cells one chunk
+// touches.  Before each chunk the block stages the states of the cells I-2 .. I+TA+2
+// of its lines in LDS (coalesced along x in every direction), so the stages of the
+// interface product, which re-read the states rather than hold them, and the
+// transposes at write-out read LDS instead of the caches.
 // ---------------------------------------------------------------------------
 template <int DIR> struct AdjConvShape;
-template <> struct AdjConvShape<0> { static constexpr int TA = 64, TB = 4, RS = 256; };
-template <> struct AdjConvShape<1> { static constexpr int TA = 8, TB = 32, RS = 32; };
-template <> struct AdjConvShape<2> { static constexpr int TA = 8, TB = 32, RS = 32; };
+template <> struct AdjConvShape<0> { static constexpr int TA = 64, LW = 1, RS = 128; };
+template <> struct AdjConvShape<1> { static constexpr int TA = 8, LW = 8, RS = 16; };
+template <> struct AdjConvShape<2> { static constexpr int TA = 8, LW = 8, RS = 16; };
 
 template <int DIR, int WW>
 __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__restrict__ u,
                                                      const double *__restrict__ rbar, double *__restrict__ ubar,
                                                      int accumulate) {
     using S = AdjConvShape<DIR>;
-    constexpr int TA = S::TA, TB = S::TB, RS = S::RS;
+    constexpr int TA = S::TA, LW = S::LW, RS = S::RS, TB = 4 * LW;
     constexpr int NC = TA + 5;  // staged cells per line
-    __shared__ double ring[TB * 5 * RS];
+    static_assert(TA * LW == 64 && RS >= TA + 5 && (RS & (RS - 1)) == 0, "chunk shape");
+    // staged state of line l, component v, cell k: x: (l * 5 + v) * NC + k; y, z:
+    // k * KS + v * TB + l, the cell stride padded so that the eight cells a wave reads
+    // in one instruction fall in both halves of the LDS banks
+    constexpr int KS = 5 * TB + 8;
+    constexpr int cs = DIR == 0 ? NC : TB;  // component stride of stg
+    __shared__ double ringF[4 * 5 * RS * LW];
+    __shared__ double ringU[4 * 5 * RS * LW];
     __shared__ double head[TB * 25];
-    __shared__ double stg[TB * 5 * NC];
-    // lane roles: ta along the line, tb across lines; lanes are consecutive in x
-    const int ta = DIR == 0 ? (int)threadIdx.x % TA : (int)threadIdx.x / TB;
-    const int tb = DIR == 0 ? (int)threadIdx.x / TA : (int)threadIdx.x % TB;
-    // ring slot of cell e for component v (conflict-free for the phase pattern)
-    auto slot = [&](int e, int v) -> int {
-        const int r = (e + 2) & (RS - 1);
-        return DIR == 0 ? (tb * 5 + v) * RS + r : (r * 5 + v) * TB + tb;
-    };
+    __shared__ double stg[DIR == 0 ? TB * 5 * NC : NC * KS];
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const int ta = DIR == 0 ? lane : lane >> 3;  // interface within the chunk
+    const int tl = DIR == 0 ? 0 : lane & 7;      // line within the wave
+    const int tb = w * LW + tl;                   // line within the block
+    // ring slot of cell e for component v: the wave's own region, consecutive lanes
+    // on consecutive doubles
+    auto slot = [&](int e, int v) -> int { return ((w * 5 + v) * RS + ((e + 2) & (RS - 1))) * LW + tl; };
+    // offset in stg of this lane's line at staged cell k
+    auto cell = [&](int k) -> int { return DIR == 0 ? tb * 5 * NC + k : k * KS + tb; };
     const size_t n3 = g.n3;
     const int n = DIR == 0 ? g.nx : (DIR == 1 ? g.ny : g.nz);
     const size_t stride = DIR == 0 ? 1 : (DIR == 1 ? (size_t)g.nx : (size_t)g.nx * g.ny);
     const int ntx = (g.nx + TB - 1) / TB;
+    const double gm1 = g.gamma - 1.0;
     // the line of lane column t: whether it exists, and the offset of its cell 0
     auto line = [&](int t, size_t &lb) -> bool {
         if (DIR == 0) {
@@ -119,84 +133,104 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
         lb = (DIR == 1 ? (size_t)o * g.nx * g.ny : (size_t)o * g.nx) + (size_t)x;
         return x < g.nx;
     };
+    // the finished adjoint of cell e, staged at k: J^T ringF + ringU
+    auto finish = [&](int e, int k, double out[5]) {
+        double wc[5], fb[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            wc[v] = stg[v * cs + cell(k)];
+            fb[v] = ringF[slot(e, v)];
+            out[v] = ringU[slot(e, v)];
+        }
+        euler_flux_vjp<DIR>(wc, gm1, fb, out);
+    };
     size_t base;
     const bool lane_ok = line(tb, base);
     const double ih = g.ih[DIR];
-    for (int t = threadIdx.x; t < TB * 5 * RS; t += 256) ring[t] = 0.0;
-    __syncthreads();
+    for (int t = threadIdx.x; t < 4 * 5 * RS * LW; t += 256) {
+        ringF[t] = 0.0;
+        ringU[t] = 0.0;
+    }
     int I = 0;
     for (;; I += TA) {
+        // the previous chunk's write-out has read stg
+        __syncthreads();
         // stage cells I-2 .. I+TA+2 (any number of periods: short lines wrap more than once)
         for (int t = threadIdx.x; t < TB * 5 * NC; t += 256) {
-            int k, v, l;
+            int k, v, l, at;
             if (DIR == 0) {
                 k = t % NC;
                 v = (t / NC) % 5;
                 l = t / (5 * NC);
+                at = t;
             } else {
                 l = t % TB;
                 v = (t / TB) % 5;
                 k = t / (5 * TB);
+                at = k * KS + v * TB + l;
             }
             size_t lb;
             const bool ok = line(l, lb);
-            int cell = (I - 2 + k) % n;
-            if (cell < 0) cell += n;
-            stg[t] = ok ? u[v * n3 + lb + (size_t)cell * stride] : 0.0;
+            int c = (I - 2 + k) % n;
+            if (c < 0) c += n;
+            stg[at] = ok ? u[v * n3 + lb + (size_t)c * stride] : 0.0;
         }
         __syncthreads();
         const int j = I + ta;
-        const bool act = lane_ok && j < n;
-        double wb[6][5];
-        if (act) {
+        if (lane_ok && j < n) {
             // cell j-2+m is staged cell ta+m
             int c[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) c[m] = DIR == 0 ? tb * 5 * NC + ta + m : (ta + m) * 5 * TB + tb;
+            for (int m = 0; m < 6; ++m) c[m] = cell(ta + m);
             const size_t p = base + (size_t)j * stride, pn = base + (size_t)wrapj(j + 1, n) * stride;
             double Hb[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) Hb[v] = (rbar[v * n3 + pn] - rbar[v * n3 + p]) * ih;
-            interface_flux_vjp<DIR, WW>(stg, DIR == 0 ? NC : TB, c, Hb, g.gamma, g.eps, g.delta, wb);
+            interface_flux_vjp<DIR, WW>(
+                stg, cs, c, Hb, g.gamma, g.eps, g.delta,
+                [&](int m, int v, double x) { atomicAdd(&ringF[slot(j + m - 2, v)], x); },
+                [&](int m, int v, double x) { atomicAdd(&ringU[slot(j + m - 2, v)], x); });
         }
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            if (act) {
-#pragma unroll
-                for (int v = 0; v < 5; ++v) ring[slot(j + m - 2, v)] += wb[m][v];
-            }
-            __syncthreads();
-        }
+        // every addition of this wave precedes the reads of the write-out
+        adj_stage_fence();
         const bool last = I + TA >= n;
         const int e = I - 2 + ta;  // completed by this chunk (all of them unless last)
         if (lane_ok && e <= 2) {
+            double out[5];
+            finish(e, ta, out);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) head[tb * 25 + (e + 2) * 5 + v] = ring[slot(e, v)];
+            for (int v = 0; v < 5; ++v) head[tb * 25 + (e + 2) * 5 + v] = out[v];
         } else if (lane_ok && !last && e <= n - 3) {
+            double out[5];
+            finish(e, ta, out);
             const size_t q = base + (size_t)e * stride;
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double s = ring[slot(e, v)];
-                if (accumulate) ubar[v * n3 + q] += s;
-                else ubar[v * n3 + q] = s;
+                if (accumulate) ubar[v * n3 + q] += out[v];
+                else ubar[v * n3 + q] = out[v];
             }
         }
-        if (!last) {
+        if (last) break;
+        adj_stage_fence();
 #pragma unroll
-            for (int v = 0; v < 5; ++v) ring[slot(e, v)] = 0.0;
-        } else {
-            break;
+        for (int v = 0; v < 5; ++v) {
+            ringF[slot(e, v)] = 0.0;
+            ringU[slot(e, v)] = 0.0;
         }
+        adj_stage_fence();
     }
-    __syncthreads();
-    // the rest of the line: cells max(I-2, 3) .. n+2, folding e >= n-2 with the head
+    // the rest of the line: cells max(I-2, 3) .. n+2 (staged at e - (I-2)), folding
+    // e >= n-2 with the head; the wave reads only what it wrote itself
+    adj_stage_fence();
     for (int e = I - 2 + ta; e <= n + 2; e += TA) {
         if (!lane_ok || e < 3) continue;
         const int r = e >= n ? e - n : e;
         const size_t q = base + (size_t)r * stride;
+        double out[5];
+        finish(e, e - (I - 2), out);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            double s = ring[slot(e, v)];
+            double s = out[v];
             if (e >= n - 2) s += head[tb * 25 + (e - n + 2) * 5 + v];
             if (accumulate) ubar[v * n3 + q] += s;
             else ubar[v * n3 + q] = s;

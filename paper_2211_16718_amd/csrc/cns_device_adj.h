@@ -85,6 +85,32 @@ __device__ __forceinline__ void weno_side_vjp(double s1, double s2, double s3, d
     }
 }
 
+// One Jiang-Shu side in the scaled form of the forward (weno5_lr6): candidates Q_k six
+// times the plain ones, S_k = 4 (eps + beta_k), weights w_k = g_k A_k / sum with
+// g = (1, 6, 3), A_k = t_k^2 and t_k the product of the other two S.  Given the
+// adjoint Vb6 of V6 = sum w_k Q_k: V6, the candidate adjoints Qb_k = Vb6 w_k and TWICE
+// the adjoints of S_k, from dV6/dS_k = -2 w_k (Q_k - V6) / S_k with 1/S_k = t_k / P,
+// P = S1 S2 S3 (one reciprocal, of P sum).
+__device__ __forceinline__ void js_side_vjp(double S1, double S2, double S3, double Q1, double Q2, double Q3,
+                                            double Vb6, double &V6, double Qb[3], double Sb2[3]) {
+    const double t1 = S2 * S3, t2 = S1 * S3, t3 = S1 * S2;
+    const double A1 = t1 * t1, A2 = t2 * t2, A3 = t3 * t3;
+    const double P = t1 * S1;
+    const double sum = A1 + 6.0 * A2 + 3.0 * A3;
+    const double num = A1 * Q1 + (6.0 * A2) * Q2 + (3.0 * A3) * Q3;
+    const double iD = rcp(P * sum);
+    const double iS = P * iD;
+    V6 = num * iS;
+    const double h = Vb6 * iS;
+    Qb[0] = h * A1;
+    Qb[1] = (6.0 * h) * A2;
+    Qb[2] = (3.0 * h) * A3;
+    const double g = -4.0 * Vb6 * iD;
+    Sb2[0] = g * ((Q1 - V6) * (A1 * t1));
+    Sb2[1] = (6.0 * g) * ((Q2 - V6) * (A2 * t2));
+    Sb2[2] = (3.0 * g) * ((Q3 - V6) * (A3 * t3));
+}
+
 // ---------------------------------------------------------------------------
 // WENO5 pair (weno5_lr with the weights WW): given the adjoints Lb, Rb of the left-
 // and right-biased values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5]
@@ -94,6 +120,41 @@ template <int WW = CNS_WENO_JS>
 __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, double Lb, double Rb, double qb[6],
                                              double &Lv, double &Rv) {
     const double m2 = q[0], m1 = q[1], c0 = q[2], p1 = q[3], p2 = q[4], p3 = q[5];
+    if constexpr (WW == CNS_WENO_JS) {
+        // six times the candidates; the right-biased side reuses L2, L3 mirrored
+        const double L1 = 2.0 * m2 - 7.0 * m1 + 11.0 * c0;
+        const double L2 = -m1 + 5.0 * c0 + 2.0 * p1;
+        const double L3 = 2.0 * c0 + 5.0 * p1 - p2;
+        const double R1 = 2.0 * p3 - 7.0 * p2 + 11.0 * p1;
+        const double da = m2 - 2.0 * m1 + c0, db = m1 - 2.0 * c0 + p1, dc = c0 - 2.0 * p1 + p2,
+                     dd = p1 - 2.0 * p2 + p3;
+        const double ea = m2 - 4.0 * m1 + 3.0 * c0, eb = m1 - p1, ec = 3.0 * c0 - 4.0 * p1 + p2;
+        const double fa = p3 - 4.0 * p2 + 3.0 * p1, fb = p2 - c0, fc = 3.0 * p1 - 4.0 * c0 + m1;
+        // S = 4 eps + (13/3) d^2 + e^2
+        const double k = 13.0 / 3.0, e4 = 4.0 * eps;
+        const double kda = k * da, kdb = k * db, kdc = k * dc, kdd = k * dd;
+        const double sb = kdb * db + e4, sc = kdc * dc + e4;
+        const double SL1 = (kda * da + e4) + ea * ea, SL2 = sb + eb * eb, SL3 = sc + ec * ec;
+        const double SR1 = (kdd * dd + e4) + fa * fa, SR2 = sc + fb * fb, SR3 = sb + fc * fc;
+        double VL, VR, QL[3], QR[3], BL[3], BR[3];
+        js_side_vjp(SL1, SL2, SL3, L1, L2, L3, Lb * (1.0 / 6.0), VL, QL, BL);
+        js_side_vjp(SR1, SR2, SR3, R1, L3, L2, Rb * (1.0 / 6.0), VR, QR, BR);
+        Lv = VL * (1.0 / 6.0);
+        Rv = VR * (1.0 / 6.0);
+        // adjoints of the candidates, and of d and e through S (dS/dd = 2 k d, dS/de = 2 e;
+        // BL, BR carry the factor 2)
+        const double cL1 = QL[0], cL2 = QL[1] + QR[2], cL3 = QL[2] + QR[1], cR1 = QR[0];
+        const double dab = kda * BL[0], dbb = kdb * (BL[1] + BR[2]), dcb = kdc * (BL[2] + BR[1]), ddb = kdd * BR[0];
+        const double eab = ea * BL[0], ebb = eb * BL[1], ecb = ec * BL[2];
+        const double fab = fa * BR[0], fbb = fb * BR[1], fcb = fc * BR[2];
+        qb[0] += dab + eab + 2.0 * cL1;
+        qb[1] += -2.0 * dab + dbb - 4.0 * eab + ebb + fcb - 7.0 * cL1 - cL2;
+        qb[2] += dab - 2.0 * dbb + dcb + 3.0 * eab + 3.0 * ecb - fbb - 4.0 * fcb + 11.0 * cL1 + 5.0 * cL2 + 2.0 * cL3;
+        qb[3] += dbb - 2.0 * dcb + ddb - ebb - 4.0 * ecb + 3.0 * fab + 3.0 * fcb + 2.0 * cL2 + 5.0 * cL3 + 11.0 * cR1;
+        qb[4] += dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb - cL3 - 7.0 * cR1;
+        qb[5] += ddb + fab + 2.0 * cR1;
+        return;
+    }
     const double r6 = 1.0 / 6.0, k13 = 13.0 / 12.0;
     const double L1 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0) * r6;
     const double L2 = (-m1 + 5.0 * c0 + 2.0 * p1) * r6;
@@ -144,47 +205,26 @@ __device__ __forceinline__ double euler_flux_comp(const double w[5], double gm1,
     return w[v] * vn + (v == 1 + DIR ? p : 0.0);
 }
 
-// wb += (df/dw)^T fb for the convective flux along DIR (the Euler flux Jacobian)
+// wb += (df/dw)^T fb for the convective flux along DIR (the Euler flux Jacobian).
+// With v = m / rho, K = |v|^2 / 2, p = (gamma-1)(e - rho K), H = (e + p) / rho,
+// phi = fb[1..3], psi = fb[4] and s = (gamma-1)(phi_n + psi v_n):
+//   rho:  s K - v_n (phi.v + psi H)
+//   m_j:  v_n phi_j - s v_j, plus fb[0] + phi.v + psi H for j = n
+//   e:    s + psi v_n
 template <int DIR>
 __device__ __forceinline__ void euler_flux_vjp(const double w[5], double gm1, const double fb[5], double wb[5]) {
     const double inv = rcp(w[0]);
     const double v[3] = {w[1] * inv, w[2] * inv, w[3] * inv};
-    const double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const double p = gm1 * (w[4] - 0.5 * w[0] * q2);
+    const double K = 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double p = gm1 * (w[4] - w[0] * K);
     const double H = (w[4] + p) * inv;
     const double vn = v[DIR];
-    // dp/drho = gm1 q2/2, dp/dm_k = -gm1 v_k, dp/de = gm1;  dvn/drho = -vn/rho, dvn/dm_n = 1/rho
-    double rb = 0.0, mb[3] = {0.0, 0.0, 0.0}, eb = 0.0;
-    // f0 = m_n
-    mb[DIR] += fb[0];
-    // f_{1+k} = m_k vn + delta_kn p
+    const double s = gm1 * (fb[1 + DIR] + fb[4] * vn);
+    const double dotH = fb[1] * v[0] + fb[2] * v[1] + fb[3] * v[2] + fb[4] * H;
+    wb[0] += s * K - vn * dotH;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double g = fb[1 + k];
-        rb += g * (-v[k] * vn);
-        mb[k] += g * vn;
-        mb[DIR] += g * v[k];
-        if (k == DIR) {
-            rb += g * (0.5 * gm1 * q2);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) mb[j] += g * (-gm1 * v[j]);
-            eb += g * gm1;
-        }
-    }
-    // f4 = (e + p) vn = rho H vn
-    {
-        const double g = fb[4];
-        rb += g * vn * (0.5 * gm1 * q2 - H);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) mb[j] += g * (-gm1 * v[j] * vn);
-        mb[DIR] += g * H;
-        eb += g * (1.0 + gm1) * vn;
-    }
-    wb[0] += rb;
-    wb[1] += mb[0];
-    wb[2] += mb[1];
-    wb[3] += mb[2];
-    wb[4] += eb;
+    for (int j = 0; j < 3; ++j) wb[1 + j] += vn * fb[1 + j] - s * v[j] + (j == DIR ? fb[0] + dotH : 0.0);
+    wb[4] += s + fb[4] * vn;
 }
 
 // ---------------------------------------------------------------------------
@@ -371,69 +411,60 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
 }
 
 // ---------------------------------------------------------------------------
-// convective interface flux H (interface_flux without the viscous part): given
-// Hb, ASSIGN to wb[m] the adjoints of the six cell states j-2 .. j+3, which sit
-// at offsets c[0..5] of the array st (component stride cs; the caller stages
-// them in LDS).
-//
-// The six states and their adjoints do not fit in registers together with the
-// intermediates of the Roe and WENO products, so the states are read again from
-// st at each stage instead of being held, and the compiler barrier between
-// stages keeps it from merging the loads back into one live set.  The
-// stage with the most live values, the reconstructed point fluxes (their 30
-// values, then their 30 adjoints in place), runs first, while wb is not yet live;
-// the Roe dissipation and the reconstructed states follow.
+// Convective interface flux H = (FL + FR)/2 - D/2 (interface_flux without the viscous
+// part), transposed for the six cell states j-2 .. j+3, which sit at offsets c[0..5]
+// of the array st (component stride cs; the caller stages them in LDS).  The
+// contributions leave through two callbacks as soon as they are formed, so that no
+// 6 x 5 array of them is ever held:
+//   addF(m, v, x): x is a term of the adjoint of the POINT FLUX of cell j-2+m, component
+//     v (each reconstruction carries Hb/2); the flux Jacobian transpose that takes it to
+//     the cell state is linear in it, so the caller sums these terms over the six
+//     interfaces that read a cell and applies the transpose once per cell;
+//   addU(m, v, x): a term of the adjoint of the STATE of cell j-2+m, through the Roe
+//     dissipation and the reconstructed states.
+// For each (m, v) the terms are produced in a fixed order.  The states are read again
+// from st at each stage instead of being held, and the compiler barrier between stages
+// keeps it from merging the loads back into one live set.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void adj_stage_fence() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int DIR, int WW>
+template <int DIR, int WW, class AddF, class AddU>
 __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, const int c[6], const double Hb[5],
-                                                   double gamma, double eps, double delta, double wb[6][5]) {
+                                                   double gamma, double eps, double delta, AddF addF, AddU addU) {
     const double gm1 = gamma - 1.0;
-    // H = (FL + FR)/2 - D/2.  Point fluxes F[m][v], then component by component the
-    // adjoints of the reconstructed fluxes FL, FR (each Hb/2), in place
-    double F[6][5];
+    {
+        // point fluxes, then component by component the adjoints of their reconstructions
+        double F[6][5];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        double w[5];
+        for (int m = 0; m < 6; ++m) {
+            double w[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) w[v] = st[v * cs + c[m]];
+            for (int v = 0; v < 5; ++v) w[v] = st[v * cs + c[m]];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) F[m][v] = euler_flux_comp<DIR>(w, gm1, v);
+            for (int v = 0; v < 5; ++v) F[m][v] = euler_flux_comp<DIR>(w, gm1, v);
+            adj_stage_fence();
+        }
         adj_stage_fence();
-    }
-    adj_stage_fence();
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int m = 0; m < 6; ++m) q[m] = F[m][v];
-        double Lv, Rv;
-        weno5_lr_vjp<WW>(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb, Lv, Rv);
-#pragma unroll
-        for (int m = 0; m < 6; ++m) F[m][v] = qb[m];
-        adj_stage_fence();
-    }
-    adj_stage_fence();
-    // through the point fluxes to the cell states
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        double w[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            w[v] = st[v * cs + c[m]];
-            wb[m][v] = 0.0;
+            double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int m = 0; m < 6; ++m) q[m] = F[m][v];
+            double Lv, Rv;
+            weno5_lr_vjp<WW>(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb, Lv, Rv);
+#pragma unroll
+            for (int m = 0; m < 6; ++m) addF(m, v, qb[m]);
+            adj_stage_fence();
         }
-        euler_flux_vjp<DIR>(w, gm1, F[m], wb[m]);
     }
-    adj_stage_fence();
     // dissipation D = M(a, b) du at cells a = j, b = j+1: first dub = M^T Db, which needs
     // no du; the reverse of the reconstructed states then yields du itself (UR - UL);
     // last the adjoints of a and b through M
     double a[5], b[5], Db[5], du[5], dub[5] = {0, 0, 0, 0, 0};
+    double ab[5] = {0, 0, 0, 0, 0}, bb[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         a[v] = st[v * cs + c[2]];
@@ -441,7 +472,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         Db[v] = -0.5 * Hb[v];
         du[v] = 0.0;
     }
-    roe_dissipation_vjp<DIR, false>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
+    roe_dissipation_vjp<DIR, false>(a, b, du, gamma, delta, Db, ab, bb, dub);
     adj_stage_fence();
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -452,7 +483,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         weno5_lr_vjp<WW>(q, eps, -dub[v], dub[v], qb, UL, UR);
         du[v] = UR - UL;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) wb[m][v] += qb[m];
+        for (int m = 0; m < 6; ++m) addU(m, v, qb[m]);
         adj_stage_fence();
     }
 #pragma unroll
@@ -460,7 +491,12 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         a[v] = st[v * cs + c[2]];
         b[v] = st[v * cs + c[3]];
     }
-    roe_dissipation_vjp<DIR, true>(a, b, du, gamma, delta, Db, wb[2], wb[3], dub);
+    roe_dissipation_vjp<DIR, true>(a, b, du, gamma, delta, Db, ab, bb, dub);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        addU(2, v, ab[v]);
+        addU(3, v, bb[v]);
+    }
 }
 
 }  // namespace cns

@@ -82,9 +82,10 @@ __device__ __forceinline__ size_t shift_idx(const AdjGeom &g, int i, int j, int 
 // five grid cells (e = n-2 .. n+2); the transpose is linear, so the two parts are
 // transposed separately.  The rings hold RS >= TA + 5 cells, the cells one chunk
 // touches.  Before each chunk the block stages the states of the cells I-2 .. I+TA+2
-// of its lines in LDS (coalesced along x in every direction), so the stages of the
-// interface product, which re-read the states rather than hold them, and the
-// transposes at write-out read LDS instead of the caches.
+// of its lines and their point fluxes along DIR in LDS (coalesced along x in every
+// direction; each flux formed once instead of by each of the six interfaces that
+// read it), so the stages of the interface product, which re-read the states rather
+// than hold them, and the transposes at write-out read LDS instead of the caches.
 // ---------------------------------------------------------------------------
 template <int DIR> struct AdjConvShape;
 template <> struct AdjConvShape<0> { static constexpr int TA = 64, LW = 1, RS = 128; };
@@ -99,15 +100,17 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
     constexpr int TA = S::TA, LW = S::LW, RS = S::RS, TB = 4 * LW;
     constexpr int NC = TA + 5;  // staged cells per line
     static_assert(TA * LW == 64 && RS >= TA + 5 && (RS & (RS - 1)) == 0, "chunk shape");
-    // staged state of line l, component v, cell k: x: (l * 5 + v) * NC + k; y, z:
-    // k * KS + v * TB + l, the cell stride padded so that the eight cells a wave reads
-    // in one instruction fall in both halves of the LDS banks
-    constexpr int KS = 5 * TB + 8;
+    // staged component v of line l, cell k (v = 0-4 the state, 5-9 its point flux along
+    // DIR): x: (l * 10 + v) * NC + k; y, z: k * KS + v * TB + l, the cell stride padded
+    // so that the eight cells a wave reads in one instruction fall in both halves of
+    // the LDS banks.  Both rings, the head and the staged cells of a block fit twice
+    // in the 160 KiB of LDS of a compute unit.
+    constexpr int KS = 10 * TB + 8;
     constexpr int cs = DIR == 0 ? NC : TB;  // component stride of stg
     __shared__ double ringF[4 * 5 * RS * LW];
     __shared__ double ringU[4 * 5 * RS * LW];
     __shared__ double head[TB * 25];
-    __shared__ double stg[DIR == 0 ? TB * 5 * NC : NC * KS];
+    __shared__ double stg[DIR == 0 ? TB * 10 * NC : NC * KS];
     const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
     const int ta = DIR == 0 ? lane : lane >> 3;  // interface within the chunk
     const int tl = DIR == 0 ? 0 : lane & 7;      // line within the wave
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
     // on consecutive doubles
     auto slot = [&](int e, int v) -> int { return ((w * 5 + v) * RS + ((e + 2) & (RS - 1))) * LW + tl; };
     // offset in stg of this lane's line at staged cell k
-    auto cell = [&](int k) -> int { return DIR == 0 ? tb * 5 * NC + k : k * KS + tb; };
+    auto cell = [&](int k) -> int { return DIR == 0 ? tb * 10 * NC + k : k * KS + tb; };
     const size_t n3 = g.n3;
     const int n = DIR == 0 ? g.nx : (DIR == 1 ? g.ny : g.nz);
     const size_t stride = DIR == 0 ? 1 : (DIR == 1 ? (size_t)g.nx : (size_t)g.nx * g.ny);
@@ -155,25 +158,24 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
     for (;; I += TA) {
         // the previous chunk's write-out has read stg
         __syncthreads();
-        // stage cells I-2 .. I+TA+2 (any number of periods: short lines wrap more than once)
-        for (int t = threadIdx.x; t < TB * 5 * NC; t += 256) {
-            int k, v, l, at;
-            if (DIR == 0) {
-                k = t % NC;
-                v = (t / NC) % 5;
-                l = t / (5 * NC);
-                at = t;
-            } else {
-                l = t % TB;
-                v = (t / TB) % 5;
-                k = t / (5 * TB);
-                at = k * KS + v * TB + l;
-            }
+        // stage cells I-2 .. I+TA+2 (any number of periods: short lines wrap more than
+        // once) and their point fluxes
+        for (int t = threadIdx.x; t < TB * NC; t += 256) {
+            const int k = DIR == 0 ? t % NC : t / TB, l = DIR == 0 ? t / NC : t % TB;
+            const int at = DIR == 0 ? l * 10 * NC + k : k * KS + l;
             size_t lb;
-            const bool ok = line(l, lb);
-            int c = (I - 2 + k) % n;
-            if (c < 0) c += n;
-            stg[at] = ok ? u[v * n3 + lb + (size_t)c * stride] : 0.0;
+            if (line(l, lb)) {
+                int c = (I - 2 + k) % n;
+                if (c < 0) c += n;
+                double wc[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) wc[v] = u[v * n3 + lb + (size_t)c * stride];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    stg[at + v * cs] = wc[v];
+                    stg[at + (5 + v) * cs] = euler_flux_comp<DIR>(wc, gm1, v);
+                }
+            }
         }
         __syncthreads();
         const int j = I + ta;

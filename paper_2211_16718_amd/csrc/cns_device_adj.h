@@ -1,6 +1,7 @@
 // cns_device_adj.h -- hand-written reverse-mode (vector-Jacobian) products of the
 // device arithmetic in cns_device.h, FP64.  Each *_vjp function recomputes the
-// forward values it needs and ADDS the input adjoints to its outputs.
+// forward values it needs and ADDS the input adjoints to its outputs (weno5_lr_vjp
+// sets them).
 #pragma once
 #include "cns_device.h"
 
@@ -94,26 +95,26 @@ __device__ __forceinline__ void weno_side_vjp(double s1, double s2, double s3, d
 __device__ __forceinline__ void js_side_vjp(double S1, double S2, double S3, double Q1, double Q2, double Q3,
                                             double Vb6, double &V6, double Qb[3], double Sb2[3]) {
     const double t1 = S2 * S3, t2 = S1 * S3, t3 = S1 * S2;
-    const double A1 = t1 * t1, A2 = t2 * t2, A3 = t3 * t3;
+    const double B1 = t1 * t1, B2 = 6.0 * (t2 * t2), B3 = 3.0 * (t3 * t3);  // g_k A_k
     const double P = t1 * S1;
-    const double sum = A1 + 6.0 * A2 + 3.0 * A3;
-    const double num = A1 * Q1 + (6.0 * A2) * Q2 + (3.0 * A3) * Q3;
+    const double sum = B1 + B2 + B3;
+    const double num = B1 * Q1 + B2 * Q2 + B3 * Q3;
     const double iD = rcp(P * sum);
     const double iS = P * iD;
     V6 = num * iS;
     const double h = Vb6 * iS;
-    Qb[0] = h * A1;
-    Qb[1] = (6.0 * h) * A2;
-    Qb[2] = (3.0 * h) * A3;
+    Qb[0] = h * B1;
+    Qb[1] = h * B2;
+    Qb[2] = h * B3;
     const double g = -4.0 * Vb6 * iD;
-    Sb2[0] = g * ((Q1 - V6) * (A1 * t1));
-    Sb2[1] = (6.0 * g) * ((Q2 - V6) * (A2 * t2));
-    Sb2[2] = (3.0 * g) * ((Q3 - V6) * (A3 * t3));
+    Sb2[0] = g * ((Q1 - V6) * (B1 * t1));
+    Sb2[1] = g * ((Q2 - V6) * (B2 * t2));
+    Sb2[2] = g * ((Q3 - V6) * (B3 * t3));
 }
 
 // ---------------------------------------------------------------------------
 // WENO5 pair (weno5_lr with the weights WW): given the adjoints Lb, Rb of the left-
-// and right-biased values at j+1/2, add dL/dq^T Lb + dR/dq^T Rb to qb[0..5]
+// and right-biased values at j+1/2, SET qb[0..5] to dL/dq^T Lb + dR/dq^T Rb
 // (q = j-2 .. j+3); the values L and R themselves are returned in Lv, Rv.
 // ---------------------------------------------------------------------------
 template <int WW = CNS_WENO_JS>
@@ -147,12 +148,12 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
         const double dab = kda * BL[0], dbb = kdb * (BL[1] + BR[2]), dcb = kdc * (BL[2] + BR[1]), ddb = kdd * BR[0];
         const double eab = ea * BL[0], ebb = eb * BL[1], ecb = ec * BL[2];
         const double fab = fa * BR[0], fbb = fb * BR[1], fcb = fc * BR[2];
-        qb[0] += dab + eab + 2.0 * cL1;
-        qb[1] += -2.0 * dab + dbb - 4.0 * eab + ebb + fcb - 7.0 * cL1 - cL2;
-        qb[2] += dab - 2.0 * dbb + dcb + 3.0 * eab + 3.0 * ecb - fbb - 4.0 * fcb + 11.0 * cL1 + 5.0 * cL2 + 2.0 * cL3;
-        qb[3] += dbb - 2.0 * dcb + ddb - ebb - 4.0 * ecb + 3.0 * fab + 3.0 * fcb + 2.0 * cL2 + 5.0 * cL3 + 11.0 * cR1;
-        qb[4] += dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb - cL3 - 7.0 * cR1;
-        qb[5] += ddb + fab + 2.0 * cR1;
+        qb[0] = dab + eab + 2.0 * cL1;
+        qb[1] = -2.0 * dab + dbb - 4.0 * eab + ebb + fcb - 7.0 * cL1 - cL2;
+        qb[2] = dab - 2.0 * dbb + dcb + 3.0 * eab + 3.0 * ecb - fbb - 4.0 * fcb + 11.0 * cL1 + 5.0 * cL2 + 2.0 * cL3;
+        qb[3] = dbb - 2.0 * dcb + ddb - ebb - 4.0 * ecb + 3.0 * fab + 3.0 * fcb + 2.0 * cL2 + 5.0 * cL3 + 11.0 * cR1;
+        qb[4] = dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb - cL3 - 7.0 * cR1;
+        qb[5] = ddb + fab + 2.0 * cR1;
         return;
     }
     const double r6 = 1.0 / 6.0, k13 = 13.0 / 12.0;
@@ -182,14 +183,14 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
     const double dbb = 2.0 * k13 * db * (bL2 + bR3), ebb = 0.5 * eb * bL2, fcb = 0.5 * fc * bR3;
     const double dcb = 2.0 * k13 * dc * (bL3 + bR2), ecb = 0.5 * ec * bL3, fbb = 0.5 * fb * bR2;
     const double ddb = 2.0 * k13 * dd * bR1, fab = 0.5 * fa * bR1;
-    qb[0] += 2.0 * r6 * cL1 + dab + eab;
-    qb[1] += -7.0 * r6 * cL1 - r6 * cL2 - 2.0 * dab + dbb - 4.0 * eab + ebb + fcb;
-    qb[2] += 11.0 * r6 * cL1 + 5.0 * r6 * cL2 + 2.0 * r6 * cL3 + dab - 2.0 * dbb + dcb + 3.0 * eab + 3.0 * ecb -
+    qb[0] = 2.0 * r6 * cL1 + dab + eab;
+    qb[1] = -7.0 * r6 * cL1 - r6 * cL2 - 2.0 * dab + dbb - 4.0 * eab + ebb + fcb;
+    qb[2] = 11.0 * r6 * cL1 + 5.0 * r6 * cL2 + 2.0 * r6 * cL3 + dab - 2.0 * dbb + dcb + 3.0 * eab + 3.0 * ecb -
              fbb - 4.0 * fcb;
-    qb[3] += 2.0 * r6 * cL2 + 5.0 * r6 * cL3 + 11.0 * r6 * cR1 + dbb - 2.0 * dcb + ddb - ebb - 4.0 * ecb + 3.0 * fab +
+    qb[3] = 2.0 * r6 * cL2 + 5.0 * r6 * cL3 + 11.0 * r6 * cR1 + dbb - 2.0 * dcb + ddb - ebb - 4.0 * ecb + 3.0 * fab +
              3.0 * fcb;
-    qb[4] += -r6 * cL3 - 7.0 * r6 * cR1 + dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb;
-    qb[5] += 2.0 * r6 * cR1 + ddb + fab;
+    qb[4] = -r6 * cL3 - 7.0 * r6 * cR1 + dcb - 2.0 * ddb + ecb - 4.0 * fab + fbb;
+    qb[5] = 2.0 * r6 * cR1 + ddb + fab;
     Lv = L;
     Rv = R;
 }
@@ -413,7 +414,8 @@ __device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const dou
 // ---------------------------------------------------------------------------
 // Convective interface flux H = (FL + FR)/2 - D/2 (interface_flux without the viscous
 // part), transposed for the six cell states j-2 .. j+3, which sit at offsets c[0..5]
-// of the array st (component stride cs; the caller stages them in LDS).  The
+// of the array st, components 0-4, with their point fluxes along DIR as components
+// 5-9 (component stride cs; the caller stages them in LDS).  The
 // contributions leave through two callbacks as soon as they are formed, so that no
 // 6 x 5 array of them is ever held:
 //   addF(m, v, x): x is a term of the adjoint of the POINT FLUX of cell j-2+m, component
@@ -434,25 +436,14 @@ __device__ __forceinline__ void adj_stage_fence() {
 template <int DIR, int WW, class AddF, class AddU>
 __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, const int c[6], const double Hb[5],
                                                    double gamma, double eps, double delta, AddF addF, AddU addU) {
-    const double gm1 = gamma - 1.0;
     {
-        // point fluxes, then component by component the adjoints of their reconstructions
-        double F[6][5];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            double w[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) w[v] = st[v * cs + c[m]];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) F[m][v] = euler_flux_comp<DIR>(w, gm1, v);
-            adj_stage_fence();
-        }
-        adj_stage_fence();
+        // component by component, the adjoints of the reconstructions of the point fluxes
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            double q[6], qb[6] = {0, 0, 0, 0, 0, 0};
+            const double *f = st + (5 + v) * cs;
+            double q[6], qb[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) q[m] = F[m][v];
+            for (int m = 0; m < 6; ++m) q[m] = f[c[m]];
             double Lv, Rv;
             weno5_lr_vjp<WW>(q, eps, 0.5 * Hb[v], 0.5 * Hb[v], qb, Lv, Rv);
 #pragma unroll
@@ -477,7 +468,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         const double *f = st + v * cs;
-        double q[6], qb[6] = {0, 0, 0, 0, 0, 0}, UL, UR;
+        double q[6], qb[6], UL, UR;
 #pragma unroll
         for (int m = 0; m < 6; ++m) q[m] = f[c[m]];
         weno5_lr_vjp<WW>(q, eps, -dub[v], dub[v], qb, UL, UR);

@@ -8,8 +8,8 @@ namespace cns {
 // What the reverse RK4 sweep does with a finished stage adjoint Ub at each point, done
 // by the last kernel of the product when the box is viscous (else by a separate launch):
 //   S = Ub (s_first) or S += Ub, when S is set;
-//   kb = a ub + b Ub, when kb is set (the next product's seed; the product that reads
-//   the current kb has finished with it by then);
+//   kb = a ub + b Ub, when kb is set (the next product's seed: a buffer other than the
+//   seed rbar of this product, which its last kernel still reads around each point);
 //   ubf = ubf + (S + Ub), when ubf is set (the step's last stage; S is read, not written);
 //   Ub itself is stored only when store_ub is set.
 struct AdjEpilogue {
@@ -24,6 +24,6 @@ struct AdjEpilogue {
 
 // adj_rhs_vjp followed by the epilogue
 void adj_rhs_vjp_epi(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
-                     double *Gb, const AdjEpilogue &epi);
+                     const AdjEpilogue &epi);
 
 }  // namespace cns

@@ -8,9 +8,9 @@
 //     interface flux (30 contributions to the six cells it reads) and adds them,
 //     in a fixed order, into LDS accumulators of the cells, which are then written;
 //   viscous part: the adjoint of a central difference is minus the same central
-//     difference, so Gbar_d = -D_d rbar; k_adj_visc1 maps it through the viscous
+//     difference, so Gbar_d = -D_d rbar; k_adj_visc maps it through the viscous
 //     fluxes to the adjoints of the velocity/temperature gradients and of the
-//     point velocities; k_adj_visc2 applies -D once more and the primitive map.
+//     point velocities, applies -D once more and the primitive map, in one pass.
 // Every sum is formed in a fixed order (deterministic, no atomics).
 #include <hip/hip_runtime.h>
 
@@ -241,214 +241,307 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
 }
 
 // ---------------------------------------------------------------------------
-// Viscous adjoint on the tiles of the forward viscous-flux kernel: a block owns a
-// 32 x 8 (x, y) tile and marches along z over kViscSZ planes; the x and y stencil
-// operands of the current plane sit in LDS (with a +-2 halo), each thread keeps its
-// own column's z operands at planes k-2 .. k+2 in registers.
-//
-// Part 1: Gbar_d = -D_d rbar (momentum and energy rows), through tau, q and E to the
-// adjoints of the 12 gradients g[a][b] = d W_a / dx_b (W = u, v, w, T) and of the
-// point velocities.  tau is symmetric, so the 12 gradient adjoints hold 9 distinct
-// values; Gb stores gxx, gyy, gzz, gxy, gxz, gyz, kappa E_x, kappa E_y, kappa E_z,
-// then the three point-velocity adjoints: kAdjGbFields fields.
+// Viscous adjoint in one pass.  With Gbar_d = -D_d rbar (rows 1-4: momentum x, y, z and
+// energy) the viscous fluxes give at every point
+//   the stencil fields f_d, the adjoints that the transposed gradients D_d carry back:
+//     f_x = (gxx, gxy, gxz, kappa E_x), f_y = (gxy, gyy, gyz, kappa E_y),
+//     f_z = (gxz, gyz, gzz, kappa E_z), linear in Gbar with the point velocity as
+//     coefficient (tau is symmetric: nine distinct values);
+//   the point fields pa, the adjoints of the point velocities in the energy fluxes;
+// and Wbar = pa - sum_d D_d f_d for W = (u, v, w, T), which the primitive map takes to
+// ubar.  A block owns a 32 x 8 (x, y) tile and marches along z.  Per plane it forms f_x
+// on the tile and its +-2 x halo and f_y on the tile and its +-2 y halo, from rbar
+// staged in LDS with the +-4 halo these need and from the z derivatives of rbar at
+// those points (register rings of five planes for the tile's columns, an LDS ring for
+// the halo points), and f_z on the tile, whose z difference is applied two planes
+// later from a register ring: the fields never go through memory.
 // ---------------------------------------------------------------------------
+constexpr int kAvTX = kViscTX, kAvTY = kViscTY;
+constexpr int kAvRX = kAvTX + 8, kAvRY = kAvTY + 8;    // rbar box, origin (x0-4, y0-4)
+constexpr int kAvHalo = 4 * kAvTY + 4 * kAvTX;         // x-halo then y-halo points of the tile
+constexpr int kAvExt = 16 + 4 * kAvTY + 4 * kAvTX;     // further rbar points: corners, x and y extensions
+static_assert(kAvHalo <= kPointThreads && kAvExt <= kPointThreads && kAvTX * kAvTY == kPointThreads, "tile");
 
-// W = (u, v, w, T = gamma p / rho) of the state at linear index i: the forward's
-// primitive map, the linearisation point of the viscous terms
-__device__ __forceinline__ void adj_prim_at(const double *__restrict__ u, size_t n3, size_t i, double gamma,
-                                            double W[4]) {
-    const double r = u[i], mx = u[n3 + i], my = u[2 * n3 + i], mz = u[3 * n3 + i], e = u[4 * n3 + i];
-    const double inv = rcp(r);
-    W[0] = mx * inv;
-    W[1] = my * inv;
-    W[2] = mz * inv;
-    const double p = (gamma - 1.0) * (e - 0.5 * (mx * W[0] + my * W[1] + mz * W[2]));
-    W[3] = gamma * p * inv;
+// planes per block: the two planes of lookahead on either side are formed again by the
+// next block along z, so long columns take more planes
+__host__ __device__ __forceinline__ int adj_visc_planes(int nz) { return nz >= 256 ? 32 : 16; }
+
+// position in the rbar box of halo point h (x-halo: columns x0-2, x0-1, x0+TX, x0+TX+1
+// of the tile's rows; y-halo: rows y0-2, y0-1, y0+TY, y0+TY+1 of the tile's columns)
+__device__ __forceinline__ void av_halo_pos(int h, int &bx, int &by) {
+    if (h < 4 * kAvTY) {
+        const int c = h & 3;
+        bx = c < 2 ? 2 + c : kAvTX + 2 + c;
+        by = 4 + (h >> 2);
+    } else {
+        const int q = h - 4 * kAvTY, r = q / kAvTX;
+        bx = 4 + q % kAvTX;
+        by = r < 2 ? 2 + r : kAvTY + 2 + r;
+    }
+}
+// position in the rbar box of further point e: the 2 x 2 corners between the halos,
+// then columns x0-4, x0-3, x0+TX+2, x0+TX+3 of the tile's rows, then rows y0-4, y0-3,
+// y0+TY+2, y0+TY+3 of its columns
+__device__ __forceinline__ void av_ext_pos(int e, int &bx, int &by) {
+    if (e < 16) {
+        const int cc = e >> 2;
+        bx = (cc & 1 ? kAvTX + 4 : 2) + (e & 1);
+        by = (cc & 2 ? kAvTY + 4 : 2) + ((e >> 1) & 1);
+    } else if (e < 16 + 4 * kAvTY) {
+        const int q = e - 16, c = q & 3;
+        bx = c < 2 ? c : kAvTX + 4 + c;
+        by = 4 + (q >> 2);
+    } else {
+        const int q = e - 16 - 4 * kAvTY, r = q / kAvTX;
+        bx = 4 + q % kAvTX;
+        by = r < 2 ? r : kAvTY + 4 + r;
+    }
 }
 
-struct AdjTile {
-    int x0, y0, z0, z1, tx, ty;
-    bool act;
-    size_t col;
+// the fields of a point from its rbar gradient (Gbar[d][c] = -D_d rbar_c) and velocity
+struct AvFields {
+    double gxx, gyy, gzz, gxy, gxz, gyz, ex, ey, ez;
 };
-__device__ __forceinline__ AdjTile adj_tile(const AdjGeom &g) {
-    AdjTile t;
-    const int ntx = (g.nx + kViscTX - 1) / kViscTX, nty = (g.ny + kViscTY - 1) / kViscTY;
-    const long long lb = blockIdx.x;
-    t.x0 = (int)(lb % ntx) * kViscTX;
-    t.y0 = (int)((lb / ntx) % nty) * kViscTY;
-    t.z0 = (int)(lb / ((long long)ntx * nty)) * kViscSZ;
-    t.z1 = min(t.z0 + kViscSZ, g.nz);
-    t.tx = threadIdx.x % kViscTX;
-    t.ty = threadIdx.x / kViscTX;
-    t.act = t.x0 + t.tx < g.nx && t.y0 + t.ty < g.ny;
-    t.col = (size_t)min(t.y0 + t.ty, g.ny - 1) * g.nx + min(t.x0 + t.tx, g.nx - 1);
-    return t;
+__device__ __forceinline__ AvFields av_fields(const double Gbar[3][4], const double v[3], double mu, double kc) {
+    const double Ex = Gbar[0][3], Ey = Gbar[1][3], Ez = Gbar[2][3];
+    const double bxx = Gbar[0][0] + Ex * v[0];
+    const double byy = Gbar[1][1] + Ey * v[1];
+    const double bzz = Gbar[2][2] + Ez * v[2];
+    const double bxy = Gbar[0][1] + Gbar[1][0] + Ex * v[1] + Ey * v[0];
+    const double bxz = Gbar[0][2] + Gbar[2][0] + Ex * v[2] + Ez * v[0];
+    const double byz = Gbar[1][2] + Gbar[2][1] + Ey * v[2] + Ez * v[1];
+    // tau_aa = mu (2 g_aa - 2/3 div), tau_ab = mu (g_ab + g_ba)
+    const double divb = -2.0 / 3.0 * mu * (bxx + byy + bzz);
+    AvFields f;
+    f.gxx = 2.0 * mu * bxx + divb;
+    f.gyy = 2.0 * mu * byy + divb;
+    f.gzz = 2.0 * mu * bzz + divb;
+    f.gxy = mu * bxy;
+    f.gxz = mu * bxz;
+    f.gyz = mu * byz;
+    f.ex = kc * Ex;
+    f.ey = kc * Ey;
+    f.ez = kc * Ez;
+    return f;
 }
 
-__global__ __launch_bounds__(kPointThreads) void k_adj_visc1(AdjGeom g, const double *__restrict__ u,
-                                                             const double *__restrict__ rbar, double *__restrict__ Gb) {
-    constexpr int TX = kViscTX, TY = kViscTY;
-    __shared__ double pw[4][TY + 4][TX + 4];  // W of the plane
-    __shared__ double pr[4][TY + 4][TX + 4];  // rbar rows 1..4 of the plane
-    const AdjTile t = adj_tile(g);
+__global__ __launch_bounds__(kPointThreads, 2) void k_adj_visc(AdjGeom g, const double *__restrict__ u,
+                                                               const double *__restrict__ rbar,
+                                                               double *__restrict__ ubar, AdjEpilogue ep) {
+    constexpr int TX = kAvTX, TY = kAvTY, RX = kAvRX, RY = kAvRY;
+    __shared__ double sR[4][RY][RX];             // rbar rows 1-4 of the plane
+    __shared__ double sV[3][TY + 4][TX + 4];     // velocity of the plane, tile and +-2 halo
+    __shared__ double sFx[4][TY][TX + 4];        // f_x, tile rows, x halo
+    __shared__ double sFy[4][TY + 4][TX];        // f_y, tile columns, y halo
+    __shared__ double hR[5][4][kAvHalo];         // rbar of the halo points, slot (plane - z0 + 4) mod 5
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const size_t n3 = g.n3, sz = (size_t)nx * ny;
-    const double *rb = rbar + n3;  // rows 1..4: momentum x, y, z, energy
-    double Wz[5][4], Rz[5][4];     // this column at planes k-2 .. k+2
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, zp = adj_visc_planes(nz);
+    const long long lb = blockIdx.x;
+    const int x0 = (int)(lb % ntx) * TX, y0 = (int)((lb / ntx) % nty) * TY;
+    const int z0 = (int)(lb / ((long long)ntx * nty)) * zp, z1 = min(z0 + zp, nz);
+    const int t = threadIdx.x, tx = t % TX, ty = t / TX;
+    const bool act = x0 + tx < nx && y0 + ty < ny;
+    // a column past a ragged edge wraps periodically: its values are halo values of the
+    // active columns beside it
+    const size_t col = (size_t)wrapn(y0 + ty, ny) * nx + wrapn(x0 + tx, nx);
+    const bool own_h = t < kAvHalo, own_e = t < kAvExt;
+    int hbx = 0, hby = 0, ebx = 0, eby = 0;
+    if (own_h) av_halo_pos(t, hbx, hby);
+    if (own_e) av_ext_pos(t, ebx, eby);
+    const size_t hcol = (size_t)wrapn(y0 - 4 + hby, ny) * nx + wrapn(x0 - 4 + hbx, nx);
+    const size_t ecol = (size_t)wrapn(y0 - 4 + eby, ny) * nx + wrapn(x0 - 4 + ebx, nx);
+    const double *rb = rbar + n3;  // rows 1..4
+    const double mu = g.mu, kc = g.mu / ((g.gamma - 1.0) * g.prandtl), gm1 = g.gamma - 1.0;
+    const double ihx = g.ih[0], ihy = g.ih[1], ihz = g.ih[2];
+    auto slot = [&](int p) { return (p - z0 + 4) % 5; };
+    auto vel_at = [&](size_t i, double v[3]) {
+        const double inv = rcp(u[i]);
+        v[0] = u[n3 + i] * inv;
+        v[1] = u[2 * n3 + i] * inv;
+        v[2] = u[3 * n3 + i] * inv;
+    };
+    double Rz[5][4];  // rbar of this column at planes k-2 .. k+2
+    double Vz[5][3];  // velocity of this column at planes k-2 .. k+2
+    // Wbar of this column at planes k-2 .. k+2 as it accumulates: pa - D_x f_x - D_y f_y
+    // when its plane is formed, and the terms of -D_z f_z as the f_z of the planes two
+    // on either side are formed (the plane k-2 is complete after plane k)
+    double Tq[5][4];
+    const int k0 = z0 - 2;
+    auto is_full = [&](int k) { return k >= z0 && k < z1; };
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const size_t q = t.col + (size_t)wrapj(t.z0 - 2 + m, nz) * sz;
-        adj_prim_at(u, n3, q, g.gamma, Wz[m]);
+    for (int m = 0; m < 5; ++m) {
+        const size_t q = col + (size_t)wrapn(k0 - 2 + m, nz) * sz;
 #pragma unroll
         for (int c = 0; c < 4; ++c) Rz[m][c] = rb[c * n3 + q];
-    }
-    const double mu = g.mu, kc = g.mu / ((g.gamma - 1.0) * g.prandtl);
-    for (int k = t.z0; k < t.z1; ++k) {
-        {
-            const size_t q = t.col + (size_t)wrapj(k + 2, nz) * sz;
-            adj_prim_at(u, n3, q, g.gamma, Wz[4]);
+        vel_at(q, Vz[m]);
+        if (own_h) {
+            const size_t qh = hcol + (size_t)wrapn(k0 - 2 + m, nz) * sz;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Rz[4][c] = rb[c * n3 + q];
+            for (int c = 0; c < 4; ++c) hR[slot(k0 - 2 + m)][c][t] = rb[c * n3 + qh];
         }
-        for (int h = threadIdx.x; h < (TX + 4) * (TY + 4); h += blockDim.x) {
-            const int hx = h % (TX + 4), hy = h / (TX + 4);
-            const size_t q = (size_t)k * sz + (size_t)wrapn(t.y0 - 2 + hy, ny) * nx + wrapn(t.x0 - 2 + hx, nx);
-            double w4[4];
-            adj_prim_at(u, n3, q, g.gamma, w4);
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Tq[m][c] = 0.0;
+    const double cz = ihz * (1.0 / 12.0);
+    // loads for the plane after the current one (halo velocities, further rbar points)
+    double hu[4] = {1.0, 0.0, 0.0, 0.0}, er[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = k0; k < z1 + 2; ++k) {
+        // planes z0 .. z1-1 are formed in full; the two planes on either side only for f_z.
+        // Every load is issued one iteration (the rings three planes) ahead of its use.
+        const bool full = is_full(k);
+        double Rn[4], Un[4], Hn[4];  // plane k+3 of the column and of the halo point
+        {
+            const size_t q = col + (size_t)wrapn(k + 3, nz) * sz;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                pw[c][hy][hx] = w4[c];
-                pr[c][hy][hx] = rb[c * n3 + q];
+                Rn[c] = rb[c * n3 + q];
+                Un[c] = u[c * n3 + q];
+            }
+            if (own_h) {
+                const size_t qh = hcol + (size_t)wrapn(k + 3, nz) * sz;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Hn[c] = rb[c * n3 + qh];
             }
         }
-        __syncthreads();
-        if (t.act) {
-            const int X = t.tx + 2, Y = t.ty + 2;
-            // forward at the point: gradients and stresses
-            double gr[4][3];
+        const int ko = k - 2;  // finished in this iteration: its f_z are known two planes on either side
+        const bool out = ko >= z0 && act;
+        const size_t po = (size_t)wrapn(ko, nz) * sz + col;
+        double us[5], ubv[5];
+        if (out) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                gr[a][0] = dcen(pw[a][Y][X - 2], pw[a][Y][X - 1], pw[a][Y][X + 1], pw[a][Y][X + 2]) * g.ih[0];
-                gr[a][1] = dcen(pw[a][Y - 2][X], pw[a][Y - 1][X], pw[a][Y + 1][X], pw[a][Y + 2][X]) * g.ih[1];
-                gr[a][2] = dcen(Wz[0][a], Wz[1][a], Wz[3][a], Wz[4][a]) * g.ih[2];
+            for (int v = 0; v < 5; ++v) {
+                us[v] = u[v * n3 + po];
+                ubv[v] = ubar[v * n3 + po];
             }
-            const double div = gr[0][0] + gr[1][1] + gr[2][2];
-            const double tdiv = 2.0 / 3.0 * div;
-            const double txx = mu * (2.0 * gr[0][0] - tdiv), tyy = mu * (2.0 * gr[1][1] - tdiv),
-                         tzz = mu * (2.0 * gr[2][2] - tdiv);
-            const double txy = mu * (gr[0][1] + gr[1][0]), txz = mu * (gr[0][2] + gr[2][0]),
-                         tyz = mu * (gr[1][2] + gr[2][1]);
-            const double vx = Wz[2][0], vy = Wz[2][1], vz = Wz[2][2];
-            // Gbar_d[c] = -(D_d rbar_{1+c}), c: x-, y-, z-momentum, energy
+        }
+        if (own_h) {
+            const int s0 = slot(k);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sR[c][hby][hbx] = hR[s0][c][t];
+            if (full) {
+                const double inv = rcp(hu[0]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sV[c][hby - 2][hbx - 2] = hu[1 + c] * inv;
+            }
+        }
+        if (own_e && full) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sR[c][eby][ebx] = er[c];
+        }
+        if (is_full(k + 1)) {
+            if (own_h) {
+                const size_t qh = hcol + (size_t)wrapn(k + 1, nz) * sz;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) hu[c] = u[c * n3 + qh];
+            }
+            if (own_e) {
+                const size_t qe = ecol + (size_t)wrapn(k + 1, nz) * sz;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) er[c] = rb[c * n3 + qe];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sR[c][ty + 4][tx + 4] = Rz[2][c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sV[c][ty + 2][tx + 2] = Vz[2][c];
+        __syncthreads();
+        double pa[3] = {0.0, 0.0, 0.0};
+        {
+            // the tile's point: rbar gradient, fields
+            const int X = tx + 4, Y = ty + 4;
             double Gbar[3][4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                Gbar[0][c] = -dcen(pr[c][Y][X - 2], pr[c][Y][X - 1], pr[c][Y][X + 1], pr[c][Y][X + 2]) * g.ih[0];
-                Gbar[1][c] = -dcen(pr[c][Y - 2][X], pr[c][Y - 1][X], pr[c][Y + 1][X], pr[c][Y + 2][X]) * g.ih[1];
-                Gbar[2][c] = -dcen(Rz[0][c], Rz[1][c], Rz[3][c], Rz[4][c]) * g.ih[2];
+                Gbar[0][c] = -dcen(sR[c][Y][X - 2], sR[c][Y][X - 1], sR[c][Y][X + 1], sR[c][Y][X + 2]) * ihx;
+                Gbar[1][c] = -dcen(sR[c][Y - 2][X], sR[c][Y - 1][X], sR[c][Y + 1][X], sR[c][Y + 2][X]) * ihy;
+                Gbar[2][c] = -dcen(Rz[0][c], Rz[1][c], Rz[3][c], Rz[4][c]) * ihz;
             }
-            // G_x = [txx, txy, txz, Ex], G_y = [txy, tyy, tyz, Ey], G_z = [txz, tyz, tzz, Ez],
-            // E_x = vx txx + vy txy + vz txz + kc dT/dx, etc.
-            const double Ex = Gbar[0][3], Ey = Gbar[1][3], Ez = Gbar[2][3];
-            const double bxx = Gbar[0][0] + Ex * vx;
-            const double byy = Gbar[1][1] + Ey * vy;
-            const double bzz = Gbar[2][2] + Ez * vz;
-            const double bxy = Gbar[0][1] + Gbar[1][0] + Ex * vy + Ey * vx;
-            const double bxz = Gbar[0][2] + Gbar[2][0] + Ex * vz + Ez * vx;
-            const double byz = Gbar[1][2] + Gbar[2][1] + Ey * vz + Ez * vy;
-            // tau_aa = mu (2 g_aa - 2/3 div), tau_ab = mu (g_ab + g_ba)
-            const double divb = -2.0 / 3.0 * mu * (bxx + byy + bzz);
-            const size_t idx = (size_t)k * sz + t.col;
-            // non-temporal stores: the fields are streamed to memory for the second
-            // kernel, so they do not displace the state's halo lines in L2
-            __builtin_nontemporal_store(2.0 * mu * bxx + divb, &Gb[idx]);
-            __builtin_nontemporal_store(2.0 * mu * byy + divb, &Gb[n3 + idx]);
-            __builtin_nontemporal_store(2.0 * mu * bzz + divb, &Gb[2 * n3 + idx]);
-            __builtin_nontemporal_store(mu * bxy, &Gb[3 * n3 + idx]);
-            __builtin_nontemporal_store(mu * bxz, &Gb[4 * n3 + idx]);
-            __builtin_nontemporal_store(mu * byz, &Gb[5 * n3 + idx]);
-            __builtin_nontemporal_store(kc * Ex, &Gb[6 * n3 + idx]);
-            __builtin_nontemporal_store(kc * Ey, &Gb[7 * n3 + idx]);
-            __builtin_nontemporal_store(kc * Ez, &Gb[8 * n3 + idx]);
-            __builtin_nontemporal_store(Ex * txx + Ey * txy + Ez * txz, &Gb[9 * n3 + idx]);
-            __builtin_nontemporal_store(Ex * txy + Ey * tyy + Ez * tyz, &Gb[10 * n3 + idx]);
-            __builtin_nontemporal_store(Ex * txz + Ey * tyz + Ez * tzz, &Gb[11 * n3 + idx]);
-        }
-        __syncthreads();  // the next plane overwrites the LDS tile
+            const AvFields f = av_fields(Gbar, Vz[2], mu, kc);
+            // -D_z f_z: dcen(m2, m1, p1, p2) = (8 (p1 - m1) - (p2 - m2)) / 12, so f_z of this
+            // plane enters the planes k+2, k+1, k-1, k-2 with -1, 8, -8, 1 times cz
+            const double fz[4] = {f.gxz, f.gyz, f.gzz, f.ez};
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int a = 0; a < 4; ++a) {
+                const double w = cz * fz[a];
+                Tq[4][a] = -w;
+                Tq[3][a] += 8.0 * w;
+                Tq[1][a] -= 8.0 * w;
+                Tq[0][a] += w;
+            }
+            if (full) {
+                sFx[0][ty][tx + 2] = f.gxx;
+                sFx[1][ty][tx + 2] = f.gxy;
+                sFx[2][ty][tx + 2] = f.gxz;
+                sFx[3][ty][tx + 2] = f.ex;
+                sFy[0][ty + 2][tx] = f.gxy;
+                sFy[1][ty + 2][tx] = f.gyy;
+                sFy[2][ty + 2][tx] = f.gyz;
+                sFy[3][ty + 2][tx] = f.ey;
+                // point fields: the velocity gradients of the plane, tau
+                double gv[3][3];  // gv[a][b] = d v_a / d x_b
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    gv[a][0] = dcen(sV[a][ty + 2][tx], sV[a][ty + 2][tx + 1], sV[a][ty + 2][tx + 3],
+                                    sV[a][ty + 2][tx + 4]) * ihx;
+                    gv[a][1] = dcen(sV[a][ty][tx + 2], sV[a][ty + 1][tx + 2], sV[a][ty + 3][tx + 2],
+                                    sV[a][ty + 4][tx + 2]) * ihy;
+                    gv[a][2] = dcen(Vz[0][a], Vz[1][a], Vz[3][a], Vz[4][a]) * ihz;
+                }
+                const double div = gv[0][0] + gv[1][1] + gv[2][2];
+                const double tdiv = 2.0 / 3.0 * div;
+                const double txx = mu * (2.0 * gv[0][0] - tdiv), tyy = mu * (2.0 * gv[1][1] - tdiv),
+                             tzz = mu * (2.0 * gv[2][2] - tdiv);
+                const double txy = mu * (gv[0][1] + gv[1][0]), txz = mu * (gv[0][2] + gv[2][0]),
+                             tyz = mu * (gv[1][2] + gv[2][1]);
+                const double Ex = Gbar[0][3], Ey = Gbar[1][3], Ez = Gbar[2][3];
+                pa[0] = Ex * txx + Ey * txy + Ez * txz;
+                pa[1] = Ex * txy + Ey * tyy + Ez * tyz;
+                pa[2] = Ex * txz + Ey * tyz + Ez * tzz;
+            }
+        }
+        if (own_h && full) {
+            // a halo point: rbar gradient (z from the halo ring), its f_x or f_y
+            double Gbar[3][4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                Wz[m][c] = Wz[m + 1][c];
-                Rz[m][c] = Rz[m + 1][c];
+                Gbar[0][c] = -dcen(sR[c][hby][hbx - 2], sR[c][hby][hbx - 1], sR[c][hby][hbx + 1],
+                                   sR[c][hby][hbx + 2]) * ihx;
+                Gbar[1][c] = -dcen(sR[c][hby - 2][hbx], sR[c][hby - 1][hbx], sR[c][hby + 1][hbx],
+                                   sR[c][hby + 2][hbx]) * ihy;
+                Gbar[2][c] = -dcen(hR[slot(k - 2)][c][t], hR[slot(k - 1)][c][t], hR[slot(k + 1)][c][t],
+                                   hR[slot(k + 2)][c][t]) * ihz;
             }
-    }
-}
-
-// Part 2: Wbar_a = (point adjoint) - sum_b D_b gbar[a][b], then through
-// W(u) = (m/rho, gamma p / rho) to ubar (accumulated).  The x derivatives act on
-// (gxx, gxy, gxz, kappa E_x), the y derivatives on (gxy, gyy, gyz, kappa E_y), the z
-// derivatives on (gxz, gyz, gzz, kappa E_z).
-__global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const double *__restrict__ u,
-                                                             const double *__restrict__ Gb, double *__restrict__ ubar,
-                                                             AdjEpilogue ep) {
-    constexpr int TX = kViscTX, TY = kViscTY;
-    constexpr int fx[4] = {0, 3, 4, 6}, fy[4] = {3, 1, 5, 7}, fz[4] = {4, 5, 2, 8};
-    __shared__ double qx[4][TY][TX + 4];  // x-differenced fields of the plane, x halo
-    __shared__ double qy[4][TY + 4][TX];  // y-differenced fields of the plane, y halo
-    const AdjTile t = adj_tile(g);
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const size_t n3 = g.n3, sz = (size_t)nx * ny;
-    double Gz[5][4];  // z-differenced fields of this column at planes k-2 .. k+2
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const size_t q = t.col + (size_t)wrapj(t.z0 - 2 + m, nz) * sz;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) Gz[m][a] = Gb[fz[a] * n3 + q];
-    }
-    const double gm1 = g.gamma - 1.0;
-    for (int k = t.z0; k < t.z1; ++k) {
-        {
-            const size_t q = t.col + (size_t)wrapj(k + 2, nz) * sz;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) Gz[4][a] = Gb[fz[a] * n3 + q];
-        }
-        const size_t plane = (size_t)k * sz;
-        // the point's own operands, loaded ahead of the plane staging and its barrier
-        const size_t p = plane + t.col;
-        double pa[3], us[5], ub[5];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) pa[a] = Gb[(9 + a) * n3 + p];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            us[v] = u[v * n3 + p];
-            ub[v] = ubar[v * n3 + p];
-        }
-        for (int h = threadIdx.x; h < (TX + 4) * TY; h += blockDim.x) {
-            const int hx = h % (TX + 4), hy = h / (TX + 4);
-            const size_t q = plane + (size_t)min(t.y0 + hy, ny - 1) * nx + wrapn(t.x0 - 2 + hx, nx);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) qx[a][hy][hx] = Gb[fx[a] * n3 + q];
-        }
-        for (int h = threadIdx.x; h < TX * (TY + 4); h += blockDim.x) {
-            const int hx = h % TX, hy = h / TX;
-            const size_t q = plane + (size_t)wrapn(t.y0 - 2 + hy, ny) * nx + min(t.x0 + hx, nx - 1);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) qy[a][hy][hx] = Gb[fy[a] * n3 + q];
+            const double v[3] = {sV[0][hby - 2][hbx - 2], sV[1][hby - 2][hbx - 2], sV[2][hby - 2][hbx - 2]};
+            const AvFields f = av_fields(Gbar, v, mu, kc);
+            if (t < 4 * TY) {
+                const int r = hby - 4, cx = hbx - 2;
+                sFx[0][r][cx] = f.gxx;
+                sFx[1][r][cx] = f.gxy;
+                sFx[2][r][cx] = f.gxz;
+                sFx[3][r][cx] = f.ex;
+            } else {
+                const int r = hby - 2, cx = hbx - 4;
+                sFy[0][r][cx] = f.gxy;
+                sFy[1][r][cx] = f.gyy;
+                sFy[2][r][cx] = f.gyz;
+                sFy[3][r][cx] = f.ey;
+            }
         }
         __syncthreads();
-        if (t.act) {
-            const int X = t.tx + 2, Y = t.ty + 2;
-            double Wb[4];
+        if (full) {
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 double s = a < 3 ? pa[a] : 0.0;
-                s -= dcen(qx[a][t.ty][X - 2], qx[a][t.ty][X - 1], qx[a][t.ty][X + 1], qx[a][t.ty][X + 2]) * g.ih[0];
-                s -= dcen(qy[a][Y - 2][t.tx], qy[a][Y - 1][t.tx], qy[a][Y + 1][t.tx], qy[a][Y + 2][t.tx]) * g.ih[1];
-                s -= dcen(Gz[0][a], Gz[1][a], Gz[3][a], Gz[4][a]) * g.ih[2];
-                Wb[a] = s;
+                s -= dcen(sFx[a][ty][tx], sFx[a][ty][tx + 1], sFx[a][ty][tx + 3], sFx[a][ty][tx + 4]) * ihx;
+                s -= dcen(sFy[a][ty][tx], sFy[a][ty + 1][tx], sFy[a][ty + 3][tx], sFy[a][ty + 4][tx]) * ihy;
+                Tq[2][a] += s;
             }
+        }
+        if (out) {
+            const double *Wb = Tq[0];
             // W = (m_k / rho, gamma p / rho), p = (gamma-1)(e - m.v/2)
             const double r = us[0], m[3] = {us[1], us[2], us[3]}, e = us[4];
             const double inv = rcp(r);
@@ -467,26 +560,44 @@ __global__ __launch_bounds__(kPointThreads) void k_adj_visc2(AdjGeom g, const do
                 mb[c] = qqb * v[c] + vb * inv;
                 invb += vb * m[c];
             }
-            const double fin[5] = {ub[0] + -invb * inv * inv, ub[1] + mb[0], ub[2] + mb[1], ub[3] + mb[2],
-                                   ub[4] + eb};
+            const double fin[5] = {ubv[0] + -invb * inv * inv, ubv[1] + mb[0], ubv[2] + mb[1], ubv[3] + mb[2],
+                                   ubv[4] + eb};
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const size_t o = v * n3 + p;
+                const size_t o = v * n3 + po;
                 if (ep.store_ub) ubar[o] = fin[v];
                 if (ep.ubf) {
-                    const double t = ep.S[o] + fin[v];
-                    ep.ubf[o] = ep.ubf[o] + t;
+                    const double tt = ep.S[o] + fin[v];
+                    ep.ubf[o] = ep.ubf[o] + tt;
                 } else if (ep.S) {
                     ep.S[o] = ep.s_first ? fin[v] : ep.S[o] + fin[v];
                 }
                 if (ep.kb) ep.kb[o] = __fma_rn(ep.a, ep.ub[o], ep.b * fin[v]);
             }
         }
-        __syncthreads();  // the next plane overwrites the LDS tiles
+        // advance the rings; plane k+3 enters them
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) Gz[m][a] = Gz[m + 1][a];
+            for (int c = 0; c < 4; ++c) {
+                Rz[m][c] = Rz[m + 1][c];
+                Tq[m][c] = Tq[m + 1][c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Vz[m][c] = Vz[m + 1][c];
+        }
+        {
+            const double inv = rcp(Un[0]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Rz[4][c] = Rn[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Vz[4][c] = Un[1 + c] * inv;
+        }
+        if (own_h) {
+            const int s3 = slot(k + 3);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) hR[s3][c][t] = Hn[c];
+        }
     }
 }
 
@@ -564,19 +675,17 @@ __global__ void k_epilogue(size_t n, const double *__restrict__ fin, AdjEpilogue
 }
 
 static void rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
-                    double *Gb, const AdjEpilogue *epi) {
+                    const AdjEpilogue *epi) {
     const AdjGeom g = adj_geom(b);
-    const bool visc = b.mu > 0.0;
-    const unsigned tiles = (unsigned)(((b.nx + kViscTX - 1) / kViscTX) * (long long)((b.ny + kViscTY - 1) / kViscTY) *
-                                      ((b.nz + kViscSZ - 1) / kViscSZ));
-    if (visc) hipLaunchKernelGGL(k_adj_visc1, dim3(tiles), dim3(kPointThreads), 0, s, g, u, rbar, Gb);
     if (weights == CNS_WENO_Z) adj_conv<CNS_WENO_Z>(b, s, g, u, rbar, ubar);
     else if (weights == CNS_WENO_M) adj_conv<CNS_WENO_M>(b, s, g, u, rbar, ubar);
     else adj_conv<CNS_WENO_JS>(b, s, g, u, rbar, ubar);
     AdjEpilogue e;
     if (epi) e = *epi;
-    if (visc) {
-        hipLaunchKernelGGL(k_adj_visc2, dim3(tiles), dim3(kPointThreads), 0, s, g, u, (const double *)Gb, ubar, e);
+    if (b.mu > 0.0) {
+        const unsigned tiles = (unsigned)(((b.nx + kAvTX - 1) / kAvTX) * (long long)((b.ny + kAvTY - 1) / kAvTY) *
+                                          ((b.nz + adj_visc_planes(b.nz) - 1) / adj_visc_planes(b.nz)));
+        hipLaunchKernelGGL(k_adj_visc, dim3(tiles), dim3(kPointThreads), 0, s, g, u, rbar, ubar, e);
     } else if (epi) {
         // ubar holds the finished product; the epilogue reads it from there
         const size_t n5 = 5 * b.n3;
@@ -584,14 +693,13 @@ static void rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *
     }
 }
 
-void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
-                 double *Gb) {
-    rhs_vjp(b, weights, s, u, rbar, ubar, Gb, nullptr);
+void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar) {
+    rhs_vjp(b, weights, s, u, rbar, ubar, nullptr);
 }
 
 void adj_rhs_vjp_epi(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
-                     double *Gb, const AdjEpilogue &epi) {
-    rhs_vjp(b, weights, s, u, rbar, ubar, Gb, &epi);
+                     const AdjEpilogue &epi) {
+    rhs_vjp(b, weights, s, u, rbar, ubar, &epi);
 }
 
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s) {

@@ -979,7 +979,7 @@ int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t 
 // adjoint (FP64, single box): workspace layout and the checkpointed reverse RK4
 // ----------------------------------------------------------------------------
 struct AdjLayout {
-    size_t ck, seg, X, ub, kb, Ub, S, Gb, rec, total;
+    size_t ck, seg, X, ub, kb, kb2, Ub, S, rec, total;
     int nck, K;
 };
 
@@ -999,12 +999,12 @@ static AdjLayout adj_layout(size_t n3, int nsteps, int K) {
     off += st;
     L.kb = off;                      // stage-rate adjoint (and forward stage rates)
     off += st;
+    L.kb2 = off;                     // the next stage-rate adjoint, while kb is read
+    off += st;
     L.Ub = off;                      // adjoint of the current stage state
     off += st;
     L.S = off;                       // sum of the stage adjoints
     off += st;
-    L.Gb = off;                      // viscous adjoint fields [kAdjGbFields][n3]
-    off += align256(kAdjGbFields * n3 * sizeof(double));
     L.rec = off;                     // a diagnostics record
     off += align256(CNS_NDIAG * sizeof(double));
     L.total = off;
@@ -1090,7 +1090,7 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
     char *w = (char *)adj_ws;
     auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
     double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
-    double *Gb = (double *)(w + L.Gb);
+    double *kb2 = state(L.kb2, 0);
     hipStream_t s = c.stream;
     Batch bt = c.batch();
     bt.prof = nullptr;
@@ -1116,13 +1116,13 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
                 // (S holds Ubar2 and X, free during the reverse steps, holds Ubar1)
                 const double *U1 = state(L.seg, 4 * (n - n0) + 1), *U2 = state(L.seg, 4 * (n - n0) + 2);
                 adj_lincomb(n5, 2.0 / 3.0 * dt, ub, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, c.weights, s, U2, kb, Ub, Gb);
+                adj_rhs_vjp(b, c.weights, s, U2, kb, Ub);
                 adj_lincomb(n5, 2.0 / 3.0, ub, 1.0, Ub, S, s);
                 adj_lincomb(n5, 0.25 * dt, S, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, c.weights, s, U1, kb, Ub, Gb);
+                adj_rhs_vjp(b, c.weights, s, U1, kb, Ub);
                 adj_lincomb(n5, 0.25, S, 1.0, Ub, X, s);
                 adj_lincomb(n5, dt, X, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, c.weights, s, Y, kb, Ub, Gb);
+                adj_rhs_vjp(b, c.weights, s, Y, kb, Ub);
                 adj_lincomb(n5, 1.0 / 3.0, ub, 0.75, S, ub, s);
                 adj_accum(n5, X, ub, s);
                 adj_accum(n5, Ub, ub, s);
@@ -1132,17 +1132,19 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
                          *U4 = state(L.seg, 4 * (n - n0) + 3);
             // reverse stages: kbar_4 = dt/6 ub, kbar_3 = dt/3 ub + dt Ub4, kbar_2 = dt/3 ub + dt/2 Ub3,
             // kbar_1 = dt/6 ub + dt/2 Ub2; ub <- ub + sum_s Ub_s.  Each stage adjoint Ub_s goes
-            // straight into the running sum S and the next seed kb at the end of its product.
+            // straight into the running sum S and the next seed at the end of its product;
+            // the seeds alternate between kb and kb2, since the product still reads its
+            // own seed (with halos) while it writes the next.
             AdjEpilogue e4, e3, e2, e1;
-            e4.S = S, e4.s_first = 1, e4.kb = kb, e4.ub = ub, e4.a = dt / 3.0, e4.b = dt, e4.store_ub = 0;
+            e4.S = S, e4.s_first = 1, e4.kb = kb2, e4.ub = ub, e4.a = dt / 3.0, e4.b = dt, e4.store_ub = 0;
             e3.S = S, e3.kb = kb, e3.ub = ub, e3.a = dt / 3.0, e3.b = 0.5 * dt, e3.store_ub = 0;
-            e2.S = S, e2.kb = kb, e2.ub = ub, e2.a = dt / 6.0, e2.b = 0.5 * dt, e2.store_ub = 0;
+            e2.S = S, e2.kb = kb2, e2.ub = ub, e2.a = dt / 6.0, e2.b = 0.5 * dt, e2.store_ub = 0;
             e1.S = S, e1.ubf = ub, e1.store_ub = 0;
             adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
-            adj_rhs_vjp_epi(b, c.weights, s, U4, kb, Ub, Gb, e4);
-            adj_rhs_vjp_epi(b, c.weights, s, U3, kb, Ub, Gb, e3);
-            adj_rhs_vjp_epi(b, c.weights, s, U2, kb, Ub, Gb, e2);
-            adj_rhs_vjp_epi(b, c.weights, s, Y, kb, Ub, Gb, e1);
+            adj_rhs_vjp_epi(b, c.weights, s, U4, kb, Ub, e4);
+            adj_rhs_vjp_epi(b, c.weights, s, U3, kb2, Ub, e3);
+            adj_rhs_vjp_epi(b, c.weights, s, U2, kb, Ub, e2);
+            adj_rhs_vjp_epi(b, c.weights, s, Y, kb2, Ub, e1);
         }
     }
     adj_copy(n5, ub, (double *)u0_bar, s);
@@ -1175,9 +1177,7 @@ int cns_rhs_vjp(const cns_plan *plan, const void *u, const void *rbar, void *uba
     const BoxDesc &b = plan->c.boxes[0];
     const AdjLayout L = adj_layout(b.n3, 0, 1);
     if (bytes < L.total) return set_err(CNS_EWORKSPACE, "adjoint workspace of %zu bytes required", L.total);
-    char *w = (char *)adj_ws;
-    adj_rhs_vjp(b, plan->c.weights, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar,
-                (double *)(w + L.Gb));
+    adj_rhs_vjp(b, plan->c.weights, plan->c.stream, (const double *)u, (const double *)rbar, (double *)ubar);
     return check_hip("rhs_vjp");
 }
 

@@ -203,10 +203,8 @@ bool spectrum_supported(const BoxDesc &b);
 void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, double *E, int nshell, double *mom);
 
 // adjoint launchers (cns_adjoint.hip), FP64, one box
-// adjoint of the full RHS at u: ubar = (dR/du)^T rbar; Gb: kAdjGbFields x n3 scratch
-constexpr int kAdjGbFields = 12;
-void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,
-                 double *Gb);
+// adjoint of the full RHS at u: ubar = (dR/du)^T rbar
+void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar);
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
 void adj_accum(size_t n, const double *x, double *out, hipStream_t s);
 void adj_copy(size_t n, const double *x, double *out, hipStream_t s);

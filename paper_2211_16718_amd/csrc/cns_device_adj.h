@@ -235,35 +235,53 @@ __device__ __forceinline__ void euler_flux_vjp(const double w[5], double gm1, co
 //   STATES = false: dub += M^T Db (needs no du);
 //   STATES = true:  ab, bb += the adjoints of a and b through M (needs du).
 // ---------------------------------------------------------------------------
+// The Roe average of the cell states a, b and the fixed eigenvalues: formed once per
+// interface for both parts of the transpose product.
+struct RoeAvg {
+    double ra, rb, ia, ib, va[3], vb[3], pa, pb, Ha, Hb, sa, sb, iw, wa, wb, v[3], H, q2, c, ic, ic2, l1, l2, l5;
+};
+template <int DIR>
+__device__ __forceinline__ RoeAvg roe_avg(const double a[5], const double b[5], double gamma, double delta) {
+    const double gm1 = gamma - 1.0;
+    RoeAvg R;
+    R.ra = rsq(a[0]), R.rb = rsq(b[0]);
+    R.ia = R.ra * R.ra, R.ib = R.rb * R.rb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        R.va[k] = a[1 + k] * R.ia;
+        R.vb[k] = b[1 + k] * R.ib;
+    }
+    const double qa = a[1] * R.va[0] + a[2] * R.va[1] + a[3] * R.va[2];
+    const double qb = b[1] * R.vb[0] + b[2] * R.vb[1] + b[3] * R.vb[2];
+    R.pa = gm1 * (a[4] - 0.5 * qa), R.pb = gm1 * (b[4] - 0.5 * qb);
+    R.Ha = (a[4] + R.pa) * R.ia, R.Hb = (b[4] + R.pb) * R.ib;
+    R.sa = a[0] * R.ra, R.sb = b[0] * R.rb;
+    R.iw = rcp(R.sa + R.sb);
+    R.wa = R.sa * R.iw, R.wb = R.sb * R.iw;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) R.v[k] = R.wa * R.va[k] + R.wb * R.vb[k];
+    R.H = R.wa * R.Ha + R.wb * R.Hb;
+    R.q2 = R.v[0] * R.v[0] + R.v[1] * R.v[1] + R.v[2] * R.v[2];
+    const double c2 = gm1 * (R.H - 0.5 * R.q2);
+    R.ic = rsq(c2);
+    R.c = c2 * R.ic, R.ic2 = R.ic * R.ic;
+    const double vn = R.v[DIR], hd = 0.5 / delta;
+    R.l1 = harten_abs(vn - R.c, delta, hd), R.l2 = harten_abs(vn, delta, hd), R.l5 = harten_abs(vn + R.c, delta, hd);
+    return R;
+}
+
 template <int DIR, bool STATES>
-__device__ __forceinline__ void roe_dissipation_vjp(const double a[5], const double b[5], const double du[5],
-                                                    double gamma, double delta, const double Db[5], double ab[5],
-                                                    double bb[5], double dub[5]) {
+__device__ __forceinline__ void roe_dissipation_vjp(const RoeAvg &R, const double a[5], const double b[5],
+                                                    const double du[5], double gamma, double delta,
+                                                    const double Db[5], double ab[5], double bb[5], double dub[5]) {
     constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
     const double gm1 = gamma - 1.0;
-    // ---- forward recompute: the Roe average
-    const double ra = rsq(a[0]), rb = rsq(b[0]);
-    const double ia = ra * ra, ib = rb * rb;
-    const double va[3] = {a[1] * ia, a[2] * ia, a[3] * ia};
-    const double vb[3] = {b[1] * ib, b[2] * ib, b[3] * ib};
-    const double qa = a[1] * va[0] + a[2] * va[1] + a[3] * va[2];
-    const double qb = b[1] * vb[0] + b[2] * vb[1] + b[3] * vb[2];
-    const double pa = gm1 * (a[4] - 0.5 * qa), pb = gm1 * (b[4] - 0.5 * qb);
-    const double Ha = (a[4] + pa) * ia, Hb = (b[4] + pb) * ib;
-    const double sa = a[0] * ra, sb = b[0] * rb;
-    const double iw = rcp(sa + sb);
-    const double wa = sa * iw, wb = sb * iw;
-    double v[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = wa * va[k] + wb * vb[k];
-    const double H = wa * Ha + wb * Hb;
-    const double q2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const double c2 = gm1 * (H - 0.5 * q2);
-    const double ic = rsq(c2);
-    const double c = c2 * ic, ic2 = ic * ic;
+    const double ra = R.ra, rb = R.rb, ia = R.ia, ib = R.ib, pa = R.pa, pb = R.pb, Ha = R.Ha, Hb = R.Hb;
+    const double sa = R.sa, sb = R.sb, iw = R.iw, wa = R.wa, wb = R.wb, H = R.H, q2 = R.q2;
+    const double c = R.c, ic = R.ic, ic2 = R.ic2, l1 = R.l1, l2 = R.l2, l5 = R.l5;
+    const double *va = R.va, *vb = R.vb, *v = R.v;
     const double vn = v[N];
-    const double hd = 0.5 / delta, idelta = 1.0 / delta;  // loop invariant
-    const double l1 = harten_abs(vn - c, delta, hd), l2 = harten_abs(vn, delta, hd), l5 = harten_abs(vn + c, delta, hd);
+    const double idelta = 1.0 / delta;
     // ---- forward recompute: the wave strengths of du (only the state adjoints need them)
     double at1 = 0, at2 = 0, a1 = 0, a2 = 0, a5 = 0, s1 = 0, s2 = 0, s5 = 0, st1 = 0, st2 = 0, ssum = 0;
     if constexpr (STATES) {
@@ -463,7 +481,8 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         Db[v] = -0.5 * Hb[v];
         du[v] = 0.0;
     }
-    roe_dissipation_vjp<DIR, false>(a, b, du, gamma, delta, Db, ab, bb, dub);
+    const RoeAvg R = roe_avg<DIR>(a, b, gamma, delta);
+    roe_dissipation_vjp<DIR, false>(R, a, b, du, gamma, delta, Db, ab, bb, dub);
     adj_stage_fence();
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -482,7 +501,7 @@ __device__ __forceinline__ void interface_flux_vjp(const double *st, int cs, con
         a[v] = st[v * cs + c[2]];
         b[v] = st[v * cs + c[3]];
     }
-    roe_dissipation_vjp<DIR, true>(a, b, du, gamma, delta, Db, ab, bb, dub);
+    roe_dissipation_vjp<DIR, true>(R, a, b, du, gamma, delta, Db, ab, bb, dub);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         addU(2, v, ab[v]);

@@ -1139,8 +1139,8 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
             e4.S = S, e4.s_first = 1, e4.kb = kb2, e4.ub = ub, e4.a = dt / 3.0, e4.b = dt, e4.store_ub = 0;
             e3.S = S, e3.kb = kb, e3.ub = ub, e3.a = dt / 3.0, e3.b = 0.5 * dt, e3.store_ub = 0;
             e2.S = S, e2.kb = kb2, e2.ub = ub, e2.a = dt / 6.0, e2.b = 0.5 * dt, e2.store_ub = 0;
-            e1.S = S, e1.ubf = ub, e1.store_ub = 0;
-            adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);
+            e1.S = S, e1.ubf = ub, e1.kb = kb, e1.a = dt / 6.0, e1.store_ub = 0;
+            if (n == nsteps - 1) adj_lincomb(n5, dt / 6.0, ub, 0.0, nullptr, kb, s);  // later steps: seeded by e1
             adj_rhs_vjp_epi(b, c.weights, s, U4, kb, Ub, e4);
             adj_rhs_vjp_epi(b, c.weights, s, U3, kb2, Ub, e3);
             adj_rhs_vjp_epi(b, c.weights, s, U2, kb, Ub, e2);

@@ -63,8 +63,8 @@ __device__ __forceinline__ size_t shift_idx(const AdjGeom &g, int i, int j, int 
 //
 // A block of 256 threads owns TB whole periodic lines along DIR and marches along
 // them in chunks of TA interfaces; each wave owns LW of the lines and all TA
-// interfaces of a chunk on them (x: one row, 64 interfaces; y, z: 8 lines consecutive
-// in x, 8 interfaces each).  Each thread forms the product of one interface (j+1/2,
+// interfaces of a chunk on them (x: one row, 64 interfaces; y, z: 4 lines consecutive
+// in x, 16 interfaces each).  Each thread forms the product of one interface (j+1/2,
 // cells j-2 .. j+3) and adds its terms, as they are formed, to two LDS rings of cell
 // accumulators: the adjoints of the cells' point fluxes (ringF) and those of their
 // states through the dissipation (ringU).  Every cell of a wave's lines is touched by
@@ -88,9 +88,9 @@ __device__ __forceinline__ size_t shift_idx(const AdjGeom &g, int i, int j, int 
 // than hold them, and the transposes at write-out read LDS instead of the caches.
 // ---------------------------------------------------------------------------
 template <int DIR> struct AdjConvShape;
-template <> struct AdjConvShape<0> { static constexpr int TA = 64, LW = 1, RS = 128; };
-template <> struct AdjConvShape<1> { static constexpr int TA = 8, LW = 8, RS = 16; };
-template <> struct AdjConvShape<2> { static constexpr int TA = 8, LW = 8, RS = 16; };
+template <> struct AdjConvShape<0> { static constexpr int TA = 64, LW = 1, RS = 128, PAD = 0; };
+template <> struct AdjConvShape<1> { static constexpr int TA = 16, LW = 4, RS = 32, PAD = 4; };
+template <> struct AdjConvShape<2> { static constexpr int TA = 16, LW = 4, RS = 32, PAD = 4; };
 
 template <int DIR, int WW>
 __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__restrict__ u,
@@ -102,18 +102,18 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
     static_assert(TA * LW == 64 && RS >= TA + 5 && (RS & (RS - 1)) == 0, "chunk shape");
     // staged component v of line l, cell k (v = 0-4 the state, 5-9 its point flux along
     // DIR): x: (l * 10 + v) * NC + k; y, z: k * KS + v * TB + l, the cell stride padded
-    // so that the eight cells a wave reads in one instruction fall in both halves of
-    // the LDS banks.  Both rings, the head and the staged cells of a block fit twice
-    // in the 160 KiB of LDS of a compute unit.
-    constexpr int KS = 10 * TB + 8;
+    // so that the sixteen cells a wave reads in one instruction spread over all LDS
+    // banks.  Both rings, the head and the staged cells of a block fit twice in the
+    // 160 KiB of LDS of a compute unit.
+    constexpr int KS = 10 * TB + S::PAD;
     constexpr int cs = DIR == 0 ? NC : TB;  // component stride of stg
     __shared__ double ringF[4 * 5 * RS * LW];
     __shared__ double ringU[4 * 5 * RS * LW];
     __shared__ double head[TB * 25];
     __shared__ double stg[DIR == 0 ? TB * 10 * NC : NC * KS];
     const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
-    const int ta = DIR == 0 ? lane : lane >> 3;  // interface within the chunk
-    const int tl = DIR == 0 ? 0 : lane & 7;      // line within the wave
+    const int ta = lane / LW;  // interface within the chunk
+    const int tl = lane % LW;  // line within the wave
     const int tb = w * LW + tl;                   // line within the block
     // ring slot of cell e for component v: the wave's own region, consecutive lanes
     // on consecutive doubles
@@ -653,9 +653,11 @@ static inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 template <int WW>
 static void adj_conv(const BoxDesc &b, hipStream_t s, const AdjGeom &g, const double *u, const double *rbar,
                      double *ubar) {
-    // blocks: x, TB = 4 rows each; y, z: one 32-wide x tile of the lines at one z (y) each
+    // blocks: x, 4 rows each; y, z: one x tile of the lines at one z (y) each
     const unsigned bx = (unsigned)(((size_t)b.ny * b.nz + 3) / 4);
-    const unsigned ntx = (unsigned)((b.nx + 31) / 32);
+    constexpr int TB = 4 * AdjConvShape<1>::LW;
+    static_assert(AdjConvShape<2>::LW == AdjConvShape<1>::LW, "y and z blocks alike");
+    const unsigned ntx = (unsigned)((b.nx + TB - 1) / TB);
     hipLaunchKernelGGL((k_adj_conv<0, WW>), dim3(bx), dim3(256), 0, s, g, u, rbar, ubar, 0);
     hipLaunchKernelGGL((k_adj_conv<1, WW>), dim3(ntx * (unsigned)b.nz), dim3(256), 0, s, g, u, rbar, ubar, 1);
     hipLaunchKernelGGL((k_adj_conv<2, WW>), dim3(ntx * (unsigned)b.ny), dim3(256), 0, s, g, u, rbar, ubar, 1);

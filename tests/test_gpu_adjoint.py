@@ -49,13 +49,16 @@ def test_rhs_vjp_matches_reverse_mode_reference(orc, shape, mu, delta):
     assert err <= 1e-11
 
 
-@pytest.mark.parametrize("shape", [(9, 11, 70), (8, 8, 8), (130, 8, 9), (8, 8, 260)])
+@pytest.mark.parametrize("shape", [(9, 11, 70), (8, 8, 8), (130, 8, 9), (8, 8, 260), (260, 9, 8)])
 def test_rhs_vjp_ragged_lines(orc, shape):
     """Line lengths and counts that leave chunks, lane tiles and blocks of the fused
     convective adjoint partly filled (70 = 64 + 6 along x, 11 and 9 along y, z; 99 rows;
-    x tiles of 32 over 70 or 9 points), lines shorter than a chunk whose staged cells
-    wrap several periods (8^3), many chunks along z (130), and x rows long enough for
-    the cell-accumulator ring to wrap (260 > 252 cells)."""
+    x tiles of 16 over 70 or 9 points), lines shorter than a chunk whose staged cells
+    wrap several periods (8^3), many chunks along z (130), x rows long enough for the
+    cell-accumulator ring to wrap (260 > 252 cells), and for the one-pass viscous
+    adjoint: 32 x 8 tiles over 70 x 11 or 8 x 9 points (halos wrapping several
+    periods), 16-plane blocks over 130 planes and 32-plane blocks over 260 (ragged
+    last blocks)."""
     case(f"rhs_vjp ragged {shape}")
     rho, vel, p, _ = I.smooth_primitives(shape, seed=5, amp=0.3, kmax=3)
     rng = np.random.default_rng(7)  # small-scale noise: nonlinear WENO weights everywhere

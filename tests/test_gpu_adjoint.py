@@ -139,6 +139,30 @@ def test_autograd_function_gradient_16(orc):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("mu", [0.02, 0.0])
+def test_adjoint_is_deterministic_and_independent_of_checkpointing(mu):
+    """The cell accumulators of the convective product are summed by in-order LDS atomics
+    in a fixed order, so repeated products are bitwise equal, also with other work on the
+    device between them; a segment recomputed from its checkpoint reproduces the forward
+    run's stage states bitwise, so the gradient does not depend on the checkpoint
+    interval (every interval from 1 to the whole run)."""
+    case(f"adjoint determinism, checkpoint intervals, mu={mu}")
+    shape = (20, 18, 36)  # ragged for every tile of the adjoint kernels
+    rho, vel, p = state(shape, seed=9)
+    plan = Plan(shape, mu_eff=mu)
+    u0 = plan.init_state(*(torch.from_numpy(a).cuda() for a in (rho, vel, p)))
+    rbar = torch.from_numpy(np.random.default_rng(3).standard_normal((5,) + shape)).cuda()
+    a = plan.rhs_vjp(u0, rbar)
+    noise = torch.randn(1 << 20, device="cuda", dtype=torch.float64).cumsum(0)  # other work between
+    b = plan.rhs_vjp(u0, rbar)
+    assert torch.equal(a, b) and torch.isfinite(noise).all()
+    dt = I.dt_from_speed(plan.diagnostics_host(u0)[7], max(shape))
+    J0, g0 = plan.adjoint_rk4(u0, dt, 6, 6)
+    for ckpt in (1, 2, 4, 5):
+        J, g = plan.adjoint_rk4(u0, dt, 6, ckpt)
+        assert torch.equal(J, J0) and torch.equal(g, g0), ckpt
+
+
 @pytest.mark.parametrize("scheme", ["rk4", "tvdrk3"])
 def test_autograd_forward_returns_J_and_backward_runs_the_reverse_sweep(orc, scheme):
     """The autograd Function's forward runs only the forward pass (checkpoints in a

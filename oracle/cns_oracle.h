@@ -117,6 +117,11 @@ int oracle_cs_rhs_jvp(const orc_grid *g, const orc_phys *ph, const double *u, co
  * the final mean kinetic energy K(u_N); K (may be NULL) = K(u_N) itself. */
 int oracle_cs_step_jvp(const orc_grid *g, const orc_phys *ph, int scheme, const double *u0, const double *d,
                        double dt, int nsteps, double h, double *du, double *dK, double *K);
+/* The gradient dK/du0 of the final mean kinetic energy after nsteps steps (scheme 0 =
+ * RK4, 1 = TVD-RK3) from u0, every component by its own complex-step derivative (5 N^3
+ * complex runs: small grids only); K (may be NULL) = K(u_N). */
+int oracle_adjoint_rk4(const orc_grid *g, const orc_phys *ph, int scheme, const double *u0, double dt, int nsteps,
+                       double h, double *grad, double *K);
 
 #ifdef __cplusplus
 }

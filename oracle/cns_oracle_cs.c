@@ -14,7 +14,9 @@
  * is the derivative of |x| wherever it exists.
  *
  * These derivatives pin the adjoints: <w, R'(u) d> must equal <R'(u)^T w, d>, and the
- * derivative of the final kinetic energy along d must equal <dK/du0, d>.
+ * derivative of the final kinetic energy along d must equal <dK/du0, d>.  On small grids
+ * oracle_adjoint_rk4 forms the whole gradient dK/du0 by its definition, one complex-step
+ * derivative per component of u0.
  */
 #include "cns_oracle.h"
 
@@ -86,5 +88,35 @@ int oracle_cs_step_jvp(const orc_grid *g, const orc_phys *ph, int scheme, const 
         if (K) *K = creal(diag[0]);
     }
     free(z);
+    return rc;
+}
+
+/* The gradient of the final mean kinetic energy with respect to every component of u0,
+ * each entry the complex-step derivative along that unit vector: 5 N^3 complex runs of
+ * nsteps steps (small grids only).  The runs are independent; OpenMP shares them out, and
+ * the loops inside a run stay serial (nested regions are inactive). */
+int oracle_adjoint_rk4(const orc_grid *g, const orc_phys *ph, int scheme, const double *u0, double dt, int nsteps,
+                       double h, double *grad, double *K) {
+    if (!g || !u0 || !grad || !(h > 0.0) || nsteps < 0 || (scheme != 0 && scheme != 1)) return ORC_EINVAL;
+    const long n5 = (long)(5 * npts(g));
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(| : rc)
+    for (long q = 0; q < n5; ++q) {
+        double complex *z = (double complex *)malloc((size_t)n5 * sizeof(double complex));
+        double complex diag[ORC_NDIAG];
+        int r = z ? 0 : ORC_EINVAL;
+        if (!r) {
+            for (long i = 0; i < n5; ++i) z[i] = u0[i];
+            z[q] += I * h;
+            r = scheme == 0 ? orc_cs_rk4(g, ph, z, dt, nsteps, NULL) : orc_cs_tvdrk3(g, ph, z, dt, nsteps, NULL);
+        }
+        if (!r) r = orc_cs_diag(g, ph, z, diag);
+        if (!r) {
+            grad[q] = cimag(diag[0]) / h;
+            if (K && q == 0) *K = creal(diag[0]);
+        }
+        free(z);
+        rc |= r;
+    }
     return rc;
 }

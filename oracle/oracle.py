@@ -72,6 +72,8 @@ def lib():
         L.oracle_cs_rhs_jvp.argtypes = [C.POINTER(Grid), C.POINTER(Phys), _dp, _dp, C.c_double, _dp, _dp]
         L.oracle_cs_step_jvp.argtypes = [C.POINTER(Grid), C.POINTER(Phys), C.c_int, _dp, _dp, C.c_double, C.c_int,
                                          C.c_double, _dp, _dp, _dp]
+        L.oracle_adjoint_rk4.argtypes = [C.POINTER(Grid), C.POINTER(Phys), C.c_int, _dp, C.c_double, C.c_int,
+                                         C.c_double, _dp, _dp]
         _LIB = L
     return _LIB
 
@@ -257,3 +259,17 @@ def step_jvp_cs(u0, d, dt, nsteps, phys: Phys, scheme="rk4", length=(2 * math.pi
     _chk(lib().oracle_cs_step_jvp(C.byref(g), C.byref(phys), sch, _ptr(u0), _ptr(d), float(dt), int(nsteps), float(h),
                                   _ptr(du), C.pointer(dK), C.pointer(K)), "cs_step_jvp")
     return du, dK.value, K.value
+
+
+def adjoint_cs(u0, dt, nsteps, phys: Phys, scheme="rk4", length=(2 * math.pi,) * 3, h=CS_STEP):
+    """``(dK/du0, K)``: the gradient of the final mean kinetic energy after ``nsteps``
+    steps of ``scheme`` with respect to every component of u0, each entry its own
+    complex-step derivative (5 N^3 runs: small grids only)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    grad = np.zeros_like(u0)
+    K = C.c_double(0.0)
+    g = _grid_of(u0, length)
+    sch = {"rk4": 0, "tvdrk3": 1}[scheme]
+    _chk(lib().oracle_adjoint_rk4(C.byref(g), C.byref(phys), sch, _ptr(u0), float(dt), int(nsteps), float(h),
+                                  _ptr(grad), C.pointer(K)), "adjoint_rk4")
+    return grad, K.value

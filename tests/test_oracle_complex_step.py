@@ -7,7 +7,8 @@ along d, which central differences of the FP64 oracle approach quadratically in 
 step.  Those derivatives then pin the reverse-mode reference used for the GPU adjoint
 (oracle/torch_ref.py): <w, R'(u) d> = <R'(u)^T w, d> for the right-hand side and
 <dK/du0, d> = dK(d) through RK4 and TVD-RK3 steps, to rounding rather than to the 1e-7
-of a finite difference.
+of a finite difference; on an 8^3 grid the oracle's whole gradient (every component by
+its own complex step) equals the reference's reverse mode entry by entry.
 """
 import numpy as np
 import pytest
@@ -131,3 +132,24 @@ def test_reverse_mode_reference_gradient_by_complex_step(orc, tr, scheme):
         d = direction(u, 20 + k)
         _, dK, _ = orc.step_jvp_cs(u, d, dt, nsteps, ph, scheme=scheme)
         assert float(np.sum(g * d)) == pytest.approx(dK, rel=1e-12), (k, dK)
+
+
+def test_oracle_gradient_by_complex_step_equals_reverse_mode_reference(orc, tr):
+    # every entry of dK/du0 by its own complex-step run of the oracle (5 x 8^3 runs of 2
+    # RK4 steps) against the reverse-mode reference, entry by entry
+    u = hit_state(orc, (8, 8, 8), seed=6)
+    ph = orc.make_phys(mu_eff=0.02)
+    dt = I.dt_from_speed(orc.diag(u, ph)[7], 8)
+    g_cs, K = orc.adjoint_cs(u, dt, 2, ph)
+    uN, _ = orc.rk4(u, dt, 2, ph, with_diag=False)
+    assert K == orc.diag(uN, ph)[0]
+    uNt = torch.from_numpy(uN).requires_grad_(True)
+    (seed,) = torch.autograd.grad(tr.kinetic_energy(uNt), uNt)
+    g = tr.rk4_vjp(torch.from_numpy(u), seed, dt, 2, tr.make_phys(mu=0.02)).numpy()
+    err = rel_max(g, g_cs)
+    print("reverse mode vs complex-step gradient", err)
+    assert err <= 1e-12
+    # and the directional derivative is its inner product with a direction
+    d = direction(u, 30)
+    _, dK, _ = orc.step_jvp_cs(u, d, dt, 2, ph)
+    assert float(np.sum(g_cs * d)) == pytest.approx(dK, rel=1e-12)

@@ -604,6 +604,7 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
         J.backward()
         return J, v0.grad
 
+    grad()  # warm: the workspace allocation and the first launches stay out of the timing
     gsec, (J, g) = _timed(plan.stream, grad)
     # J alone: the autograd forward (the steps with checkpoints), no reverse sweep
     v0 = vel.clone().requires_grad_(True)
@@ -613,6 +614,14 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
            "autograd_forward_s": jsec, "reverse_over_forward": (gsec - jsec) / fsec,
            "value": 4.0 * n ** 3 * steps / gsec, "unit": "point-RHS/s (forward-step equivalents of the gradient)",
            "J": float(J.detach()), "grad_norm": float(g.norm())}
+    # one vector-Jacobian product against one right-hand side at the same state
+    rbar = torch.randn(u0.shape, dtype=torch.float64, device=u0.device)
+    ub = plan.rhs_vjp(u0, rbar)
+    r = plan.rhs(u0)
+    psec, _ = _timed(plan.stream, lambda: [plan.rhs_vjp(u0, rbar, out=ub) for _ in range(20)])
+    rsec, _ = _timed(plan.stream, lambda: [plan.rhs(u0, out=r) for _ in range(20)])
+    out["product_ms"], out["rhs_ms"] = psec / 20 * 1e3, rsec / 20 * 1e3
+    out["product_over_rhs"] = psec / rsec
     # the same gradient through the TVD-RK3 integrator (checkpoints every ckpt steps)
     plan.tvdrk3(plan.init_state(rho, vel, p), dt, 1, diag=False)
     u3 = plan.init_state(rho, vel, p)
@@ -624,6 +633,7 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
         J.backward()
         return J, v0.grad
 
+    grad3()
     g3, (J3, _) = _timed(plan.stream, grad3)
     out["tvdrk3"] = {"forward_s": f3, "gradient_s": g3, "gradient_over_forward": g3 / f3, "J": float(J3.detach())}
     # one segment (checkpoint interval = all steps): the forward pass keeps the start and
@@ -639,6 +649,7 @@ def bench_adjoint(n=128, steps=200, ckpt=20):
             J.backward()
             return J, v0.grad
 
+        grad1()
         gsec1, (J1, g1) = _timed(plan.stream, grad1)
         out["one_segment"] = {"ckpt_every": steps, "workspace_GB": need / 1e9, "gradient_s": gsec1,
                               "gradient_over_forward": gsec1 / fsec,

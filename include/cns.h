@@ -264,8 +264,9 @@ int cns_ensemble_profile_read(const cns_ensemble *ens, double *ms_host, int64_t 
  * terms.  Extension beyond the paper.
  * adj_ws: caller-owned device scratch of cns_adjoint_workspace_bytes bytes. */
 size_t cns_adjoint_workspace_bytes(const cns_plan *plan, int32_t nsteps, int32_t ckpt_every);
-/* ubar = (dR/du)^T rbar at u (all [5][N3] device arrays, FP64); needs
- * cns_adjoint_workspace_bytes(plan, 0, 1) bytes of adj_ws. */
+/* ubar = (dR/du)^T rbar at u (all [5][N3] device arrays, FP64; ubar must not alias u
+ * or rbar).  The product needs no scratch: adj_ws and bytes are not read (NULL and 0
+ * are fine). */
 int cns_rhs_vjp(const cns_plan *plan, const void *u_dev, const void *rbar_dev, void *ubar_dev, void *adj_ws,
                 size_t bytes);
 /* J = K(u^N) after nsteps RK4 steps of size dt from u0 (K = <|m|^2/(2 rho)>), and

@@ -197,8 +197,7 @@ class Plan:
         self._state(u)
         self._state(rbar, "rbar")
         out = self.empty_state() if out is None else self._state(out, "out")
-        ws, n = self._adj_ws(0, 1)
-        check(self.lib.cns_rhs_vjp(self.h, _ptr(u), _ptr(rbar), _ptr(out), _ptr(ws), n), "cns_rhs_vjp")
+        check(self.lib.cns_rhs_vjp(self.h, _ptr(u), _ptr(rbar), _ptr(out), None, 0), "cns_rhs_vjp")
         return out
 
     def adjoint_rk4(self, u0, dt, nsteps, ckpt_every):

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_conv(AdjGeom g, const double *__
     const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
     const int ta = lane / LW;  // interface within the chunk
     const int tl = lane % LW;  // line within the wave
-    const int tb = w * LW + tl;                   // line within the block
+    const int tb = w * LW + tl;  // line within the block
     // ring slot of cell e for component v: the wave's own region, consecutive lanes
     // on consecutive doubles
     auto slot = [&](int e, int v) -> int { return ((w * 5 + v) * RS + ((e + 2) & (RS - 1))) * LW + tl; };

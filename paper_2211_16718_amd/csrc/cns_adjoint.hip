@@ -566,14 +566,7 @@ __global__ __launch_bounds__(kPointThreads, 2) void k_adj_visc(AdjGeom g, const 
             for (int v = 0; v < 5; ++v) {
                 const size_t o = v * n3 + po;
                 if (ep.store_ub) ubar[o] = fin[v];
-                if (ep.ubf) {
-                    const double tt = ep.S[o] + fin[v], nu = ep.ubf[o] + tt;
-                    ep.ubf[o] = nu;
-                    if (ep.kb) ep.kb[o] = ep.a * nu;
-                } else {
-                    if (ep.S) ep.S[o] = ep.s_first ? fin[v] : ep.S[o] + fin[v];
-                    if (ep.kb) ep.kb[o] = __fma_rn(ep.a, ep.ub[o], ep.b * fin[v]);
-                }
+                adj_epilogue_at(ep, o, fin[v]);
             }
         }
         // advance the rings; plane k+3 enters them
@@ -667,15 +660,7 @@ static void adj_conv(const BoxDesc &b, hipStream_t s, const AdjGeom &g, const do
 __global__ void k_epilogue(size_t n, const double *__restrict__ fin, AdjEpilogue e) {
     const size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (o >= n) return;
-    const double f = fin[o];
-    if (e.ubf) {
-        const double t = e.S[o] + f, nu = e.ubf[o] + t;
-        e.ubf[o] = nu;
-        if (e.kb) e.kb[o] = e.a * nu;
-    } else {
-        if (e.S) e.S[o] = e.s_first ? f : e.S[o] + f;
-        if (e.kb) e.kb[o] = __fma_rn(e.a, e.ub[o], e.b * f);
-    }
+    adj_epilogue_at(e, o, fin[o]);
 }
 
 static void rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,

@@ -1091,6 +1091,7 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
     auto state = [&](size_t base, int i) { return (double *)(w + base + (size_t)i * st); };
     double *X = state(L.X, 0), *ub = state(L.ub, 0), *kb = state(L.kb, 0), *Ub = state(L.Ub, 0), *S = state(L.S, 0);
     double *kb2 = state(L.kb2, 0);
+    double *seed = kb, *other = kb2;  // TVD-RK3: the buffer holding the next product's seed
     hipStream_t s = c.stream;
     Batch bt = c.batch();
     bt.prof = nullptr;
@@ -1113,19 +1114,20 @@ static int adjoint_reverse(cns_plan *plan, int scheme, double dt, int32_t nsteps
                 //   Ubar2 = 2/3 ub + R'(U2)^T (2/3 dt ub)
                 //   Ubar1 = 1/4 Ubar2 + R'(U1)^T (1/4 dt Ubar2)
                 //   ub   <- 1/3 ub + 3/4 Ubar2 + Ubar1 + R'(u)^T (dt Ubar1)
-                // (S holds Ubar2 and X, free during the reverse steps, holds Ubar1)
+                // (S holds Ubar2 and X, free during the reverse steps, holds Ubar1).  Each
+                // combination and the next seed (2/3 dt ub for the next step) are formed
+                // at the end of the product that finishes them.
                 const double *U1 = state(L.seg, 4 * (n - n0) + 1), *U2 = state(L.seg, 4 * (n - n0) + 2);
-                adj_lincomb(n5, 2.0 / 3.0 * dt, ub, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, c.weights, s, U2, kb, Ub);
-                adj_lincomb(n5, 2.0 / 3.0, ub, 1.0, Ub, S, s);
-                adj_lincomb(n5, 0.25 * dt, S, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, c.weights, s, U1, kb, Ub);
-                adj_lincomb(n5, 0.25, S, 1.0, Ub, X, s);
-                adj_lincomb(n5, dt, X, 0.0, nullptr, kb, s);
-                adj_rhs_vjp(b, c.weights, s, Y, kb, Ub);
-                adj_lincomb(n5, 1.0 / 3.0, ub, 0.75, S, ub, s);
-                adj_accum(n5, X, ub, s);
-                adj_accum(n5, Ub, ub, s);
+                if (n == nsteps - 1) adj_lincomb(n5, 2.0 / 3.0 * dt, ub, 0.0, nullptr, seed, s);
+                AdjEpilogue t2, t1, t0;
+                t2.la = ub, t2.pa = 2.0 / 3.0, t2.ld = S, t2.lkb = other, t2.ls = 0.25 * dt, t2.store_ub = 0;
+                t1.la = S, t1.pa = 0.25, t1.ld = X, t1.lkb = seed, t1.ls = dt, t1.store_ub = 0;
+                t0.la = ub, t0.pa = 1.0 / 3.0, t0.lb = S, t0.pb = 0.75, t0.lc = X, t0.pc = 1.0, t0.ld = ub;
+                t0.lkb = other, t0.ls = 2.0 / 3.0 * dt, t0.store_ub = 0;
+                adj_rhs_vjp_epi(b, c.weights, s, U2, seed, Ub, t2);
+                adj_rhs_vjp_epi(b, c.weights, s, U1, other, Ub, t1);
+                adj_rhs_vjp_epi(b, c.weights, s, Y, seed, Ub, t0);
+                std::swap(seed, other);  // three seeds a step: the buffers trade places
                 continue;
             }
             const double *U2 = state(L.seg, 4 * (n - n0) + 1), *U3 = state(L.seg, 4 * (n - n0) + 2),

@@ -5,13 +5,15 @@
 // + sum_d D_d G^v_d is assembled as
 //   convective part, per direction d:  Hbar_{j+1/2} = (rbar_{j+1} - rbar_j)/dx_d;
 //     k_adj_conv<d>: one thread per interface forms the local product of the
-//     interface flux (30 contributions to the six cells it reads) and adds them,
-//     in a fixed order, into LDS accumulators of the cells, which are then written;
+//     interface flux (the point-flux and state adjoints of the six cells it reads)
+//     and adds them, in a fixed order, into LDS accumulators of the cells, which are
+//     then finished and written;
 //   viscous part: the adjoint of a central difference is minus the same central
 //     difference, so Gbar_d = -D_d rbar; k_adj_visc maps it through the viscous
 //     fluxes to the adjoints of the velocity/temperature gradients and of the
 //     point velocities, applies -D once more and the primitive map, in one pass.
-// Every sum is formed in a fixed order (deterministic, no atomics).
+// Every sum is formed in a fixed order (deterministic: the LDS atomic adds into a cell
+// come from one wave, whose LDS operations take effect in program order).
 #include <hip/hip_runtime.h>
 
 #include "cns_adjoint.h"
@@ -603,12 +605,7 @@ __global__ void k_lincomb(size_t n, double a, const double *__restrict__ x, doub
     out[i] = y ? a * x[i] + b * y[i] : a * x[i];
 }
 
-// out += x
-__global__ void k_accum(size_t n, const double *__restrict__ x, double *__restrict__ out) {
-    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] += x[i];
-}
-
+// out = x
 __global__ void k_copy(size_t n, const double *__restrict__ x, double *__restrict__ out) {
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (i < n) out[i] = x[i];
@@ -693,9 +690,6 @@ void adj_rhs_vjp_epi(const BoxDesc &b, int weights, hipStream_t s, const double 
 
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_lincomb, grid1(n), dim3(256), 0, s, n, a, x, b, y, out);
-}
-void adj_accum(size_t n, const double *x, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_accum, grid1(n), dim3(256), 0, s, n, x, out);
 }
 void adj_copy(size_t n, const double *x, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, grid1(n), dim3(256), 0, s, n, x, out);

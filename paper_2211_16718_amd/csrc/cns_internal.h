@@ -206,7 +206,6 @@ void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, d
 // adjoint of the full RHS at u: ubar = (dR/du)^T rbar
 void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar);
 void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
-void adj_accum(size_t n, const double *x, double *out, hipStream_t s);
 void adj_copy(size_t n, const double *x, double *out, hipStream_t s);
 void adj_ke_seed(size_t n3, const double *u, double *ubar, hipStream_t s);
 void adj_ic_vjp(size_t n3, const double *rho, const double *vel, const double *ubar, double *vbar, hipStream_t s);

@@ -1,4 +1,5 @@
-// cns_adjoint.h -- the stage-combination epilogue of the reverse RK4 sweep (cns_adjoint.hip).
+// cns_adjoint.h -- launchers of the reverse-mode kernels (cns_adjoint.hip), FP64, one box,
+// and the stage-combination epilogue of the reverse sweeps.
 #pragma once
 
 #include "cns_internal.h"
@@ -49,6 +50,13 @@ __device__ __forceinline__ void adj_epilogue_at(const AdjEpilogue &ep, size_t o,
         if (ep.kb) ep.kb[o] = __fma_rn(ep.a, ep.ub[o], ep.b * f);
     }
 }
+
+// adjoint of the full RHS at u: ubar = (dR/du)^T rbar
+void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar);
+void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
+void adj_copy(size_t n, const double *x, double *out, hipStream_t s);
+void adj_ke_seed(size_t n3, const double *u, double *ubar, hipStream_t s);
+void adj_ic_vjp(size_t n3, const double *rho, const double *vel, const double *ubar, double *vbar, hipStream_t s);
 
 // adj_rhs_vjp followed by the epilogue
 void adj_rhs_vjp_epi(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar,

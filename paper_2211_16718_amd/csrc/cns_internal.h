@@ -202,12 +202,4 @@ int spectrum_shells(const BoxDesc &b);
 bool spectrum_supported(const BoxDesc &b);
 void launch_spectrum(const BoxDesc &b, int prec, hipStream_t s, const void *u, double *E, int nshell, double *mom);
 
-// adjoint launchers (cns_adjoint.hip), FP64, one box
-// adjoint of the full RHS at u: ubar = (dR/du)^T rbar
-void adj_rhs_vjp(const BoxDesc &b, int weights, hipStream_t s, const double *u, const double *rbar, double *ubar);
-void adj_lincomb(size_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
-void adj_copy(size_t n, const double *x, double *out, hipStream_t s);
-void adj_ke_seed(size_t n3, const double *u, double *ubar, hipStream_t s);
-void adj_ic_vjp(size_t n3, const double *rho, const double *vel, const double *ubar, double *vbar, hipStream_t s);
-
 }  // namespace cns

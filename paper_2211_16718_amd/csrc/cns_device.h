@@ -149,10 +149,10 @@ __device__ __forceinline__ T weno5_combine(B b1, B b2, B b3, T eps, T c1, T c2, 
 
 // The Jiang-Shu weighted sum of one reconstruction as numerator and denominator
 // (the weights' common scale s_1^2 s_2^2 s_3^2 divided out by the caller): 10 alpha_k
-// s1^2 s2^2 s3^2 = (d2 d3, 6 d1 d3, 3 d1 d2) with d_k = s_k^2.
+// s1^2 s2^2 s3^2 = (d2 d3, 6 d1 d3, 3 d1 d2) with d_k = s_k^2, s_k = eps + beta_k (in
+// any common scale).
 template <typename T>
-__device__ __forceinline__ void weno5_js_terms(T b1, T b2, T b3, T eps, T c1, T c2, T c3, T &num, T &den) {
-    T s1 = eps + b1, s2 = eps + b2, s3 = eps + b3;
+__device__ __forceinline__ void weno5_js_terms(T s1, T s2, T s3, T c1, T c2, T c3, T &num, T &den) {
     T d1 = s1 * s1, d2 = s2 * s2, d3 = s3 * s3;
     T a1 = d2 * d3, a2 = d1 * d3, a3 = d1 * d2;
     num = a1 * c1 + a2 * (T(6) * c2) + a3 * (T(3) * c3);
@@ -184,26 +184,31 @@ __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T 
     B fa = bp3 - B(4) * bp2 + B(3) * bp1;
     B fb = bp2 - bc0;
     B fc = B(3) * bp1 - B(4) * bc0 + bm1;
-    const B qb = k * db * db, qc = k * dc * dc;  // shared by the two biases
-    B bL1 = k * da * da + ea * ea;
-    B bL2 = qb + eb * eb;
-    B bL3 = qc + ec * ec;
-    B bR1 = k * dd * dd + fa * fa;
-    B bR2 = qc + fb * fb;
-    B bR3 = qb + fc * fc;
-
     if constexpr (WW == CNS_WENO_JS && sizeof(T) == sizeof(B)) {
-        // FP64 Jiang-Shu: the two weight denominators share one reciprocal,
+        // FP64 Jiang-Shu.  eps4 enters each sum before the E^2 term, S = ((13/3) D^2 +
+        // eps4) + E^2 = 4 (eps + beta): one fused multiply-add per indicator instead of a
+        // product and an addition.  The two weight denominators share one reciprocal,
         // 1/D_L = D_R / (D_L D_R) (one refined reciprocal and three products instead of
         // two reciprocals; the product of the two is a product of eight (eps + beta)
         // factors, inside the FP64 range for the eps and beta the plan admits)
+        const T kda = k * da, kdb = k * db, kdc = k * dc, kdd = k * dd;
+        const T sb = kdb * db + eps4, sc = kdc * dc + eps4;  // shared by the two biases
+        const T SL1 = (kda * da + eps4) + ea * ea, SL2 = sb + eb * eb, SL3 = sc + ec * ec;
+        const T SR1 = (kdd * dd + eps4) + fa * fa, SR2 = sc + fb * fb, SR3 = sb + fc * fc;
         T nL, dL, nR, dR;
-        weno5_js_terms<T>(bL1, bL2, bL3, eps4, L1, L2, L3, nL, dL);
-        weno5_js_terms<T>(bR1, bR2, bR3, eps4, R1, L3, L2, nR, dR);
+        weno5_js_terms<T>(SL1, SL2, SL3, L1, L2, L3, nL, dL);
+        weno5_js_terms<T>(SR1, SR2, SR3, R1, L3, L2, nR, dR);
         const T r = rcp(dL * dR);
         L6 = nL * (dR * r);
         R6 = nR * (dL * r);
     } else {
+        const B qb = k * db * db, qc = k * dc * dc;  // shared by the two biases
+        B bL1 = k * da * da + ea * ea;
+        B bL2 = qb + eb * eb;
+        B bL3 = qc + ec * ec;
+        B bR1 = k * dd * dd + fa * fa;
+        B bR2 = qc + fb * fb;
+        B bR3 = qb + fc * fc;
         L6 = weno5_combine<T, B, WW>(bL1, bL2, bL3, eps4, L1, L2, L3);
         R6 = weno5_combine<T, B, WW>(bR1, bR2, bR3, eps4, R1, L3, L2);
     }

@@ -165,25 +165,38 @@ __device__ __forceinline__ void weno5_js_terms(T s1, T s2, T s3, T c1, T c2, T c
 // the indicators saves a multiplication per candidate and per indicator.
 template <typename T, typename B, int WW = CNS_WENO_JS>
 __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T eps4, T &L6, T &R6) {
-    // third-order candidates (times 6); the mirror reconstruction reuses L2 and L3
-    T L1 = T(2) * m2 - T(7) * m1 + T(11) * c0;
-    T L2 = -m1 + T(5) * c0 + T(2) * p1;
-    T L3 = T(2) * c0 + T(5) * p1 - p2;
-    T R1 = T(2) * p3 - T(7) * p2 + T(11) * p1;
-
-    // 4 x Jiang-Shu smoothness indicators, (13/3) D^2 + E^2, accumulated in B
+    // 4 x Jiang-Shu smoothness indicators, (13/3) D^2 + E^2, accumulated in B, from the
+    // first differences g_i = q_{i+1} - q_i of the stencil (q = m2, m1, c0, p1, p2, p3):
+    // the second differences D and the one-sided E are short combinations of them
     const B k = B(13) / B(3);
     const B bm2 = B(m2), bm1 = B(m1), bc0 = B(c0), bp1 = B(p1), bp2 = B(p2), bp3 = B(p3);
-    B da = bm2 - B(2) * bm1 + bc0;  // second differences centred at j-1, j, j+1, j+2
-    B db = bm1 - B(2) * bc0 + bp1;
-    B dc = bc0 - B(2) * bp1 + bp2;
-    B dd = bp1 - B(2) * bp2 + bp3;
-    B ea = bm2 - B(4) * bm1 + B(3) * bc0;
-    B eb = bm1 - bp1;
-    B ec = B(3) * bc0 - B(4) * bp1 + bp2;
-    B fa = bp3 - B(4) * bp2 + B(3) * bp1;
-    B fb = bp2 - bc0;
-    B fc = B(3) * bp1 - B(4) * bc0 + bm1;
+    const B g0 = bm1 - bm2, g1 = bc0 - bm1, g2 = bp1 - bc0, g3 = bp2 - bp1, g4 = bp3 - bp2;
+    B da = g1 - g0;  // second differences centred at j-1, j, j+1, j+2
+    B db = g2 - g1;
+    B dc = g3 - g2;
+    B dd = g4 - g3;
+    B ea = B(3) * g1 - g0;  // m2 - 4 m1 + 3 c0
+    B eb = g1 + g2;         // p1 - m1 (squared: the sign does not matter)
+    B ec = g3 - B(3) * g2;  // 3 c0 - 4 p1 + p2
+    B fa = g4 - B(3) * g3;  // p3 - 4 p2 + 3 p1
+    B fb = g2 + g3;         // p2 - c0
+    B fc = B(3) * g2 - g1;  // 3 p1 - 4 c0 + m1
+    // third-order candidates (times 6); the mirror reconstruction reuses L2 and L3.  In
+    // FP64 from the same first differences (L1 = 6 c0 + 5 g1 - 2 g0, L2 = 6 c0 + g1 +
+    // 2 g2, L3 = 6 c0 + 4 g2 - g3, R1 = 6 p1 - 5 g3 + 2 g4), in FP32 from the points.
+    T L1, L2, L3, R1;
+    if constexpr (sizeof(T) == sizeof(B)) {
+        const T c6 = T(6) * c0;
+        L1 = c6 + T(5) * g1 - T(2) * g0;
+        L2 = c6 + g1 + T(2) * g2;
+        L3 = c6 + T(4) * g2 - g3;
+        R1 = T(6) * p1 - T(5) * g3 + T(2) * g4;
+    } else {
+        L1 = T(2) * m2 - T(7) * m1 + T(11) * c0;
+        L2 = -m1 + T(5) * c0 + T(2) * p1;
+        L3 = T(2) * c0 + T(5) * p1 - p2;
+        R1 = T(2) * p3 - T(7) * p2 + T(11) * p1;
+    }
     if constexpr (WW == CNS_WENO_JS && sizeof(T) == sizeof(B)) {
         // FP64 Jiang-Shu.  eps4 enters each sum before the E^2 term, S = ((13/3) D^2 +
         // eps4) + E^2 = 4 (eps + beta): one fused multiply-add per indicator instead of a

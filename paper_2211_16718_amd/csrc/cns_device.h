@@ -175,10 +175,12 @@ __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T 
     B db = g2 - g1;
     B dc = g3 - g2;
     B dd = g4 - g3;
+    // the one-sided terms only enter squared, so each is formed with whichever sign
+    // keeps it one fused multiply-add
     B ea = B(3) * g1 - g0;  // m2 - 4 m1 + 3 c0
-    B eb = g1 + g2;         // p1 - m1 (squared: the sign does not matter)
-    B ec = g3 - B(3) * g2;  // 3 c0 - 4 p1 + p2
-    B fa = g4 - B(3) * g3;  // p3 - 4 p2 + 3 p1
+    B eb = g1 + g2;         // -(m1 - p1)
+    B ec = B(3) * g2 - g3;  // -(3 c0 - 4 p1 + p2)
+    B fa = B(3) * g3 - g4;  // -(p3 - 4 p2 + 3 p1)
     B fb = g2 + g3;         // p2 - c0
     B fc = B(3) * g2 - g1;  // 3 p1 - 4 c0 + m1
     // third-order candidates (times 6); the mirror reconstruction reuses L2 and L3.  In
@@ -186,10 +188,12 @@ __device__ __forceinline__ void weno5_lr6(T m2, T m1, T c0, T p1, T p2, T p3, T 
     // 2 g2, L3 = 6 c0 + 4 g2 - g3, R1 = 6 p1 - 5 g3 + 2 g4), in FP32 from the points.
     T L1, L2, L3, R1;
     if constexpr (sizeof(T) == sizeof(B)) {
+        // 6 c0 enters last, by an addition: as the accumulator of a chain of fused
+        // multiply-adds it would be copied for each of the three
         const T c6 = T(6) * c0;
-        L1 = c6 + T(5) * g1 - T(2) * g0;
-        L2 = c6 + g1 + T(2) * g2;
-        L3 = c6 + T(4) * g2 - g3;
+        L1 = (T(5) * g1 - T(2) * g0) + c6;
+        L2 = (g1 + T(2) * g2) + c6;
+        L3 = (T(4) * g2 - g3) + c6;
         R1 = T(6) * p1 - T(5) * g3 + T(2) * g4;
     } else {
         L1 = T(2) * m2 - T(7) * m1 + T(11) * c0;

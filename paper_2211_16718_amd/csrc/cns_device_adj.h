@@ -122,15 +122,23 @@ __device__ __forceinline__ void weno5_lr_vjp(const double q[6], double eps, doub
                                              double &Lv, double &Rv) {
     const double m2 = q[0], m1 = q[1], c0 = q[2], p1 = q[3], p2 = q[4], p3 = q[5];
     if constexpr (WW == CNS_WENO_JS) {
-        // six times the candidates; the right-biased side reuses L2, L3 mirrored
-        const double L1 = 2.0 * m2 - 7.0 * m1 + 11.0 * c0;
-        const double L2 = -m1 + 5.0 * c0 + 2.0 * p1;
-        const double L3 = 2.0 * c0 + 5.0 * p1 - p2;
-        const double R1 = 2.0 * p3 - 7.0 * p2 + 11.0 * p1;
-        const double da = m2 - 2.0 * m1 + c0, db = m1 - 2.0 * c0 + p1, dc = c0 - 2.0 * p1 + p2,
-                     dd = p1 - 2.0 * p2 + p3;
-        const double ea = m2 - 4.0 * m1 + 3.0 * c0, eb = m1 - p1, ec = 3.0 * c0 - 4.0 * p1 + p2;
-        const double fa = p3 - 4.0 * p2 + 3.0 * p1, fb = p2 - c0, fc = 3.0 * p1 - 4.0 * c0 + m1;
+        // six times the candidates (the right-biased side reuses L2, L3 mirrored), the
+        // second differences and the one-sided terms, all from the first differences
+        // g_i = q_{i+1} - q_i as in the forward (the terms keep their signs here: the
+        // scatter below uses them unsquared)
+        const double g0 = m1 - m2, g1 = c0 - m1, g2 = p1 - c0, g3 = p2 - p1, g4 = p3 - p2;
+        const double c6 = 6.0 * c0;
+        const double L1 = (5.0 * g1 - 2.0 * g0) + c6;     // 2 m2 - 7 m1 + 11 c0
+        const double L2 = (g1 + 2.0 * g2) + c6;           // -m1 + 5 c0 + 2 p1
+        const double L3 = (4.0 * g2 - g3) + c6;           // 2 c0 + 5 p1 - p2
+        const double R1 = 6.0 * p1 - 5.0 * g3 + 2.0 * g4;  // 2 p3 - 7 p2 + 11 p1
+        const double da = g1 - g0, db = g2 - g1, dc = g3 - g2, dd = g4 - g3;
+        const double ea = 3.0 * g1 - g0;     // m2 - 4 m1 + 3 c0
+        const double eb = -(g1 + g2);        // m1 - p1
+        const double ec = -(3.0 * g2 - g3);  // 3 c0 - 4 p1 + p2
+        const double fa = -(3.0 * g3 - g4);  // p3 - 4 p2 + 3 p1
+        const double fb = g2 + g3;           // p2 - c0
+        const double fc = 3.0 * g2 - g1;     // 3 p1 - 4 c0 + m1
         // S = 4 eps + (13/3) d^2 + e^2
         const double k = 13.0 / 3.0, e4 = 4.0 * eps;
         const double kda = k * da, kdb = k * db, kdc = k * dc, kdd = k * dd;

@@ -620,26 +620,34 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
         const gptr<T> rhs_out = uni(glob((T *)(L.out_ov ? L.out_ov : bx.rhs)));
 
         T w[6][5], g[4][4], Hp[5], nw[5];
-        // One loop computes everything, so every point flux and every interface flux
-        // runs the same machine code wherever a segment starts: results are bitwise
-        // independent of the segment length.  Iteration j takes point j+3 (loaded one
-        // iteration ahead) and the viscous fluxes of point j+2; from j = j0-1 on it
-        // forms the interface flux at j+1/2 and from j = j0 on the flux difference at
-        // point j.
+        // One step body computes everything, so every point flux and every interface
+        // flux takes the same arithmetic in the same order wherever a segment starts:
+        // results are bitwise independent of the segment length.  Step j takes point
+        // j+3 (loaded one step ahead) and the viscous fluxes of point j+2; from j = j0-1
+        // on it forms the interface flux at j+1/2 and from j = j0 on the flux difference
+        // at point j.
         {
             const uint32_t bo = (uint32_t)((base + wrapi(j0 - 3, n) * sg.lstride) * sizeof(T));
 #pragma unroll
             for (int v = 0; v < 5; ++v) nw[v] = *elem(u, n3, v, bo);
         }
         int snew = 3;  // ring slot of point j+3; point j-2+m sits in slot (snew + 1 + m) mod 6
-#pragma nounroll
-        for (int j = j0 - 6; j < j1; ++j) {
+        auto step = [&](const int j) {
 #pragma unroll
             for (int m = 0; m < 5; ++m)
 #pragma unroll
                 for (int v = 0; v < 5; ++v) w[m][v] = w[m + 1][v];
 #pragma unroll
             for (int v = 0; v < 5; ++v) w[5][v] = nw[v];
+            // The window enters each step through an empty asm, so the two steps of a
+            // pass share no arithmetic (the optimiser would otherwise form a point's Roe
+            // terms once for both interfaces, outside the block where the other step
+            // fuses them into multiply-adds): every interface flux is computed by the
+            // same instructions in either step, bitwise as with one step per pass.
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) asm volatile("" : "+v"(w[m][v]));
             {
                 const uint32_t bo = (uint32_t)((base + wrapi(j + 4, n) * sg.lstride) * sizeof(T));
 #pragma unroll
@@ -655,6 +663,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
                 g[3][1] = load_gb<DIR, 1>(G, n3, bog);
                 g[3][2] = load_gb<DIR, 2>(G, n3, bog);
                 g[3][3] = load_gb<DIR, 3>(G, n3, bog);
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(g[m][c]));
             }
             const int sold = snew;
             {
@@ -664,7 +676,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
                 for (int v = 0; v < 5; ++v) ring[(snew * 5 + v) * bdim] = fn[v];
                 snew = snew == 5 ? 0 : snew + 1;
             }
-            if (j < j0 - 1) continue;
+            if (j < j0 - 1) return;
 
             // output operands of point j, loaded before the interface-flux arithmetic
             const size_t o = base + (size_t)(j >= j0 ? j : j0) * sg.lstride;
@@ -763,7 +775,17 @@ __global__ __launch_bounds__(256, 2) void k_sweep(Launch L0) {
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) Hp[v] = H[v];
+        };
+        // Two steps per pass: the window shifts of the first step become register
+        // renamings instead of copies (y sweep 64 -> 26, z sweep 66 -> 30 64-bit moves
+        // per point).
+        int j = j0 - 6;
+#pragma nounroll
+        for (; j + 1 < j1; j += 2) {
+            step(j);
+            step(j + 1);
         }
+        if (j < j1) step(j);
     }
 }
 

@@ -939,8 +939,13 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
 constexpr int kChunkPts = kRowThreads + 5;  // points staged per chunk
 __host__ __device__ __forceinline__ size_t chunk_lds_bytes(size_t esz) { return (14 * kChunkPts + 5) * esz; }
 
+// FP64 Jiang-Shu and WENO-Z: at least five waves per SIMD (96 VGPRs, two of them
+// spilled around the chunk loop) hide the chunk barriers better than four: 512^3 x
+// sweep -3 %.  The mapped weights would spill more; FP32 states need fewer registers
+// (more waves by themselves, which the bound would cap).
 template <typename T, typename B, bool VISC, int WW>
-__global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_chunks(Launch L0) {
+__global__ __launch_bounds__(kRowThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && WW != CNS_WENO_M ? 5 : 2))) void k_sweep_x_chunks(Launch L0) {
     const Launch L = with_params(L0);
     extern __shared__ unsigned char lds_raw[];
     T *su = reinterpret_cast<T *>(lds_raw);  // [5][kChunkPts] states, later the interface fluxes

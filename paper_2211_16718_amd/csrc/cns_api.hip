@@ -248,7 +248,8 @@ struct Core {
             bt.total[f] = total[f];
         }
         bt.rowP = rowP;
-        bt.rowLds = rowLds;
+        // with one point per thread the rows kernel lays its fields 256 points apart
+        bt.rowLds = rowP == 1 && rowLds > 0 ? (size_t)14 * kRowThreads * esz : rowLds;
         bt.esz = esz;
         for (int f = 0; f < F_N; ++f) bt.grid[f] = grid[f];
         bt.stream = stream;

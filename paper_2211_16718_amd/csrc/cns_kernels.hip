@@ -839,10 +839,13 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_sweep_x_rows(Launch L0) {
         const int bi = find_box(L.off, L.nbox, vb);
         const BoxDesc &bx = L.boxes[bi];
         const int nx = bx.nx;
-        const int per = bx.rows * nx;  // points of the block
-        T *su = lds;                   // [5][per] states, later the interface fluxes
-        T *sf = su + 5 * per;          // [5][per] point fluxes
-        T *sg = sf + 5 * per;          // [4][per] viscous fluxes (VISC)
+        // LDS stride of a field: the block's points, or with one point per thread (every
+        // block of rows fits 256 points) the constant 256, which turns the component
+        // offsets of the stencil reads into immediates
+        const int per = P == 1 ? kRowThreads : bx.rows * nx;
+        T *su = lds;           // [5][per] states, later the interface fluxes
+        T *sf = su + 5 * per;  // [5][per] point fluxes
+        T *sg = sf + 5 * per;  // [4][per] viscous fluxes (VISC)
         const size_t n3 = bx.n3;
         const T gamma = T(bx.gamma), eps4 = T(4.0 * bx.eps), delta = T(bx.delta);
         const T gm1 = gamma - T(1);
